@@ -1,0 +1,339 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these tests touches the HIP library.  Each pin is chosen so that a
+plausible slip in the oracle (a wrong bucket start, a dropped term, an order
+swap, a wrong chunk mapping, a missed wrap-around) fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from paper_2209_00103_amd import workloads as wl
+from tests.conftest import read_golden
+
+U32 = (1 << 32) - 1
+U64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------------------
+# Generators: published SplitMix64 output; the oracle's and numpy's copies.
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_vectors():
+    for state, out in read_golden("splitmix64_vectors.txt"):
+        s, o = int(state, 16), int(out, 16)
+        assert oracle.splitmix64(s) == o
+        assert int(wl.splitmix64(np.array([s], dtype=np.uint64))[0]) == o
+
+
+def test_generator_K_oracle_matches_numpy():
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 1 << 48, size=4096, dtype=np.uint64)
+    b = rng.integers(0, 256, size=4096, dtype=np.uint64)
+    for seed in (0, 1, 42, 209, 255):
+        ref = wl.K(seed, a, b)
+        for i in range(0, 4096, 97):
+            assert oracle.K(seed, int(a[i]), int(b[i])) == int(ref[i])
+
+
+def test_generator_K_field_layout():
+    # K packs seed, a, b into disjoint bit fields: changing any one changes the input word.
+    assert oracle.K(1, 0, 0) == oracle.splitmix64(1 << 56)
+    assert oracle.K(0, 1, 0) == oracle.splitmix64(1 << 8)
+    assert oracle.K(0, 0, 1) == oracle.splitmix64(1)
+    assert oracle.K(3, 5, 7) == oracle.splitmix64((3 << 56) | (5 << 8) | 7)
+
+
+def test_poisson_thresholds_distribution():
+    thr = wl.poisson_thresholds(3, 16)
+    assert np.all(np.diff(thr.astype(object)) > 0)
+    # T[0] = floor(2^64 e^-3); compare with float to 1e-12 relative.
+    assert abs(int(thr[0]) / 2.0 ** 64 - np.exp(-3.0)) < 1e-12
+    c = wl.poisson_counts(1, 0, 1 << 20, thr).astype(np.float64)
+    assert abs(c.mean() - 3.0) < 0.01
+    assert abs(c.var() - 3.0) < 0.03
+    assert abs((c == 0).mean() - np.exp(-3.0)) < 0.002
+    assert c.max() <= 16
+
+
+# ---------------------------------------------------------------------------
+# Bucket law and index mapping (Alg. 1 get_bucket, Alg. 2 bucket size).
+# ---------------------------------------------------------------------------
+def test_walk_hand_examples():
+    for F, idx, b, off in read_golden("bucket_map_hand.txt"):
+        assert oracle.walk(int(F), int(idx)) == (int(b), int(off))
+
+
+def _closed_form(F, idx):
+    # p = idx + F has its top bit at h; bucket b = h - log2 F, offset p - 2^h.
+    p = idx + F
+    h = p.bit_length() - 1
+    return h - (F.bit_length() - 1), p - (1 << h)
+
+
+@pytest.mark.parametrize("logF", range(0, 15))
+def test_walk_equals_closed_form_exhaustive(logF):
+    F = 1 << logF
+    n = 1 << 16
+    idx = np.arange(n, dtype=np.uint64)
+    b, off = oracle.walk_many(F, idx)
+    p = idx + np.uint64(F)
+    h = np.floor(np.log2(p.astype(np.float64))).astype(np.int64)  # exact below 2^53
+    assert np.array_equal(b.astype(np.int64), h - logF)
+    assert np.array_equal(off.astype(np.int64), (p - (np.uint64(1) << h.astype(np.uint64))).astype(np.int64))
+
+
+def test_walk_bucket_boundaries_up_to_40():
+    for logF in (0, 3, 10, 14):
+        F = 1 << logF
+        for b in range(0, 41 - logF if logF else 41):
+            start = F * ((1 << b) - 1)
+            assert oracle.bucket_start(F, b) == start
+            for idx in (start - 1, start, start + 1):
+                if idx < 0:
+                    continue
+                assert oracle.walk(F, idx) == _closed_form(F, idx)
+
+
+def test_nbuckets_and_capacity_closed_form():
+    # nb(s) = min k with F(2^k - 1) >= s; hand values for F = 4.
+    hand = {0: 0, 1: 1, 4: 1, 5: 2, 12: 2, 13: 3, 28: 3, 29: 4}
+    for s, nb in hand.items():
+        assert oracle.nbuckets_for(4, s) == nb
+    for logF in range(0, 12):
+        F = 1 << logF
+        for s in list(range(0, 300)) + [F * ((1 << k) - 1) + d for k in range(1, 20) for d in (-1, 0, 1)]:
+            nb = oracle.nbuckets_for(F, s)
+            assert (nb == 0) == (s == 0)
+            if s:
+                assert F * ((1 << nb) - 1) >= s > F * ((1 << (nb - 1)) - 1)
+                # exact memory bound: capacity <= 2 s + F - 1
+                assert F * ((1 << nb) - 1) <= 2 * s + F - 1
+
+
+# ---------------------------------------------------------------------------
+# Insertion: hand example, stream compaction, chunk mapping, order.
+# ---------------------------------------------------------------------------
+def _golden_dict(name):
+    return {row[0]: [int(x) for x in row[1:]] for row in read_golden(name)}
+
+
+def test_tiny_hand_example():
+    g = _golden_dict("tiny_insert_hand.txt")
+    o = Oracle(4, 2, 1)
+    o.insert(np.array(g["values"], dtype=np.uint32), np.array(g["flags"], dtype=np.uint8))
+    assert o.vector_sizes().tolist() == g["after_insert_sizes"]
+    assert o.flatten().tolist() == g["after_insert_flatten"]
+    assert o.capacity() == g["after_insert_capacity"][0]
+    assert o.vector_nbuckets().tolist() == g["after_insert_nbuckets"]
+    assert o.check() == 0
+    o.shrink(1, 2)
+    assert o.vector_sizes().tolist() == g["after_shrink_sizes"]
+    assert o.flatten().tolist() == g["after_shrink_flatten"]
+    assert o.capacity() == g["after_shrink_capacity"][0]
+    o.rw(oracle.OP_ADD1)
+    assert o.flatten().tolist() == g["after_rw_flatten"]
+    assert o.check() == 0
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+@pytest.mark.parametrize("V,n,p", [(1, 1000, 0.5), (7, 1000, 0.3), (64, 5000, 0.9), (300, 257, 0.5),
+                                   (16, 0, 0.5), (5, 3, 1.0)])
+def test_single_round_is_stream_compaction(elem, V, n, p):
+    rng = np.random.default_rng(V * 1000 + n)
+    values, flags = wl.random_round(rng, n, p, elem)
+    o = Oracle(elem, V, 2)
+    o.insert(values, flags)
+    # One round with contiguous chunks: flatten equals numpy's boolean compaction.
+    assert np.array_equal(o.flatten(), values[flags.astype(bool)])
+    # Per-vector sizes: flags summed over chunks of ceil(n/V) threads.
+    chunk = -(-n // V) if n else 1
+    starts = np.arange(0, V) * chunk
+    expect = np.array([int(flags[s:s + chunk].sum()) if s < n else 0 for s in starts])
+    assert np.array_equal(o.vector_sizes().astype(np.int64), expect)
+    assert o.check() == 0
+
+
+def test_chunk_mapping_hand():
+    o = Oracle(4, 3, 1)
+    o.insert(np.arange(7, dtype=np.uint32))  # chunk 3: [0,1,2] [3,4,5] [6]
+    assert o.vector_sizes().tolist() == [3, 3, 1]
+    o = Oracle(4, 4, 1)
+    o.insert(np.arange(2, dtype=np.uint32))  # chunk 1: [0] [1] [] []
+    assert o.vector_sizes().tolist() == [1, 1, 0, 0]
+    assert o.vector_nbuckets().tolist() == [1, 1, 0, 0]
+
+
+def test_multi_round_order_and_conservation():
+    # Payload encodes (round, gid): inside each LFVector values strictly increase
+    # (rounds in call order, threads in rank order) and every gid belongs to the
+    # vector's chunk of its round.
+    V, F = 5, 2
+    o = Oracle(8, V, F)
+    sent = []
+    rng = np.random.default_rng(0)
+    ns = [37, 0, 100, 3, 64]
+    for r, n in enumerate(ns):
+        vals = (np.uint64(r) << np.uint64(32)) | np.arange(n, dtype=np.uint64)
+        flags = (rng.random(n) < 0.6).astype(np.uint8)
+        o.insert(vals, flags)
+        sent.append(vals[flags.astype(bool)])
+    flat = o.flatten()
+    assert np.array_equal(np.sort(flat), np.sort(np.concatenate(sent)))
+    pre = o.prefix().astype(np.int64)
+    for v in range(V):
+        seg = flat[pre[v]:pre[v + 1]]
+        assert np.all(np.diff(seg.astype(np.float64)) > 0)
+        for x in seg:
+            r, gid = int(x) >> 32, int(x) & U32
+            chunk = -(-ns[r] // V)
+            assert gid // chunk == v
+    assert o.check() == 0
+
+
+def test_insert_counts_order():
+    o = Oracle(4, 2, 4)
+    vals = np.arange(12, dtype=np.uint32)  # 4 threads x 3 slots
+    counts = np.array([2, 0, 3, 1], dtype=np.uint8)  # chunk 2: threads 0,1 -> v0; 2,3 -> v1
+    o.insert_counts(vals, counts, 3)
+    assert o.vector_sizes().tolist() == [2, 4]
+    assert o.flatten().tolist() == [0, 1, 6, 7, 8, 9]
+
+
+# ---------------------------------------------------------------------------
+# Generated workloads: gen mode equals buffer mode built by the numpy generator.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("elem", [4, 8])
+def test_gen_bernoulli_equals_buffer(elem):
+    n, V = 5000, 9
+    a, b = Oracle(elem, V, 8), Oracle(elem, V, 8)
+    for r in range(3):
+        a.insert_gen(oracle.GEN_BERNOULLI, n, seed=42, round=r)
+        vals, flags = wl.bernoulli_round(42, r, n, elem)
+        b.insert(vals, flags)
+    assert np.array_equal(a.flatten(), b.flatten())
+    assert np.array_equal(a.vector_sizes(), b.vector_sizes())
+
+
+def test_gen_round_tag_equals_buffer():
+    a, b = Oracle(4, 8, 16), Oracle(4, 8, 16)
+    for r, n in enumerate([1000, 2000, 4000]):
+        a.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=27)
+        b.insert(wl.round_tag_values(r, n, 27, 4))
+    assert np.array_equal(a.flatten(), b.flatten())
+
+
+def test_gen_poisson_equals_buffer():
+    thr = wl.poisson_thresholds(3, 16)
+    n, V = 3000, 16
+    a, b = Oracle(8, V, 16), Oracle(8, V, 16)
+    for i in range(4):
+        a.insert_gen(oracle.GEN_POISSON, n, seed=1, round=i, max_count=16, thresholds=thr)
+        counts = wl.poisson_counts(1, i, n, thr)
+        gid = np.repeat(np.arange(n, dtype=np.uint64), 16)
+        j = np.tile(np.arange(16, dtype=np.uint64), n)
+        vals = wl.poisson_payload(1, i, gid, j)
+        b.insert_counts(vals, counts, 16)
+    assert np.array_equal(a.flatten(), b.flatten())
+    assert a.size() == b.size()
+
+
+# ---------------------------------------------------------------------------
+# Shrink, r/w, flatten.
+# ---------------------------------------------------------------------------
+def test_shrink_is_prefix_and_frees_buckets():
+    rng = np.random.default_rng(3)
+    V, F = 6, 4
+    o = Oracle(4, V, F)
+    for _ in range(3):
+        o.insert(*wl.random_round(rng, 400, 0.7, 4))
+    before = o.flatten()
+    pre_b = o.prefix().astype(np.int64)
+    sizes_b = o.vector_sizes().astype(np.int64)
+    allocs = o.alloc_count()
+    o.shrink(3, 7)
+    after = o.flatten()
+    pre_a = o.prefix().astype(np.int64)
+    sizes_a = o.vector_sizes().astype(np.int64)
+    assert np.array_equal(sizes_a, sizes_b - (sizes_b * 3) // 7)
+    for v in range(V):
+        assert np.array_equal(after[pre_a[v]:pre_a[v + 1]], before[pre_b[v]:pre_b[v] + sizes_a[v]])
+    freed = sum(oracle.nbuckets_for(F, int(s)) - oracle.nbuckets_for(F, int(t))
+                for s, t in zip(sizes_b, sizes_a))
+    assert o.free_count() == freed
+    assert o.alloc_count() == allocs
+    assert o.check() == 0
+    o.shrink(1, 1)
+    assert o.size() == 0 and o.capacity() == 0
+
+
+def _affine_power(a, b, k, mask):
+    # x -> a x + b applied k times is x -> a^k x + b (a^k - 1)/(a - 1) (a != 1).
+    ak = pow(a, k)
+    return ak & mask, (b * (ak - 1) // (a - 1)) & mask
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_rw_closed_forms(elem):
+    mask = U32 if elem == 4 else U64
+    vals = np.array([0, 1, 2, 12345, mask - 30, mask - 1, mask], dtype=np.uint32 if elem == 4 else np.uint64)
+    o = Oracle(elem, 3, 2)
+    o.insert(vals)
+    o.rw(oracle.OP_ADD1)
+    o.rw(oracle.OP_ADD1)
+    assert [int(x) for x in o.flatten()] == [(int(x) + 2) & mask for x in vals]
+    o.rw(oracle.OP_ADD1_X30)
+    assert [int(x) for x in o.flatten()] == [(int(x) + 32) & mask for x in vals]
+    for _ in range(5):
+        o.rw(oracle.OP_MUL3ADD1)
+    A, B = _affine_power(3, 1, 5, mask)
+    assert [int(x) for x in o.flatten()] == [(A * ((int(x) + 32) & mask) + B) & mask for x in vals]
+    assert o.check() == 0
+
+
+def test_flatten_too_small_writes_nothing():
+    o = Oracle(4, 2, 1)
+    o.insert(np.arange(1, 6, dtype=np.uint32))
+    out = np.full(4, 77, dtype=np.uint32)
+    assert o.flatten_status(out) == oracle.ERANGE
+    assert out.tolist() == [77] * 4
+
+
+def test_invalid_arguments():
+    for args in [(3, 4, 1), (4, 0, 1), (4, 4, 3), (8, 1, 0)]:
+        with pytest.raises(oracle.OracleError):
+            Oracle(*args)
+    o = Oracle(4, 2, 1)
+    with pytest.raises(oracle.OracleError):
+        o.shrink(2, 1)
+    with pytest.raises(oracle.OracleError):
+        o.shrink(0, 0)
+
+
+# ---------------------------------------------------------------------------
+# Configuration 2 (scaled per LFVector): closed-form sizes, the zero-growth
+# rounds the paper remarks on (Sec. VI-C, capacity tends to grow by two), the
+# memory bound, and the final aggregate capacity / live ratio.
+# ---------------------------------------------------------------------------
+def test_cfg2_sizes_closed_form_and_growth_rounds():
+    F, V_real = 1024, 512
+    V = 2  # each vector sees n_r / 512 threads per round, as at V = 512
+    o = Oracle(4, V, F, forms=oracle.FORM_LIST | oracle.FORM_BUCKETS)
+    s = 0
+    zero_growth = []
+    for r, n_r in enumerate(wl.cfg2_round_threads()):
+        n = n_r // V_real * V
+        before = o.alloc_count()
+        o.insert(wl.round_tag_values(r, n, 27, 4))
+        if o.alloc_count() == before:
+            zero_growth.append(r)
+        o.shrink(1, 10)
+        t = s + n_r // V_real
+        s = t - t // 10
+        assert o.vector_sizes().tolist() == [s] * V
+        caps = [F * ((1 << oracle.nbuckets_for(F, s)) - 1)] * V
+        assert o.capacity() == sum(caps)
+        assert all(c <= 2 * s + F - 1 for c in caps)
+    assert zero_growth == [1, 2]
+    assert o.capacity() / o.size() <= 2.0
+    assert o.check() == 0
