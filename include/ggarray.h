@@ -1,0 +1,215 @@
+/*
+ * ggarray.h - C ABI of the GGArray library for AMD Instinct MI355X (gfx950).
+ *
+ * A GGArray (Meneses, Navarro, Ferrada, "GGArray: A Dynamically Growable GPU
+ * Array", arXiv 2209.00103) is an array of V LFVectors.  Each LFVector is a table
+ * of buckets: bucket b holds first_bucket * 2^b elements (Alg. 2), buckets are
+ * allocated only when an insertion first reaches them (Alg. 1), and elements never
+ * move once written.  Insertion is block-cooperative: a block of threads computes
+ * the prefix sum of its insertion counts and claims one index range per round
+ * (Sec. III-B, parallel prefix-sum insertion), growing the LFVector from the GPU
+ * without a host round trip (Sec. IV).  The global size is the sum of the
+ * LFVector sizes and the prefix sum of those sizes locates each LFVector's
+ * elements (Sec. IV); flatten copies the elements into one contiguous buffer
+ * (Sec. VI-C, two-phase use).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: GGA_OK (0) or a negative GGA_E* status.  Nothing throws across
+ *    the ABI.  Argument errors are detected on the host and returned at once,
+ *    before any work is queued.
+ *  - Device-side errors (bucket pool exhausted, flatten output too small) are
+ *    sticky per array: the first one is kept and reported by the next call that
+ *    synchronises (ggarray_last_error, ggarray_size, ggarray_capacity).
+ *  - Streams: every call is ordered on the caller's stream `s` (a hipStream_t
+ *    passed as void*; NULL is the default stream).  Only calls documented as
+ *    synchronising block the host.  Handles are not thread-safe, and two streams
+ *    must not work on one array at the same time.
+ *  - Memory: pointers named dev_* / values / flags / counts / out are device
+ *    pointers owned by the caller.  The bucket pool memory is owned by the
+ *    caller; the library owns the buckets it carves from it and its own small
+ *    metadata allocations.
+ *  - Element types: 4-byte or 8-byte unsigned integers; element arithmetic wraps
+ *    modulo 2^(8 * elem_bytes).
+ *  - Thread -> LFVector mapping: an insertion round with n logical threads feeds
+ *    LFVector v with threads [v*c, (v+1)*c) where c = ceil(n / V).  Inside a round
+ *    the elements land in thread-rank order, a thread's own elements contiguous
+ *    and in their order.  The result is therefore a pure function of the inputs,
+ *    V and first_bucket; block size and launch shape never change it.
+ */
+#ifndef GGARRAY_H
+#define GGARRAY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status --- */
+#define GGA_OK 0
+#define GGA_EINVAL (-1) /* invalid argument */
+#define GGA_ENOMEM (-2) /* bucket pool exhausted (device side, sticky) */
+#define GGA_ERANGE (-3) /* output buffer or static capacity too small (sticky) */
+#define GGA_EHIP (-4)   /* a HIP runtime call failed */
+#define GGA_EBUSY (-5)  /* object still referenced (pool with live arrays) */
+
+typedef void *gga_stream; /* hipStream_t */
+typedef struct gga_pool gga_pool;
+typedef struct ggarray ggarray;
+typedef struct gga_static gga_static;
+typedef struct gga_semistatic gga_semistatic;
+
+/* r/w operations (Sec. VI-C times an operation over every element; the paper's
+ * kernel adds 1 thirty times, GGA_ADD1_X30). */
+#define GGA_ADD1 0     /* x = x + 1 */
+#define GGA_MUL3ADD1 1 /* x = 3x + 1 */
+#define GGA_ADD1_X30 2 /* x = x + 1, thirty times */
+
+/* Generated payloads: the insertion workloads produced on the device, the way a
+ * user kernel computes the element it pushes back.  K(seed, a, b) is
+ * SplitMix64 (Steele, Lea, Flood 2014) applied to (seed << 56) ^ (a << 8) ^ b. */
+#define GGA_GEN_BERNOULLI 1 /* h = K(seed, gid, round); insert h iff h >> 63 */
+#define GGA_GEN_ROUND_TAG 2 /* insert (round << tag_shift) | gid */
+#define GGA_GEN_POISSON 3   /* u = K(seed, gid, 0x80 | round);
+                               c = #{k < max_count : u >= thresholds[k]};
+                               insert K(seed, gid, 16 * round + j), j < c */
+typedef struct {
+    uint32_t kind;           /* GGA_GEN_* */
+    uint32_t round;          /* BERNOULLI: < 256; POISSON: < 8 */
+    uint64_t seed;           /* < 256 */
+    uint32_t tag_shift;      /* ROUND_TAG: < 64 */
+    uint32_t max_count;      /* POISSON: 1..16 */
+    uint64_t thresholds[16]; /* POISSON: host copy, the first max_count used */
+} gga_gen;
+
+/* Human-readable name of a status code (static string). */
+const char *gga_strerror(int status);
+
+/* ------------------------------------------------------------ bucket pool --- */
+/* Device sub-allocator that serves bucket allocations from inside the insertion
+ * kernels (Alg. 2 allocates with device malloc; here a lock-free pool over
+ * caller-owned HBM does, so growth needs no host round trip).
+ *
+ * gga_pool_create: dev_base is caller-owned device memory of `bytes` bytes,
+ *   256-byte aligned, at least 1 MiB; it must outlive the pool.  The pool keeps
+ *   its header at the start and carves buckets (power-of-two sizes, >= 256 B)
+ *   from the rest.  Queued on s.  EINVAL on a NULL/unaligned/small buffer.
+ * gga_pool_destroy: frees the host handle; EBUSY while arrays still use it.
+ * gga_pool_stats: out[0..6] = bytes in use, high-water bytes, allocations,
+ *   frees, bump offset, region bytes, allocation attempts.  Synchronises s.
+ * gga_pool_set_fault: the fault_at-th allocation attempt from now fails as if
+ *   the pool were exhausted (0 disables).  For failure-handling tests. */
+int gga_pool_create(gga_pool **out, void *dev_base, uint64_t bytes, gga_stream s);
+int gga_pool_destroy(gga_pool *p);
+int gga_pool_stats(gga_pool *p, uint64_t out[7], gga_stream s);
+int gga_pool_set_fault(gga_pool *p, uint64_t fault_at, gga_stream s);
+
+/* ---------------------------------------------------------------- GGArray --- */
+/* ggarray_create: an empty GGArray of n_vectors LFVectors (Sec. IV, Fig. 1-2)
+ *   whose first bucket holds first_bucket elements (Alg. 2).  elem_bytes is 4 or
+ *   8; first_bucket is a power of two >= 1; n_vectors is 1..2^20.  No bucket is
+ *   allocated (lazy growth, Alg. 1).  Metadata is device memory the library
+ *   allocates here (about 350 bytes per LFVector).  Queued on s. */
+int ggarray_create(ggarray **out, gga_pool *p, uint32_t elem_bytes, uint32_t n_vectors,
+                   uint64_t first_bucket, gga_stream s);
+
+/* ggarray_destroy: returns every bucket to the pool and frees the metadata.  The
+ *   caller guarantees no work on the array is pending on other streams; the
+ *   call synchronises s. */
+int ggarray_destroy(ggarray *a, gga_stream s);
+
+/* ggarray_insert: one insertion round, LFVector push_back (Alg. 1) with
+ *   new_bucket (Alg. 2).  Logical thread gid (0 <= gid < n_threads) inserts
+ *   values[gid] iff flags == NULL or flags[gid] != 0.  values: n_threads
+ *   elements; flags: n_threads bytes or NULL; both device memory.  Missing buckets
+ *   are allocated on the device.  Pool exhaustion leaves every affected LFVector
+ *   exactly as it was before the round, freezes it for later insertions and sets
+ *   the sticky GGA_ENOMEM. */
+int ggarray_insert(ggarray *a, const void *values, const uint8_t *flags, uint64_t n_threads,
+                   gga_stream s);
+
+/* ggarray_insert_counts: as ggarray_insert, but thread gid inserts
+ *   values[gid * max_count + j] for j < counts[gid]; 1 <= max_count <= 16 and
+ *   counts[gid] <= max_count (larger counts are clamped to max_count). */
+int ggarray_insert_counts(ggarray *a, const void *values, const uint8_t *counts,
+                          uint32_t max_count, uint64_t n_threads, gga_stream s);
+
+/* ggarray_insert_gen: one insertion round whose payloads are generated on the
+ *   device by g (see GGA_GEN_*); `g` is a host pointer read before returning. */
+int ggarray_insert_gen(ggarray *a, const gga_gen *g, uint64_t n_threads, gga_stream s);
+
+/* ggarray_shrink: every LFVector pops floor(s_v * num / den) trailing elements
+ *   and returns each bucket that starts at or past its new size to the pool.
+ *   0 <= num <= den, den > 0.  (The paper studies growth only; shrinking follows
+ *   the generic vector interface it names in Sec. I.) */
+int ggarray_shrink(ggarray *a, uint32_t num, uint32_t den, gga_stream s);
+
+/* ggarray_rw: x = op(x) for every live element, in place, LFVector by LFVector
+ *   through the bucket tables (the per-block read/write rw_b of Sec. VI-B). */
+int ggarray_rw(ggarray *a, uint32_t op, gga_stream s);
+
+/* ggarray_flatten: copies LFVector 0, then 1, ... into out (device memory of
+ *   out_cap_elems elements), element i of LFVector v landing at P[v] + i where P
+ *   is the exclusive prefix sum of the LFVector sizes (Sec. IV).  The GGArray is
+ *   unchanged.  If out_cap_elems is smaller than the size, nothing is written and
+ *   the sticky GGA_ERANGE is set. */
+int ggarray_flatten(ggarray *a, void *out, uint64_t out_cap_elems, gga_stream s);
+
+/* ggarray_size: global size = sum of the LFVector sizes (Sec. IV), into *out_host.
+ *   Synchronises s.  Returns the sticky device error if one is set. */
+int ggarray_size(ggarray *a, uint64_t *out_host, gga_stream s);
+
+/* ggarray_capacity: elements held by the allocated buckets, into *out_host.
+ *   Synchronises s. */
+int ggarray_capacity(ggarray *a, uint64_t *out_host, gga_stream s);
+
+/* ggarray_vector_sizes: copies the V LFVector sizes (uint64) to dev_out. Queued. */
+int ggarray_vector_sizes(ggarray *a, uint64_t *dev_out, gga_stream s);
+
+/* ggarray_prefix: writes the V + 1 entries of the exclusive prefix sum of the
+ *   LFVector sizes (uint64; the last entry is the global size) to dev_out. Queued. */
+int ggarray_prefix(ggarray *a, uint64_t *dev_out, gga_stream s);
+
+/* ggarray_last_error: the sticky device error of the array (GGA_OK if none).
+ *   Synchronises s.  Does not clear it. */
+int ggarray_last_error(ggarray *a, gga_stream s);
+
+/* ------------------------------------------------- static array baseline --- */
+/* The pre-allocated flat array of Sec. III-A1: caller-owned device buffer of
+ * cap_elems elements; insertion uses the same block prefix sum and one global
+ * atomic per block round (Sec. III-B2), so the order across blocks is not fixed.
+ * Insertions past the capacity are dropped and set the sticky GGA_ERANGE. */
+int gga_static_create(gga_static **out, void *dev_buf, uint64_t cap_elems, uint32_t elem_bytes,
+                      gga_stream s);
+int gga_static_destroy(gga_static *st, gga_stream s);
+int gga_static_insert(gga_static *st, const void *values, const uint8_t *flags,
+                      uint64_t n_threads, gga_stream s);
+int gga_static_insert_gen(gga_static *st, const gga_gen *g, uint64_t n_threads, gga_stream s);
+int gga_static_rw(gga_static *st, uint32_t op, gga_stream s);
+int gga_static_size(gga_static *st, uint64_t *out_host, gga_stream s); /* synchronises */
+int gga_static_last_error(gga_static *st, gga_stream s);                /* synchronises */
+
+/* ----------------------------------------- semi-static array baseline ------ */
+/* The host-resized array of Sec. III-A2: before each insertion round the host
+ * reads the size, and if the worst case of the round does not fit it doubles
+ * the capacity (new device allocation, device-to-device copy, free of the old
+ * one, all on s).  Insertion and r/w then run as for the static array.  The
+ * library allocates its buffer with the stream-ordered HIP allocator. */
+int gga_semi_create(gga_semistatic **out, uint32_t elem_bytes, uint64_t initial_cap,
+                    gga_stream s);
+int gga_semi_destroy(gga_semistatic *ss, gga_stream s);
+int gga_semi_insert(gga_semistatic *ss, const void *values, const uint8_t *flags,
+                    uint64_t n_threads, gga_stream s);
+int gga_semi_insert_gen(gga_semistatic *ss, const gga_gen *g, uint64_t n_threads, gga_stream s);
+int gga_semi_rw(gga_semistatic *ss, uint32_t op, gga_stream s);
+int gga_semi_size(gga_semistatic *ss, uint64_t *out_host, gga_stream s); /* synchronises */
+/* Current device buffer and capacity (elements); valid until the next insert. */
+int gga_semi_data(gga_semistatic *ss, void **dev_data, uint64_t *cap_elems);
+/* Number of host-driven resizes so far. */
+int gga_semi_resizes(gga_semistatic *ss, uint64_t *out_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GGARRAY_H */

@@ -1,0 +1,337 @@
+// Size/prefix scan, shrink, regular read/write, flatten and bucket release.
+//
+// Regular access walks the LFVectors bucket by bucket (the per-block access rw_b
+// of Sec. VI-B), but the work is cut into bucket-aligned tiles of at most 16 KiB
+// that are spread evenly over a persistent grid, so the number of LFVectors and
+// their uneven sizes do not set the parallelism.  A tile lies inside one bucket,
+// so it costs one bucket-pointer load and streams 16-byte vectors.
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kStreamBlocks = 2048;  // 8 workgroups per CU on 256 CUs
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
+
+// Tiles of an LFVector of s elements: every bucket below s contributes
+// ceil(live elements of the bucket / te) tiles.
+__device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
+  uint64_t n = 0;
+  const uint32_t nb = nbuckets_for(log2F, s);
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint64_t st = bucket_start(log2F, b);
+    uint64_t live = bucket_len(log2F, b);
+    if (s - st < live) live = s - st;
+    n += (live + (1ull << te_log2) - 1) >> te_log2;
+  }
+  return n;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Exclusive prefix sums of the LFVector sizes (element offsets, Sec. IV) and of
+// their tile counts, by one workgroup; entry V holds the totals.
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2) {
+  __shared__ uint64_t wsum_e[kScanThreads / 64], wsum_t[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t V = A.V;
+  const uint32_t per = (V + kScanThreads - 1) / kScanThreads;
+  const uint32_t v0 = tid * per < V ? tid * per : V;
+  const uint32_t v1 = v0 + per < V ? v0 + per : V;
+  uint64_t e = 0, t = 0;
+  for (uint32_t v = v0; v < v1; ++v) {
+    const uint64_t s = A.size[v];
+    e += s;
+    t += tiles_for(A.log2F, s, te_log2);
+  }
+  const uint64_t ie = wave_incl_scan64(e), it = wave_incl_scan64(t);
+  if (lane == 63) {
+    wsum_e[w] = ie;
+    wsum_t[w] = it;
+  }
+  __syncthreads();
+  uint64_t be = 0, bt = 0, te = 0, tt = 0;
+  for (uint32_t k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) {
+      be += wsum_e[k];
+      bt += wsum_t[k];
+    }
+    te += wsum_e[k];
+    tt += wsum_t[k];
+  }
+  uint64_t re = be + ie - e, rt = bt + it - t;
+  for (uint32_t v = v0; v < v1; ++v) {
+    const uint64_t s = A.size[v];
+    A.prefix[v] = re;
+    A.tprefix[v] = rt;
+    re += s;
+    rt += tiles_for(A.log2F, s, te_log2);
+  }
+  if (tid == 0) {
+    A.prefix[V] = te;
+    A.tprefix[V] = tt;
+  }
+}
+
+// Shrink (pop floor(s num / den) per LFVector) and bucket release.
+__global__ void shrink_kernel(ArrRef A, uint32_t num, uint32_t den, uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.V) return;
+  const uint64_t s = A.size[v];
+  const uint64_t k = (s / den) * num + ((s % den) * num) / den;
+  const uint64_t ns = s - k;
+  A.size[v] = ns;
+  const uint32_t lo = nbuckets_for(A.log2F, ns);
+  uint32_t hi = A.dead[v] ? (uint32_t)kMaxBuckets : nbuckets_for(A.log2F, s);
+  if (hi > (uint32_t)kMaxBuckets) hi = kMaxBuckets;
+  uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
+  for (uint32_t b = lo; b < hi; ++b) {
+    const uint64_t p = row[b];
+    if (p > kFailedPtr) pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), v);
+    if (p) row[b] = 0;
+  }
+}
+
+// Returns every bucket of the array to the pool (destroy).
+__global__ void free_all_kernel(ArrRef A, uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.V) return;
+  uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
+  for (uint32_t b = 0; b < (uint32_t)kMaxBuckets; ++b) {
+    const uint64_t p = row[b];
+    if (p > kFailedPtr) pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), v);
+    row[b] = 0;
+  }
+}
+
+// Elements held by allocated buckets.
+__global__ void capacity_kernel(ArrRef A, uint64_t* out) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= A.V) return;
+  const uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
+  uint64_t c = 0;
+  for (uint32_t b = 0; b < (uint32_t)kMaxBuckets; ++b)
+    if (row[b] > kFailedPtr) c += bucket_len(A.log2F, b);
+  if (c) fetch_add(out, c);
+}
+
+// Per-lane 16-byte vector <-> elements.
+template <typename T>
+__device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
+  if (sizeof(T) == 4) {
+    x.x = apply_op<uint32_t>(op, x.x);
+    x.y = apply_op<uint32_t>(op, x.y);
+    x.z = apply_op<uint32_t>(op, x.z);
+    x.w = apply_op<uint32_t>(op, x.w);
+  } else {
+    uint64_t lo = ((uint64_t)x.y << 32) | x.x, hi = ((uint64_t)x.w << 32) | x.z;
+    lo = apply_op<uint64_t>(op, lo);
+    hi = apply_op<uint64_t>(op, hi);
+    x.x = (uint32_t)lo;
+    x.y = (uint32_t)(lo >> 32);
+    x.z = (uint32_t)hi;
+    x.w = (uint32_t)(hi >> 32);
+  }
+  return x;
+}
+
+// One tile: cnt (<= te) elements at src (16-byte aligned); rw in place, or copy
+// to dst (element aligned) for flatten.  Lane i of slot k handles the 16 bytes
+// at element k * (256 * VPL) + i * VPL.
+template <typename T, bool kFlatten>
+__device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32_t op) {
+  constexpr uint32_t VPL = 16 / sizeof(T);
+  constexpr uint32_t kSlots = 4;
+  constexpr uint32_t kSpan = kRwThreads * VPL;
+  const uint32_t tid = threadIdx.x;
+  if (cnt == kSlots * kSpan) {
+    u32x4 r[kSlots];
+#pragma unroll
+    for (uint32_t k = 0; k < kSlots; ++k)
+      r[k] = *reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL);
+#pragma unroll
+    for (uint32_t k = 0; k < kSlots; ++k) {
+      if (kFlatten)
+        *reinterpret_cast<u32x4_a4*>(dst + k * kSpan + tid * VPL) = r[k];
+      else
+        *reinterpret_cast<u32x4*>(src + k * kSpan + tid * VPL) = op_vec<T>(op, r[k]);
+    }
+    return;
+  }
+  for (uint32_t k = 0; k < kSlots; ++k) {
+    const uint32_t e = k * kSpan + tid * VPL;
+    if (e + VPL <= cnt) {
+      const u32x4 x = *reinterpret_cast<const u32x4*>(src + e);
+      if (kFlatten)
+        *reinterpret_cast<u32x4_a4*>(dst + e) = x;
+      else
+        *reinterpret_cast<u32x4*>(src + e) = op_vec<T>(op, x);
+    } else {
+      for (uint32_t q = e; q < cnt && q < e + VPL; ++q) {
+        if (kFlatten)
+          dst[q] = src[q];
+        else
+          src[q] = apply_op<T>(op, src[q]);
+      }
+    }
+  }
+}
+
+// Persistent walk over the bucket-aligned tiles: workgroup w takes the w-th
+// contiguous share of the tiles, finds its first LFVector by binary search over
+// the tile prefix, then walks forward.
+template <typename T, bool kFlatten>
+__global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t op, T* out,
+                                                           uint64_t out_cap, uint32_t te_log2) {
+  const uint32_t V = A.V;
+  const uint64_t total = A.tprefix[V];
+  if (kFlatten && A.prefix[V] > out_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(A.err, kErrRange);
+    return;
+  }
+  const uint64_t G = gridDim.x;
+  const uint64_t t0 = total * blockIdx.x / G, t1 = total * (blockIdx.x + 1) / G;
+  if (t0 >= t1) return;
+  uint32_t lo = 0, hi = V;  // tprefix[lo] <= t0 < tprefix[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (A.tprefix[mid] <= t0) lo = mid; else hi = mid;
+  }
+  uint32_t v = lo;
+  uint64_t s = A.size[v];
+  uint64_t k = t0 - A.tprefix[v];
+  const uint32_t log2F = A.log2F;
+  const uint64_t te = 1ull << te_log2;
+  uint32_t b = 0;
+  uint64_t live, nt;
+  for (;;) {
+    live = bucket_len(log2F, b);
+    const uint64_t st = bucket_start(log2F, b);
+    if (s - st < live) live = s - st;
+    nt = (live + te - 1) >> te_log2;
+    if (k < nt) break;
+    k -= nt;
+    ++b;
+  }
+  for (uint64_t t = t0;;) {
+    T* src = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + (k << te_log2);
+    const uint64_t rem = live - (k << te_log2);
+    const uint32_t cnt = (uint32_t)(rem < te ? rem : te);
+    T* dst = kFlatten ? out + A.prefix[v] + bucket_start(log2F, b) + (k << te_log2) : nullptr;
+    stream_tile<T, kFlatten>(src, dst, cnt, op);
+    if (++t >= t1) break;
+    if (++k == nt) {
+      k = 0;
+      ++b;
+      if (bucket_start(log2F, b) >= s) {
+        b = 0;
+        do {
+          ++v;
+          s = A.size[v];
+        } while (s == 0);
+      }
+      live = bucket_len(log2F, b);
+      const uint64_t st = bucket_start(log2F, b);
+      if (s - st < live) live = s - st;
+      nt = (live + te - 1) >> te_log2;
+    }
+  }
+}
+
+// Static / semi-static array r/w: a flat grid-stride stream over [0, size).
+template <typename T>
+__global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const uint64_t* size,
+                                                              uint64_t cap, uint32_t op) {
+  constexpr uint32_t VPL = 16 / sizeof(T);
+  uint64_t n = *size;
+  if (n > cap) n = cap;
+  const uint64_t nv = n / VPL;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  u32x4* d = reinterpret_cast<u32x4*>(data);
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < nv; i += 4 * stride) {
+    u32x4 r0 = d[i], r1 = d[i + stride], r2 = d[i + 2 * stride], r3 = d[i + 3 * stride];
+    d[i] = op_vec<T>(op, r0);
+    d[i + stride] = op_vec<T>(op, r1);
+    d[i + 2 * stride] = op_vec<T>(op, r2);
+    d[i + 3 * stride] = op_vec<T>(op, r3);
+  }
+  for (; i < nv; i += stride) d[i] = op_vec<T>(op, d[i]);
+  const uint64_t tail = nv * VPL + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tail < n) data[tail] = apply_op<T>(op, data[tail]);
+}
+
+}  // namespace
+
+int launch_scan(ggarray* a, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref,
+                     14u - a->elem_log2);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) a->prefix_valid = true;
+  return hip_status(e);
+}
+
+int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s) {
+  const uint32_t blocks = (a->V + 255) / 256;
+  hipLaunchKernelGGL(shrink_kernel, dim3(blocks), dim3(256), 0, s, a->ref, num, den, a->elem_log2);
+  a->prefix_valid = false;
+  return hip_status(hipGetLastError());
+}
+
+int launch_free_all(ggarray* a, hipStream_t s) {
+  const uint32_t blocks = (a->V + 255) / 256;
+  hipLaunchKernelGGL(free_all_kernel, dim3(blocks), dim3(256), 0, s, a->ref, a->elem_log2);
+  return hip_status(hipGetLastError());
+}
+
+int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s) {
+  if (hipMemsetAsync(d_out, 0, sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+  const uint32_t blocks = (a->V + 255) / 256;
+  hipLaunchKernelGGL(capacity_kernel, dim3(blocks), dim3(256), 0, s, a->ref, d_out);
+  return hip_status(hipGetLastError());
+}
+
+int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
+  const uint32_t te_log2 = 14u - a->elem_log2;
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL((stream_kernel<uint32_t, false>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       a->ref, op, (uint32_t*)nullptr, (uint64_t)0, te_log2);
+  else
+    hipLaunchKernelGGL((stream_kernel<uint64_t, false>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       a->ref, op, (uint64_t*)nullptr, (uint64_t)0, te_log2);
+  return hip_status(hipGetLastError());
+}
+
+int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
+  const uint32_t te_log2 = 14u - a->elem_log2;
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL((stream_kernel<uint32_t, true>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       a->ref, 0u, static_cast<uint32_t*>(out), cap, te_log2);
+  else
+    hipLaunchKernelGGL((stream_kernel<uint64_t, true>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       a->ref, 0u, static_cast<uint64_t*>(out), cap, te_log2);
+  return hip_status(hipGetLastError());
+}
+
+int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
+  if (st->elem_bytes == 4)
+    hipLaunchKernelGGL((static_rw_kernel<uint32_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       static_cast<uint32_t*>(st->data), st->d_size, st->cap, op);
+  else
+    hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+                       static_cast<uint64_t*>(st->data), st->d_size, st->cap, op);
+  return hip_status(hipGetLastError());
+}
+
+}  // namespace gga

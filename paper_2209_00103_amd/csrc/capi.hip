@@ -1,0 +1,499 @@
+// C ABI of the GGArray library: argument validation, object lifetimes, error
+// reporting, and the host-driven resize of the semi-static baseline.
+#include <cstddef>
+#include <new>
+
+#include "gga_internal.h"
+
+using namespace gga;
+
+namespace {
+
+hipStream_t S(gga_stream s) { return static_cast<hipStream_t>(s); }
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+uint32_t ilog2(uint64_t x) { return 63u - (uint32_t)__builtin_clzll(x); }
+
+int map_device_error(uint32_t e) {
+  if (e == 0) return GGA_OK;
+  if (e == kErrNoMem) return GGA_ENOMEM;
+  if (e == kErrRange) return GGA_ERANGE;
+  return GGA_EHIP;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) & ~(a - 1); }
+
+// Per-array host scratch for synchronising reads (pinned, so copies are async).
+struct Pinned {
+  uint64_t* p = nullptr;
+  int init() { return hipHostMalloc(reinterpret_cast<void**>(&p), 64, hipHostMallocDefault) == hipSuccess ? GGA_OK : GGA_EHIP; }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+  }
+};
+
+struct ArrayExtra {
+  Pinned pin;
+  uint64_t* d_scratch;
+};
+
+int check_gen(const gga_gen* g, uint32_t* mode, uint32_t* maxc) {
+  if (!g || g->seed >= 256) return GGA_EINVAL;
+  switch (g->kind) {
+    case GGA_GEN_BERNOULLI:
+      if (g->round >= 256) return GGA_EINVAL;
+      *mode = kModeBernoulli;
+      *maxc = 1;
+      return GGA_OK;
+    case GGA_GEN_ROUND_TAG:
+      if (g->tag_shift >= 64) return GGA_EINVAL;
+      *mode = kModeRoundTag;
+      *maxc = 1;
+      return GGA_OK;
+    case GGA_GEN_POISSON:
+      if (g->round >= 8 || g->max_count == 0 || g->max_count > 16) return GGA_EINVAL;
+      *mode = kModePoisson;
+      *maxc = g->max_count;
+      return GGA_OK;
+    default:
+      return GGA_EINVAL;
+  }
+}
+
+InsertDesc gen_desc(const gga_gen* g, uint32_t mode, uint64_t n) {
+  InsertDesc d{};
+  d.mode = mode;
+  d.n_threads = n;
+  d.seed = g->seed;
+  d.round = g->round;
+  d.tag_shift = g->tag_shift;
+  d.max_count = g->max_count;
+  for (int k = 0; k < 16; ++k) d.thresholds[k] = g->thresholds[k];
+  return d;
+}
+
+}  // namespace
+
+// The host part of an array keeps a pointer to its extra host state right after
+// the public struct.
+struct ggarray_full {
+  ggarray a;
+  ArrayExtra x;
+};
+
+extern "C" {
+
+const char* gga_strerror(int status) {
+  switch (status) {
+    case GGA_OK: return "ok";
+    case GGA_EINVAL: return "invalid argument";
+    case GGA_ENOMEM: return "bucket pool exhausted";
+    case GGA_ERANGE: return "output or capacity too small";
+    case GGA_EHIP: return "HIP runtime error";
+    case GGA_EBUSY: return "object still in use";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------------- pool --
+int gga_pool_create(gga_pool** out, void* dev_base, uint64_t bytes, gga_stream s) {
+  if (!out || !dev_base || (reinterpret_cast<uintptr_t>(dev_base) & 255u) || bytes < (1u << 20))
+    return GGA_EINVAL;
+  *out = nullptr;
+  gga_pool* p = new (std::nothrow) gga_pool();
+  if (!p) return GGA_EHIP;
+  p->dev_base = dev_base;
+  p->bytes = bytes;
+  p->ref.hdr = static_cast<PoolHdr*>(dev_base);
+  p->ref.base = static_cast<uint8_t*>(dev_base) + kPoolHdrBytes;
+  PoolHdr h{};
+  h.limit = (bytes - kPoolHdrBytes) & ~255ull;
+  if (hipMemcpyAsync(p->ref.hdr, &h, sizeof(h), hipMemcpyHostToDevice, S(s)) != hipSuccess ||
+      hipStreamSynchronize(S(s)) != hipSuccess) {
+    delete p;
+    return GGA_EHIP;
+  }
+  *out = p;
+  return GGA_OK;
+}
+
+int gga_pool_destroy(gga_pool* p) {
+  if (!p) return GGA_EINVAL;
+  if (p->n_arrays) return GGA_EBUSY;
+  delete p;
+  return GGA_OK;
+}
+
+int gga_pool_stats(gga_pool* p, uint64_t out[7], gga_stream s) {
+  if (!p || !out) return GGA_EINVAL;
+  PoolHdr h;
+  if (hipMemcpyAsync(&h, p->ref.hdr, sizeof(h), hipMemcpyDeviceToHost, S(s)) != hipSuccess ||
+      hipStreamSynchronize(S(s)) != hipSuccess)
+    return GGA_EHIP;
+  out[0] = h.in_use;
+  out[1] = h.high_water;
+  out[2] = h.n_alloc;
+  out[3] = h.n_free;
+  out[4] = h.bump;
+  out[5] = h.limit;
+  out[6] = h.n_attempt;
+  return GGA_OK;
+}
+
+int gga_pool_set_fault(gga_pool* p, uint64_t fault_at, gga_stream s) {
+  if (!p) return GGA_EINVAL;
+  uint64_t v[2] = {0, fault_at};  // n_attempt, fault_at are adjacent
+  static_assert(offsetof(PoolHdr, fault_at) == offsetof(PoolHdr, n_attempt) + 8, "layout");
+  if (hipMemcpyAsync(&p->ref.hdr->n_attempt, v, sizeof(v), hipMemcpyHostToDevice, S(s)) != hipSuccess ||
+      hipStreamSynchronize(S(s)) != hipSuccess)
+    return GGA_EHIP;
+  return GGA_OK;
+}
+
+// ------------------------------------------------------------------- GGArray --
+int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_vectors,
+                   uint64_t first_bucket, gga_stream s) {
+  if (!out) return GGA_EINVAL;
+  *out = nullptr;
+  if (!p || (elem_bytes != 4 && elem_bytes != 8) || n_vectors == 0 || n_vectors > (1u << 20) ||
+      !is_pow2(first_bucket) || first_bucket > (1ull << 32))
+    return GGA_EINVAL;
+  ggarray_full* f = new (std::nothrow) ggarray_full();
+  if (!f) return GGA_EHIP;
+  ggarray* a = &f->a;
+  a->pool = p;
+  a->elem_bytes = elem_bytes;
+  a->elem_log2 = elem_bytes == 4 ? 2 : 3;
+  a->V = n_vectors;
+  a->log2F = ilog2(first_bucket);
+  const uint64_t V = n_vectors;
+  size_t off = 0;
+  const size_t o_size = off;       off = align_up(off + 8 * V, 256);
+  const size_t o_bptr = off;       off = align_up(off + 8 * V * kMaxBuckets, 256);
+  const size_t o_dead = off;       off = align_up(off + 4 * V, 256);
+  const size_t o_done = off;       off = align_up(off + 4 * V, 256);
+  const size_t o_prefix = off;     off = align_up(off + 8 * (V + 1), 256);
+  const size_t o_tprefix = off;    off = align_up(off + 8 * (V + 1), 256);
+  const size_t o_misc = off;       off = align_up(off + 64, 256);  // err, ticket, scratch
+  if (hipMalloc(&a->meta, off) != hipSuccess) {
+    delete f;
+    return GGA_EHIP;
+  }
+  if (hipMemsetAsync(a->meta, 0, off, S(s)) != hipSuccess || f->x.pin.init() != GGA_OK) {
+    (void)hipFree(a->meta);
+    f->x.pin.release();
+    delete f;
+    return GGA_EHIP;
+  }
+  uint8_t* m = static_cast<uint8_t*>(a->meta);
+  ArrRef& R = a->ref;
+  R.size = reinterpret_cast<uint64_t*>(m + o_size);
+  R.bptr = reinterpret_cast<uint64_t*>(m + o_bptr);
+  R.dead = reinterpret_cast<uint32_t*>(m + o_dead);
+  R.alloc_done = reinterpret_cast<uint32_t*>(m + o_done);
+  R.prefix = reinterpret_cast<uint64_t*>(m + o_prefix);
+  R.tprefix = reinterpret_cast<uint64_t*>(m + o_tprefix);
+  R.err = reinterpret_cast<uint32_t*>(m + o_misc);
+  R.ticket = reinterpret_cast<uint64_t*>(m + o_misc + 8);
+  f->x.d_scratch = reinterpret_cast<uint64_t*>(m + o_misc + 16);
+  R.status = nullptr;
+  R.pool = p->ref;
+  R.V = n_vectors;
+  R.log2F = a->log2F;
+  a->status_cap = 0;
+  a->epoch = 0;
+  a->ticket_base = 0;
+  a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
+  p->n_arrays += 1;
+  *out = a;
+  return GGA_OK;
+}
+
+int ggarray_destroy(ggarray* a, gga_stream s) {
+  if (!a) return GGA_EINVAL;
+  ggarray_full* f = reinterpret_cast<ggarray_full*>(a);
+  int rc = launch_free_all(a, S(s));
+  if (a->ref.status && hipFreeAsync(a->ref.status, S(s)) != hipSuccess) rc = GGA_EHIP;
+  if (hipStreamSynchronize(S(s)) != hipSuccess) rc = GGA_EHIP;
+  if (hipFree(a->meta) != hipSuccess) rc = GGA_EHIP;
+  f->x.pin.release();
+  a->pool->n_arrays -= 1;
+  delete f;
+  return rc;
+}
+
+int ggarray_insert(ggarray* a, const void* values, const uint8_t* flags, uint64_t n_threads,
+                   gga_stream s) {
+  if (!a || (n_threads && !values)) return GGA_EINVAL;
+  InsertDesc d{};
+  d.mode = kModeBuffer;
+  d.values = values;
+  d.flags = flags;
+  d.max_count = 1;
+  d.n_threads = n_threads;
+  return launch_insert(a, d, S(s));
+}
+
+int ggarray_insert_counts(ggarray* a, const void* values, const uint8_t* counts, uint32_t max_count,
+                          uint64_t n_threads, gga_stream s) {
+  if (!a || max_count == 0 || max_count > 16 || (n_threads && (!values || !counts)))
+    return GGA_EINVAL;
+  InsertDesc d{};
+  d.mode = kModeCounts;
+  d.values = values;
+  d.flags = counts;
+  d.max_count = max_count;
+  d.n_threads = n_threads;
+  return launch_insert(a, d, S(s));
+}
+
+int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!a) return GGA_EINVAL;
+  const int rc = check_gen(g, &mode, &maxc);
+  if (rc) return rc;
+  const InsertDesc d = gen_desc(g, mode, n_threads);
+  return launch_insert(a, d, S(s));
+}
+
+int ggarray_shrink(ggarray* a, uint32_t num, uint32_t den, gga_stream s) {
+  if (!a || den == 0 || num > den) return GGA_EINVAL;
+  if (num == 0) return GGA_OK;
+  return launch_shrink(a, num, den, S(s));
+}
+
+static int ensure_prefix(ggarray* a, hipStream_t s) {
+  return a->prefix_valid ? GGA_OK : launch_scan(a, s);
+}
+
+int ggarray_rw(ggarray* a, uint32_t op, gga_stream s) {
+  if (!a || op > GGA_ADD1_X30) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  return rc ? rc : launch_rw(a, op, S(s));
+}
+
+int ggarray_flatten(ggarray* a, void* out, uint64_t out_cap_elems, gga_stream s) {
+  if (!a || (!out && out_cap_elems)) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  return rc ? rc : launch_flatten(a, out, out_cap_elems, S(s));
+}
+
+static int read_back(ggarray* a, const uint64_t* dev_word, uint64_t* out_host, hipStream_t s) {
+  ggarray_full* f = reinterpret_cast<ggarray_full*>(a);
+  uint64_t* h = f->x.pin.p;
+  if (dev_word && hipMemcpyAsync(h, dev_word, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return GGA_EHIP;
+  if (hipMemcpyAsync(h + 1, a->ref.err, 4, hipMemcpyDeviceToHost, s) != hipSuccess) return GGA_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return GGA_EHIP;
+  if (out_host && dev_word) *out_host = h[0];
+  return map_device_error((uint32_t)h[1]);
+}
+
+int ggarray_size(ggarray* a, uint64_t* out_host, gga_stream s) {
+  if (!a || !out_host) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  return rc ? rc : read_back(a, a->ref.prefix + a->V, out_host, S(s));
+}
+
+int ggarray_capacity(ggarray* a, uint64_t* out_host, gga_stream s) {
+  if (!a || !out_host) return GGA_EINVAL;
+  ggarray_full* f = reinterpret_cast<ggarray_full*>(a);
+  int rc = launch_capacity(a, f->x.d_scratch, S(s));
+  return rc ? rc : read_back(a, f->x.d_scratch, out_host, S(s));
+}
+
+int ggarray_vector_sizes(ggarray* a, uint64_t* dev_out, gga_stream s) {
+  if (!a || !dev_out) return GGA_EINVAL;
+  return hip_status(hipMemcpyAsync(dev_out, a->ref.size, 8ull * a->V, hipMemcpyDeviceToDevice, S(s)));
+}
+
+int ggarray_prefix(ggarray* a, uint64_t* dev_out, gga_stream s) {
+  if (!a || !dev_out) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  if (rc) return rc;
+  return hip_status(hipMemcpyAsync(dev_out, a->ref.prefix, 8ull * (a->V + 1), hipMemcpyDeviceToDevice, S(s)));
+}
+
+int ggarray_last_error(ggarray* a, gga_stream s) {
+  if (!a) return GGA_EINVAL;
+  return read_back(a, nullptr, nullptr, S(s));
+}
+
+// -------------------------------------------------------------- static array --
+static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_bytes, hipStream_t s) {
+  st->data = buf;
+  st->cap = cap;
+  st->elem_bytes = elem_bytes;
+  st->ticket_base = 0;
+  if (hipMalloc(&st->meta, 256) != hipSuccess) return GGA_EHIP;
+  if (hipMemsetAsync(st->meta, 0, 256, s) != hipSuccess) {
+    (void)hipFree(st->meta);
+    return GGA_EHIP;
+  }
+  uint8_t* m = static_cast<uint8_t*>(st->meta);
+  st->d_size = reinterpret_cast<uint64_t*>(m);
+  st->d_ticket = reinterpret_cast<uint64_t*>(m + 8);
+  st->d_err = reinterpret_cast<uint32_t*>(m + 16);
+  return GGA_OK;
+}
+
+static int static_read(gga_static* st, uint64_t* size_out, hipStream_t s) {
+  uint64_t h[2] = {0, 0};
+  if (hipMemcpyAsync(&h[0], st->d_size, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&h[1], st->d_err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GGA_EHIP;
+  if (size_out) *size_out = h[0] < st->cap ? h[0] : st->cap;
+  return map_device_error((uint32_t)h[1]);
+}
+
+int gga_static_create(gga_static** out, void* dev_buf, uint64_t cap_elems, uint32_t elem_bytes,
+                      gga_stream s) {
+  if (!out) return GGA_EINVAL;
+  *out = nullptr;
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) & 15u) || (elem_bytes != 4 && elem_bytes != 8))
+    return GGA_EINVAL;
+  gga_static* st = new (std::nothrow) gga_static();
+  if (!st) return GGA_EHIP;
+  const int rc = static_init(st, dev_buf, cap_elems, elem_bytes, S(s));
+  if (rc) {
+    delete st;
+    return rc;
+  }
+  *out = st;
+  return GGA_OK;
+}
+
+int gga_static_destroy(gga_static* st, gga_stream s) {
+  if (!st) return GGA_EINVAL;
+  int rc = hip_status(hipStreamSynchronize(S(s)));
+  if (hipFree(st->meta) != hipSuccess) rc = GGA_EHIP;
+  delete st;
+  return rc;
+}
+
+int gga_static_insert(gga_static* st, const void* values, const uint8_t* flags, uint64_t n_threads,
+                      gga_stream s) {
+  if (!st || (n_threads && !values)) return GGA_EINVAL;
+  InsertDesc d{};
+  d.mode = kModeBuffer;
+  d.values = values;
+  d.flags = flags;
+  d.max_count = 1;
+  d.n_threads = n_threads;
+  return launch_static_insert(st, d, S(s));
+}
+
+int gga_static_insert_gen(gga_static* st, const gga_gen* g, uint64_t n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!st) return GGA_EINVAL;
+  const int rc = check_gen(g, &mode, &maxc);
+  if (rc) return rc;
+  return launch_static_insert(st, gen_desc(g, mode, n_threads), S(s));
+}
+
+int gga_static_rw(gga_static* st, uint32_t op, gga_stream s) {
+  if (!st || op > GGA_ADD1_X30) return GGA_EINVAL;
+  return launch_static_rw(st, op, S(s));
+}
+
+int gga_static_size(gga_static* st, uint64_t* out_host, gga_stream s) {
+  if (!st || !out_host) return GGA_EINVAL;
+  return static_read(st, out_host, S(s));
+}
+
+int gga_static_last_error(gga_static* st, gga_stream s) {
+  if (!st) return GGA_EINVAL;
+  return static_read(st, nullptr, S(s));
+}
+
+// --------------------------------------------------------- semi-static array --
+int gga_semi_create(gga_semistatic** out, uint32_t elem_bytes, uint64_t initial_cap, gga_stream s) {
+  if (!out) return GGA_EINVAL;
+  *out = nullptr;
+  if ((elem_bytes != 4 && elem_bytes != 8) || initial_cap == 0) return GGA_EINVAL;
+  gga_semistatic* ss = new (std::nothrow) gga_semistatic();
+  if (!ss) return GGA_EHIP;
+  void* buf = nullptr;
+  if (hipMallocAsync(&buf, initial_cap * elem_bytes, S(s)) != hipSuccess) {
+    delete ss;
+    return GGA_EHIP;
+  }
+  const int rc = static_init(&ss->st, buf, initial_cap, elem_bytes, S(s));
+  if (rc) {
+    (void)hipFreeAsync(buf, S(s));
+    delete ss;
+    return rc;
+  }
+  *out = ss;
+  return GGA_OK;
+}
+
+int gga_semi_destroy(gga_semistatic* ss, gga_stream s) {
+  if (!ss) return GGA_EINVAL;
+  int rc = hip_status(hipFreeAsync(ss->st.data, S(s)));
+  if (hipStreamSynchronize(S(s)) != hipSuccess) rc = GGA_EHIP;
+  if (hipFree(ss->st.meta) != hipSuccess) rc = GGA_EHIP;
+  delete ss;
+  return rc;
+}
+
+// Host-driven resize (Sec. III-A2): read the size, double until the round's
+// worst case fits, reallocate and copy.
+static int semi_reserve(gga_semistatic* ss, uint64_t worst, hipStream_t s) {
+  uint64_t size = 0;
+  int rc = static_read(&ss->st, &size, s);
+  if (rc) return rc;
+  if (size + worst <= ss->st.cap) return GGA_OK;
+  uint64_t cap = ss->st.cap;
+  while (cap < size + worst) cap *= 2;
+  void* nb = nullptr;
+  if (hipMallocAsync(&nb, cap * ss->st.elem_bytes, s) != hipSuccess) return GGA_EHIP;
+  if (size && hipMemcpyAsync(nb, ss->st.data, size * ss->st.elem_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return GGA_EHIP;
+  if (hipFreeAsync(ss->st.data, s) != hipSuccess) return GGA_EHIP;
+  ss->st.data = nb;
+  ss->st.cap = cap;
+  ss->resizes += 1;
+  return GGA_OK;
+}
+
+int gga_semi_insert(gga_semistatic* ss, const void* values, const uint8_t* flags, uint64_t n_threads,
+                    gga_stream s) {
+  if (!ss || (n_threads && !values)) return GGA_EINVAL;
+  int rc = semi_reserve(ss, n_threads, S(s));
+  return rc ? rc : gga_static_insert(&ss->st, values, flags, n_threads, s);
+}
+
+int gga_semi_insert_gen(gga_semistatic* ss, const gga_gen* g, uint64_t n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!ss) return GGA_EINVAL;
+  int rc = check_gen(g, &mode, &maxc);
+  if (rc) return rc;
+  rc = semi_reserve(ss, n_threads * maxc, S(s));
+  return rc ? rc : launch_static_insert(&ss->st, gen_desc(g, mode, n_threads), S(s));
+}
+
+int gga_semi_rw(gga_semistatic* ss, uint32_t op, gga_stream s) {
+  if (!ss) return GGA_EINVAL;
+  return gga_static_rw(&ss->st, op, s);
+}
+
+int gga_semi_size(gga_semistatic* ss, uint64_t* out_host, gga_stream s) {
+  if (!ss || !out_host) return GGA_EINVAL;
+  return static_read(&ss->st, out_host, S(s));
+}
+
+int gga_semi_data(gga_semistatic* ss, void** dev_data, uint64_t* cap_elems) {
+  if (!ss || !dev_data || !cap_elems) return GGA_EINVAL;
+  *dev_data = ss->st.data;
+  *cap_elems = ss->st.cap;
+  return GGA_OK;
+}
+
+int gga_semi_resizes(gga_semistatic* ss, uint64_t* out_host) {
+  if (!ss || !out_host) return GGA_EINVAL;
+  *out_host = ss->resizes;
+  return GGA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,606 @@
+// Insertion rounds: block-cooperative push_back (Alg. 1) with in-kernel bucket
+// growth (Alg. 2), for the GGArray and for the static-array baseline.
+//
+// One workgroup handles one tile of logical threads.  Tiles are numbered in
+// (LFVector, position) order and handed out by a ticket counter, so a tile's
+// predecessors inside its LFVector always belong to workgroups already running;
+// that is what makes the waits below safe.  Per tile:
+//   1. each thread produces its candidates (loads or generates them);
+//   2. the block computes the exclusive prefix sum of the insertion counts
+//      (0/1 producers: one wave ballot + mbcnt per candidate slot and a 64-entry
+//      wave scan of the per-wave totals; multi-element producers: a wave scan of
+//      the per-thread counts) and stages the kept elements in LDS, compacted;
+//   3. wave 0 obtains the tile's first index in its LFVector: the first tile of
+//      the LFVector reads the LFVector size, later tiles use a decoupled
+//      look-back over the tiles before them (each tile publishes its count, then
+//      its inclusive prefix, in one tagged 64-bit word);
+//   4. wave 0 allocates every bucket whose first index falls in the tile's
+//      range (exactly one tile holds each bucket start, which makes it the
+//      Alg. 2 winner without a CAS) and waits for the buckets a predecessor
+//      allocates;
+//   5. the last tile of the LFVector commits the new size, or, if any bucket
+//      allocation of the round failed, leaves the size as it was and freezes
+//      the LFVector;
+//   6. the block scatters the staged elements to their buckets, coalesced.
+// The static baseline replaces 3-5 by one global atomicAdd per tile.
+#include "gga_internal.h"
+
+namespace gga {
+namespace {
+
+constexpr int kB = 256;                  // threads per insertion workgroup
+constexpr int kW = kB / 64;              // waves per workgroup
+constexpr int kFlagK = 16;               // candidate slots per thread, 0/1 producers
+constexpr int kFlagTile = kB * kFlagK;   // 4096 logical threads per tile
+constexpr int kCountK = 4;               // candidates per thread, multi-element producers
+constexpr int kCountTile = kB * kCountK; // 1024 logical threads per tile
+constexpr int kStage = 4096;             // LDS staging capacity, elements
+static_assert(kFlagK * kW == 64, "one wave scans the per-(slot, wave) totals");
+static_assert(kFlagTile <= kStage, "a 0/1 tile stages in one pass");
+
+constexpr uint64_t kStA = 1;  // status flag: tile count published
+constexpr uint64_t kStP = 2;  // status flag: inclusive prefix published
+constexpr uint64_t kValMask = (1ull << 38) - 1;
+
+struct TileArgs {
+  uint64_t n_threads;
+  uint64_t chunk;        // logical threads per LFVector, ceil(n / V)
+  uint64_t tpv;          // tiles per LFVector
+  uint64_t ticket_base;
+  uint64_t epoch;        // 24-bit launch tag of the status words
+  uint32_t elem_log2;
+};
+
+struct StaticRef {
+  void* data;
+  uint64_t cap;
+  uint64_t* size;
+  uint64_t* ticket;
+  uint32_t* err;
+};
+
+struct TileShared {
+  uint64_t tile;
+  uint64_t base;
+  uint64_t bp[64];     // bucket pointers of buckets b_lo .. b_lo + nb - 1
+  uint32_t b_lo;
+  uint32_t nb;
+  uint32_t n_tile;
+  uint32_t writable;   // static baseline: elements that fit
+  uint32_t cnt[64];
+};
+
+__device__ __forceinline__ uint64_t pack_status(uint64_t epoch, uint64_t flag, uint64_t value) {
+  return (epoch << 40) | (flag << 38) | (value & kValMask);
+}
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------- producers --
+template <typename T>
+struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
+  static constexpr bool kMulti = false;
+  const T* values;
+  const uint8_t* flags;
+  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
+    x = values[g];
+    return flags ? (flags[g] != 0) : 1u;
+  }
+};
+template <typename T>
+struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
+  static constexpr bool kMulti = false;
+  uint64_t seed;
+  uint32_t round;
+  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
+    const uint64_t h = K(seed, g, round);
+    x = (T)h;
+    return (uint32_t)(h >> 63);
+  }
+};
+template <typename T>
+struct ProdRoundTag {  // insert (round << shift) | gid
+  static constexpr bool kMulti = false;
+  uint32_t round;
+  uint32_t shift;
+  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
+    x = (T)(((uint64_t)round << shift) | g);
+    return 1u;
+  }
+};
+template <typename T>
+struct ProdCounts {  // insert values[gid * max + j], j < counts[gid]
+  static constexpr bool kMulti = true;
+  const T* values;
+  const uint8_t* counts;
+  uint32_t max_count;
+  __device__ __forceinline__ uint32_t count(uint64_t g) const {
+    const uint32_t c = counts[g];
+    return c < max_count ? c : max_count;
+  }
+  __device__ __forceinline__ T value(uint64_t g, uint32_t r) const {
+    return values[g * max_count + r];
+  }
+};
+template <typename T>
+struct ProdPoisson {  // c = #{k : K(seed,gid,0x80|round) >= thr[k]}; insert K(seed,gid,16 round + j)
+  static constexpr bool kMulti = true;
+  uint64_t seed;
+  uint32_t round;
+  uint32_t max_count;
+  uint64_t thr[16];
+  __device__ __forceinline__ uint32_t count(uint64_t g) const {
+    const uint64_t u = K(seed, g, 0x80u | round);
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) c += (k < (int)max_count && u >= thr[k]) ? 1u : 0u;
+    return c;
+  }
+  __device__ __forceinline__ T value(uint64_t g, uint32_t r) const {
+    return (T)K(seed, g, 16u * round + r);
+  }
+};
+
+// -------------------------------------------------------- look-back (wave 0) --
+// Exclusive prefix of tile `tile`, which is tile t > 0 of its LFVector.  Lane l
+// inspects predecessor tile - 1 - l (window of 64), waiting until it has
+// published; the nearest predecessor with an inclusive prefix ends the search.
+// Returns false if a bounded wait expired.
+__device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint64_t epoch,
+                         uint64_t& out) {
+  const uint32_t lane = lane_id();
+  const int64_t lo = (int64_t)(tile - t);
+  int64_t hi = (int64_t)tile - 1;
+  uint64_t sum = 0;
+  for (;;) {
+    const int64_t mine = hi - (int64_t)lane;
+    const bool in = mine >= lo;
+    uint64_t w = 0;
+    bool ok = true;
+    if (in) {
+      for (uint32_t spins = 0;; ++spins) {
+        w = ld_rlx(&status[mine]);
+        if ((w >> 40) == epoch && ((w >> 38) & 3u) != 0) break;
+        if (spins >= kSpinLimit) {
+          ok = false;
+          break;
+        }
+        spin_pause();
+      }
+    }
+    if (__ballot(!ok)) return false;
+    const uint64_t pmask = __ballot(in && ((w >> 38) & 3u) == kStP);
+    if (pmask) {
+      const uint32_t first = (uint32_t)__ffsll((unsigned long long)pmask) - 1u;
+      sum += wave_sum64((in && lane <= first) ? (w & kValMask) : 0ull);
+      out = sum;
+      return true;
+    }
+    sum += wave_sum64(in ? (w & kValMask) : 0ull);
+    hi -= 64;
+  }
+}
+
+// ----------------------------------------------- growth + commit (wave 0) --
+// Resolves the tile's first index, allocates or waits for its buckets, and lets
+// the last tile of the LFVector commit the round.  Leaves base, b_lo, nb, the
+// bucket pointers and the number of elements to scatter in LDS.
+__device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
+                             uint64_t tile, bool is_last, uint32_t n_t, TileShared& sh) {
+  const uint32_t lane = lane_id();
+  const uint32_t log2F = A.log2F;
+  uint64_t old_size = 0;
+  uint64_t base = 0;
+  bool stalled = false;
+  if (t == 0) {
+    if (lane == 0) {
+      old_size = ld_rlx(&A.size[v]);
+      if (!is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStP, old_size + n_t));
+    }
+    base = __shfl(old_size, 0, 64);
+  } else {
+    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStA, n_t));
+    stalled = !lookback(A.status, tile, t, I.epoch, base);
+    if (lane == 0 && !is_last && !stalled)
+      st_rlx(&A.status[tile], pack_status(I.epoch, kStP, base + n_t));
+  }
+  if (stalled) {
+    // Predecessors never published: leave the LFVector as it was and freeze it.
+    if (lane == 0) {
+      set_error(A.err, kErrStall);
+      st_rlx32(&A.dead[v], 1u);
+      sh.n_tile = 0;
+      sh.nb = 0;
+    }
+    return;
+  }
+
+  uint32_t b_lo = 0, nb = 0;
+  if (n_t) {
+    b_lo = bucket_of(log2F, base);
+    nb = bucket_of(log2F, base + n_t - 1) - b_lo + 1;
+    const uint32_t b = b_lo + lane;
+    bool allocated = false, failed = false, late = false;
+    if (lane < nb) {
+      uint64_t p = kFailedPtr;
+      const bool holds_start = bucket_start(log2F, b) >= base;
+      if (b >= (uint32_t)kMaxBuckets) {
+        allocated = failed = holds_start;
+      } else {
+        uint64_t* slot = &A.bptr[(uint64_t)v * kMaxBuckets + b];
+        if (holds_start) {
+          // This tile writes the bucket's first index: it is the one that allocates.
+          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), v);
+          p = q ? (uint64_t)q : kFailedPtr;
+          st_rlx(slot, p);
+          allocated = true;
+          failed = !q;
+        } else {
+          uint32_t spins = 0;
+          while ((p = ld_rlx(slot)) == 0 && spins < kSpinLimit) {
+            ++spins;
+            spin_pause();
+          }
+          if (p == 0) {
+            p = kFailedPtr;
+            late = true;
+          }
+        }
+      }
+      sh.bp[lane] = p;
+    }
+    // One atomic reports this tile's allocations: the count in the low half,
+    // the failures in the high half.
+    const uint32_t n_alloc = (uint32_t)__popcll(__ballot(allocated));
+    const uint32_t n_fail = (uint32_t)__popcll(__ballot(failed));
+    if (lane == 0 && n_fail) set_error(A.err, kErrNoMem);
+    if (lane == 0 && __ballot(late)) set_error(A.err, kErrStall);
+    if (lane == 0 && n_alloc) fetch_add32(&A.alloc_done[v], n_alloc | (n_fail << 16));
+  }
+
+  if (is_last && lane == 0) {
+    const uint64_t old = (t == 0) ? old_size : ld_rlx(&A.size[v]);
+    const uint64_t nsize = base + n_t;
+    const uint32_t expected = nbuckets_for(log2F, nsize) - nbuckets_for(log2F, old);
+    uint32_t failed = 0;
+    if (expected) {
+      uint32_t done, spins = 0;
+      while (((done = ld_rlx32(&A.alloc_done[v])) & 0xFFFFu) < expected && spins < kSpinLimit) {
+        ++spins;
+        spin_pause();
+      }
+      if ((done & 0xFFFFu) < expected) {
+        set_error(A.err, kErrStall);
+        failed = 1;
+      } else {
+        failed = done >> 16;
+        st_rlx32(&A.alloc_done[v], 0u);
+      }
+    }
+    if (failed)
+      st_rlx32(&A.dead[v], 1u);
+    else
+      st_rlx(&A.size[v], nsize);
+  }
+  if (lane == 0) {
+    sh.base = base;
+    sh.b_lo = b_lo;
+    sh.nb = nb;
+    sh.n_tile = n_t;
+  }
+}
+
+// Static baseline: one global atomic per tile claims the index range.
+__device__ void resolve_static(const StaticRef& S, uint32_t n_t, TileShared& sh) {
+  if (threadIdx.x == 0) {
+    const uint64_t base = n_t ? fetch_add(S.size, n_t) : 0;
+    uint64_t fit = 0;
+    if (base < S.cap) fit = (S.cap - base) < n_t ? (S.cap - base) : n_t;
+    if (fit < n_t) set_error(S.err, kErrRange);
+    sh.base = base;
+    sh.writable = (uint32_t)fit;
+  }
+}
+
+// Scatter staged elements [0, n) (tile positions p0 + i) to their buckets.
+template <typename T>
+__device__ __forceinline__ void scatter(const ArrRef& A, const TileShared& sh, const T* stage,
+                                        uint64_t p0, uint32_t n) {
+  const uint32_t log2F = A.log2F;
+  const uint64_t first = sh.base + p0;
+  if (sh.nb == 1) {
+    const uint64_t p = sh.bp[0];
+    if (p <= kFailedPtr) return;
+    T* dst = reinterpret_cast<T*>(p) + (first - bucket_start(log2F, sh.b_lo));
+    for (uint32_t i = threadIdx.x; i < n; i += kB) dst[i] = stage[i];
+    return;
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kB) {
+    const uint64_t idx = first + i;
+    const uint32_t b = bucket_of(log2F, idx);
+    const uint64_t p = sh.bp[b - sh.b_lo];
+    if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = stage[i];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void scatter_static(const StaticRef& S, const TileShared& sh,
+                                               const T* stage, uint64_t p0, uint32_t n) {
+  T* dst = reinterpret_cast<T*>(S.data) + sh.base + p0;
+  uint32_t lim = sh.writable > p0 ? (uint32_t)(sh.writable - p0) : 0u;
+  if (lim > n) lim = n;
+  for (uint32_t i = threadIdx.x; i < lim; i += kB) dst[i] = stage[i];
+}
+
+// ------------------------------------------------------ 0/1 producer kernel --
+// Candidate slot j of thread tid is logical thread g0 + j * 256 + tid, so every
+// load of a buffer-mode producer is coalesced and the tile order (j, wave, lane)
+// equals the logical-thread order.
+template <typename T, class Prod, bool kStatic>
+__global__ __launch_bounds__(kB) void insert_flag_kernel(ArrRef A, StaticRef S, TileArgs I,
+                                                         Prod prod) {
+  __shared__ T stage[kStage];
+  __shared__ TileShared sh;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  if (tid == 0) sh.tile = fetch_add(kStatic ? S.ticket : A.ticket, 1) - I.ticket_base;
+  __syncthreads();
+  const uint64_t tile = sh.tile;
+  uint32_t v = 0;
+  uint64_t t, g0, gend;
+  if (kStatic) {
+    t = tile;
+    g0 = tile * kFlagTile;
+    gend = I.n_threads;
+  } else {
+    v = (uint32_t)(tile / I.tpv);
+    t = tile - (uint64_t)v * I.tpv;
+    const uint64_t c0 = (uint64_t)v * I.chunk;
+    g0 = c0 + t * kFlagTile;
+    gend = c0 + I.chunk < I.n_threads ? c0 + I.chunk : I.n_threads;
+  }
+  if (g0 >= gend) return;
+  if (!kStatic && ld_rlx32(&A.dead[v])) return;
+  const bool is_last = g0 + kFlagTile >= gend;
+
+  T val[kFlagK];
+  uint32_t pos[kFlagK];
+  uint32_t fbits = 0;
+#pragma unroll
+  for (int j = 0; j < kFlagK; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * kB + tid;
+    T x = 0;
+    uint32_t f = 0;
+    if (g < gend) f = prod.count(g, x);
+    val[j] = x;
+    const uint64_t m = __ballot(f != 0);
+    pos[j] = mbcnt(m);
+    fbits |= (f != 0 ? 1u : 0u) << j;
+    if (lane == 0) sh.cnt[j * kW + w] = (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  const uint32_t c = sh.cnt[lane];
+  const uint32_t incl = wave_incl_scan(c);
+  const uint32_t excl = incl - c;
+  const uint32_t n_t = __shfl(incl, 63, 64);
+#pragma unroll
+  for (int j = 0; j < kFlagK; ++j) {
+    const uint32_t off = __shfl(excl, j * kW + (int)w, 64);
+    if ((fbits >> j) & 1u) stage[off + pos[j]] = val[j];
+  }
+  if (kStatic) {
+    resolve_static(S, n_t, sh);
+  } else if (w == 0) {
+    resolve_tile(A, I, v, t, tile, is_last, n_t, sh);
+  }
+  __syncthreads();
+  if (kStatic)
+    scatter_static<T>(S, sh, stage, 0, n_t);
+  else
+    scatter<T>(A, sh, stage, 0, sh.n_tile);
+}
+
+// --------------------------------------------- multi-element producer kernel --
+// Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
+// plain scan of per-thread counts orders the elements.  A tile may emit up to
+// 16384 elements; they are staged and scattered in passes of kStage.
+template <typename T, class Prod, bool kStatic>
+__global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S, TileArgs I,
+                                                          Prod prod) {
+  __shared__ T stage[kStage];
+  __shared__ TileShared sh;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  if (tid == 0) sh.tile = fetch_add(kStatic ? S.ticket : A.ticket, 1) - I.ticket_base;
+  __syncthreads();
+  const uint64_t tile = sh.tile;
+  uint32_t v = 0;
+  uint64_t t, g0, gend;
+  if (kStatic) {
+    t = tile;
+    g0 = tile * kCountTile;
+    gend = I.n_threads;
+  } else {
+    v = (uint32_t)(tile / I.tpv);
+    t = tile - (uint64_t)v * I.tpv;
+    const uint64_t c0 = (uint64_t)v * I.chunk;
+    g0 = c0 + t * kCountTile;
+    gend = c0 + I.chunk < I.n_threads ? c0 + I.chunk : I.n_threads;
+  }
+  if (g0 >= gend) return;
+  if (!kStatic && ld_rlx32(&A.dead[v])) return;
+  const bool is_last = g0 + kCountTile >= gend;
+
+  uint32_t cnt[kCountK];
+  uint32_t c = 0;
+  const uint64_t gt = g0 + (uint64_t)tid * kCountK;
+#pragma unroll
+  for (int j = 0; j < kCountK; ++j) {
+    cnt[j] = (gt + j < gend) ? prod.count(gt + j) : 0u;
+    c += cnt[j];
+  }
+  const uint32_t incl = wave_incl_scan(c);
+  if (lane == 63) sh.cnt[w] = incl;
+  __syncthreads();
+  uint32_t before = 0, n_t = 0;
+#pragma unroll
+  for (int k = 0; k < kW; ++k) {
+    const uint32_t x = sh.cnt[k];
+    before += (k < (int)w) ? x : 0u;
+    n_t += x;
+  }
+  const uint32_t excl = before + incl - c;
+  if (kStatic) {
+    resolve_static(S, n_t, sh);
+  } else if (w == 0) {
+    resolve_tile(A, I, v, t, tile, is_last, n_t, sh);
+  }
+  __syncthreads();
+  const uint32_t n_out = kStatic ? n_t : sh.n_tile;  // 0 if the tile stalled
+  for (uint32_t p0 = 0; p0 < n_out; p0 += kStage) {
+    const uint32_t p1 = p0 + kStage;
+    uint32_t run = excl;
+#pragma unroll
+    for (int j = 0; j < kCountK; ++j) {
+      const uint32_t cj = cnt[j];
+      if (run < p1 && run + cj > p0) {
+        for (uint32_t r = 0; r < cj; ++r) {
+          const uint32_t q = run + r;
+          if (q >= p0 && q < p1) stage[q - p0] = prod.value(gt + j, r);
+        }
+      }
+      run += cj;
+    }
+    __syncthreads();
+    const uint32_t n = (n_out - p0) < (uint32_t)kStage ? (n_out - p0) : (uint32_t)kStage;
+    if (kStatic)
+      scatter_static<T>(S, sh, stage, p0, n);
+    else
+      scatter<T>(A, sh, stage, p0, n);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- dispatch --
+template <typename T, bool kStatic>
+int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const InsertDesc& d,
+             uint64_t ntiles, hipStream_t s) {
+  const dim3 grid((uint32_t)ntiles), block(kB);
+  switch (d.mode) {
+    case kModeBuffer: {
+      ProdBuffer<T> p{static_cast<const T*>(d.values), d.flags};
+      hipLaunchKernelGGL((insert_flag_kernel<T, ProdBuffer<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      break;
+    }
+    case kModeBernoulli: {
+      ProdBernoulli<T> p{d.seed, d.round};
+      hipLaunchKernelGGL((insert_flag_kernel<T, ProdBernoulli<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      break;
+    }
+    case kModeRoundTag: {
+      ProdRoundTag<T> p{d.round, d.tag_shift};
+      hipLaunchKernelGGL((insert_flag_kernel<T, ProdRoundTag<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      break;
+    }
+    case kModeCounts: {
+      ProdCounts<T> p{static_cast<const T*>(d.values), d.flags, d.max_count};
+      hipLaunchKernelGGL((insert_count_kernel<T, ProdCounts<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      break;
+    }
+    case kModePoisson: {
+      ProdPoisson<T> p;
+      p.seed = d.seed;
+      p.round = d.round;
+      p.max_count = d.max_count;
+      for (int k = 0; k < 16; ++k) p.thr[k] = d.thresholds[k];
+      hipLaunchKernelGGL((insert_count_kernel<T, ProdPoisson<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      break;
+    }
+    default:
+      return GGA_EINVAL;
+  }
+  return hip_status(hipGetLastError());
+}
+
+bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePoisson; }
+
+}  // namespace
+
+int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
+  if (d.n_threads == 0) return GGA_OK;
+  const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
+  const uint64_t chunk = (d.n_threads + a->V - 1) / a->V;
+  const uint64_t tpv = (chunk + tile - 1) / tile;
+  const uint64_t ntiles = tpv * a->V;
+  if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
+
+  // Look-back words: grown on demand; cleared when new or when the 24-bit epoch wraps.
+  if (ntiles > a->status_cap) {
+    uint64_t cap = a->status_cap ? a->status_cap : 4096;
+    while (cap < ntiles) cap *= 2;
+    if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
+    a->ref.status = nullptr;
+    a->status_cap = 0;
+    void* p = nullptr;
+    if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+    if (hipMemsetAsync(p, 0, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+    a->ref.status = static_cast<uint64_t*>(p);
+    a->status_cap = cap;
+    a->epoch = 0;
+  }
+  a->epoch += 1;
+  if (a->epoch >= (1ull << 24)) {
+    if (hipMemsetAsync(a->ref.status, 0, a->status_cap * sizeof(uint64_t), s) != hipSuccess)
+      return GGA_EHIP;
+    a->epoch = 1;
+  }
+
+  TileArgs I;
+  I.n_threads = d.n_threads;
+  I.chunk = chunk;
+  I.tpv = tpv;
+  I.ticket_base = a->ticket_base;
+  I.epoch = a->epoch;
+  I.elem_log2 = a->elem_log2;
+  StaticRef S{};
+  const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
+                                    : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
+  if (st == GGA_OK) {
+    a->ticket_base += ntiles;
+    a->prefix_valid = false;
+  }
+  return st;
+}
+
+int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
+  if (d.n_threads == 0) return GGA_OK;
+  const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
+  const uint64_t ntiles = (d.n_threads + tile - 1) / tile;
+  if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
+  TileArgs I{};
+  I.n_threads = d.n_threads;
+  I.ticket_base = st->ticket_base;
+  I.elem_log2 = st->elem_bytes == 4 ? 2u : 3u;
+  StaticRef S{st->data, st->cap, st->d_size, st->d_ticket, st->d_err};
+  ArrRef A{};
+  const int rc = st->elem_bytes == 4 ? dispatch<uint32_t, true>(A, S, I, d, ntiles, s)
+                                     : dispatch<uint64_t, true>(A, S, I, d, ntiles, s);
+  if (rc == GGA_OK) st->ticket_base += ntiles;
+  return rc;
+}
+
+}  // namespace gga

@@ -1,0 +1,362 @@
+"""ctypes binding of ``libggarray.so`` (the C ABI in ``include/ggarray.h``).
+
+Argument marshalling only: every operation runs in the library's HIP kernels.
+PyTorch supplies device memory (tensors) and streams (the current stream unless
+one is given).  Elements live in int32 / int64 tensors that hold the unsigned
+bit patterns; ``as_unsigned`` views them as numpy uint32 / uint64.
+
+The library must be built in-tree (``__graft_entry__.build()``); importing this
+module raises if it is missing, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libggarray.so")
+
+OK, EINVAL, ENOMEM, ERANGE, EHIP, EBUSY = 0, -1, -2, -3, -4, -5
+ADD1, MUL3ADD1, ADD1_X30 = 0, 1, 2
+GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON = 1, 2, 3
+
+_u32, _u64, _i32, _vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
+_P = ctypes.POINTER
+
+
+class GenSpec(ctypes.Structure):
+    _fields_ = [("kind", _u32), ("round", _u32), ("seed", _u64), ("tag_shift", _u32),
+                ("max_count", _u32), ("thresholds", _u64 * 16)]
+
+
+# name -> argtypes (every entry point returns int status unless listed in _RES)
+_SIGS = {
+    "gga_strerror": [_i32],
+    "gga_pool_create": [_P(_vp), _vp, _u64, _vp],
+    "gga_pool_destroy": [_vp],
+    "gga_pool_stats": [_vp, _P(_u64), _vp],
+    "gga_pool_set_fault": [_vp, _u64, _vp],
+    "ggarray_create": [_P(_vp), _vp, _u32, _u32, _u64, _vp],
+    "ggarray_destroy": [_vp, _vp],
+    "ggarray_insert": [_vp, _vp, _vp, _u64, _vp],
+    "ggarray_insert_counts": [_vp, _vp, _vp, _u32, _u64, _vp],
+    "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
+    "ggarray_shrink": [_vp, _u32, _u32, _vp],
+    "ggarray_rw": [_vp, _u32, _vp],
+    "ggarray_flatten": [_vp, _vp, _u64, _vp],
+    "ggarray_size": [_vp, _P(_u64), _vp],
+    "ggarray_capacity": [_vp, _P(_u64), _vp],
+    "ggarray_vector_sizes": [_vp, _vp, _vp],
+    "ggarray_prefix": [_vp, _vp, _vp],
+    "ggarray_last_error": [_vp, _vp],
+    "gga_static_create": [_P(_vp), _vp, _u64, _u32, _vp],
+    "gga_static_destroy": [_vp, _vp],
+    "gga_static_insert": [_vp, _vp, _vp, _u64, _vp],
+    "gga_static_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
+    "gga_static_rw": [_vp, _u32, _vp],
+    "gga_static_size": [_vp, _P(_u64), _vp],
+    "gga_static_last_error": [_vp, _vp],
+    "gga_semi_create": [_P(_vp), _u32, _u64, _vp],
+    "gga_semi_destroy": [_vp, _vp],
+    "gga_semi_insert": [_vp, _vp, _vp, _u64, _vp],
+    "gga_semi_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
+    "gga_semi_rw": [_vp, _u32, _vp],
+    "gga_semi_size": [_vp, _P(_u64), _vp],
+    "gga_semi_data": [_vp, _P(_vp), _P(_u64)],
+    "gga_semi_resizes": [_vp, _P(_u64)],
+}
+_RES = {"gga_strerror": ctypes.c_char_p}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = _RES.get(name, _i32)
+        _lib = L
+    return _lib
+
+
+class GGAError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = lib().gga_strerror(status).decode()
+        super().__init__(f"{what}: {msg} ({status})")
+        self.status = status
+
+
+def _check(status: int, what: str) -> None:
+    if status != OK:
+        raise GGAError(status, what)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype(elem_bytes: int) -> torch.dtype:
+    return torch.int32 if elem_bytes == 4 else torch.int64
+
+
+def _dev_ptr(t: torch.Tensor | None, what: str, min_numel: int = 0, itemsize: int | None = None):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous device tensor")
+    if itemsize is not None and t.element_size() != itemsize:
+        raise ValueError(f"{what} must have {itemsize}-byte elements")
+    if t.numel() < min_numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {min_numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def to_device(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """numpy uint32/uint64/uint8 array -> device tensor with the same bits."""
+    a = np.ascontiguousarray(a)
+    view = {np.dtype(np.uint32): np.int32, np.dtype(np.uint64): np.int64,
+            np.dtype(np.uint8): np.uint8}[a.dtype]
+    return torch.from_numpy(a.view(view)).to(device)
+
+
+def as_unsigned(t: torch.Tensor) -> np.ndarray:
+    """Device or host int32/int64 tensor -> numpy uint32/uint64 array."""
+    a = t.detach().cpu().numpy()
+    return a.view(np.uint32 if a.dtype == np.int32 else np.uint64)
+
+
+def make_gen(kind: int, seed: int = 0, round: int = 0, tag_shift: int = 0, max_count: int = 0,
+             thresholds=None) -> GenSpec:
+    g = GenSpec()
+    g.kind, g.round, g.seed, g.tag_shift, g.max_count = kind, round, seed, tag_shift, max_count
+    if thresholds is not None:
+        thr = [int(x) for x in np.asarray(thresholds, dtype=np.uint64)]
+        for k, x in enumerate(thr[:16]):
+            g.thresholds[k] = x
+    return g
+
+
+class Pool:
+    """Device bucket pool over a caller-owned HBM tensor."""
+
+    def __init__(self, nbytes: int, device="cuda", stream=None):
+        self.mem = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self._h = _vp()
+        _check(lib().gga_pool_create(ctypes.byref(self._h), self.mem.data_ptr(), int(nbytes),
+                                     _stream(stream)), "gga_pool_create")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self, stream=None) -> dict:
+        out = (_u64 * 7)()
+        _check(lib().gga_pool_stats(self._h, out, _stream(stream)), "gga_pool_stats")
+        keys = ("in_use", "high_water", "allocs", "frees", "bump", "limit", "attempts")
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def set_fault(self, fault_at: int, stream=None):
+        _check(lib().gga_pool_set_fault(self._h, int(fault_at), _stream(stream)), "gga_pool_set_fault")
+
+    def close(self):
+        if self._h:
+            _check(lib().gga_pool_destroy(self._h), "gga_pool_destroy")
+            self._h = _vp()
+
+
+class GGArray:
+    """An array of LFVectors on the GPU (see include/ggarray.h)."""
+
+    def __init__(self, pool: Pool, elem_bytes: int, n_vectors: int, first_bucket: int, stream=None):
+        self.pool = pool
+        self.elem_bytes = elem_bytes
+        self.n_vectors = n_vectors
+        self.first_bucket = first_bucket
+        self.dtype = _dtype(elem_bytes)
+        self._h = _vp()
+        _check(lib().ggarray_create(ctypes.byref(self._h), pool.handle, elem_bytes, n_vectors,
+                                    first_bucket, _stream(stream)), "ggarray_create")
+
+    def insert(self, values: torch.Tensor, flags: torch.Tensor | None = None, n_threads=None,
+               stream=None):
+        n = values.numel() if n_threads is None else int(n_threads)
+        vp = _dev_ptr(values, "values", n, self.elem_bytes)
+        fp = _dev_ptr(flags, "flags", n, 1)
+        _check(lib().ggarray_insert(self._h, vp, fp, n, _stream(stream)), "ggarray_insert")
+
+    def insert_counts(self, values: torch.Tensor, counts: torch.Tensor, max_count: int, stream=None):
+        n = counts.numel()
+        vp = _dev_ptr(values, "values", n * max_count, self.elem_bytes)
+        cp = _dev_ptr(counts, "counts", n, 1)
+        _check(lib().ggarray_insert_counts(self._h, vp, cp, max_count, n, _stream(stream)),
+               "ggarray_insert_counts")
+
+    def insert_gen(self, gen: GenSpec, n_threads: int, stream=None):
+        _check(lib().ggarray_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
+               "ggarray_insert_gen")
+
+    def shrink(self, num: int, den: int, stream=None):
+        _check(lib().ggarray_shrink(self._h, num, den, _stream(stream)), "ggarray_shrink")
+
+    def rw(self, op: int, stream=None):
+        _check(lib().ggarray_rw(self._h, op, _stream(stream)), "ggarray_rw")
+
+    def flatten_into(self, out: torch.Tensor, stream=None):
+        _check(lib().ggarray_flatten(self._h, _dev_ptr(out, "out", 0, self.elem_bytes), out.numel(),
+                                     _stream(stream)), "ggarray_flatten")
+
+    def flatten(self, stream=None) -> torch.Tensor:
+        n = self.size(stream)
+        out = torch.empty(max(n, 1), dtype=self.dtype, device=self.pool.mem.device)
+        self.flatten_into(out[:n] if n else out[:0], stream)
+        return out[:n]
+
+    def size(self, stream=None) -> int:
+        v = _u64()
+        _check(lib().ggarray_size(self._h, ctypes.byref(v), _stream(stream)), "ggarray_size")
+        return int(v.value)
+
+    def capacity(self, stream=None) -> int:
+        v = _u64()
+        _check(lib().ggarray_capacity(self._h, ctypes.byref(v), _stream(stream)), "ggarray_capacity")
+        return int(v.value)
+
+    def vector_sizes(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n_vectors, dtype=torch.int64, device=self.pool.mem.device)
+        _check(lib().ggarray_vector_sizes(self._h, _dev_ptr(out, "out"), _stream(stream)),
+               "ggarray_vector_sizes")
+        return out
+
+    def prefix(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n_vectors + 1, dtype=torch.int64, device=self.pool.mem.device)
+        _check(lib().ggarray_prefix(self._h, _dev_ptr(out, "out"), _stream(stream)), "ggarray_prefix")
+        return out
+
+    def last_error(self, stream=None) -> int:
+        return int(lib().ggarray_last_error(self._h, _stream(stream)))
+
+    def close(self, stream=None):
+        if self._h:
+            _check(lib().ggarray_destroy(self._h, _stream(stream)), "ggarray_destroy")
+            self._h = _vp()
+
+
+class StaticArray:
+    """Pre-allocated flat array baseline (caller-owned buffer of cap elements)."""
+
+    def __init__(self, cap: int, elem_bytes: int, device="cuda", stream=None):
+        self.elem_bytes = elem_bytes
+        self.buf = torch.empty(max(int(cap), 1), dtype=_dtype(elem_bytes), device=device)
+        self.cap = int(cap)
+        self._h = _vp()
+        _check(lib().gga_static_create(ctypes.byref(self._h), self.buf.data_ptr(), self.cap,
+                                       elem_bytes, _stream(stream)), "gga_static_create")
+
+    def insert(self, values, flags=None, stream=None):
+        n = values.numel()
+        _check(lib().gga_static_insert(self._h, _dev_ptr(values, "values", n, self.elem_bytes),
+                                       _dev_ptr(flags, "flags", n, 1), n, _stream(stream)),
+               "gga_static_insert")
+
+    def insert_gen(self, gen: GenSpec, n_threads: int, stream=None):
+        _check(lib().gga_static_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
+               "gga_static_insert_gen")
+
+    def rw(self, op: int, stream=None):
+        _check(lib().gga_static_rw(self._h, op, _stream(stream)), "gga_static_rw")
+
+    def size(self, stream=None) -> int:
+        v = _u64()
+        _check(lib().gga_static_size(self._h, ctypes.byref(v), _stream(stream)), "gga_static_size")
+        return int(v.value)
+
+    def last_error(self, stream=None) -> int:
+        return int(lib().gga_static_last_error(self._h, _stream(stream)))
+
+    def data(self, stream=None) -> torch.Tensor:
+        return self.buf[: self.size(stream)]
+
+    def close(self, stream=None):
+        if self._h:
+            _check(lib().gga_static_destroy(self._h, _stream(stream)), "gga_static_destroy")
+            self._h = _vp()
+
+
+class SemiStaticArray:
+    """Host-resized doubling array baseline."""
+
+    def __init__(self, elem_bytes: int, initial_cap: int, stream=None):
+        self.elem_bytes = elem_bytes
+        self.dtype = _dtype(elem_bytes)
+        self._h = _vp()
+        _check(lib().gga_semi_create(ctypes.byref(self._h), elem_bytes, int(initial_cap),
+                                     _stream(stream)), "gga_semi_create")
+
+    def insert(self, values, flags=None, stream=None):
+        n = values.numel()
+        _check(lib().gga_semi_insert(self._h, _dev_ptr(values, "values", n, self.elem_bytes),
+                                     _dev_ptr(flags, "flags", n, 1), n, _stream(stream)),
+               "gga_semi_insert")
+
+    def insert_gen(self, gen: GenSpec, n_threads: int, stream=None):
+        _check(lib().gga_semi_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
+               "gga_semi_insert_gen")
+
+    def rw(self, op: int, stream=None):
+        _check(lib().gga_semi_rw(self._h, op, _stream(stream)), "gga_semi_rw")
+
+    def size(self, stream=None) -> int:
+        v = _u64()
+        _check(lib().gga_semi_size(self._h, ctypes.byref(v), _stream(stream)), "gga_semi_size")
+        return int(v.value)
+
+    def resizes(self) -> int:
+        v = _u64()
+        _check(lib().gga_semi_resizes(self._h, ctypes.byref(v)), "gga_semi_resizes")
+        return int(v.value)
+
+    def data(self, stream=None) -> torch.Tensor:
+        """Copy of the live elements (device tensor)."""
+        n = self.size(stream)
+        p, cap = _vp(), _u64()
+        _check(lib().gga_semi_data(self._h, ctypes.byref(p), ctypes.byref(cap)), "gga_semi_data")
+        out = torch.empty(max(n, 1), dtype=self.dtype, device="cuda")
+        if n:
+            torch.cuda.current_stream().synchronize()
+            _copy_from_ptr(out, p.value, n * self.elem_bytes)
+        return out[:n]
+
+    def close(self, stream=None):
+        if self._h:
+            _check(lib().gga_semi_destroy(self._h, _stream(stream)), "gga_semi_destroy")
+            self._h = _vp()
+
+
+def _copy_from_ptr(out: torch.Tensor, src_ptr: int, nbytes: int):
+    """Device-to-device copy from a raw device pointer into `out` (HIP runtime)."""
+    hip = _hip_runtime()
+    rc = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(src_ptr), ctypes.c_size_t(nbytes),
+                       ctypes.c_int(3))
+    if rc != 0:
+        raise GGAError(EHIP, "hipMemcpy")
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = ctypes.c_int
+    return _hip
