@@ -1,0 +1,315 @@
+#!/usr/bin/env python
+"""Benchmark of the GGArray hot path on one MI355X.
+
+Workload (one step): configuration 2 of the project, the paper's doubling-growth
+experiment at scale (Sec. VI-C) -- a GGArray of 512 LFVectors of uint32 with
+first bucket 1024 receives 2^28 insertions over 12 growth rounds (n_0 = 2^17,
+n_r = 2^(16+r)); after every round each LFVector pops a tenth of its elements
+(shrink 1/10); then one r/w pass x = 3x + 1 over every live element; then the
+prefix-sum flatten into a contiguous buffer; then the array is emptied (shrink
+1/1) for the next step.  Payloads are generated on the device: thread gid of
+round r inserts (r << 27) | gid.  All input is synthetic.
+
+`value` is the step throughput in inserted elements per second (Gelem/s) with
+nothing but the array metadata resident when the timed region starts.  Per-kernel
+HIP-event timings give insert Gelem/s and r/w / flatten HBM GB/s; the static
+array and the host-resized (semi-static) array run the same insertion rounds
+and r/w pass beside it.  The CPU oracle runs the same workload on the host.
+
+One JSON line is printed.  Only one GPU is used; --gpus above 1 is refused.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "insert Gelem/s + r/w HBM GB/s (vs static array); p50/p99 latency served"
+HBM_PEAK_GBPS = 8000.0
+F, ELEM, TAG_SHIFT = 1024, 4, 27
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--vectors", type=int, default=512, help="LFVectors (the paper's 32 / 512 sweep)")
+    ap.add_argument("--no-baselines", action="store_true", help="skip static / semi-static arrays")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and its parity check")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Timer:
+    """HIP events on torch's current stream, the stream every library call uses."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.marks = {}
+
+    def span(self, name):
+        torch = self.torch
+        t = self
+
+        class _S:
+            def __enter__(self):
+                self.a = torch.cuda.Event(enable_timing=True)
+                self.b = torch.cuda.Event(enable_timing=True)
+                self.a.record()
+
+            def __exit__(self, *exc):
+                self.b.record()
+                t.marks.setdefault(name, []).append((self.a, self.b))
+
+        return _S()
+
+    def ms(self, name):
+        return [a.elapsed_time(b) for a, b in self.marks.get(name, [])]
+
+
+def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None):
+    def span(name):
+        return timer.span(name) if timer else _Null()
+
+    for r, n in enumerate(rounds):
+        with span(f"insert{r}"):
+            arr.insert_gen(gens[r], n)
+        with span(f"shrink{r}"):
+            arr.shrink(1, 10)
+    with span("prefix"):
+        arr.prefix_into(prefix_buf)
+    with span("rw"):
+        arr.rw(G.MUL3ADD1)
+    with span("flatten"):
+        arr.flatten_into(out)
+    with span("clear"):
+        arr.shrink(1, 1)
+
+
+class _Null:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
+    """The CPU oracle (list form, one thread) on the full workload, repeated until
+    about min_seconds of work; returns (Gelem/s, seconds per pass, last flatten)."""
+    import oracle
+    times, flat = [], None
+    while len(times) < max_reps and (sum(times) < min_seconds or len(times) < 2):
+        o = oracle.Oracle(ELEM, V, F, forms=oracle.FORM_LIST)
+        t0 = time.perf_counter()
+        for r, n in enumerate(rounds):
+            o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=TAG_SHIFT)
+            o.shrink(1, 10)
+        o.rw(oracle.OP_MUL3ADD1)
+        flat = o.flatten()
+        times.append(time.perf_counter() - t0)
+        o.close()
+    t = statistics.median(times)
+    return (1 << 28) / t / 1e9, t, len(times), flat
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                          "not part of this build (LFVectors shard without communication, "
+                          "see the design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2209_00103_amd import ggarray as G
+    from paper_2209_00103_amd import workloads as wl
+
+    torch.cuda.set_device(0)
+    V = args.vectors
+    rounds = wl.cfg2_round_threads()
+    gens = [G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=TAG_SHIFT) for r in range(len(rounds))]
+    pool = G.Pool(8 << 30)
+    arr = G.GGArray(pool, ELEM, V, F)
+    prefix_buf = torch.empty(V + 1, dtype=torch.int64, device="cuda")
+
+    # Size the flatten buffer with one untimed pass.
+    for r, n in enumerate(rounds):
+        arr.insert_gen(gens[r], n)
+        arr.shrink(1, 10)
+    final_size = arr.size()
+    capacity = arr.capacity()
+    pool_stats = pool.stats()
+    arr.shrink(1, 1)
+    out = torch.empty(final_size, dtype=torch.int32, device="cuda")
+    log(f"final size {final_size}, capacity {capacity} ({capacity / final_size:.3f} x live)")
+
+    for _ in range(args.warmup):
+        ggarray_step(G, arr, gens, rounds, out, prefix_buf)
+    torch.cuda.synchronize()
+
+    # Timed region: K steps back to back, events only at the two ends.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        ggarray_step(G, arr, gens, rounds, out, prefix_buf)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    assert arr.last_error() == 0, "device error during the timed steps"
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    ms_step_wall = wall * 1e3 / args.steps
+
+    # Per-kernel durations: the same K steps again with events around every call.
+    timer = Timer(torch)
+    for _ in range(args.steps):
+        ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer)
+    torch.cuda.synchronize()
+    assert arr.last_error() == 0, "device error during the per-kernel pass"
+
+    # Per-kernel figures (algorithmic bytes, SURVEY-style accounting in the design notes).
+    ins_ms = [statistics.mean(timer.ms(f"insert{r}")) for r in range(len(rounds))]
+    shr_ms = [statistics.mean(timer.ms(f"shrink{r}")) for r in range(len(rounds))]
+    rw_ms = statistics.mean(timer.ms("rw"))
+    fl_ms = statistics.mean(timer.ms("flatten"))
+    pre_ms = statistics.mean(timer.ms("prefix"))
+    clr_ms = statistics.mean(timer.ms("clear"))
+    ins_bytes = [ELEM * n for n in rounds]
+    rw_bytes = 2 * ELEM * final_size
+    fl_bytes = 2 * ELEM * final_size + 8 * (V + 1)
+    gbps = lambda b, ms: b / (ms * 1e-3) / 1e9  # noqa: E731
+    kernels = {
+        "insert": {"launches_per_step": len(rounds), "avg_us": 1e3 * sum(ins_ms) / len(rounds),
+                   "bytes_per_launch": sum(ins_bytes) / len(rounds),
+                   "GBps": gbps(sum(ins_bytes), sum(ins_ms)),
+                   "Gelem_s": (1 << 28) / (sum(ins_ms) * 1e-3) / 1e9,
+                   "per_round_us": [round(1e3 * x, 2) for x in ins_ms],
+                   "last_round_GBps": gbps(ins_bytes[-1], ins_ms[-1])},
+        "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,
+               "GBps": gbps(rw_bytes, rw_ms)},
+        "flatten": {"launches_per_step": 1, "avg_us": 1e3 * fl_ms, "bytes_per_launch": fl_bytes,
+                    "GBps": gbps(fl_bytes, fl_ms)},
+        "shrink": {"launches_per_step": len(rounds) + 1, "avg_us": 1e3 * statistics.mean(shr_ms + [clr_ms])},
+        "prefix_scan": {"launches_per_step": 1, "avg_us": 1e3 * pre_ms},
+    }
+    for k in ("insert", "rw", "flatten"):
+        kernels[k]["frac"] = kernels[k]["GBps"] / HBM_PEAK_GBPS
+    totals = {"insert": sum(ins_ms), "rw": rw_ms, "flatten": fl_ms}
+    dom = max(totals, key=totals.get)
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get(dom)
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"], "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": kernels[dom]["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
+                "avg_launch_us": kernels[dom]["avg_us"], "bytes_per_launch": kernels[dom]["bytes_per_launch"]}
+    log(f"ms/step {ms_step:.3f} (wall {ms_step_wall:.3f}); insert {kernels['insert']['Gelem_s']:.1f} Gelem/s "
+        f"rw {kernels['rw']['GBps']:.0f} GB/s flatten {kernels['flatten']['GBps']:.0f} GB/s")
+
+    # Baselines beside it: the static array (pre-allocated for 2^28) and the
+    # host-resized array, same insertion rounds (they have no shrink) and r/w.
+    baselines = None
+    if not args.no_baselines:
+        baselines = {}
+        st = G.StaticArray(1 << 28, ELEM)
+        for rep in range(args.warmup + args.steps):
+            st.clear()
+            tm = Timer(torch)
+            for r, n in enumerate(rounds):
+                with tm.span("ins"):
+                    st.insert_gen(gens[r], n)
+            with tm.span("rw"):
+                st.rw(G.MUL3ADD1)
+            if rep == args.warmup:
+                torch.cuda.synchronize()
+                s_ins, s_rw = [], []
+            if rep >= args.warmup:
+                torch.cuda.synchronize()
+                s_ins.append(sum(tm.ms("ins")))
+                s_rw.append(tm.ms("rw")[0])
+        st_size = st.size()
+        assert st.last_error() == 0 and st_size == 1 << 28
+        baselines["static"] = {"insert_Gelem_s": (1 << 28) / (statistics.mean(s_ins) * 1e-3) / 1e9,
+                               "rw_GBps": gbps(2 * ELEM * st_size, statistics.mean(s_rw)),
+                               "capacity_elems": 1 << 28, "live_elems": st_size}
+        st.close()
+        sem_ins, sem_rw, resizes = [], [], 0
+        for rep in range(max(2, min(args.steps, 3)) + 1):
+            ss = G.SemiStaticArray(ELEM, rounds[0])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for r, n in enumerate(rounds):
+                ss.insert_gen(gens[r], n)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ss.rw(G.MUL3ADD1)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep > 0:
+                sem_ins.append(t1 - t0)
+                sem_rw.append(t2 - t1)
+            resizes = ss.resizes()
+            ss.close()
+        baselines["semi_static"] = {"insert_Gelem_s": (1 << 28) / statistics.mean(sem_ins) / 1e9,
+                                    "rw_GBps": 2 * ELEM * (1 << 28) / statistics.mean(sem_rw) / 1e9,
+                                    "resizes": resizes, "timing": "host wall clock (resizes synchronise)"}
+        log(f"static insert {baselines['static']['insert_Gelem_s']:.1f} Gelem/s rw "
+            f"{baselines['static']['rw_GBps']:.0f} GB/s; semi-static insert "
+            f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        rate, secs, reps, ref = cpu_baseline(rounds, V)
+        got = G.as_unsigned(out)
+        parity = bool(got.shape == ref.shape and np.array_equal(got, ref))
+        cpu = {"value": rate, "unit": "Gelem/s", "cores": 1, "kind": "oracle",
+               "sample": f"the full workload (2^28 insertions, 12 rounds with shrink, r/w, flatten), "
+                         f"single-threaded list-form oracle, median of {reps} passes of {secs:.2f} s",
+               "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+        log(f"cpu oracle {rate:.4f} Gelem/s ({secs:.2f} s/pass); flatten parity with oracle: {parity}")
+
+    value = (1 << 28) / (ms_step * 1e-3) / 1e9
+    line = {
+        "metric": METRIC, "value": value, "unit": "Gelem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "growth at scale: 2^28 uint32 insertions over 12 rounds (live count "
+                               "doubling, shrink 1/10 per round), r/w x=3x+1, flatten",
+                   "n_vectors": V, "first_bucket": F, "elem": "u32", "inserts": 1 << 28, "rounds": len(rounds),
+                   "final_size": final_size},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "baselines": baselines,
+        "memory": {"capacity_elems": capacity, "live_elems": final_size, "capacity_over_live": capacity / final_size,
+                   "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
+        "parity_with_oracle": parity,
+        "ms_per_step_wall": ms_step_wall,
+    }
+    arr.close()
+    pool.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -92,11 +92,15 @@ const char *gga_strerror(int status);
  *
  * gga_pool_create: dev_base is caller-owned device memory of `bytes` bytes,
  *   256-byte aligned, at least 1 MiB; it must outlive the pool.  The pool keeps
- *   its header at the start and carves buckets (power-of-two sizes, >= 256 B)
- *   from the rest.  Queued on s.  EINVAL on a NULL/unaligned/small buffer.
+ *   a 128 KiB header at the start and carves buckets (power-of-two sizes,
+ *   >= 256 B) from the rest, through 256 shards that each sub-allocate chunks
+ *   of about 1/1024 of the region (64 KiB .. 16 MiB), so up to 256 chunks may
+ *   be partly used.  Synchronises s.  EINVAL on a NULL/unaligned/small buffer.
  * gga_pool_destroy: frees the host handle; EBUSY while arrays still use it.
- * gga_pool_stats: out[0..6] = bytes in use, high-water bytes, allocations,
- *   frees, bump offset, region bytes, allocation attempts.  Synchronises s.
+ * gga_pool_stats: out[0..6] = bytes in use, bytes carved from the region so far
+ *   (an upper bound of the peak in use), allocations, frees, the same carved
+ *   bytes, region bytes, allocation attempts counted for fault injection.
+ *   Synchronises s.
  * gga_pool_set_fault: the fault_at-th allocation attempt from now fails as if
  *   the pool were exhausted (0 disables).  For failure-handling tests. */
 int gga_pool_create(gga_pool **out, void *dev_base, uint64_t bytes, gga_stream s);
@@ -156,7 +160,8 @@ int ggarray_rw(ggarray *a, uint32_t op, gga_stream s);
 int ggarray_flatten(ggarray *a, void *out, uint64_t out_cap_elems, gga_stream s);
 
 /* ggarray_size: global size = sum of the LFVector sizes (Sec. IV), into *out_host.
- *   Synchronises s.  Returns the sticky device error if one is set. */
+ *   Synchronises s.  Returns the sticky device error if one is set; *out_host is
+ *   written in that case too (the size of the committed contents). */
 int ggarray_size(ggarray *a, uint64_t *out_host, gga_stream s);
 
 /* ggarray_capacity: elements held by the allocated buckets, into *out_host.
@@ -188,6 +193,8 @@ int gga_static_insert_gen(gga_static *st, const gga_gen *g, uint64_t n_threads, 
 int gga_static_rw(gga_static *st, uint32_t op, gga_stream s);
 int gga_static_size(gga_static *st, uint64_t *out_host, gga_stream s); /* synchronises */
 int gga_static_last_error(gga_static *st, gga_stream s);                /* synchronises */
+/* Empties the array and clears its sticky error (the buffer is kept).  Queued. */
+int gga_static_clear(gga_static *st, gga_stream s);
 
 /* ----------------------------------------- semi-static array baseline ------ */
 /* The host-resized array of Sec. III-A2: before each insertion round the host

@@ -84,35 +84,41 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t t
   }
 }
 
-// Shrink (pop floor(s num / den) per LFVector) and bucket release.
-__global__ void shrink_kernel(ArrRef A, uint32_t num, uint32_t den, uint32_t elem_log2) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+// Shrink (pop floor(s num / den) per LFVector) and bucket release: one wave per
+// LFVector, lane b looks after bucket b, so the releases of one LFVector run in
+// parallel and go to different pool shards.
+constexpr uint32_t kVecPerBlock = 4;  // 256 threads = 4 waves = 4 LFVectors
+
+__global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uint32_t den,
+                                                     uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  const uint32_t b = threadIdx.x & 63u;
   if (v >= A.V) return;
   const uint64_t s = A.size[v];
-  const uint64_t k = (s / den) * num + ((s % den) * num) / den;
-  const uint64_t ns = s - k;
-  A.size[v] = ns;
+  const uint64_t ns = s - ((s / den) * num + ((s % den) * num) / den);
   const uint32_t lo = nbuckets_for(A.log2F, ns);
   uint32_t hi = A.dead[v] ? (uint32_t)kMaxBuckets : nbuckets_for(A.log2F, s);
   if (hi > (uint32_t)kMaxBuckets) hi = kMaxBuckets;
-  uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
-  for (uint32_t b = lo; b < hi; ++b) {
-    const uint64_t p = row[b];
-    if (p > kFailedPtr) pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), v);
-    if (p) row[b] = 0;
+  if (b >= lo && b < hi) {
+    uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
+    const uint64_t p = *slot;
+    if (p > kFailedPtr)
+      pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b));
+    if (p) *slot = 0;
   }
+  if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
 }
 
 // Returns every bucket of the array to the pool (destroy).
-__global__ void free_all_kernel(ArrRef A, uint32_t elem_log2) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= A.V) return;
-  uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
-  for (uint32_t b = 0; b < (uint32_t)kMaxBuckets; ++b) {
-    const uint64_t p = row[b];
-    if (p > kFailedPtr) pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), v);
-    row[b] = 0;
-  }
+__global__ __launch_bounds__(256) void free_all_kernel(ArrRef A, uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  const uint32_t b = threadIdx.x & 63u;
+  if (v >= A.V || b >= (uint32_t)kMaxBuckets) return;
+  uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
+  const uint64_t p = *slot;
+  if (p > kFailedPtr)
+    pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b));
+  *slot = 0;
 }
 
 // Elements held by allocated buckets.
@@ -148,7 +154,8 @@ __device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
 
 // One tile: cnt (<= te) elements at src (16-byte aligned); rw in place, or copy
 // to dst (element aligned) for flatten.  Lane i of slot k handles the 16 bytes
-// at element k * (256 * VPL) + i * VPL.
+// at element k * (256 * VPL) + i * VPL.  Every byte is touched once, so loads and
+// stores are non-temporal.
 template <typename T, bool kFlatten>
 __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32_t op) {
   constexpr uint32_t VPL = 16 / sizeof(T);
@@ -159,24 +166,24 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
     u32x4 r[kSlots];
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k)
-      r[k] = *reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL);
+      r[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL));
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k) {
       if (kFlatten)
-        *reinterpret_cast<u32x4_a4*>(dst + k * kSpan + tid * VPL) = r[k];
+        __builtin_nontemporal_store(r[k], reinterpret_cast<u32x4_a4*>(dst + k * kSpan + tid * VPL));
       else
-        *reinterpret_cast<u32x4*>(src + k * kSpan + tid * VPL) = op_vec<T>(op, r[k]);
+        __builtin_nontemporal_store(op_vec<T>(op, r[k]), reinterpret_cast<u32x4*>(src + k * kSpan + tid * VPL));
     }
     return;
   }
   for (uint32_t k = 0; k < kSlots; ++k) {
     const uint32_t e = k * kSpan + tid * VPL;
     if (e + VPL <= cnt) {
-      const u32x4 x = *reinterpret_cast<const u32x4*>(src + e);
+      const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + e));
       if (kFlatten)
-        *reinterpret_cast<u32x4_a4*>(dst + e) = x;
+        __builtin_nontemporal_store(x, reinterpret_cast<u32x4_a4*>(dst + e));
       else
-        *reinterpret_cast<u32x4*>(src + e) = op_vec<T>(op, x);
+        __builtin_nontemporal_store(op_vec<T>(op, x), reinterpret_cast<u32x4*>(src + e));
     } else {
       for (uint32_t q = e; q < cnt && q < e + VPL; ++q) {
         if (kFlatten)
@@ -190,7 +197,8 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
 
 // Persistent walk over the bucket-aligned tiles: workgroup w takes the w-th
 // contiguous share of the tiles, finds its first LFVector by binary search over
-// the tile prefix, then walks forward.
+// the tile prefix, then walks forward; the bucket pointer and the destination
+// offset are reloaded only when the walk enters a new bucket.
 template <typename T, bool kFlatten>
 __global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t op, T* out,
                                                            uint64_t out_cap, uint32_t te_log2) {
@@ -224,12 +232,13 @@ __global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t o
     k -= nt;
     ++b;
   }
+  T* bucket = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]);
+  T* dbase = kFlatten ? out + A.prefix[v] + bucket_start(log2F, b) : nullptr;
   for (uint64_t t = t0;;) {
-    T* src = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + (k << te_log2);
-    const uint64_t rem = live - (k << te_log2);
+    const uint64_t e0 = k << te_log2;
+    const uint64_t rem = live - e0;
     const uint32_t cnt = (uint32_t)(rem < te ? rem : te);
-    T* dst = kFlatten ? out + A.prefix[v] + bucket_start(log2F, b) + (k << te_log2) : nullptr;
-    stream_tile<T, kFlatten>(src, dst, cnt, op);
+    stream_tile<T, kFlatten>(bucket + e0, kFlatten ? dbase + e0 : nullptr, cnt, op);
     if (++t >= t1) break;
     if (++k == nt) {
       k = 0;
@@ -245,31 +254,29 @@ __global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t o
       const uint64_t st = bucket_start(log2F, b);
       if (s - st < live) live = s - st;
       nt = (live + te - 1) >> te_log2;
+      bucket = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]);
+      if (kFlatten) dbase = out + A.prefix[v] + st;
     }
   }
 }
 
-// Static / semi-static array r/w: a flat grid-stride stream over [0, size).
+// Static / semi-static array r/w: the flat array cut into 16 KiB tiles, each
+// workgroup streaming a contiguous share of them (the same access pattern as the
+// GGArray r/w, without the bucket indirection).
 template <typename T>
 __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const uint64_t* size,
-                                                              uint64_t cap, uint32_t op) {
-  constexpr uint32_t VPL = 16 / sizeof(T);
+                                                              uint64_t cap, uint32_t op, uint32_t te_log2) {
   uint64_t n = *size;
   if (n > cap) n = cap;
-  const uint64_t nv = n / VPL;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  u32x4* d = reinterpret_cast<u32x4*>(data);
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + 3 * stride < nv; i += 4 * stride) {
-    u32x4 r0 = d[i], r1 = d[i + stride], r2 = d[i + 2 * stride], r3 = d[i + 3 * stride];
-    d[i] = op_vec<T>(op, r0);
-    d[i + stride] = op_vec<T>(op, r1);
-    d[i + 2 * stride] = op_vec<T>(op, r2);
-    d[i + 3 * stride] = op_vec<T>(op, r3);
+  const uint64_t te = 1ull << te_log2;
+  const uint64_t total = (n + te - 1) >> te_log2;
+  const uint64_t G = gridDim.x;
+  const uint64_t t0 = total * blockIdx.x / G, t1 = total * (blockIdx.x + 1) / G;
+  for (uint64_t t = t0; t < t1; ++t) {
+    const uint64_t e0 = t << te_log2;
+    const uint64_t rem = n - e0;
+    stream_tile<T, false>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
   }
-  for (; i < nv; i += stride) d[i] = op_vec<T>(op, d[i]);
-  const uint64_t tail = nv * VPL + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tail < n) data[tail] = apply_op<T>(op, data[tail]);
 }
 
 }  // namespace
@@ -283,14 +290,14 @@ int launch_scan(ggarray* a, hipStream_t s) {
 }
 
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s) {
-  const uint32_t blocks = (a->V + 255) / 256;
+  const uint32_t blocks = (a->V + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(shrink_kernel, dim3(blocks), dim3(256), 0, s, a->ref, num, den, a->elem_log2);
   a->prefix_valid = false;
   return hip_status(hipGetLastError());
 }
 
 int launch_free_all(ggarray* a, hipStream_t s) {
-  const uint32_t blocks = (a->V + 255) / 256;
+  const uint32_t blocks = (a->V + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(free_all_kernel, dim3(blocks), dim3(256), 0, s, a->ref, a->elem_log2);
   return hip_status(hipGetLastError());
 }
@@ -327,10 +334,10 @@ int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
   if (st->elem_bytes == 4)
     hipLaunchKernelGGL((static_rw_kernel<uint32_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
-                       static_cast<uint32_t*>(st->data), st->d_size, st->cap, op);
+                       static_cast<uint32_t*>(st->data), st->d_size, st->cap, op, 12u);
   else
     hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
-                       static_cast<uint64_t*>(st->data), st->d_size, st->cap, op);
+                       static_cast<uint64_t*>(st->data), st->d_size, st->cap, op, 11u);
   return hip_status(hipGetLastError());
 }
 

@@ -106,10 +106,20 @@ int gga_pool_create(gga_pool** out, void* dev_base, uint64_t bytes, gga_stream s
   p->bytes = bytes;
   p->ref.hdr = static_cast<PoolHdr*>(dev_base);
   p->ref.base = static_cast<uint8_t*>(dev_base) + kPoolHdrBytes;
-  PoolHdr h{};
-  h.limit = (bytes - kPoolHdrBytes) & ~255ull;
-  if (hipMemcpyAsync(p->ref.hdr, &h, sizeof(h), hipMemcpyHostToDevice, S(s)) != hipSuccess ||
-      hipStreamSynchronize(S(s)) != hipSuccess) {
+  PoolHdr* h = new (std::nothrow) PoolHdr();
+  if (!h) {
+    delete p;
+    return GGA_EHIP;
+  }
+  h->limit = (bytes - kPoolHdrBytes) & ~255ull;
+  // Arena chunks: about 1/1024 of the region, between 64 KiB and 16 MiB.
+  uint64_t clog = 16;
+  while (clog < 24 && (2ull << clog) <= h->limit / 1024) ++clog;
+  h->chunk_log2 = clog;
+  const bool ok = hipMemcpyAsync(p->ref.hdr, h, sizeof(PoolHdr), hipMemcpyHostToDevice, S(s)) == hipSuccess &&
+                  hipStreamSynchronize(S(s)) == hipSuccess;
+  delete h;
+  if (!ok) {
     delete p;
     return GGA_EHIP;
   }
@@ -126,17 +136,27 @@ int gga_pool_destroy(gga_pool* p) {
 
 int gga_pool_stats(gga_pool* p, uint64_t out[7], gga_stream s) {
   if (!p || !out) return GGA_EINVAL;
-  PoolHdr h;
-  if (hipMemcpyAsync(&h, p->ref.hdr, sizeof(h), hipMemcpyDeviceToHost, S(s)) != hipSuccess ||
-      hipStreamSynchronize(S(s)) != hipSuccess)
+  PoolHdr* h = new (std::nothrow) PoolHdr();
+  if (!h) return GGA_EHIP;
+  if (hipMemcpyAsync(h, p->ref.hdr, sizeof(PoolHdr), hipMemcpyDeviceToHost, S(s)) != hipSuccess ||
+      hipStreamSynchronize(S(s)) != hipSuccess) {
+    delete h;
     return GGA_EHIP;
-  out[0] = h.in_use;
-  out[1] = h.high_water;
-  out[2] = h.n_alloc;
-  out[3] = h.n_free;
-  out[4] = h.bump;
-  out[5] = h.limit;
-  out[6] = h.n_attempt;
+  }
+  uint64_t in_use = 0, n_alloc = 0, n_free = 0;
+  for (int k = 0; k < kShards; ++k) {  // per-shard counters wrap individually; the sums do not
+    in_use += h->shard[k].in_use;
+    n_alloc += h->shard[k].n_alloc;
+    n_free += h->shard[k].n_free;
+  }
+  out[0] = in_use;
+  out[1] = h->bump;
+  out[2] = n_alloc;
+  out[3] = n_free;
+  out[4] = h->bump;
+  out[5] = h->limit;
+  out[6] = h->n_attempt;
+  delete h;
   return GGA_OK;
 }
 
@@ -174,7 +194,8 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   const size_t o_done = off;       off = align_up(off + 4 * V, 256);
   const size_t o_prefix = off;     off = align_up(off + 8 * (V + 1), 256);
   const size_t o_tprefix = off;    off = align_up(off + 8 * (V + 1), 256);
-  const size_t o_misc = off;       off = align_up(off + 64, 256);  // err, ticket, scratch
+  const size_t o_vticket = off;    off = align_up(off + 8 * V, 256);
+  const size_t o_misc = off;       off = align_up(off + 64, 256);  // err, scratch
   if (hipMalloc(&a->meta, off) != hipSuccess) {
     delete f;
     return GGA_EHIP;
@@ -194,7 +215,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.prefix = reinterpret_cast<uint64_t*>(m + o_prefix);
   R.tprefix = reinterpret_cast<uint64_t*>(m + o_tprefix);
   R.err = reinterpret_cast<uint32_t*>(m + o_misc);
-  R.ticket = reinterpret_cast<uint64_t*>(m + o_misc + 8);
+  R.vticket = reinterpret_cast<uint64_t*>(m + o_vticket);
   f->x.d_scratch = reinterpret_cast<uint64_t*>(m + o_misc + 16);
   R.status = nullptr;
   R.pool = p->ref;
@@ -202,7 +223,6 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.log2F = a->log2F;
   a->status_cap = 0;
   a->epoch = 0;
-  a->ticket_base = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
   p->n_arrays += 1;
   *out = a;
@@ -323,7 +343,6 @@ static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_by
   st->data = buf;
   st->cap = cap;
   st->elem_bytes = elem_bytes;
-  st->ticket_base = 0;
   if (hipMalloc(&st->meta, 256) != hipSuccess) return GGA_EHIP;
   if (hipMemsetAsync(st->meta, 0, 256, s) != hipSuccess) {
     (void)hipFree(st->meta);
@@ -331,7 +350,6 @@ static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_by
   }
   uint8_t* m = static_cast<uint8_t*>(st->meta);
   st->d_size = reinterpret_cast<uint64_t*>(m);
-  st->d_ticket = reinterpret_cast<uint64_t*>(m + 8);
   st->d_err = reinterpret_cast<uint32_t*>(m + 16);
   return GGA_OK;
 }
@@ -404,6 +422,14 @@ int gga_static_size(gga_static* st, uint64_t* out_host, gga_stream s) {
 int gga_static_last_error(gga_static* st, gga_stream s) {
   if (!st) return GGA_EINVAL;
   return static_read(st, nullptr, S(s));
+}
+
+int gga_static_clear(gga_static* st, gga_stream s) {
+  if (!st) return GGA_EINVAL;
+  if (hipMemsetAsync(st->d_size, 0, 8, S(s)) != hipSuccess ||
+      hipMemsetAsync(st->d_err, 0, 4, S(s)) != hipSuccess)
+    return GGA_EHIP;
+  return GGA_OK;
 }
 
 // --------------------------------------------------------- semi-static array --

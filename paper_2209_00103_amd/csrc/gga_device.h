@@ -1,10 +1,11 @@
 // Device-side layout and primitives of the GGArray library (gfx950).
 //
 // Layout in HBM
-//   pool:   [PoolHdr | pad to 4 KiB | bucket region ...]   (caller-owned memory)
+//   pool:   [PoolHdr | pad to 128 KiB | bucket region ...]   (caller-owned memory)
 //   array:  size[V] u64 | bptr[V][kMaxBuckets] u64 | dead[V] u32 |
-//           alloc_done[V] u32 | prefix[V+1] u64 | tprefix[V+1] u64 | err u32 |
-//           ticket u64 | status[...] u64 (look-back words, grown on demand)
+//           alloc_done[V] u32 | prefix[V+1] u64 | tprefix[V+1] u64 |
+//           vticket[V] u64 | err u32 | status[...] u64 (look-back words, grown
+//           on demand)
 //
 // Bucket law (Alg. 2): bucket b of an LFVector holds F * 2^b elements, F a power
 // of two, so bucket b starts at local index F * (2^b - 1).  For local index i,
@@ -21,7 +22,7 @@ constexpr int kMaxBuckets = 40;     // F * (2^40 - 1) elements per LFVector
 constexpr int kMinClassLog2 = 8;    // smallest pool block: 256 B
 constexpr int kMaxClassLog2 = 40;   // largest pool block: 1 TiB
 constexpr int kNumClasses = kMaxClassLog2 + 1;
-constexpr int kShards = 8;          // free-list shards per size class
+constexpr int kShards = 256;        // pool shards (free lists, arenas, statistics)
 constexpr uint64_t kFailedPtr = 1;  // bucket-table marker: allocation failed
 constexpr uint64_t kIdxMask = (1ull << 40) - 1;
 
@@ -35,19 +36,27 @@ constexpr uint32_t kErrStall = 4;   // a bounded wait expired; reported as GGA_E
 // logic error surfaces as a status instead of a kernel that never ends.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-struct PoolHdr {
-  uint64_t bump;        // next unused byte of the bucket region
-  uint64_t limit;       // bytes in the bucket region
-  uint64_t in_use;      // bytes handed out and not returned
-  uint64_t high_water;  // max of in_use
+struct PoolShard {        // one 64-byte line per shard
+  uint64_t arena;         // current chunk id (offset / 256 + 1) << 32 | used 256-byte units
+  uint64_t in_use;        // bytes handed out and not returned (may wrap per shard)
   uint64_t n_alloc;
   uint64_t n_free;
-  uint64_t n_attempt;   // allocation attempts (fault injection counts these)
-  uint64_t fault_at;    // attempt number that fails; 0 = never
-  uint64_t heads[kNumClasses * kShards];  // tagged Treiber-stack heads
+  uint64_t pad[4];
 };
 
-constexpr uint64_t kPoolHdrBytes = 4096;
+struct PoolHdr {
+  uint64_t bump;          // next unused byte of the region for chunks and large blocks
+  uint64_t limit;         // bytes in the region
+  uint64_t chunk_log2;    // arena chunk size
+  uint64_t n_attempt;     // allocation attempts (fault injection counts these)
+  uint64_t fault_at;      // attempt number that fails; 0 = never
+  uint64_t pad[3];
+  uint64_t nonempty[kNumClasses][kShards / 64];  // bit s: shard s of the class may hold blocks
+  uint64_t heads[kNumClasses * kShards];         // tagged Treiber-stack heads
+  PoolShard shard[kShards];
+};
+
+constexpr uint64_t kPoolHdrBytes = 128 * 1024;
 static_assert(sizeof(PoolHdr) <= kPoolHdrBytes, "pool header too large");
 
 struct PoolRef {
@@ -64,7 +73,7 @@ struct ArrRef {
   uint64_t* prefix;
   uint64_t* tprefix;
   uint32_t* err;
-  uint64_t* ticket;
+  uint64_t* vticket;     // per-LFVector tile tickets of the insertion kernel
   uint64_t* status;
   PoolRef pool;
   uint32_t V;
@@ -105,13 +114,6 @@ __device__ __forceinline__ uint64_t fetch_add(uint64_t* p, uint64_t v) {
 __device__ __forceinline__ uint32_t fetch_add32(uint32_t* p, uint32_t v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void fetch_max(uint64_t* p, uint64_t v) {
-  __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ bool cas_acq_rel(uint64_t* p, uint64_t& expected, uint64_t desired) {
-  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
-                                              __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void set_error(uint32_t* err, uint32_t code) {
   uint32_t zero = 0;
   __hip_atomic_compare_exchange_strong(err, &zero, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -151,60 +153,144 @@ __device__ __forceinline__ uint32_t bucket_class(uint32_t log2F, uint32_t elem_l
 }
 
 // ------------------------------------------------------------- device pool --
-// Lock-free pool: one tagged Treiber stack per (size class, shard) holds freed
-// blocks, a bump pointer hands out fresh ones.  A stack head packs a 24-bit
-// version tag above the 40-bit block index (offset / 256 + 1, 0 = empty); the
-// tag changes on every successful update so a stale head never matches (ABA).
-// A free block stores the index of the next free block in its first 8 bytes.
-__device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t shard) {
+// Lock-free bucket pool over the caller's region, built so that thousands of
+// LFVectors can grow in the same kernel without meeting on one address:
+//
+//  * 256 shards.  Bucket b of LFVector v belongs to shard (v + b) mod 256; the
+//    shard's words (arena, statistics) sit on their own 64-byte line.
+//  * Freed blocks go to one tagged Treiber stack per (size class, shard).  A
+//    head packs a 24-bit version tag above the 40-bit block index (offset / 256
+//    + 1, 0 = empty); the tag changes on every update, so a stale head never
+//    matches (ABA).  A free block keeps the index of the next one in its first
+//    8 bytes.  A per-class mask hints which shards may hold blocks.
+//  * Fresh blocks up to a quarter of a chunk come from the shard's arena: a
+//    chunk carved from the global bump pointer, sub-allocated with one atomic
+//    add on the shard's arena word (chunk id << 32 | used 256-byte units).  The
+//    add that crosses the end of the chunk installs the next chunk; adds that
+//    land past the end in the meantime take their block from the global bump
+//    pointer instead of waiting.  Larger blocks always come from the global
+//    bump pointer.
+//
+// No operation uses release/acquire fences (on gfx950 those write back or
+// invalidate the whole L2 of an XCD).  Ordering comes from completion: a push
+// writes the link with an atomic exchange and waits for its return before the
+// head CAS is issued; a pop reads the head, then the link at an address that
+// depends on it, then CASes values that depend on both.  All are agent-scope
+// atomics, performed at the coherence point in that order.
+__device__ __forceinline__ uint32_t pool_shard(uint32_t v, uint32_t b) {
+  return (v + b) & (uint32_t)(kShards - 1);
+}
+
+__device__ __forceinline__ bool cas_rlx(uint64_t* p, uint64_t& expected, uint64_t desired) {
+  return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_nr(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void sub_nr(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_sub(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint8_t* pool_pop(PoolRef P, uint32_t cls, uint32_t s) {
   PoolHdr* H = P.hdr;
-  const uint64_t bytes = 1ull << cls;
-  const uint64_t fault_at = ld_rlx(&H->fault_at);
-  if (fault_at) {
-    uint64_t n = fetch_add(&H->n_attempt, 1) + 1;
-    if (n == fault_at) return nullptr;
-  }
-  if (cls > (uint32_t)kMaxClassLog2) return nullptr;
-  for (int k = 0; k < kShards; ++k) {
-    uint64_t* head = &H->heads[cls * kShards + ((shard + k) & (kShards - 1))];
-    if ((ld_rlx(head) & kIdxMask) == 0) continue;  // empty: skip the acquire
-    uint64_t h = ld_acq(head);
-    while (h & kIdxMask) {
-      const uint64_t off = ((h & kIdxMask) - 1) << kMinClassLog2;
-      const uint64_t nxt = ld_rlx(reinterpret_cast<const uint64_t*>(P.base + off)) & kIdxMask;
-      const uint64_t nh = (((h >> 40) + 1) << 40) | nxt;
-      if (cas_acq_rel(head, h, nh)) {
-        uint64_t used = fetch_add(&H->in_use, bytes) + bytes;
-        fetch_max(&H->high_water, used);
-        fetch_add(&H->n_alloc, 1);
-        return P.base + off;
+  uint64_t* head = &H->heads[cls * kShards + s];
+  uint64_t h = ld_rlx(head);
+  while (h & kIdxMask) {
+    const uint64_t off = ((h & kIdxMask) - 1) << kMinClassLog2;
+    const uint64_t nxt = ld_rlx(reinterpret_cast<const uint64_t*>(P.base + off)) & kIdxMask;
+    const uint64_t nh = (((h >> 40) + 1) << 40) | nxt;
+    if (cas_rlx(head, h, nh)) {
+      if (nxt == 0) {
+        // The shard looks empty now: clear its hint, and restore it if a push
+        // got in between.
+        uint64_t* m = &H->nonempty[cls][s >> 6];
+        __hip_atomic_fetch_and(m, ~(1ull << (s & 63)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ld_rlx(head) & kIdxMask)
+          __hip_atomic_fetch_or(m, 1ull << (s & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
+      return P.base + off;
     }
   }
+  return nullptr;
+}
+
+__device__ __forceinline__ uint8_t* global_bump(PoolRef P, uint64_t bytes) {
+  PoolHdr* H = P.hdr;
   const uint64_t old = fetch_add(&H->bump, bytes);
   if (old + bytes > ld_rlx(&H->limit)) {
-    __hip_atomic_fetch_sub(&H->bump, bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sub_nr(&H->bump, bytes);
     return nullptr;
   }
-  uint64_t used = fetch_add(&H->in_use, bytes) + bytes;
-  fetch_max(&H->high_water, used);
-  fetch_add(&H->n_alloc, 1);
   return P.base + old;
 }
 
-__device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls, uint32_t shard) {
+__device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t bytes) {
+  PoolHdr* H = P.hdr;
+  const uint32_t clog = (uint32_t)ld_rlx(&H->chunk_log2);
+  const uint64_t units = bytes >> kMinClassLog2;
+  const uint64_t cap = 1ull << (clog - kMinClassLog2);
+  uint64_t* word = &H->shard[s].arena;
+  const uint64_t old = fetch_add(word, units);
+  const uint64_t cid = old >> 32, used = old & 0xFFFFFFFFull;
+  if (cid && used + units <= cap) return P.base + ((cid - 1) << kMinClassLog2) + (used << kMinClassLog2);
+  const bool installer = cid ? (used <= cap && used + units > cap) : (used == 0);
+  if (!installer) return nullptr;  // the caller takes the global bump pointer
+  uint8_t* c = global_bump(P, 1ull << clog);
+  if (!c) {
+    __hip_atomic_exchange(word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return nullptr;
+  }
+  const uint64_t ncid = ((uint64_t)(c - P.base) >> kMinClassLog2) + 1;
+  __hip_atomic_exchange(word, (ncid << 32) | units, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return c;
+}
+
+__device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t shard) {
   PoolHdr* H = P.hdr;
   const uint64_t bytes = 1ull << cls;
+  if (ld_rlx(&H->fault_at)) {
+    const uint64_t n = fetch_add(&H->n_attempt, 1) + 1;
+    if (n == ld_rlx(&H->fault_at)) return nullptr;
+  }
+  if (cls > (uint32_t)kMaxClassLog2) return nullptr;
+  uint8_t* q = pool_pop(P, cls, shard);
+  for (uint32_t wi = 0; !q && wi < (uint32_t)kShards / 64; ++wi) {
+    uint64_t mask = ld_rlx(&H->nonempty[cls][wi]);
+    if ((shard >> 6) == wi) mask &= ~(1ull << (shard & 63));
+    while (!q && mask) {
+      const uint32_t s = wi * 64 + (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+      q = pool_pop(P, cls, s);
+      mask &= mask - 1;
+    }
+  }
+  if (!q && cls + 2 <= (uint32_t)ld_rlx(&H->chunk_log2)) q = arena_alloc(P, shard, bytes);
+  if (!q) q = global_bump(P, bytes);
+  if (!q) return nullptr;
+  add_nr(&H->shard[shard].in_use, bytes);
+  add_nr(&H->shard[shard].n_alloc, 1ull);
+  return q;
+}
+
+__device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls, uint32_t s) {
+  PoolHdr* H = P.hdr;
   const uint64_t idx = ((uint64_t)(ptr - P.base) >> kMinClassLog2) + 1;
-  uint64_t* head = &H->heads[cls * kShards + (shard & (kShards - 1))];
+  uint64_t* head = &H->heads[cls * kShards + s];
   uint64_t h = ld_rlx(head);
   for (;;) {
-    st_rlx(reinterpret_cast<uint64_t*>(ptr), h & kIdxMask);
+    const uint64_t prev = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(ptr), h & kIdxMask,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Consuming the exchange's result makes the wave wait until the link has
+    // landed before the CAS below can publish the block.
+    asm volatile("" ::"v"((uint32_t)prev) : "memory");
     const uint64_t nh = (((h >> 40) + 1) << 40) | idx;
-    if (cas_acq_rel(head, h, nh)) break;
+    if (cas_rlx(head, h, nh)) break;
   }
-  __hip_atomic_fetch_sub(&H->in_use, bytes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  fetch_add(&H->n_free, 1);
+  if ((h & kIdxMask) == 0)
+    __hip_atomic_fetch_or(&H->nonempty[cls][s >> 6], 1ull << (s & 63), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+  sub_nr(&H->shard[s].in_use, 1ull << cls);
+  add_nr(&H->shard[s].n_free, 1ull);
 }
 
 // ------------------------------------------------------------------ payloads --

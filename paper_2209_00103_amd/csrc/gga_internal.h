@@ -23,7 +23,6 @@ struct ggarray {
   gga::ArrRef ref;
   uint64_t status_cap;    // look-back words available
   uint64_t epoch;         // look-back epoch of the last insertion launch
-  uint64_t ticket_base;   // ticket counter value at the start of the next launch
   bool prefix_valid;      // prefix / tprefix match the current sizes
 };
 
@@ -31,11 +30,9 @@ struct gga_static {
   void* data;
   uint64_t cap;
   uint32_t elem_bytes;
-  void* meta;          // device block: size counter, ticket counter, sticky error
+  void* meta;          // device block: size counter, sticky error
   uint64_t* d_size;
-  uint64_t* d_ticket;
   uint32_t* d_err;
-  uint64_t ticket_base;
 };
 
 struct gga_semistatic {

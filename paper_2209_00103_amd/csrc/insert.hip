@@ -46,7 +46,6 @@ struct TileArgs {
   uint64_t n_threads;
   uint64_t chunk;        // logical threads per LFVector, ceil(n / V)
   uint64_t tpv;          // tiles per LFVector
-  uint64_t ticket_base;
   uint64_t epoch;        // 24-bit launch tag of the status words
   uint32_t elem_log2;
 };
@@ -55,7 +54,6 @@ struct StaticRef {
   void* data;
   uint64_t cap;
   uint64_t* size;
-  uint64_t* ticket;
   uint32_t* err;
 };
 
@@ -74,6 +72,7 @@ __device__ __forceinline__ uint64_t pack_status(uint64_t epoch, uint64_t flag, u
   return (epoch << 40) | (flag << 38) | (value & kValMask);
 }
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -98,31 +97,24 @@ struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
   static constexpr bool kMulti = false;
   const T* values;
   const uint8_t* flags;
-  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
-    x = values[g];
-    return flags ? (flags[g] != 0) : 1u;
-  }
+  __device__ __forceinline__ bool flag(uint64_t g) const { return flags ? flags[g] != 0 : true; }
+  __device__ __forceinline__ T value(uint64_t g) const { return values[g]; }
 };
 template <typename T>
 struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
   static constexpr bool kMulti = false;
   uint64_t seed;
   uint32_t round;
-  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
-    const uint64_t h = K(seed, g, round);
-    x = (T)h;
-    return (uint32_t)(h >> 63);
-  }
+  __device__ __forceinline__ bool flag(uint64_t g) const { return (K(seed, g, round) >> 63) != 0; }
+  __device__ __forceinline__ T value(uint64_t g) const { return (T)K(seed, g, round); }
 };
 template <typename T>
 struct ProdRoundTag {  // insert (round << shift) | gid
   static constexpr bool kMulti = false;
   uint32_t round;
   uint32_t shift;
-  __device__ __forceinline__ uint32_t count(uint64_t g, T& x) const {
-    x = (T)(((uint64_t)round << shift) | g);
-    return 1u;
-  }
+  __device__ __forceinline__ bool flag(uint64_t) const { return true; }
+  __device__ __forceinline__ T value(uint64_t g) const { return (T)(((uint64_t)round << shift) | g); }
 };
 template <typename T>
 struct ProdCounts {  // insert values[gid * max + j], j < counts[gid]
@@ -197,12 +189,21 @@ __device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint
   }
 }
 
-// ----------------------------------------------- growth + commit (wave 0) --
+// ------------------------------------------------ growth + commit (one wave) --
+// What a tile needs to store its elements.  Wave-uniform except bp.
+struct WaveRes {
+  uint64_t base;   // index of the tile's first element in its LFVector
+  uint64_t bp;     // lane i: pointer of bucket b_lo + i (kFailedPtr if none)
+  uint32_t b_lo;
+  uint32_t nb;
+  uint32_t n_out;  // elements to store: the tile count, or 0 if the tile stalled
+};
+
 // Resolves the tile's first index, allocates or waits for its buckets, and lets
-// the last tile of the LFVector commit the round.  Leaves base, b_lo, nb, the
-// bucket pointers and the number of elements to scatter in LDS.
-__device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
-                             uint64_t tile, bool is_last, uint32_t n_t, TileShared& sh) {
+// the last tile of the LFVector commit the round.  Executed by one whole wave.
+__device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
+                                uint64_t tile, bool is_last, uint32_t n_t) {
+  WaveRes r{0, kFailedPtr, 0, 0, 0};
   const uint32_t lane = lane_id();
   const uint32_t log2F = A.log2F;
   uint64_t old_size = 0;
@@ -225,10 +226,8 @@ __device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uin
     if (lane == 0) {
       set_error(A.err, kErrStall);
       st_rlx32(&A.dead[v], 1u);
-      sh.n_tile = 0;
-      sh.nb = 0;
     }
-    return;
+    return r;
   }
 
   uint32_t b_lo = 0, nb = 0;
@@ -246,7 +245,7 @@ __device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uin
         uint64_t* slot = &A.bptr[(uint64_t)v * kMaxBuckets + b];
         if (holds_start) {
           // This tile writes the bucket's first index: it is the one that allocates.
-          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), v);
+          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b));
           p = q ? (uint64_t)q : kFailedPtr;
           st_rlx(slot, p);
           allocated = true;
@@ -263,7 +262,7 @@ __device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uin
           }
         }
       }
-      sh.bp[lane] = p;
+      r.bp = p;
     }
     // One atomic reports this tile's allocations: the count in the low half,
     // the failures in the high half.
@@ -298,11 +297,24 @@ __device__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uin
     else
       st_rlx(&A.size[v], nsize);
   }
+  r.base = base;
+  r.b_lo = b_lo;
+  r.nb = nb;
+  r.n_out = n_t;
+  return r;
+}
+
+// Block kernels: wave 0 resolves and leaves the result in LDS.
+__device__ __forceinline__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
+                                             uint64_t tile, bool is_last, uint32_t n_t, TileShared& sh) {
+  const WaveRes r = resolve_wave(A, I, v, t, tile, is_last, n_t);
+  const uint32_t lane = lane_id();
+  if (lane < r.nb) sh.bp[lane] = r.bp;
   if (lane == 0) {
-    sh.base = base;
-    sh.b_lo = b_lo;
-    sh.nb = nb;
-    sh.n_tile = n_t;
+    sh.base = r.base;
+    sh.b_lo = r.b_lo;
+    sh.nb = r.nb;
+    sh.n_tile = r.n_out;
   }
 }
 
@@ -318,156 +330,246 @@ __device__ void resolve_static(const StaticRef& S, uint32_t n_t, TileShared& sh)
   }
 }
 
-// Scatter staged elements [0, n) (tile positions p0 + i) to their buckets.
+// Copy n staged elements to dst, which is element aligned: element stores for the
+// ragged head and tail, 16-byte stores for the aligned middle.
+template <typename T>
+__device__ __forceinline__ void scatter_run(T* dst, const T* stage, uint32_t n) {
+  constexpr uint32_t VPL = 16 / sizeof(T);
+  const uint32_t tid = threadIdx.x;
+  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst) & 15u) / sizeof(T));
+  uint32_t head = mis ? VPL - mis : 0u;
+  if (head > n) head = n;
+  const uint32_t nv = (n - head) / VPL;
+  if (tid < head) dst[tid] = stage[tid];
+  for (uint32_t q = tid; q < nv; q += kB) {
+    const uint32_t e = head + q * VPL;
+    T tmp[VPL];
+#pragma unroll
+    for (uint32_t k = 0; k < VPL; ++k) tmp[k] = stage[e + k];
+    u32x4 x;
+    __builtin_memcpy(&x, tmp, 16);
+    *reinterpret_cast<u32x4*>(dst + e) = x;
+  }
+  const uint32_t tail = head + nv * VPL + tid;
+  if (tail < n) dst[tail] = stage[tail];
+}
+
+// Scatter staged elements [0, n) (tile positions p0 + i) to their buckets, one
+// contiguous run per bucket the range touches.
 template <typename T>
 __device__ __forceinline__ void scatter(const ArrRef& A, const TileShared& sh, const T* stage,
                                         uint64_t p0, uint32_t n) {
   const uint32_t log2F = A.log2F;
-  const uint64_t first = sh.base + p0;
-  if (sh.nb == 1) {
-    const uint64_t p = sh.bp[0];
-    if (p <= kFailedPtr) return;
-    T* dst = reinterpret_cast<T*>(p) + (first - bucket_start(log2F, sh.b_lo));
-    for (uint32_t i = threadIdx.x; i < n; i += kB) dst[i] = stage[i];
-    return;
-  }
-  for (uint32_t i = threadIdx.x; i < n; i += kB) {
-    const uint64_t idx = first + i;
-    const uint32_t b = bucket_of(log2F, idx);
-    const uint64_t p = sh.bp[b - sh.b_lo];
-    if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = stage[i];
+  const uint64_t first = sh.base + p0, last = first + n;
+  for (uint32_t i = 0; i < sh.nb; ++i) {
+    const uint32_t b = sh.b_lo + i;
+    const uint64_t bs = bucket_start(log2F, b), be = bs + bucket_len(log2F, b);
+    const uint64_t lo = first > bs ? first : bs, hi = last < be ? last : be;
+    if (lo >= hi) continue;
+    const uint64_t p = sh.bp[i];
+    if (p <= kFailedPtr) continue;
+    scatter_run<T>(reinterpret_cast<T*>(p) + (lo - bs), stage + (lo - first), (uint32_t)(hi - lo));
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void scatter_static(const StaticRef& S, const TileShared& sh,
                                                const T* stage, uint64_t p0, uint32_t n) {
-  T* dst = reinterpret_cast<T*>(S.data) + sh.base + p0;
   uint32_t lim = sh.writable > p0 ? (uint32_t)(sh.writable - p0) : 0u;
   if (lim > n) lim = n;
-  for (uint32_t i = threadIdx.x; i < lim; i += kB) dst[i] = stage[i];
+  scatter_run<T>(reinterpret_cast<T*>(S.data) + sh.base + p0, stage, lim);
+}
+
+// Takes this block's ticket of LFVector v (thread 0 only; the result is waited
+// for later).  The LFVector's tpv blocks each take one; the last taker resets
+// the counter for the next launch.
+__device__ __forceinline__ uint64_t take_ticket(const ArrRef& A, uint32_t v) {
+  return fetch_add(&A.vticket[v], 1);
+}
+__device__ __forceinline__ void settle_ticket(const ArrRef& A, uint32_t v, uint64_t k, uint64_t tpv) {
+  if (k == tpv - 1) st_rlx(&A.vticket[v], 0);
+}
+
+// Logical-thread range of tile t of LFVector v.
+__device__ __forceinline__ void tile_range(const TileArgs& I, uint32_t v, uint64_t t, uint64_t tile_len,
+                                           uint64_t& g0, uint64_t& gend) {
+  const uint64_t c0 = (uint64_t)v * I.chunk;
+  g0 = c0 + t * tile_len;
+  gend = c0 + I.chunk < I.n_threads ? c0 + I.chunk : I.n_threads;
 }
 
 // ------------------------------------------------------ 0/1 producer kernel --
-// Candidate slot j of thread tid is logical thread g0 + j * 256 + tid, so every
-// load of a buffer-mode producer is coalesced and the tile order (j, wave, lane)
-// equals the logical-thread order.
+// One wavefront handles one tile of 4096 logical threads: slot j of lane l is
+// logical thread g0 + 64 j + l, so every producer load is coalesced and the
+// order (slot, lane) is the logical-thread order.  A first pass keeps only the
+// insert flags, one bit per slot in a 64-bit mask, and counts them.  Once the
+// tile's first index is known, a second pass re-derives every kept candidate's
+// position from the slot ballots (running total + mbcnt) and stores the value,
+// which the producer computes or loads again: a slot's stores by the wave cover
+// one contiguous range.  Holding a mask instead of the values keeps the wave to
+// a few registers and no LDS, so a CU keeps 32 tiles in flight.
+//
+// Static tiles never wait on one another, nor does the only tile of an
+// LFVector, so their position is the block index.  Otherwise the wave takes the
+// next ticket of its LFVector, so every tile it may wait for is held by a wave
+// that is already running.  Blocks are normally dispatched in index order, so
+// the first pass runs for the position the index suggests while the ticket is
+// in flight, and is redone in the rare case the ticket differs.
+constexpr int kWaveSlots = 64;
+constexpr int kWaveTile = 64 * kWaveSlots;
+static_assert(kWaveTile == kFlagTile, "0/1 tiles hold 4096 logical threads");
+
+template <class Prod>
+__device__ __forceinline__ uint64_t wave_flags(const Prod& prod, uint64_t g0, uint64_t gend) {
+  const uint32_t lane = lane_id();
+  uint64_t bits = 0;
+#pragma unroll 16
+  for (int j = 0; j < kWaveSlots; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * 64 + lane;
+    if (g < gend && prod.flag(g)) bits |= 1ull << j;
+  }
+  return bits;
+}
+
 template <typename T, class Prod, bool kStatic>
-__global__ __launch_bounds__(kB) void insert_flag_kernel(ArrRef A, StaticRef S, TileArgs I,
-                                                         Prod prod) {
-  __shared__ T stage[kStage];
-  __shared__ TileShared sh;
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-  if (tid == 0) sh.tile = fetch_add(kStatic ? S.ticket : A.ticket, 1) - I.ticket_base;
-  __syncthreads();
-  const uint64_t tile = sh.tile;
-  uint32_t v = 0;
-  uint64_t t, g0, gend;
+__global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, TileArgs I, Prod prod) {
+  const uint32_t lane = lane_id();
+  const bool ticketed = !kStatic && I.tpv > 1;
+  const uint32_t v = kStatic ? 0u : (uint32_t)(blockIdx.x / I.tpv);
+  uint64_t t = kStatic ? blockIdx.x : blockIdx.x - (uint64_t)v * I.tpv;
+  uint64_t k = 0;
+  if (ticketed && lane == 0) k = take_ticket(A, v);
+  uint64_t g0, gend;
   if (kStatic) {
-    t = tile;
-    g0 = tile * kFlagTile;
+    g0 = t * kWaveTile;
     gend = I.n_threads;
   } else {
-    v = (uint32_t)(tile / I.tpv);
-    t = tile - (uint64_t)v * I.tpv;
-    const uint64_t c0 = (uint64_t)v * I.chunk;
-    g0 = c0 + t * kFlagTile;
-    gend = c0 + I.chunk < I.n_threads ? c0 + I.chunk : I.n_threads;
+    tile_range(I, v, t, kWaveTile, g0, gend);
+  }
+  uint64_t bits = wave_flags<Prod>(prod, g0, gend);
+  if (ticketed) {
+    if (lane == 0) settle_ticket(A, v, k, I.tpv);
+    k = __shfl(k, 0, 64);
+    if (k != t) {  // dispatched out of order: redo the first pass for the ticket
+      t = k;
+      tile_range(I, v, t, kWaveTile, g0, gend);
+      bits = wave_flags<Prod>(prod, g0, gend);
+    }
   }
   if (g0 >= gend) return;
   if (!kStatic && ld_rlx32(&A.dead[v])) return;
-  const bool is_last = g0 + kFlagTile >= gend;
+  const bool is_last = g0 + kWaveTile >= gend;
+  const uint32_t n_t = (uint32_t)wave_sum64((uint64_t)__popcll(bits));
 
-  T val[kFlagK];
-  uint32_t pos[kFlagK];
-  uint32_t fbits = 0;
-#pragma unroll
-  for (int j = 0; j < kFlagK; ++j) {
-    const uint64_t g = g0 + (uint64_t)j * kB + tid;
-    T x = 0;
-    uint32_t f = 0;
-    if (g < gend) f = prod.count(g, x);
-    val[j] = x;
-    const uint64_t m = __ballot(f != 0);
-    pos[j] = mbcnt(m);
-    fbits |= (f != 0 ? 1u : 0u) << j;
-    if (lane == 0) sh.cnt[j * kW + w] = (uint32_t)__popcll(m);
-  }
-  __syncthreads();
-  const uint32_t c = sh.cnt[lane];
-  const uint32_t incl = wave_incl_scan(c);
-  const uint32_t excl = incl - c;
-  const uint32_t n_t = __shfl(incl, 63, 64);
-#pragma unroll
-  for (int j = 0; j < kFlagK; ++j) {
-    const uint32_t off = __shfl(excl, j * kW + (int)w, 64);
-    if ((fbits >> j) & 1u) stage[off + pos[j]] = val[j];
-  }
+  T* dst;
+  uint64_t lim = n_t;
+  const uint32_t log2F = A.log2F;
+  WaveRes r{0, kFailedPtr, 0, 0, 0};
   if (kStatic) {
-    resolve_static(S, n_t, sh);
-  } else if (w == 0) {
-    resolve_tile(A, I, v, t, tile, is_last, n_t, sh);
+    uint64_t base = 0;
+    if (lane == 0 && n_t) base = fetch_add(S.size, n_t);
+    base = __shfl(base, 0, 64);
+    lim = base < S.cap ? (S.cap - base < n_t ? S.cap - base : n_t) : 0;
+    if (lane == 0 && lim < n_t) set_error(S.err, kErrRange);
+    dst = reinterpret_cast<T*>(S.data) + base;
+  } else {
+    r = resolve_wave(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t);
+    if (r.n_out == 0) return;
+    const uint64_t p0 = __shfl(r.bp, 0, 64);
+    dst = reinterpret_cast<T*>(p0) + (r.base - bucket_start(log2F, r.b_lo));
+    if (r.nb == 1 && p0 <= kFailedPtr) return;
   }
-  __syncthreads();
-  if (kStatic)
-    scatter_static<T>(S, sh, stage, 0, n_t);
-  else
-    scatter<T>(A, sh, stage, 0, sh.n_tile);
+  uint32_t run = 0;
+  if (kStatic || r.nb == 1) {
+#pragma unroll 16
+    for (int j = 0; j < kWaveSlots; ++j) {
+      const bool f = (bits >> j) & 1u;
+      const uint64_t m = __ballot(f);
+      const uint32_t q = run + mbcnt(m);
+      if (f && q < lim) dst[q] = prod.value(g0 + (uint64_t)j * 64 + lane);
+      run += (uint32_t)__popcll(m);
+    }
+    return;
+  }
+  // The tile spans several buckets: locate each element by the closed form.
+  for (int j = 0; j < kWaveSlots; ++j) {
+    const bool f = (bits >> j) & 1u;
+    const uint64_t m = __ballot(f);
+    const uint64_t idx = r.base + run + mbcnt(m);
+    const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
+    const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
+    if (f && p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
+    run += (uint32_t)__popcll(m);
+  }
 }
 
 // --------------------------------------------- multi-element producer kernel --
 // Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
 // plain scan of per-thread counts orders the elements.  A tile may emit up to
 // 16384 elements; they are staged and scattered in passes of kStage.
+template <typename Prod>
+__device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt, uint64_t gend,
+                                                   uint32_t* cnt) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kCountK; ++j) {
+    cnt[j] = (gt + j < gend) ? prod.count(gt + j) : 0u;
+    c += cnt[j];
+  }
+  return c;
+}
+
 template <typename T, class Prod, bool kStatic>
 __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S, TileArgs I,
                                                           Prod prod) {
   __shared__ T stage[kStage];
   __shared__ TileShared sh;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-  if (tid == 0) sh.tile = fetch_add(kStatic ? S.ticket : A.ticket, 1) - I.ticket_base;
-  __syncthreads();
-  const uint64_t tile = sh.tile;
-  uint32_t v = 0;
-  uint64_t t, g0, gend;
+  const bool ticketed = !kStatic && I.tpv > 1;
+  const uint32_t v = kStatic ? 0u : (uint32_t)(blockIdx.x / I.tpv);
+  uint64_t t = kStatic ? blockIdx.x : blockIdx.x - (uint64_t)v * I.tpv;
+  uint64_t k = 0;
+  if (ticketed && tid == 0) k = take_ticket(A, v);
+  uint64_t g0, gend;
   if (kStatic) {
-    t = tile;
-    g0 = tile * kCountTile;
+    g0 = t * kCountTile;
     gend = I.n_threads;
   } else {
-    v = (uint32_t)(tile / I.tpv);
-    t = tile - (uint64_t)v * I.tpv;
-    const uint64_t c0 = (uint64_t)v * I.chunk;
-    g0 = c0 + t * kCountTile;
-    gend = c0 + I.chunk < I.n_threads ? c0 + I.chunk : I.n_threads;
+    tile_range(I, v, t, kCountTile, g0, gend);
+  }
+  uint32_t cnt[kCountK];
+  uint64_t gt = g0 + (uint64_t)tid * kCountK;
+  uint32_t c = produce_counts<Prod>(prod, gt, gend, cnt);
+  if (ticketed && tid == 0) {
+    sh.tile = k;
+    settle_ticket(A, v, k, I.tpv);
+  }
+  __syncthreads();
+  if (ticketed && sh.tile != t) {  // dispatched out of order: produce for the ticket
+    t = sh.tile;
+    tile_range(I, v, t, kCountTile, g0, gend);
+    gt = g0 + (uint64_t)tid * kCountK;
+    c = produce_counts<Prod>(prod, gt, gend, cnt);
   }
   if (g0 >= gend) return;
   if (!kStatic && ld_rlx32(&A.dead[v])) return;
   const bool is_last = g0 + kCountTile >= gend;
 
-  uint32_t cnt[kCountK];
-  uint32_t c = 0;
-  const uint64_t gt = g0 + (uint64_t)tid * kCountK;
-#pragma unroll
-  for (int j = 0; j < kCountK; ++j) {
-    cnt[j] = (gt + j < gend) ? prod.count(gt + j) : 0u;
-    c += cnt[j];
-  }
   const uint32_t incl = wave_incl_scan(c);
   if (lane == 63) sh.cnt[w] = incl;
   __syncthreads();
   uint32_t before = 0, n_t = 0;
 #pragma unroll
-  for (int k = 0; k < kW; ++k) {
-    const uint32_t x = sh.cnt[k];
-    before += (k < (int)w) ? x : 0u;
+  for (int q = 0; q < kW; ++q) {
+    const uint32_t x = sh.cnt[q];
+    before += (q < (int)w) ? x : 0u;
     n_t += x;
   }
   const uint32_t excl = before + incl - c;
   if (kStatic) {
     resolve_static(S, n_t, sh);
   } else if (w == 0) {
-    resolve_tile(A, I, v, t, tile, is_last, n_t, sh);
+    resolve_tile(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, sh);
   }
   __syncthreads();
   const uint32_t n_out = kStatic ? n_t : sh.n_tile;  // 0 if the tile stalled
@@ -503,17 +605,17 @@ int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const Inser
   switch (d.mode) {
     case kModeBuffer: {
       ProdBuffer<T> p{static_cast<const T*>(d.values), d.flags};
-      hipLaunchKernelGGL((insert_flag_kernel<T, ProdBuffer<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      hipLaunchKernelGGL((insert_wave_kernel<T, ProdBuffer<T>, kStatic>), grid, dim3(64), 0, s, A, S, I, p);
       break;
     }
     case kModeBernoulli: {
       ProdBernoulli<T> p{d.seed, d.round};
-      hipLaunchKernelGGL((insert_flag_kernel<T, ProdBernoulli<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      hipLaunchKernelGGL((insert_wave_kernel<T, ProdBernoulli<T>, kStatic>), grid, dim3(64), 0, s, A, S, I, p);
       break;
     }
     case kModeRoundTag: {
       ProdRoundTag<T> p{d.round, d.tag_shift};
-      hipLaunchKernelGGL((insert_flag_kernel<T, ProdRoundTag<T>, kStatic>), grid, block, 0, s, A, S, I, p);
+      hipLaunchKernelGGL((insert_wave_kernel<T, ProdRoundTag<T>, kStatic>), grid, dim3(64), 0, s, A, S, I, p);
       break;
     }
     case kModeCounts: {
@@ -548,39 +650,40 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   const uint64_t ntiles = tpv * a->V;
   if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
 
-  // Look-back words: grown on demand; cleared when new or when the 24-bit epoch wraps.
-  if (ntiles > a->status_cap) {
-    uint64_t cap = a->status_cap ? a->status_cap : 4096;
-    while (cap < ntiles) cap *= 2;
-    if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
-    a->ref.status = nullptr;
-    a->status_cap = 0;
-    void* p = nullptr;
-    if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
-    if (hipMemsetAsync(p, 0, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
-    a->ref.status = static_cast<uint64_t*>(p);
-    a->status_cap = cap;
-    a->epoch = 0;
-  }
-  a->epoch += 1;
-  if (a->epoch >= (1ull << 24)) {
-    if (hipMemsetAsync(a->ref.status, 0, a->status_cap * sizeof(uint64_t), s) != hipSuccess)
-      return GGA_EHIP;
-    a->epoch = 1;
+  // Look-back words (needed only when an LFVector spans several tiles): grown on
+  // demand; cleared when new or when the 24-bit epoch wraps.
+  if (tpv > 1) {
+    if (ntiles > a->status_cap) {
+      uint64_t cap = a->status_cap ? a->status_cap : 4096;
+      while (cap < ntiles) cap *= 2;
+      if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
+      a->ref.status = nullptr;
+      a->status_cap = 0;
+      void* p = nullptr;
+      if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+      if (hipMemsetAsync(p, 0, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+      a->ref.status = static_cast<uint64_t*>(p);
+      a->status_cap = cap;
+      a->epoch = 0;
+    }
+    a->epoch += 1;
+    if (a->epoch >= (1ull << 24)) {
+      if (hipMemsetAsync(a->ref.status, 0, a->status_cap * sizeof(uint64_t), s) != hipSuccess)
+        return GGA_EHIP;
+      a->epoch = 1;
+    }
   }
 
   TileArgs I;
   I.n_threads = d.n_threads;
   I.chunk = chunk;
   I.tpv = tpv;
-  I.ticket_base = a->ticket_base;
   I.epoch = a->epoch;
   I.elem_log2 = a->elem_log2;
   StaticRef S{};
   const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
                                     : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
   if (st == GGA_OK) {
-    a->ticket_base += ntiles;
     a->prefix_valid = false;
   }
   return st;
@@ -593,13 +696,11 @@ int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
   if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
   TileArgs I{};
   I.n_threads = d.n_threads;
-  I.ticket_base = st->ticket_base;
   I.elem_log2 = st->elem_bytes == 4 ? 2u : 3u;
-  StaticRef S{st->data, st->cap, st->d_size, st->d_ticket, st->d_err};
+  StaticRef S{st->data, st->cap, st->d_size, st->d_err};
   ArrRef A{};
   const int rc = st->elem_bytes == 4 ? dispatch<uint32_t, true>(A, S, I, d, ntiles, s)
                                      : dispatch<uint64_t, true>(A, S, I, d, ntiles, s);
-  if (rc == GGA_OK) st->ticket_base += ntiles;
   return rc;
 }
 

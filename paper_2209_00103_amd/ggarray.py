@@ -59,6 +59,7 @@ _SIGS = {
     "gga_static_rw": [_vp, _u32, _vp],
     "gga_static_size": [_vp, _P(_u64), _vp],
     "gga_static_last_error": [_vp, _vp],
+    "gga_static_clear": [_vp, _vp],
     "gga_semi_create": [_P(_vp), _u32, _u64, _vp],
     "gga_semi_destroy": [_vp, _vp],
     "gga_semi_insert": [_vp, _vp, _vp, _u64, _vp],
@@ -216,14 +217,19 @@ class GGArray:
                                      _stream(stream)), "ggarray_flatten")
 
     def flatten(self, stream=None) -> torch.Tensor:
-        n = self.size(stream)
+        """Flattened copy of the committed contents (also after a sticky pool error)."""
+        n = self.size(stream, check_error=False)
         out = torch.empty(max(n, 1), dtype=self.dtype, device=self.pool.mem.device)
         self.flatten_into(out[:n] if n else out[:0], stream)
         return out[:n]
 
-    def size(self, stream=None) -> int:
+    def size(self, stream=None, check_error: bool = True) -> int:
+        """Global size.  With check_error=False a sticky ENOMEM / ERANGE does not raise
+        (the size of the committed contents is still returned)."""
         v = _u64()
-        _check(lib().ggarray_size(self._h, ctypes.byref(v), _stream(stream)), "ggarray_size")
+        st = lib().ggarray_size(self._h, ctypes.byref(v), _stream(stream))
+        if check_error or st not in (OK, ENOMEM, ERANGE):
+            _check(st, "ggarray_size")
         return int(v.value)
 
     def capacity(self, stream=None) -> int:
@@ -239,8 +245,12 @@ class GGArray:
 
     def prefix(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n_vectors + 1, dtype=torch.int64, device=self.pool.mem.device)
-        _check(lib().ggarray_prefix(self._h, _dev_ptr(out, "out"), _stream(stream)), "ggarray_prefix")
+        self.prefix_into(out, stream)
         return out
+
+    def prefix_into(self, out: torch.Tensor, stream=None):
+        _check(lib().ggarray_prefix(self._h, _dev_ptr(out, "out", self.n_vectors + 1, 8),
+                                    _stream(stream)), "ggarray_prefix")
 
     def last_error(self, stream=None) -> int:
         return int(lib().ggarray_last_error(self._h, _stream(stream)))
@@ -285,6 +295,9 @@ class StaticArray:
 
     def data(self, stream=None) -> torch.Tensor:
         return self.buf[: self.size(stream)]
+
+    def clear(self, stream=None):
+        _check(lib().gga_static_clear(self._h, _stream(stream)), "gga_static_clear")
 
     def close(self, stream=None):
         if self._h:
