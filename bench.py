@@ -45,12 +45,56 @@ def parse():
     ap.add_argument("--vectors", type=int, default=512, help="LFVectors (the paper's 32 / 512 sweep)")
     ap.add_argument("--no-baselines", action="store_true", help="skip static / semi-static arrays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and its parity check")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per launch")
+    ap.add_argument("--traffic", default=TRAFFIC_SUMMARY,
+                    help="rocprofv3 counter summary with measured HBM bytes per launch")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy (torch), to calibrate HBM byte counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 2 GiB read, 2 GiB written, three times."""
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.empty(1 << 29, dtype=torch.int32, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 2 * a.numel() * 4, "repeats": 3}), flush=True)
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cfg2_hbm_traffic.md")
+
+
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources; a traffic figure counts only if it was measured on them."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2209_00103_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary, or None
+    when there is none or the kernels changed since it was taken."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic_bytes_per_launch:"):
+                d = json.loads(line.split(":", 1)[1])
+                if d.get("digest") == kernel_source_digest():
+                    return d.get(kernel)
+    return None
 
 
 class Timer:
@@ -128,11 +172,13 @@ def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
-                          "not part of this build (LFVectors shard without communication, "
-                          "see the design notes)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; only the single-GPU "
+                          "path is implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -215,10 +261,7 @@ def main():
         kernels[k]["frac"] = kernels[k]["GBps"] / HBM_PEAK_GBPS
     totals = {"insert": sum(ins_ms), "rw": rw_ms, "flatten": fl_ms}
     dom = max(totals, key=totals.get)
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get(dom)
+    traffic = measured_traffic(args.traffic, dom)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": kernels[dom]["GBps"], "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": kernels[dom]["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
                 "avg_launch_us": kernels[dom]["avg_us"], "bytes_per_launch": kernels[dom]["bytes_per_launch"]}

@@ -91,11 +91,12 @@ const char *gga_strerror(int status);
  * caller-owned HBM does, so growth needs no host round trip).
  *
  * gga_pool_create: dev_base is caller-owned device memory of `bytes` bytes,
- *   256-byte aligned, at least 1 MiB; it must outlive the pool.  The pool keeps
- *   a 128 KiB header at the start and carves buckets (power-of-two sizes,
- *   >= 256 B) from the rest, through 256 shards that each sub-allocate chunks
- *   of about 1/1024 of the region (64 KiB .. 16 MiB), so up to 256 chunks may
- *   be partly used.  Synchronises s.  EINVAL on a NULL/unaligned/small buffer.
+ *   256-byte aligned, at least 3 MiB; it must outlive the pool.  The pool keeps
+ *   a 2 MiB header (4096 free lists per size class) at the start and carves
+ *   buckets (power-of-two sizes, >= 256 B) from the rest, through 256 arena
+ *   shards that each sub-allocate chunks of about 1/1024 of the region
+ *   (64 KiB .. 16 MiB), so up to 256 chunks may be partly used.  Synchronises
+ *   s.  EINVAL on a NULL/unaligned/small buffer.
  * gga_pool_destroy: frees the host handle; EBUSY while arrays still use it.
  * gga_pool_stats: out[0..6] = bytes in use, bytes carved from the region so far
  *   (an upper bound of the peak in use), allocations, frees, the same carved

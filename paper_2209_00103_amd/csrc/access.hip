@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uin
     uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
     const uint64_t p = *slot;
     if (p > kFailedPtr)
-      pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b));
+      pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b, A.salt));
     if (p) *slot = 0;
   }
   if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void free_all_kernel(ArrRef A, uint32_t elem_l
   uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
   const uint64_t p = *slot;
   if (p > kFailedPtr)
-    pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b));
+    pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b, A.salt));
   *slot = 0;
 }
 

@@ -97,7 +97,7 @@ const char* gga_strerror(int status) {
 
 // ---------------------------------------------------------------------- pool --
 int gga_pool_create(gga_pool** out, void* dev_base, uint64_t bytes, gga_stream s) {
-  if (!out || !dev_base || (reinterpret_cast<uintptr_t>(dev_base) & 255u) || bytes < (1u << 20))
+  if (!out || !dev_base || (reinterpret_cast<uintptr_t>(dev_base) & 255u) || bytes < kPoolHdrBytes + (1u << 20))
     return GGA_EINVAL;
   *out = nullptr;
   gga_pool* p = new (std::nothrow) gga_pool();
@@ -144,7 +144,7 @@ int gga_pool_stats(gga_pool* p, uint64_t out[7], gga_stream s) {
     return GGA_EHIP;
   }
   uint64_t in_use = 0, n_alloc = 0, n_free = 0;
-  for (int k = 0; k < kShards; ++k) {  // per-shard counters wrap individually; the sums do not
+  for (int k = 0; k < kArenaShards; ++k) {  // per-shard counters wrap individually; the sums do not
     in_use += h->shard[k].in_use;
     n_alloc += h->shard[k].n_alloc;
     n_free += h->shard[k].n_free;
@@ -221,6 +221,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.pool = p->ref;
   R.V = n_vectors;
   R.log2F = a->log2F;
+  R.salt = (uint32_t)((reinterpret_cast<uintptr_t>(a->meta) >> 8) * 2654435761u) & (kFreeShards - 1);
   a->status_cap = 0;
   a->epoch = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed

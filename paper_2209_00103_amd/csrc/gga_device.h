@@ -1,7 +1,7 @@
 // Device-side layout and primitives of the GGArray library (gfx950).
 //
 // Layout in HBM
-//   pool:   [PoolHdr | pad to 128 KiB | bucket region ...]   (caller-owned memory)
+//   pool:   [PoolHdr | pad to 2 MiB | bucket region ...]   (caller-owned memory)
 //   array:  size[V] u64 | bptr[V][kMaxBuckets] u64 | dead[V] u32 |
 //           alloc_done[V] u32 | prefix[V+1] u64 | tprefix[V+1] u64 |
 //           vticket[V] u64 | err u32 | status[...] u64 (look-back words, grown
@@ -22,7 +22,8 @@ constexpr int kMaxBuckets = 40;     // F * (2^40 - 1) elements per LFVector
 constexpr int kMinClassLog2 = 8;    // smallest pool block: 256 B
 constexpr int kMaxClassLog2 = 40;   // largest pool block: 1 TiB
 constexpr int kNumClasses = kMaxClassLog2 + 1;
-constexpr int kShards = 256;        // pool shards (free lists, arenas, statistics)
+constexpr int kFreeShards = 4096;   // pool free-list shards
+constexpr int kArenaShards = 256;   // pool arena / statistics shards
 constexpr uint64_t kFailedPtr = 1;  // bucket-table marker: allocation failed
 constexpr uint64_t kIdxMask = (1ull << 40) - 1;
 
@@ -51,12 +52,12 @@ struct PoolHdr {
   uint64_t n_attempt;     // allocation attempts (fault injection counts these)
   uint64_t fault_at;      // attempt number that fails; 0 = never
   uint64_t pad[3];
-  uint64_t nonempty[kNumClasses][kShards / 64];  // bit s: shard s of the class may hold blocks
-  uint64_t heads[kNumClasses * kShards];         // tagged Treiber-stack heads
-  PoolShard shard[kShards];
+  uint64_t nonempty[kNumClasses][kFreeShards / 64];  // bit s: free list s of the class may hold blocks
+  uint64_t heads[kNumClasses * kFreeShards];         // tagged Treiber-stack heads
+  PoolShard shard[kArenaShards];
 };
 
-constexpr uint64_t kPoolHdrBytes = 128 * 1024;
+constexpr uint64_t kPoolHdrBytes = 2ull << 20;
 static_assert(sizeof(PoolHdr) <= kPoolHdrBytes, "pool header too large");
 
 struct PoolRef {
@@ -78,6 +79,7 @@ struct ArrRef {
   PoolRef pool;
   uint32_t V;
   uint32_t log2F;
+  uint32_t salt;         // spreads the pool shards of different arrays
 };
 
 // ------------------------------------------------------------------ atomics --
@@ -156,20 +158,23 @@ __device__ __forceinline__ uint32_t bucket_class(uint32_t log2F, uint32_t elem_l
 // Lock-free bucket pool over the caller's region, built so that thousands of
 // LFVectors can grow in the same kernel without meeting on one address:
 //
-//  * 256 shards.  Bucket b of LFVector v belongs to shard (v + b) mod 256; the
-//    shard's words (arena, statistics) sit on their own 64-byte line.
-//  * Freed blocks go to one tagged Treiber stack per (size class, shard).  A
-//    head packs a 24-bit version tag above the 40-bit block index (offset / 256
-//    + 1, 0 = empty); the tag changes on every update, so a stale head never
+//  * Bucket b of LFVector v of an array with salt z belongs to free-list shard
+//    f = (v + b + z) mod 4096 and to arena shard f mod 256, so the LFVectors of
+//    an array (up to 4096 of them) never share a free list for a given bucket,
+//    and a bucket released by shrink is found again by the same LFVector.
+//  * Freed blocks go to one tagged Treiber stack per (size class, free shard).
+//    A head packs a 24-bit version tag above the 40-bit block index (offset /
+//    256 + 1, 0 = empty); the tag changes on every update, so a stale head never
 //    matches (ABA).  A free block keeps the index of the next one in its first
-//    8 bytes.  A per-class mask hints which shards may hold blocks.
-//  * Fresh blocks up to a quarter of a chunk come from the shard's arena: a
-//    chunk carved from the global bump pointer, sub-allocated with one atomic
-//    add on the shard's arena word (chunk id << 32 | used 256-byte units).  The
-//    add that crosses the end of the chunk installs the next chunk; adds that
-//    land past the end in the meantime take their block from the global bump
-//    pointer instead of waiting.  Larger blocks always come from the global
-//    bump pointer.
+//    8 bytes.  A per-class bit mask hints which free lists may hold blocks.
+//  * Fresh blocks up to a quarter of a chunk come from the arena shard: a chunk
+//    carved from the global bump pointer, sub-allocated with one atomic add on
+//    the shard's arena word (chunk id << 32 | used 256-byte units).  The add that
+//    crosses the end of the chunk installs the next chunk; adds that land past
+//    the end in the meantime take their block from the global bump pointer
+//    instead of waiting.  Larger blocks always come from the global bump pointer.
+//  * Only when the region is exhausted does an allocation look through the other
+//    free lists (steal), guided by the hint masks.
 //
 // No operation uses release/acquire fences (on gfx950 those write back or
 // invalidate the whole L2 of an XCD).  Ordering comes from completion: a push
@@ -177,9 +182,10 @@ __device__ __forceinline__ uint32_t bucket_class(uint32_t log2F, uint32_t elem_l
 // head CAS is issued; a pop reads the head, then the link at an address that
 // depends on it, then CASes values that depend on both.  All are agent-scope
 // atomics, performed at the coherence point in that order.
-__device__ __forceinline__ uint32_t pool_shard(uint32_t v, uint32_t b) {
-  return (v + b) & (uint32_t)(kShards - 1);
+__device__ __forceinline__ uint32_t pool_shard(uint32_t v, uint32_t b, uint32_t salt) {
+  return (v + b + salt) & (uint32_t)(kFreeShards - 1);
 }
+__device__ __forceinline__ uint32_t arena_shard(uint32_t f) { return f & (uint32_t)(kArenaShards - 1); }
 
 __device__ __forceinline__ bool cas_rlx(uint64_t* p, uint64_t& expected, uint64_t desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
@@ -194,7 +200,7 @@ __device__ __forceinline__ void sub_nr(uint64_t* p, uint64_t v) {
 
 __device__ __forceinline__ uint8_t* pool_pop(PoolRef P, uint32_t cls, uint32_t s) {
   PoolHdr* H = P.hdr;
-  uint64_t* head = &H->heads[cls * kShards + s];
+  uint64_t* head = &H->heads[(uint64_t)cls * kFreeShards + s];
   uint64_t h = ld_rlx(head);
   while (h & kIdxMask) {
     const uint64_t off = ((h & kIdxMask) - 1) << kMinClassLog2;
@@ -246,7 +252,7 @@ __device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t 
   return c;
 }
 
-__device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t shard) {
+__device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t fs) {
   PoolHdr* H = P.hdr;
   const uint64_t bytes = 1ull << cls;
   if (ld_rlx(&H->fault_at)) {
@@ -254,28 +260,28 @@ __device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t
     if (n == ld_rlx(&H->fault_at)) return nullptr;
   }
   if (cls > (uint32_t)kMaxClassLog2) return nullptr;
-  uint8_t* q = pool_pop(P, cls, shard);
-  for (uint32_t wi = 0; !q && wi < (uint32_t)kShards / 64; ++wi) {
+  const uint32_t as = arena_shard(fs);
+  uint8_t* q = pool_pop(P, cls, fs);
+  if (!q && cls + 2 <= (uint32_t)ld_rlx(&H->chunk_log2)) q = arena_alloc(P, as, bytes);
+  if (!q) q = global_bump(P, bytes);
+  for (uint32_t wi = 0; !q && wi < (uint32_t)kFreeShards / 64; ++wi) {  // region exhausted: steal
     uint64_t mask = ld_rlx(&H->nonempty[cls][wi]);
-    if ((shard >> 6) == wi) mask &= ~(1ull << (shard & 63));
     while (!q && mask) {
       const uint32_t s = wi * 64 + (uint32_t)__ffsll((unsigned long long)mask) - 1u;
       q = pool_pop(P, cls, s);
       mask &= mask - 1;
     }
   }
-  if (!q && cls + 2 <= (uint32_t)ld_rlx(&H->chunk_log2)) q = arena_alloc(P, shard, bytes);
-  if (!q) q = global_bump(P, bytes);
   if (!q) return nullptr;
-  add_nr(&H->shard[shard].in_use, bytes);
-  add_nr(&H->shard[shard].n_alloc, 1ull);
+  add_nr(&H->shard[as].in_use, bytes);
+  add_nr(&H->shard[as].n_alloc, 1ull);
   return q;
 }
 
 __device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls, uint32_t s) {
   PoolHdr* H = P.hdr;
   const uint64_t idx = ((uint64_t)(ptr - P.base) >> kMinClassLog2) + 1;
-  uint64_t* head = &H->heads[cls * kShards + s];
+  uint64_t* head = &H->heads[(uint64_t)cls * kFreeShards + s];
   uint64_t h = ld_rlx(head);
   for (;;) {
     const uint64_t prev = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(ptr), h & kIdxMask,
@@ -289,8 +295,8 @@ __device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls,
   if ((h & kIdxMask) == 0)
     __hip_atomic_fetch_or(&H->nonempty[cls][s >> 6], 1ull << (s & 63), __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_AGENT);
-  sub_nr(&H->shard[s].in_use, 1ull << cls);
-  add_nr(&H->shard[s].n_free, 1ull);
+  sub_nr(&H->shard[arena_shard(s)].in_use, 1ull << cls);
+  add_nr(&H->shard[arena_shard(s)].n_free, 1ull);
 }
 
 // ------------------------------------------------------------------ payloads --

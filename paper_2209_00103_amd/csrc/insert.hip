@@ -201,20 +201,20 @@ struct WaveRes {
 
 // Resolves the tile's first index, allocates or waits for its buckets, and lets
 // the last tile of the LFVector commit the round.  Executed by one whole wave.
+// size0 is the LFVector size the caller read when it started (used when t == 0;
+// only the last tile of the LFVector writes the size, after every other tile of
+// the round has published, so an early read is current).
 __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
-                                uint64_t tile, bool is_last, uint32_t n_t) {
+                                uint64_t tile, bool is_last, uint32_t n_t, uint64_t size0) {
   WaveRes r{0, kFailedPtr, 0, 0, 0};
   const uint32_t lane = lane_id();
   const uint32_t log2F = A.log2F;
-  uint64_t old_size = 0;
+  const uint64_t old_size = size0;
   uint64_t base = 0;
   bool stalled = false;
   if (t == 0) {
-    if (lane == 0) {
-      old_size = ld_rlx(&A.size[v]);
-      if (!is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStP, old_size + n_t));
-    }
-    base = __shfl(old_size, 0, 64);
+    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStP, old_size + n_t));
+    base = old_size;
   } else {
     if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStA, n_t));
     stalled = !lookback(A.status, tile, t, I.epoch, base);
@@ -230,7 +230,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
     return r;
   }
 
-  uint32_t b_lo = 0, nb = 0;
+  uint32_t b_lo = 0, nb = 0, n_alloc = 0, n_fail = 0;
   if (n_t) {
     b_lo = bucket_of(log2F, base);
     nb = bucket_of(log2F, base + n_t - 1) - b_lo + 1;
@@ -245,7 +245,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
         uint64_t* slot = &A.bptr[(uint64_t)v * kMaxBuckets + b];
         if (holds_start) {
           // This tile writes the bucket's first index: it is the one that allocates.
-          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b));
+          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
           p = q ? (uint64_t)q : kFailedPtr;
           st_rlx(slot, p);
           allocated = true;
@@ -264,31 +264,32 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
       }
       r.bp = p;
     }
-    // One atomic reports this tile's allocations: the count in the low half,
-    // the failures in the high half.
-    const uint32_t n_alloc = (uint32_t)__popcll(__ballot(allocated));
-    const uint32_t n_fail = (uint32_t)__popcll(__ballot(failed));
+    // One atomic reports an earlier tile's allocations to the last tile: the
+    // count in the low half, the failures in the high half.  The last tile
+    // counts its own allocations locally.
+    n_alloc = (uint32_t)__popcll(__ballot(allocated));
+    n_fail = (uint32_t)__popcll(__ballot(failed));
     if (lane == 0 && n_fail) set_error(A.err, kErrNoMem);
     if (lane == 0 && __ballot(late)) set_error(A.err, kErrStall);
-    if (lane == 0 && n_alloc) fetch_add32(&A.alloc_done[v], n_alloc | (n_fail << 16));
+    if (lane == 0 && n_alloc && !is_last) fetch_add32(&A.alloc_done[v], n_alloc | (n_fail << 16));
   }
 
   if (is_last && lane == 0) {
     const uint64_t old = (t == 0) ? old_size : ld_rlx(&A.size[v]);
     const uint64_t nsize = base + n_t;
-    const uint32_t expected = nbuckets_for(log2F, nsize) - nbuckets_for(log2F, old);
-    uint32_t failed = 0;
-    if (expected) {
+    const uint32_t others = nbuckets_for(log2F, nsize) - nbuckets_for(log2F, old) - n_alloc;
+    uint32_t failed = n_fail;
+    if (others) {
       uint32_t done, spins = 0;
-      while (((done = ld_rlx32(&A.alloc_done[v])) & 0xFFFFu) < expected && spins < kSpinLimit) {
+      while (((done = ld_rlx32(&A.alloc_done[v])) & 0xFFFFu) < others && spins < kSpinLimit) {
         ++spins;
         spin_pause();
       }
-      if ((done & 0xFFFFu) < expected) {
+      if ((done & 0xFFFFu) < others) {
         set_error(A.err, kErrStall);
         failed = 1;
       } else {
-        failed = done >> 16;
+        failed += done >> 16;
         st_rlx32(&A.alloc_done[v], 0u);
       }
     }
@@ -307,8 +308,10 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
 // Block kernels: wave 0 resolves and leaves the result in LDS.
 __device__ __forceinline__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
                                              uint64_t tile, bool is_last, uint32_t n_t, TileShared& sh) {
-  const WaveRes r = resolve_wave(A, I, v, t, tile, is_last, n_t);
   const uint32_t lane = lane_id();
+  uint64_t size0 = 0;
+  if (t == 0 && lane == 0) size0 = ld_rlx(&A.size[v]);
+  const WaveRes r = resolve_wave(A, I, v, t, tile, is_last, n_t, __shfl(size0, 0, 64));
   if (lane < r.nb) sh.bp[lane] = r.bp;
   if (lane == 0) {
     sh.base = r.base;
@@ -437,8 +440,9 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
   const bool ticketed = !kStatic && I.tpv > 1;
   const uint32_t v = kStatic ? 0u : (uint32_t)(blockIdx.x / I.tpv);
   uint64_t t = kStatic ? blockIdx.x : blockIdx.x - (uint64_t)v * I.tpv;
-  uint64_t k = 0;
+  uint64_t k = 0, size0 = 0;
   if (ticketed && lane == 0) k = take_ticket(A, v);
+  if (!kStatic && lane == 0) size0 = ld_rlx(&A.size[v]);  // needed if this is tile 0
   uint64_t g0, gend;
   if (kStatic) {
     g0 = t * kWaveTile;
@@ -473,7 +477,7 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
     if (lane == 0 && lim < n_t) set_error(S.err, kErrRange);
     dst = reinterpret_cast<T*>(S.data) + base;
   } else {
-    r = resolve_wave(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t);
+    r = resolve_wave(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, __shfl(size0, 0, 64));
     if (r.n_out == 0) return;
     const uint64_t p0 = __shfl(r.bp, 0, 64);
     dst = reinterpret_cast<T*>(p0) + (r.base - bucket_start(log2F, r.b_lo));

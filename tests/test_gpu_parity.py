@@ -306,11 +306,11 @@ def _check_round_prefixes(a, states, V):
 
 def test_pool_exhaustion_keeps_round_prefixes():
     G = gg()
-    pool = G.Pool(1 * MiB)
+    pool = G.Pool(4 * MiB)  # 2 MiB header + 2 MiB of buckets
     V, F = 4, 256
     rng = np.random.default_rng(4)
-    # 16 rounds x 32000 kept elements x 4 B = 2 MB of live data > the 1 MiB pool
-    rounds = [wl.random_round(rng, 40000, 0.8, 4) for _ in range(16)]
+    # 24 rounds x 32000 kept elements x 4 B = 3 MB of live data > the 2 MiB region
+    rounds = [wl.random_round(rng, 40000, 0.8, 4) for _ in range(24)]
     a = G.GGArray(pool, 4, V, F)
     for vals, flags in rounds:
         a.insert(dev(vals), dev(flags))
