@@ -28,6 +28,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -45,6 +47,13 @@ def parse():
     ap.add_argument("--vectors", type=int, default=512, help="LFVectors (the paper's 32 / 512 sweep)")
     ap.add_argument("--no-baselines", action="store_true", help="skip static / semi-static arrays")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and its parity check")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (512-array) leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served (4096-array request loop) leg")
+    ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
+    ap.add_argument("--serve-lanes", type=int, default=2, help="served steps in flight")
+    ap.add_argument("--serve-step", type=int, default=1024, help="requests per served step")
+    ap.add_argument("--serve-baseline-requests", type=int, default=1 << 14,
+                    help="trace prefix replayed with one launch per request")
     ap.add_argument("--traffic", default=TRAFFIC_SUMMARY,
                     help="rocprofv3 counter summary with measured HBM bytes per launch")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -149,6 +158,197 @@ class _Null:
 
     def __exit__(self, *exc):
         return False
+
+
+def _pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
+
+
+def batched_leg(G, wl, torch, np, steps, warmup):
+    """Configuration 4: 512 arrays with log-uniform target sizes 2^10..2^24 (uint32),
+    4 insertion rounds of ceil(n/4) threads each (keyed payloads), r/w x+1,
+    flatten to per-array offsets.  One step = clear + 4 rounds + r/w + flatten.
+    Timed as one launch per phase for all arrays (eager and replayed as a captured
+    HIP graph) against one launch per array and phase (eager and captured).  The
+    batched and per-array results must be identical; parity with the oracle at this
+    size is a GPU test."""
+    from paper_2209_00103_amd.autotune import AutoTuner
+
+    n_arr = 512
+    sizes = [int(x) for x in wl.cfg4_sizes(1, n_arr)]
+    vecs = [wl.cfg4_vectors(n) for n in sizes]
+    rounds = [wl.cfg4_round_threads(n, 4) for n in sizes]
+    tuner = AutoTuner(wl.cfg4_vectors, lambda n: wl.cfg4_round_threads(n, 4), elem_bytes=ELEM)
+    firsts = [tuner.first_bucket(n) for n in sizes]
+    total = sum(sizes)
+    pool = G.Pool(int(ELEM * total * 2.2) + (256 << 20))
+    arrays = [G.GGArray(pool, ELEM, vecs[i], firsts[i]) for i in range(n_arr)]
+    b = G.Batch(arrays)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    out2 = torch.empty(total, dtype=torch.int32, device="cuda")
+    counts = [[rounds[i][r] for i in range(n_arr)] for r in range(4)]
+    bgens = [G.make_gen(G.GEN_KEYED, seed=1, round=r, tag=0) for r in range(4)]
+    agens = [[G.make_gen(G.GEN_KEYED, seed=1, round=r, tag=i) for r in range(4)] for i in range(n_arr)]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    views = [out2[int(offs[i]):int(offs[i + 1])] for i in range(n_arr)]
+
+    def batched_step():
+        b.shrink(1, 1)
+        for r in range(4):
+            b.insert_gen(bgens[r], counts[r])
+        b.rw(G.ADD1)
+        b.flatten_into(out)
+
+    def per_array_step():
+        for i, a in enumerate(arrays):
+            a.shrink(1, 1)
+            for r in range(4):
+                a.insert_gen(agens[i][r], rounds[i][r])
+            a.rw(G.ADD1)
+            a.flatten_into(views[i])
+
+    def timed(fn, k):
+        ts = []
+        for _ in range(k):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return ts
+
+    s = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(s):
+        for _ in range(max(1, warmup)):
+            batched_step()
+        s.synchronize()
+        res["batched"] = timed(batched_step, steps)
+        per_array_step()  # warm-up (uploads nothing, sizes status buffers)
+        s.synchronize()
+        res["per_array"] = timed(per_array_step, max(2, min(steps, 3)))
+    g1 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g1, stream=s):
+        batched_step()
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        per_array_step()
+    with torch.cuda.stream(s):
+        g1.replay()
+        g2.replay()
+        s.synchronize()
+        res["batched_graph"] = timed(g1.replay, steps)
+        res["per_array_graph"] = timed(g2.replay, steps)
+    torch.cuda.synchronize()
+    assert b.last_error() == 0
+    got, got2 = G.as_unsigned(out), G.as_unsigned(out2)
+    same = bool(np.array_equal(got, got2))
+    cap = sum(a.capacity() for a in arrays)
+    for a in arrays:
+        a.close()
+    b.close()
+    pool.close()
+    summary = {}
+    for k, ts in res.items():
+        summary[k] = {"mean_ms": statistics.mean(ts), "p50_ms": _pct(ts, 50), "p99_ms": _pct(ts, 99),
+                      "Gelem_s": total / (statistics.mean(ts) * 1e-3) / 1e9}
+    fhist = {}
+    for F in firsts:
+        fhist[str(F)] = fhist.get(str(F), 0) + 1
+    return {"workload": "512 arrays, sizes log-uniform 2^10..2^24 uint32, 4 keyed insertion rounds, "
+                        "r/w x+1, flatten to per-array offsets",
+            "elements": total, "lfvectors": sum(vecs), "timings": summary,
+            "capacity_over_live": cap / total, "first_bucket_choices": fhist,
+            "batched_equals_per_array": same}
+
+
+def _latency(res, arrival, kind, k):
+    lat = (res["t_done_ns"][:k].astype(np.int64) - arrival[:k].astype(np.int64)) / 1e3
+    ok = res["status"][:k] == 0
+    out = {}
+    for name, sel in (("all", ok), ("append", ok & (kind[:k] == 0)), ("rw", ok & (kind[:k] == 1)),
+                      ("flatten", ok & (kind[:k] == 2))):
+        x = lat[sel]
+        out[name] = {"n": int(x.size), "p50_us": float(np.percentile(x, 50)) if x.size else None,
+                     "p99_us": float(np.percentile(x, 99)) if x.size else None,
+                     "mean_us": float(x.mean()) if x.size else None}
+    return out
+
+
+def served_leg(G, wl, torch, np_, args):
+    """Configuration 5: 4096 resident arrays (initial sizes lognormal, median 2^16
+    uint32, sigma 1), a trace of 2^20 requests (60% append of lognormal length with
+    median 2^10, 30% r/w x+1, 10% flatten; uniform targets; exponential gaps), a
+    64 GiB admission budget.  First the saturation throughput (every request queued
+    at t = 0), then offered loads of 0.25 .. 1.1 x saturation with latency
+    percentiles per request type.  Baseline: one launch per request, in arrival
+    order, on a prefix of the same trace at the same offered rate.  Every run starts
+    from the same resident state."""
+    cfg = wl.CFG5
+    seed, n_arr, n = 1, cfg["n_arrays"], int(args.serve_requests)
+    sizes = [int(x) for x in wl.cfg5_sizes(seed, n_arr, cfg["median_log2"], cfg["sigma"], cfg["size_cap_log2"])]
+    vecs = [wl.cfg4_vectors(s) for s in sizes]
+    firsts = [wl.cfg5_first_bucket(s, v) for s, v in zip(sizes, vecs)]
+    tr = wl.cfg5_trace(seed, n, n_arr, cfg["append_median_log2"], cfg["append_cap_log2"], cfg["mix"])
+    kind, target, length = tr["kind"], tr["target"], tr["length"]
+    final_live = sum(sizes) + int(length.sum())
+    pool = G.Pool(ELEM * (2 * final_live + sum(v * f for v, f in zip(vecs, firsts))) + (1 << 30))
+    arrays = [G.GGArray(pool, ELEM, v, f) for v, f in zip(vecs, firsts)]
+    fill = G.Batch(arrays)
+    fill_gen = G.make_gen(G.GEN_KEYED, seed=seed, round=cfg["fill_round"], tag=0)
+    arena = torch.empty((4 << 30) // 4, dtype=torch.int32, device="cuda")
+    out_len = torch.empty(n, dtype=torch.int64, device="cuda")
+    common = dict(seed=seed, append_round=cfg["append_round"], append_shift=cfg["append_shift"], rw_op=G.ADD1)
+    batched = G.Server(arrays, arena, cfg["cap_bytes"], mode=G.SERVE_BATCHED, lanes=args.serve_lanes,
+                       max_step=args.serve_step, **common)
+    per_req = G.Server(arrays, arena, cfg["cap_bytes"], mode=G.SERVE_PER_REQUEST, depth=1024, **common)
+
+    def run(sv, arrival, k):
+        fill.shrink(1, 1)  # back to the initial state: empty, buckets released, refilled
+        fill.insert_gen(fill_gen, sizes)
+        torch.cuda.synchronize()
+        res = sv.run(arrival[:k], kind[:k], target[:k], length[:k], out_len)
+        span = max(int(res["t_done_ns"][:k].max()), 1)
+        done = res["status"][:k] == 0
+        elems = int(length[:k][done & (kind[:k] == 0)].sum())
+        return {"requests": k, "req_per_s": k / (span * 1e-9), "span_ms": span / 1e6,
+                "appended_elems": elems, "rejected": res["rejected"], "steps": res["steps"],
+                "mean_step": res["issued"] / max(res["steps"], 1), "largest_step": res["largest_step"],
+                "memory_waits": res["memory_waits"], "peak_charged_GB": res["peak_charged_bytes"] / 1e9,
+                "arena_wraps": res["arena_wraps"], **_latency(res, arrival, kind, k)}
+
+    zeros = np_.zeros(n, dtype=np_.uint64)
+    sat = run(batched, zeros, n)
+    k_b = min(n, int(args.serve_baseline_requests))
+    sat_pr = run(per_req, zeros, k_b)
+    x = sat["req_per_s"]
+    loads = []
+    for f in cfg["loads"]:
+        arrival = wl.cfg5_arrivals_ns(tr["gap"], f * x)
+        b = run(batched, arrival, n)
+        b_prefix = run(batched, arrival, k_b)
+        p = run(per_req, arrival, k_b)
+        loads.append({"load": f, "offered_req_per_s": f * x, "batched": b,
+                      "batched_prefix": {key: b_prefix[key] for key in ("req_per_s", "all", "append", "rw", "flatten")},
+                      "per_request": p})
+        log(f"served load {f}: batched p50 {b['all']['p50_us']:.0f} us p99 {b['all']['p99_us']:.0f} us "
+            f"({b['req_per_s']:.3e} req/s, mean step {b['mean_step']:.0f}); per-request p99 "
+            f"{p['all']['p99_us']:.0f} us ({p['req_per_s']:.3e} req/s)")
+    batched.close()
+    per_req.close()
+    fill.close()
+    for a in arrays:
+        a.close()
+    pool.close()
+    return {"workload": f"{n_arr} resident arrays, initial sizes lognormal (median 2^16 uint32, sigma 1), "
+                        f"{n} requests: 60% append (lognormal length, median 2^10), 30% r/w x+1, "
+                        f"10% flatten; uniform targets; Poisson arrivals; 64 GiB admission budget",
+            "resident_initial_GB": ELEM * sum(sizes) / 1e9, "appended_GB": ELEM * int(length.sum()) / 1e9,
+            "lanes": args.serve_lanes, "max_step": args.serve_step,
+            "baseline": f"one launch per request, in order, on the first {k_b} requests, at most 1024 in flight",
+            "saturation": sat, "saturation_per_request": sat_pr, "loads": loads}
 
 
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
@@ -319,6 +519,22 @@ def main():
             f"{baselines['static']['rw_GBps']:.0f} GB/s; semi-static insert "
             f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s")
 
+    arr.close()
+    pool.close()
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(G, wl, torch, np, args.steps, args.warmup)
+        t = batched["timings"]
+        log(f"batched: one launch per phase {t['batched']['mean_ms']:.3f} ms (graph {t['batched_graph']['mean_ms']:.3f}),"
+            f" per-array launches {t['per_array']['mean_ms']:.3f} ms (graph {t['per_array_graph']['mean_ms']:.3f});"
+            f" identical {batched['batched_equals_per_array']}")
+    served = None
+    if not args.no_served:
+        served = served_leg(G, wl, torch, np, args)
+        log(f"served: saturation {served['saturation']['req_per_s']:.3e} req/s; " + "; ".join(
+            f"{p['load']}x p50 {p['batched']['all']['p50_us']:.0f} us p99 {p['batched']['all']['p99_us']:.0f} us"
+            f" (per-request p99 {p['per_request']['all']['p99_us']:.0f} us)" for p in served["loads"]))
+
     cpu = None
     parity = None
     if not args.no_cpu:
@@ -348,9 +564,9 @@ def main():
                    "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
         "parity_with_oracle": parity,
         "ms_per_step_wall": ms_step_wall,
+        "batched": batched,
+        "served": served,
     }
-    arr.close()
-    pool.close()
     print(json.dumps(line), flush=True)
 
 

@@ -58,6 +58,7 @@ typedef struct gga_pool gga_pool;
 typedef struct ggarray ggarray;
 typedef struct gga_static gga_static;
 typedef struct gga_semistatic gga_semistatic;
+typedef struct gga_batch gga_batch;
 
 /* r/w operations (Sec. VI-C times an operation over every element; the paper's
  * kernel adds 1 thirty times, GGA_ADD1_X30). */
@@ -73,13 +74,17 @@ typedef struct gga_semistatic gga_semistatic;
 #define GGA_GEN_POISSON 3   /* u = K(seed, gid, 0x80 | round);
                                c = #{k < max_count : u >= thresholds[k]};
                                insert K(seed, gid, 16 * round + j), j < c */
+#define GGA_GEN_KEYED 4     /* insert K(seed, (tag << tag_shift) | gid, round); in a
+                               batch the array's position is added to tag */
 typedef struct {
     uint32_t kind;           /* GGA_GEN_* */
-    uint32_t round;          /* BERNOULLI: < 256; POISSON: < 8 */
+    uint32_t round;          /* BERNOULLI, KEYED: < 256; POISSON: < 8 */
     uint64_t seed;           /* < 256 */
-    uint32_t tag_shift;      /* ROUND_TAG: < 64 */
+    uint32_t tag_shift;      /* ROUND_TAG: < 64; KEYED: 1..47 */
     uint32_t max_count;      /* POISSON: 1..16 */
     uint64_t thresholds[16]; /* POISSON: host copy, the first max_count used */
+    uint64_t tag;            /* KEYED: tag (+ batch position) < 2^(48 - tag_shift),
+                                gid < 2^tag_shift (so the key stays below 2^48) */
 } gga_gen;
 
 /* Human-readable name of a status code (static string). */
@@ -179,6 +184,120 @@ int ggarray_prefix(ggarray *a, uint64_t *dev_out, gga_stream s);
 /* ggarray_last_error: the sticky device error of the array (GGA_OK if none).
  *   Synchronises s.  Does not clear it. */
 int ggarray_last_error(ggarray *a, gga_stream s);
+
+/* ---------------------------------------------------------------- batches --- */
+/* A batch drives many GGArrays together: one launch inserts a round into every
+ * array, one launch scans all their sizes, one launch does the r/w or the
+ * flatten of all of them.  Each array keeps its own LFVectors, first bucket and
+ * results: a batch call gives every array exactly the result the same call on
+ * that array alone would give.  (The paper evaluates one array at a time; the
+ * batch is the multi-array form of the same operations.)
+ *
+ * gga_batch_create: arrays[0..n) are distinct GGArrays with one element size,
+ *   n >= 1; they must outlive the batch and not be used by other streams while
+ *   batch calls are pending.  The batch copies their descriptors to the device.
+ *   Synchronises s.
+ * gga_batch_insert_gen: one round: array i runs g with n_threads[i] logical
+ *   threads (host array of n entries; 0 skips the array).  Kinds ROUND_TAG,
+ *   BERNOULLI and KEYED.  The first call with a new set of thread counts uploads
+ *   a small table (and synchronises s); later calls with the same counts launch
+ *   one kernel and nothing else, so they can be captured in a HIP graph.
+ * gga_batch_shrink: ggarray_shrink(num, den) on every array, one launch.
+ * gga_batch_rw: x = op(x) over every live element of every array.
+ * gga_batch_flatten: array 0, then 1, ... into out (out_cap_elems elements);
+ *   array i starts at offset[i], the exclusive prefix of the array sizes.  If the
+ *   total exceeds out_cap_elems nothing is written and the batch's sticky
+ *   GGA_ERANGE is set.
+ * gga_batch_offsets: the n + 1 offsets (uint64, last = total) to dev_out.
+ * gga_batch_last_error: the batch's sticky error.  Synchronises s. */
+int gga_batch_create(gga_batch **out, ggarray *const *arrays, uint32_t n, gga_stream s);
+int gga_batch_destroy(gga_batch *b, gga_stream s);
+int gga_batch_insert_gen(gga_batch *b, const gga_gen *g, const uint64_t *n_threads, gga_stream s);
+int gga_batch_shrink(gga_batch *b, uint32_t num, uint32_t den, gga_stream s);
+int gga_batch_rw(gga_batch *b, uint32_t op, gga_stream s);
+int gga_batch_flatten(gga_batch *b, void *out, uint64_t out_cap_elems, gga_stream s);
+int gga_batch_offsets(gga_batch *b, uint64_t *dev_out, gga_stream s);
+int gga_batch_last_error(gga_batch *b, gga_stream s);
+
+/* ----------------------------------------------------------------- serving --- */
+/* A request loop over resident arrays (an extension of the paper's operations:
+ * the paper runs one array at a time).  A request is one operation on one array:
+ *   GGA_REQ_APPEND:  one insertion round of length[r] threads, thread j inserting
+ *                    K(seed, (r << append_shift) | j, append_round) (as a KEYED
+ *                    round with tag r), r the request's index in the trace;
+ *   GGA_REQ_RW:      ggarray_rw(rw_op);
+ *   GGA_REQ_FLATTEN: ggarray_flatten into the server's output arena.
+ * Requests on one array run in arrival order, one at a time; requests on
+ * different arrays run concurrently.  Every result therefore equals the result of
+ * running that array's requests alone, in order, with the single-array calls.
+ *
+ * GGA_SERVE_BATCHED: continuous batching.  The host admits arrived requests into
+ *   steps of at most max_step requests, at most one per array and none on an
+ *   array whose previous request is still in flight, oldest first; a step is one
+ *   table copy plus one insertion launch for its appends and one scan + one
+ *   streaming launch for its r/w and flatten requests.  Up to `lanes` steps are
+ *   in flight on their own streams, so new requests join as earlier ones finish.
+ * GGA_SERVE_PER_REQUEST: the baseline: each request issued alone with the
+ *   single-array calls, in arrival order, on one stream, at most `depth` in flight.
+ *
+ * Admission.  The server tracks each array's size on the host (initial size plus
+ * admitted appends) and charges it elem_bytes * (2 size + V F) bytes, the bound on
+ * an array's capacity (Sec. IV); a flatten also holds its output bytes in the
+ * arena until it completes.  A request waits while the charges plus the arena
+ * bytes in use would exceed cap_bytes (or the arena has no room), and is
+ * rejected (status GGA_ENOMEM, nothing run) when it could not fit even with the
+ * arena empty.
+ *
+ * gga_server_create: arrays[0..n) distinct GGArrays of one element size, which
+ *   must outlive the server and not be used elsewhere during a run; arena is a
+ *   caller-owned device buffer of arena_bytes bytes (flatten outputs, allocated
+ *   as a ring, 256-byte aligned).  The server creates its own streams (default
+ *   priority) and pinned staging.
+ * gga_server_run: replays the n requests of the trace (host arrays; arrival_ns
+ *   non-decreasing, relative to the start of the run) in real time and returns
+ *   when all have completed.  It synchronises the device before starting.
+ *   Per request (host arrays of n entries): t_issue_ns, t_done_ns (host clock,
+ *   relative to the start; t_done is when the host saw the request's work
+ *   finish), status (GGA_OK or GGA_ENOMEM), out_offset (flatten: byte offset of
+ *   its output in the arena, else UINT64_MAX; the output stays valid until the
+ *   ring reuses that space).  dev_out_len (device, n entries, may be NULL)
+ *   receives each flatten's element count.  stats (host, 8 entries, may be NULL):
+ *   steps, largest step, requests issued, rejected, waits for memory, peak
+ *   charged bytes, elapsed ns, arena wraps.  Returns GGA_ERANGE if a flatten
+ *   found its array larger than its reservation (then that output is not
+ *   written), GGA_EHIP on a runtime error. */
+#define GGA_REQ_APPEND 0
+#define GGA_REQ_RW 1
+#define GGA_REQ_FLATTEN 2
+#define GGA_SERVE_BATCHED 0
+#define GGA_SERVE_PER_REQUEST 1
+
+typedef struct gga_server gga_server;
+typedef struct gga_server_config {
+    uint64_t cap_bytes;     /* admission budget, bytes */
+    uint32_t mode;          /* GGA_SERVE_* */
+    uint32_t lanes;         /* BATCHED: steps in flight, 1..8 */
+    uint32_t max_step;      /* BATCHED: requests per step, 1..65536 */
+    uint32_t depth;         /* PER_REQUEST: requests in flight, 1..65536 */
+    uint64_t seed;          /* append payload key, < 256 */
+    uint32_t append_round;  /* < 256 */
+    uint32_t append_shift;  /* 1..47; appends need length <= 2^shift, r < 2^(48 - shift) */
+    uint32_t rw_op;         /* GGA_ADD1 .. GGA_ADD1_X30 */
+} gga_server_config;
+
+typedef struct gga_trace {
+    uint64_t n;
+    const uint64_t *arrival_ns;
+    const uint8_t *kind;     /* GGA_REQ_* */
+    const uint32_t *target;  /* array index */
+    const uint32_t *length;  /* APPEND: threads, >= 1 */
+} gga_trace;
+
+int gga_server_create(gga_server **out, ggarray *const *arrays, uint32_t n, void *arena,
+                      uint64_t arena_bytes, const gga_server_config *cfg);
+int gga_server_destroy(gga_server *sv);
+int gga_server_run(gga_server *sv, const gga_trace *tr, uint64_t *t_issue_ns, uint64_t *t_done_ns,
+                   int32_t *status, uint64_t *out_offset, uint64_t *dev_out_len, uint64_t *stats);
 
 /* ------------------------------------------------- static array baseline --- */
 /* The pre-allocated flat array of Sec. III-A1: caller-owned device buffer of

@@ -25,7 +25,7 @@ _LIB = os.path.join(_HERE, "libggoracle.so")
 OK, EINVAL, ENOMEM, ERANGE = 0, -1, -2, -3
 FORM_LIST, FORM_BUCKETS = 1, 2
 OP_ADD1, OP_MUL3ADD1, OP_ADD1_X30 = 0, 1, 2
-GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON = 1, 2, 3
+GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON, GEN_KEYED = 1, 2, 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -57,7 +57,7 @@ def lib():
             "orc_destroy": (None, [vp]),
             "orc_insert": (i32, [vp, vp, vp, u64]),
             "orc_insert_counts": (i32, [vp, vp, vp, u32, u64]),
-            "orc_insert_gen": (i32, [vp, u32, u64, u32, u32, u32, vp, u64]),
+            "orc_insert_gen": (i32, [vp, u32, u64, u32, u32, u32, vp, u64, u64]),
             "orc_shrink": (i32, [vp, u32, u32]),
             "orc_rw": (i32, [vp, u32]),
             "orc_size": (u64, [vp]),
@@ -162,10 +162,13 @@ class Oracle:
                                           counts.size), "insert_counts")
 
     def insert_gen(self, kind: int, n_threads: int, seed: int = 0, round: int = 0,
-                   tag_shift: int = 0, max_count: int = 0, thresholds: np.ndarray | None = None):
+                   tag_shift: int | None = None, max_count: int = 0,
+                   thresholds: np.ndarray | None = None, tag: int = 0):
+        if tag_shift is None:
+            tag_shift = 32 if kind == GEN_KEYED else 0
         thr = None if thresholds is None else np.ascontiguousarray(thresholds, dtype=np.uint64)
         self._chk(lib().orc_insert_gen(self._h, kind, seed, round, tag_shift, max_count,
-                                       _ptr(thr), n_threads), "insert_gen")
+                                       _ptr(thr), n_threads, tag), "insert_gen")
 
     def shrink(self, num: int, den: int):
         self._chk(lib().orc_shrink(self._h, num, den), "shrink")

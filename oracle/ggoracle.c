@@ -66,6 +66,7 @@
 #define ORC_GEN_BERNOULLI 1
 #define ORC_GEN_ROUND_TAG 2
 #define ORC_GEN_POISSON 3
+#define ORC_GEN_KEYED 4
 
 typedef struct {
     uint64_t len, cap;
@@ -326,10 +327,12 @@ int orc_insert_counts(orc_array *a, const void *values, const uint8_t *counts, u
  *   BERNOULLI: h = K(seed, gid, round); insert h iff its top bit is set;
  *   ROUND_TAG: insert (round << tag_shift) | gid;
  *   POISSON:   u = K(seed, gid, 0x80 | round); c = #{k < max_count : u >= thr[k]};
- *              insert K(seed, gid, 16 * round + j) for j < c.
+ *              insert K(seed, gid, 16 * round + j) for j < c;
+ *   KEYED:     insert K(seed, (tag << tag_shift) | gid, round), with 1 <= tag_shift <= 47,
+ *              gid < 2^tag_shift and tag < 2^(48 - tag_shift), so the key stays below 2^48.
  * Values are truncated to the element width. */
 int orc_insert_gen(orc_array *a, uint32_t kind, uint64_t seed, uint32_t round, uint32_t tag_shift,
-                   uint32_t max_count, const uint64_t *thresholds, uint64_t n_threads)
+                   uint32_t max_count, const uint64_t *thresholds, uint64_t n_threads, uint64_t tag)
 {
     if (!a || seed >= 256)
         return ORC_EINVAL;
@@ -337,9 +340,12 @@ int orc_insert_gen(orc_array *a, uint32_t kind, uint64_t seed, uint32_t round, u
         return ORC_EINVAL;
     if (kind == ORC_GEN_ROUND_TAG && tag_shift >= 64)
         return ORC_EINVAL;
-    if (kind == ORC_GEN_BERNOULLI && round >= 256)
+    if ((kind == ORC_GEN_BERNOULLI || kind == ORC_GEN_KEYED) && round >= 256)
         return ORC_EINVAL;
-    if (kind < ORC_GEN_BERNOULLI || kind > ORC_GEN_POISSON)
+    if (kind == ORC_GEN_KEYED &&
+        (tag_shift < 1 || tag_shift > 47 || (tag >> (48 - tag_shift)) != 0 || n_threads > (1ull << tag_shift)))
+        return ORC_EINVAL;
+    if (kind < ORC_GEN_BERNOULLI || kind > ORC_GEN_KEYED)
         return ORC_EINVAL;
     if (n_threads == 0)
         return ORC_OK;
@@ -355,6 +361,8 @@ int orc_insert_gen(orc_array *a, uint32_t kind, uint64_t seed, uint32_t round, u
                     st = push(a, v, h);
             } else if (kind == ORC_GEN_ROUND_TAG) {
                 st = push(a, v, ((uint64_t)round << tag_shift) | gid);
+            } else if (kind == ORC_GEN_KEYED) {
+                st = push(a, v, orc_K(seed, (tag << tag_shift) | gid, round));
             } else {
                 uint64_t u = orc_K(seed, gid, 0x80u | round);
                 uint32_t c = 0;

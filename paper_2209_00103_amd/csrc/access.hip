@@ -41,8 +41,8 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
 }
 
 // Exclusive prefix sums of the LFVector sizes (element offsets, Sec. IV) and of
-// their tile counts, by one workgroup; entry V holds the totals.
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2) {
+// their tile counts, by one workgroup of kScanThreads; entry V holds the totals.
+__device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2) {
   __shared__ uint64_t wsum_e[kScanThreads / 64], wsum_t[kScanThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const uint32_t V = A.V;
@@ -84,16 +84,18 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t t
   }
 }
 
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2) {
+  scan_array(A, te_log2);
+}
+
 // Shrink (pop floor(s num / den) per LFVector) and bucket release: one wave per
 // LFVector, lane b looks after bucket b, so the releases of one LFVector run in
 // parallel and go to different pool shards.
 constexpr uint32_t kVecPerBlock = 4;  // 256 threads = 4 waves = 4 LFVectors
 
-__global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uint32_t den,
-                                                     uint32_t elem_log2) {
-  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+__device__ __forceinline__ void shrink_vector(const ArrRef& A, uint32_t v, uint32_t num, uint32_t den,
+                                              uint32_t elem_log2) {
   const uint32_t b = threadIdx.x & 63u;
-  if (v >= A.V) return;
   const uint64_t s = A.size[v];
   const uint64_t ns = s - ((s / den) * num + ((s % den) * num) / den);
   const uint32_t lo = nbuckets_for(A.log2F, ns);
@@ -107,6 +109,12 @@ __global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uin
     if (p) *slot = 0;
   }
   if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
+}
+
+__global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uint32_t den,
+                                                     uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  if (v < A.V) shrink_vector(A, v, num, den, elem_log2);
 }
 
 // Returns every bucket of the array to the pool (destroy).
@@ -195,21 +203,14 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
   }
 }
 
-// Persistent walk over the bucket-aligned tiles: workgroup w takes the w-th
-// contiguous share of the tiles, finds its first LFVector by binary search over
-// the tile prefix, then walks forward; the bucket pointer and the destination
-// offset are reloaded only when the walk enters a new bucket.
+// Walk over the bucket-aligned tiles [t0, t1) of one array: find the first
+// LFVector by binary search over the tile prefix, then walk forward; the bucket
+// pointer and the destination offset are reloaded only when the walk enters a
+// new bucket.
 template <typename T, bool kFlatten>
-__global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t op, T* out,
-                                                           uint64_t out_cap, uint32_t te_log2) {
+__device__ __forceinline__ void stream_range(const ArrRef& A, uint64_t t0, uint64_t t1, uint32_t op,
+                                             T* out, uint32_t te_log2) {
   const uint32_t V = A.V;
-  const uint64_t total = A.tprefix[V];
-  if (kFlatten && A.prefix[V] > out_cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(A.err, kErrRange);
-    return;
-  }
-  const uint64_t G = gridDim.x;
-  const uint64_t t0 = total * blockIdx.x / G, t1 = total * (blockIdx.x + 1) / G;
   if (t0 >= t1) return;
   uint32_t lo = 0, hi = V;  // tprefix[lo] <= t0 < tprefix[hi]
   while (hi - lo > 1) {
@@ -260,6 +261,19 @@ __global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t o
   }
 }
 
+// Persistent grid over one array: workgroup w takes the w-th contiguous share.
+template <typename T, bool kFlatten>
+__global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t op, T* out,
+                                                           uint64_t out_cap, uint32_t te_log2) {
+  const uint64_t total = A.tprefix[A.V];
+  if (kFlatten && A.prefix[A.V] > out_cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(A.err, kErrRange);
+    return;
+  }
+  const uint64_t G = gridDim.x;
+  stream_range<T, kFlatten>(A, total * blockIdx.x / G, total * (blockIdx.x + 1) / G, op, out, te_log2);
+}
+
 // Static / semi-static array r/w: the flat array cut into 16 KiB tiles, each
 // workgroup streaming a contiguous share of them (the same access pattern as the
 // GGArray r/w, without the bucket indirection).
@@ -279,7 +293,151 @@ __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const ui
   }
 }
 
+
+// ----------------------------------------------------------------- batches --
+// One workgroup per array of the batch: its own prefix sums.
+__global__ __launch_bounds__(kScanThreads) void batch_scan_kernel(const BatchArr* items, uint32_t te_log2) {
+  scan_array(items[blockIdx.x].A, te_log2);
+}
+
+// Exclusive prefix over the arrays of their tile counts and sizes (entry n holds
+// the totals), by one workgroup.
+template <class Item>
+__global__ __launch_bounds__(kScanThreads) void batch_top_kernel(const Item* items, uint32_t n,
+                                                                uint64_t* tile_begin, uint64_t* elem_begin) {
+  __shared__ uint64_t wsum_e[kScanThreads / 64], wsum_t[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t per = (n + kScanThreads - 1) / kScanThreads;
+  const uint32_t i0 = tid * per < n ? tid * per : n;
+  const uint32_t i1 = i0 + per < n ? i0 + per : n;
+  uint64_t e = 0, t = 0;
+  for (uint32_t i = i0; i < i1; ++i) {
+    e += items[i].A.prefix[items[i].A.V];
+    t += items[i].A.tprefix[items[i].A.V];
+  }
+  const uint64_t ie = wave_incl_scan64(e), it = wave_incl_scan64(t);
+  if (lane == 63) {
+    wsum_e[w] = ie;
+    wsum_t[w] = it;
+  }
+  __syncthreads();
+  uint64_t be = 0, bt = 0, te = 0, tt = 0;
+  for (uint32_t k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) {
+      be += wsum_e[k];
+      bt += wsum_t[k];
+    }
+    te += wsum_e[k];
+    tt += wsum_t[k];
+  }
+  uint64_t re = be + ie - e, rt = bt + it - t;
+  for (uint32_t i = i0; i < i1; ++i) {
+    elem_begin[i] = re;
+    tile_begin[i] = rt;
+    re += items[i].A.prefix[items[i].A.V];
+    rt += items[i].A.tprefix[items[i].A.V];
+  }
+  if (tid == 0) {
+    elem_begin[n] = te;
+    tile_begin[n] = tt;
+  }
+}
+
+// Shrink of every array of the batch: one wave per LFVector; the waves of array
+// i are [vbegin[i], vbegin[i+1]).
+__global__ __launch_bounds__(256) void batch_shrink_kernel(const BatchArr* items, const uint64_t* vbegin,
+                                                           uint32_t n, uint32_t num, uint32_t den) {
+  const uint64_t w = (uint64_t)blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  if (w >= vbegin[n]) return;
+  const uint32_t i = wave_search(vbegin, n, w);
+  shrink_vector(items[i].A, (uint32_t)(w - vbegin[i]), num, den, items[i].elem_log2);
+}
+
+// Persistent grid over the tiles of every array of the batch: workgroup w takes
+// the w-th contiguous share and walks it array by array.  Flatten writes array i
+// at out + elem_begin[i].
+template <typename T, bool kFlatten>
+__global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr* items, const uint64_t* tile_begin,
+                                                                 const uint64_t* elem_begin, uint32_t n,
+                                                                 uint32_t op, T* out, uint64_t cap,
+                                                                 uint32_t* err, uint32_t te_log2) {
+  const uint64_t total = tile_begin[n];
+  if (kFlatten && elem_begin[n] > cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) set_error(err, kErrRange);
+    return;
+  }
+  const uint64_t G = gridDim.x;
+  uint64_t g0 = total * blockIdx.x / G;
+  const uint64_t g1 = total * (blockIdx.x + 1) / G;
+  if (g0 >= g1) return;
+  uint32_t i = wave_search(tile_begin, n, g0);
+  while (g0 < g1 && i < n) {
+    const uint64_t b0 = tile_begin[i], b1 = tile_begin[i + 1];
+    const uint64_t hi = b1 < g1 ? b1 : g1;
+    if (hi > g0)
+      stream_range<T, kFlatten>(items[i].A, g0 - b0, hi - b0, op, kFlatten ? out + elem_begin[i] : nullptr, te_log2);
+    if (hi > g0) g0 = hi;
+    ++i;
+  }
+}
+
+// ---------------------------------------------------------- served steps --
+__global__ __launch_bounds__(kScanThreads) void serve_scan_kernel(const ServeItem* items, uint32_t te_log2) {
+  scan_array(items[blockIdx.x].A, te_log2);
+}
+
+// The r/w and flatten requests of one served step in one persistent grid: item i
+// is r/w'd in place, or flattened to its own destination (written only if its
+// reservation holds it).  Workgroup 0 also reports each
+// flatten's length.
+template <typename T>
+__global__ __launch_bounds__(kRwThreads) void serve_stream_kernel(const ServeItem* items, const uint64_t* tile_begin,
+                                                                 uint32_t n, uint32_t* err, uint32_t te_log2) {
+  if (blockIdx.x == 0)
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
+      if (items[i].len_out) items[i].len_out[0] = items[i].A.prefix[items[i].A.V];
+  const uint64_t total = tile_begin[n];
+  const uint64_t G = gridDim.x;
+  uint64_t g0 = total * blockIdx.x / G;
+  const uint64_t g1 = total * (blockIdx.x + 1) / G;
+  if (g0 >= g1) return;
+  uint32_t i = wave_search(tile_begin, n, g0);
+  while (g0 < g1 && i < n) {
+    const uint64_t b0 = tile_begin[i], b1 = tile_begin[i + 1];
+    const uint64_t hi = b1 < g1 ? b1 : g1;
+    if (hi > g0) {
+      const ServeItem& it = items[i];
+      if (it.op != kOpFlatten)
+        stream_range<T, false>(it.A, g0 - b0, hi - b0, it.op, nullptr, te_log2);
+      else if (it.A.prefix[it.A.V] <= it.cap)
+        stream_range<T, true>(it.A, g0 - b0, hi - b0, 0u, static_cast<T*>(it.out), te_log2);
+      else if (threadIdx.x == 0)
+        set_error(err, kErrRange);
+      g0 = hi;
+    }
+    ++i;
+  }
+}
+
 }  // namespace
+
+int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin, uint64_t* elem_begin,
+                        uint32_t* err, uint32_t elem_bytes, uint32_t grid, hipStream_t s) {
+  if (n == 0) return GGA_OK;
+  const uint32_t te_log2 = elem_bytes == 4 ? 12u : 11u;
+  if (grid < 1) grid = 1;
+  if (grid > kStreamBlocks) grid = kStreamBlocks;
+  hipLaunchKernelGGL(serve_scan_kernel, dim3(n), dim3(kScanThreads), 0, s, items, te_log2);
+  hipLaunchKernelGGL(batch_top_kernel<ServeItem>, dim3(1), dim3(kScanThreads), 0, s, items, n, tile_begin,
+                     elem_begin);
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL(serve_stream_kernel<uint32_t>, dim3(grid), dim3(kRwThreads), 0, s, items, tile_begin, n, err,
+                       te_log2);
+  else
+    hipLaunchKernelGGL(serve_stream_kernel<uint64_t>, dim3(grid), dim3(kRwThreads), 0, s, items, tile_begin, n, err,
+                       te_log2);
+  return hip_status(hipGetLastError());
+}
 
 int launch_scan(ggarray* a, hipStream_t s) {
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref,
@@ -338,6 +496,47 @@ int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
   else
     hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
                        static_cast<uint64_t*>(st->data), st->d_size, st->cap, op, 11u);
+  return hip_status(hipGetLastError());
+}
+
+
+int launch_batch_scan(gga_batch* b, hipStream_t s) {
+  const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
+  hipLaunchKernelGGL(batch_scan_kernel, dim3(b->n), dim3(kScanThreads), 0, s, b->d_arrays, te_log2);
+  hipLaunchKernelGGL(batch_top_kernel<BatchArr>, dim3(1), dim3(kScanThreads), 0, s, b->d_arrays, b->n,
+                     b->d_tile_begin, b->d_elem_begin);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = true;
+  return hip_status(e);
+}
+
+int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s) {
+  const uint64_t blocks = (b->total_vectors + kVecPerBlock - 1) / kVecPerBlock;
+  hipLaunchKernelGGL(batch_shrink_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, b->d_arrays, b->d_vbegin,
+                     b->n, num, den);
+  for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = false;
+  return hip_status(hipGetLastError());
+}
+
+int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s) {
+  const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
+  const dim3 grid(kStreamBlocks), block(kRwThreads);
+  if (b->elem_bytes == 4) {
+    if (flatten)
+      hipLaunchKernelGGL((batch_stream_kernel<uint32_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
+                         b->d_elem_begin, b->n, 0u, static_cast<uint32_t*>(out), cap, b->d_err, te_log2);
+    else
+      hipLaunchKernelGGL((batch_stream_kernel<uint32_t, false>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
+                         b->d_elem_begin, b->n, op, (uint32_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
+  } else {
+    if (flatten)
+      hipLaunchKernelGGL((batch_stream_kernel<uint64_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
+                         b->d_elem_begin, b->n, 0u, static_cast<uint64_t*>(out), cap, b->d_err, te_log2);
+    else
+      hipLaunchKernelGGL((batch_stream_kernel<uint64_t, false>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
+                         b->d_elem_begin, b->n, op, (uint64_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
+  }
   return hip_status(hipGetLastError());
 }
 

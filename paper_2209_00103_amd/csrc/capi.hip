@@ -37,7 +37,7 @@ struct ArrayExtra {
   uint64_t* d_scratch;
 };
 
-int check_gen(const gga_gen* g, uint32_t* mode, uint32_t* maxc) {
+int check_gen(const gga_gen* g, uint64_t n_threads, uint32_t* mode, uint32_t* maxc) {
   if (!g || g->seed >= 256) return GGA_EINVAL;
   switch (g->kind) {
     case GGA_GEN_BERNOULLI:
@@ -55,6 +55,13 @@ int check_gen(const gga_gen* g, uint32_t* mode, uint32_t* maxc) {
       *mode = kModePoisson;
       *maxc = g->max_count;
       return GGA_OK;
+    case GGA_GEN_KEYED:
+      if (g->round >= 256 || g->tag_shift < 1 || g->tag_shift > 47 || (g->tag >> (48 - g->tag_shift)) != 0 ||
+          n_threads > (1ull << g->tag_shift))
+        return GGA_EINVAL;
+      *mode = kModeKeyed;
+      *maxc = 1;
+      return GGA_OK;
     default:
       return GGA_EINVAL;
   }
@@ -69,6 +76,7 @@ InsertDesc gen_desc(const gga_gen* g, uint32_t mode, uint64_t n) {
   d.tag_shift = g->tag_shift;
   d.max_count = g->max_count;
   for (int k = 0; k < 16; ++k) d.thresholds[k] = g->thresholds[k];
+  d.tag = g->tag;
   return d;
 }
 
@@ -223,7 +231,6 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.log2F = a->log2F;
   R.salt = (uint32_t)((reinterpret_cast<uintptr_t>(a->meta) >> 8) * 2654435761u) & (kFreeShards - 1);
   a->status_cap = 0;
-  a->epoch = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
   p->n_arrays += 1;
   *out = a;
@@ -271,7 +278,7 @@ int ggarray_insert_counts(ggarray* a, const void* values, const uint8_t* counts,
 int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_stream s) {
   uint32_t mode = 0, maxc = 0;
   if (!a) return GGA_EINVAL;
-  const int rc = check_gen(g, &mode, &maxc);
+  const int rc = check_gen(g, n_threads, &mode, &maxc);
   if (rc) return rc;
   const InsertDesc d = gen_desc(g, mode, n_threads);
   return launch_insert(a, d, S(s));
@@ -337,6 +344,128 @@ int ggarray_prefix(ggarray* a, uint64_t* dev_out, gga_stream s) {
 int ggarray_last_error(ggarray* a, gga_stream s) {
   if (!a) return GGA_EINVAL;
   return read_back(a, nullptr, nullptr, S(s));
+}
+
+// ------------------------------------------------------------------- batches --
+static void batch_free(gga_batch* b) {
+  if (b->d_arrays) (void)hipFree(b->d_arrays);
+  if (b->d_tile_begin) (void)hipFree(b->d_tile_begin);
+  if (b->h_pin) (void)hipHostFree(b->h_pin);
+  for (uint32_t k = 0; k < b->n_tables; ++k) {
+    (void)hipFree(b->tables[k].items);
+    (void)hipFree(b->tables[k].begins);
+  }
+  delete[] b->tables;
+  delete[] b->arrays;
+  delete b;
+}
+
+int gga_batch_create(gga_batch** out, ggarray* const* arrays, uint32_t n, gga_stream s) {
+  if (!out) return GGA_EINVAL;
+  *out = nullptr;
+  if (!arrays || n == 0) return GGA_EINVAL;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!arrays[i] || arrays[i]->elem_bytes != arrays[0]->elem_bytes) return GGA_EINVAL;
+    for (uint32_t j = 0; j < i; ++j)
+      if (arrays[j] == arrays[i]) return GGA_EINVAL;
+  }
+  gga_batch* b = new (std::nothrow) gga_batch();
+  if (!b) return GGA_EHIP;
+  b->n = n;
+  b->elem_bytes = arrays[0]->elem_bytes;
+  b->arrays = new (std::nothrow) ggarray*[n];
+  BatchArr* h = new (std::nothrow) BatchArr[n];
+  if (!b->arrays || !h) {
+    delete[] h;
+    batch_free(b);
+    return GGA_EHIP;
+  }
+  for (uint32_t i = 0; i < n; ++i) {
+    b->arrays[i] = arrays[i];
+    h[i] = BatchArr{arrays[i]->ref, 0, 0, 0, 0, i, arrays[i]->elem_log2};
+  }
+  const size_t words = 3 * (size_t)(n + 1) + 1;  // tile_begin, elem_begin, vbegin, error word
+  bool ok = hipMalloc(&b->d_arrays, sizeof(BatchArr) * n) == hipSuccess &&
+            hipMalloc(&b->d_tile_begin, sizeof(uint64_t) * words) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_pin), 64, hipHostMallocDefault) == hipSuccess;
+  if (ok) {
+    b->d_elem_begin = b->d_tile_begin + (n + 1);
+    b->d_vbegin = b->d_elem_begin + (n + 1);
+    b->d_err = reinterpret_cast<uint32_t*>(b->d_vbegin + (n + 1));
+    uint64_t* vb = new (std::nothrow) uint64_t[n + 1];
+    ok = vb != nullptr;
+    if (ok) {
+      vb[0] = 0;
+      for (uint32_t i = 0; i < n; ++i) vb[i + 1] = vb[i] + arrays[i]->V;
+      b->total_vectors = vb[n];
+      ok = hipMemcpyAsync(b->d_arrays, h, sizeof(BatchArr) * n, hipMemcpyHostToDevice, S(s)) == hipSuccess &&
+           hipMemsetAsync(b->d_tile_begin, 0, sizeof(uint64_t) * words, S(s)) == hipSuccess &&
+           hipMemcpyAsync(b->d_vbegin, vb, sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, S(s)) == hipSuccess &&
+           hipStreamSynchronize(S(s)) == hipSuccess;
+      delete[] vb;
+    }
+  }
+  delete[] h;
+  if (!ok) {
+    batch_free(b);
+    return GGA_EHIP;
+  }
+  *out = b;
+  return GGA_OK;
+}
+
+int gga_batch_destroy(gga_batch* b, gga_stream s) {
+  if (!b) return GGA_EINVAL;
+  const int rc = hip_status(hipStreamSynchronize(S(s)));
+  batch_free(b);
+  return rc;
+}
+
+int gga_batch_insert_gen(gga_batch* b, const gga_gen* g, const uint64_t* n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!b || !n_threads) return GGA_EINVAL;
+  const int rc = check_gen(g, 0, &mode, &maxc);
+  if (rc) return rc;
+  if (g->kind == GGA_GEN_KEYED) {
+    if (((g->tag + b->n - 1) >> (48 - g->tag_shift)) != 0) return GGA_EINVAL;
+    for (uint32_t i = 0; i < b->n; ++i)
+      if (n_threads[i] > (1ull << g->tag_shift)) return GGA_EINVAL;
+  }
+  return launch_batch_insert(b, gen_desc(g, mode, 0), n_threads, S(s));
+}
+
+int gga_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, gga_stream s) {
+  if (!b || den == 0 || num > den) return GGA_EINVAL;
+  if (num == 0) return GGA_OK;
+  return launch_batch_shrink(b, num, den, S(s));
+}
+
+int gga_batch_rw(gga_batch* b, uint32_t op, gga_stream s) {
+  if (!b || op > GGA_ADD1_X30) return GGA_EINVAL;
+  int rc = launch_batch_scan(b, S(s));
+  return rc ? rc : launch_batch_stream(b, op, nullptr, 0, false, S(s));
+}
+
+int gga_batch_flatten(gga_batch* b, void* out, uint64_t out_cap_elems, gga_stream s) {
+  if (!b || (!out && out_cap_elems)) return GGA_EINVAL;
+  int rc = launch_batch_scan(b, S(s));
+  return rc ? rc : launch_batch_stream(b, 0, out, out_cap_elems, true, S(s));
+}
+
+int gga_batch_offsets(gga_batch* b, uint64_t* dev_out, gga_stream s) {
+  if (!b || !dev_out) return GGA_EINVAL;
+  int rc = launch_batch_scan(b, S(s));
+  if (rc) return rc;
+  return hip_status(hipMemcpyAsync(dev_out, b->d_elem_begin, sizeof(uint64_t) * (b->n + 1),
+                                   hipMemcpyDeviceToDevice, S(s)));
+}
+
+int gga_batch_last_error(gga_batch* b, gga_stream s) {
+  if (!b) return GGA_EINVAL;
+  if (hipMemcpyAsync(b->h_pin, b->d_err, 4, hipMemcpyDeviceToHost, S(s)) != hipSuccess ||
+      hipStreamSynchronize(S(s)) != hipSuccess)
+    return GGA_EHIP;
+  return map_device_error((uint32_t)b->h_pin[0]);
 }
 
 // -------------------------------------------------------------- static array --
@@ -405,7 +534,7 @@ int gga_static_insert(gga_static* st, const void* values, const uint8_t* flags, 
 int gga_static_insert_gen(gga_static* st, const gga_gen* g, uint64_t n_threads, gga_stream s) {
   uint32_t mode = 0, maxc = 0;
   if (!st) return GGA_EINVAL;
-  const int rc = check_gen(g, &mode, &maxc);
+  const int rc = check_gen(g, n_threads, &mode, &maxc);
   if (rc) return rc;
   return launch_static_insert(st, gen_desc(g, mode, n_threads), S(s));
 }
@@ -494,7 +623,7 @@ int gga_semi_insert(gga_semistatic* ss, const void* values, const uint8_t* flags
 int gga_semi_insert_gen(gga_semistatic* ss, const gga_gen* g, uint64_t n_threads, gga_stream s) {
   uint32_t mode = 0, maxc = 0;
   if (!ss) return GGA_EINVAL;
-  int rc = check_gen(g, &mode, &maxc);
+  int rc = check_gen(g, n_threads, &mode, &maxc);
   if (rc) return rc;
   rc = semi_reserve(ss, n_threads * maxc, S(s));
   return rc ? rc : launch_static_insert(&ss->st, gen_desc(g, mode, n_threads), S(s));

@@ -22,7 +22,6 @@ struct ggarray {
   void* meta;             // one device allocation holding the per-array metadata
   gga::ArrRef ref;
   uint64_t status_cap;    // look-back words available
-  uint64_t epoch;         // look-back epoch of the last insertion launch
   bool prefix_valid;      // prefix / tprefix match the current sizes
 };
 
@@ -35,12 +34,81 @@ struct gga_static {
   uint32_t* d_err;
 };
 
+namespace gga {
+struct BatchArr;
+}
+
+// A set of arrays driven together (one launch per phase for all of them).
+struct gga_batch {
+  ggarray** arrays;
+  uint32_t n;
+  uint32_t elem_bytes;
+  gga::BatchArr* d_arrays;   // device: the arrays' descriptors (rw, flatten, scans)
+  uint64_t* d_tile_begin;    // device: n + 1 exclusive prefix of the arrays' tiles
+  uint64_t* d_elem_begin;    // device: n + 1 exclusive prefix of the arrays' sizes
+  uint32_t* d_err;           // device: sticky batch error (flatten output too small)
+  uint64_t* d_vbegin;        // device: n + 1 exclusive prefix of the arrays' LFVector counts
+  uint64_t total_vectors;
+  uint64_t* h_pin;           // pinned host scratch
+  // Round tables uploaded so far (descriptors + block offsets), reused when the
+  // same round shape comes again, so a captured graph always reads a stable table.
+  struct Table {
+    uint64_t key;
+    uint64_t blocks;
+    gga::BatchArr* items;
+    uint64_t* begins;
+  };
+  Table* tables;
+  uint32_t n_tables;
+  uint32_t cap_tables;
+};
+
 struct gga_semistatic {
   gga_static st;      // current buffer, resized by the host
   uint64_t resizes;
 };
 
 namespace gga {
+
+// One array of a batch as the batch kernels see it, with its share of the
+// current insertion round.
+struct BatchArr {
+  ArrRef A;
+  uint64_t n_threads;  // logical threads of this array in the round
+  uint64_t chunk;      // ceil(n_threads / V)
+  uint64_t tpv;        // tiles per LFVector
+  uint64_t tag;        // key of this array's generated payloads (keyed rounds)
+  uint32_t index;      // position in the batch
+  uint32_t elem_log2;
+};
+
+// Largest i in [0, n) with begins[i] <= x, where begins is non-decreasing and
+// begins[0] <= x: a 64-way search by one wave (each round one load per lane).
+__device__ __forceinline__ uint32_t wave_search(const uint64_t* begins, uint32_t n, uint64_t x) {
+  const uint32_t lane = threadIdx.x & 63u;
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t idx = lo + lane * step;
+    const bool ok = idx < hi && begins[idx] <= x;
+    const uint64_t m = __ballot(ok);
+    const uint32_t last = 63u - (uint32_t)__clzll(m);
+    lo = lo + last * step;
+    hi = lo + step < hi ? lo + step : hi;
+  }
+  return lo;
+}
+
+// One r/w or flatten request of a served step, on an array of its own.
+constexpr uint32_t kOpFlatten = 0xFFFFFFFFu;
+struct ServeItem {
+  ArrRef A;
+  void* out;          // flatten destination
+  uint64_t cap;       // elements reserved at out
+  uint64_t* len_out;  // device word that receives the flattened length (may be null)
+  uint32_t op;        // r/w operation, or kOpFlatten
+  uint32_t elem_log2;
+};
 
 // How an insertion round produces its candidates.
 enum InsertMode : uint32_t {
@@ -49,6 +117,7 @@ enum InsertMode : uint32_t {
   kModeBernoulli = 2,
   kModeRoundTag = 3,
   kModePoisson = 4,
+  kModeKeyed = 5,    // every thread inserts K(seed, (tag << tag_shift) | gid, round)
 };
 
 struct InsertDesc {
@@ -61,6 +130,7 @@ struct InsertDesc {
   uint32_t round;
   uint32_t tag_shift;
   uint64_t thresholds[16];
+  uint64_t tag;
 };
 
 // Tile geometry of the element-streaming kernels (rw, flatten): 16 KiB per tile.
@@ -78,6 +148,19 @@ int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s);
 int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s);
 int launch_free_all(ggarray* a, hipStream_t s);
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s);
+int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_threads, hipStream_t s);
+int launch_batch_scan(gga_batch* b, hipStream_t s);
+int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s);
+int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s);
+
+// Served steps.  prepare_round_item fills the descriptor of one insertion round of
+// n threads on a (growing its look-back words on stream s) and returns its tiles.
+int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,
+                       hipStream_t s);
+int launch_keyed_items(const BatchArr* items, const uint64_t* begins, uint32_t n, uint64_t blocks,
+                       uint32_t elem_bytes, uint64_t seed, uint32_t round, uint32_t shift, hipStream_t s);
+int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin, uint64_t* elem_begin,
+                        uint32_t* err, uint32_t elem_bytes, uint32_t grid, hipStream_t s);
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? GGA_OK : GGA_EHIP; }
 

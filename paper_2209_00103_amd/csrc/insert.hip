@@ -23,6 +23,8 @@
 //      the LFVector;
 //   6. the block scatters the staged elements to their buckets, coalesced.
 // The static baseline replaces 3-5 by one global atomicAdd per tile.
+#include <new>
+
 #include "gga_internal.h"
 
 namespace gga {
@@ -38,15 +40,20 @@ constexpr int kStage = 4096;             // LDS staging capacity, elements
 static_assert(kFlagK * kW == 64, "one wave scans the per-(slot, wave) totals");
 static_assert(kFlagTile <= kStage, "a 0/1 tile stages in one pass");
 
+// Look-back status word: epoch (30 bits) | flag (2 bits) | value (32 bits).  The
+// value is a count or an inclusive prefix relative to the LFVector's size at the
+// start of the round (the host rejects rounds that could add 2^32 or more
+// elements to one LFVector).  The epoch is the launch number carried by the
+// LFVector's ticket word, so words left by earlier launches never match.
 constexpr uint64_t kStA = 1;  // status flag: tile count published
 constexpr uint64_t kStP = 2;  // status flag: inclusive prefix published
-constexpr uint64_t kValMask = (1ull << 38) - 1;
+constexpr uint64_t kValMask = 0xFFFFFFFFull;
+constexpr uint64_t kEpochMask = (1ull << 30) - 1;
 
 struct TileArgs {
   uint64_t n_threads;
   uint64_t chunk;        // logical threads per LFVector, ceil(n / V)
   uint64_t tpv;          // tiles per LFVector
-  uint64_t epoch;        // 24-bit launch tag of the status words
   uint32_t elem_log2;
 };
 
@@ -69,7 +76,11 @@ struct TileShared {
 };
 
 __device__ __forceinline__ uint64_t pack_status(uint64_t epoch, uint64_t flag, uint64_t value) {
-  return (epoch << 40) | (flag << 38) | (value & kValMask);
+  return ((epoch & kEpochMask) << 34) | (flag << 32) | (value & kValMask);
+}
+__device__ __forceinline__ uint64_t status_flag(uint64_t w) { return (w >> 32) & 3u; }
+__device__ __forceinline__ bool status_current(uint64_t w, uint64_t epoch) {
+  return (w >> 34) == (epoch & kEpochMask) && status_flag(w) != 0;
 }
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -107,6 +118,7 @@ struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
   uint32_t round;
   __device__ __forceinline__ bool flag(uint64_t g) const { return (K(seed, g, round) >> 63) != 0; }
   __device__ __forceinline__ T value(uint64_t g) const { return (T)K(seed, g, round); }
+  __device__ __forceinline__ void bind(const BatchArr&) {}
 };
 template <typename T>
 struct ProdRoundTag {  // insert (round << shift) | gid
@@ -115,6 +127,18 @@ struct ProdRoundTag {  // insert (round << shift) | gid
   uint32_t shift;
   __device__ __forceinline__ bool flag(uint64_t) const { return true; }
   __device__ __forceinline__ T value(uint64_t g) const { return (T)(((uint64_t)round << shift) | g); }
+  __device__ __forceinline__ void bind(const BatchArr&) {}
+};
+template <typename T>
+struct ProdKeyed {  // every thread inserts K(seed, (tag << shift) | gid, round)
+  static constexpr bool kMulti = false;
+  uint64_t seed;
+  uint32_t round;
+  uint32_t shift;
+  uint64_t tag;
+  __device__ __forceinline__ bool flag(uint64_t) const { return true; }
+  __device__ __forceinline__ T value(uint64_t g) const { return (T)K(seed, (tag << shift) | g, round); }
+  __device__ __forceinline__ void bind(const BatchArr& it) { tag = it.tag; }  // each array its own key
 };
 template <typename T>
 struct ProdCounts {  // insert values[gid * max + j], j < counts[gid]
@@ -168,7 +192,7 @@ __device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint
     if (in) {
       for (uint32_t spins = 0;; ++spins) {
         w = ld_rlx(&status[mine]);
-        if ((w >> 40) == epoch && ((w >> 38) & 3u) != 0) break;
+        if (status_current(w, epoch)) break;
         if (spins >= kSpinLimit) {
           ok = false;
           break;
@@ -177,7 +201,7 @@ __device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint
       }
     }
     if (__ballot(!ok)) return false;
-    const uint64_t pmask = __ballot(in && ((w >> 38) & 3u) == kStP);
+    const uint64_t pmask = __ballot(in && status_flag(w) == kStP);
     if (pmask) {
       const uint32_t first = (uint32_t)__ffsll((unsigned long long)pmask) - 1u;
       sum += wave_sum64((in && lane <= first) ? (w & kValMask) : 0ull);
@@ -205,7 +229,8 @@ struct WaveRes {
 // only the last tile of the LFVector writes the size, after every other tile of
 // the round has published, so an early read is current).
 __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
-                                uint64_t tile, bool is_last, uint32_t n_t, uint64_t size0) {
+                                uint64_t tile, bool is_last, uint32_t n_t, uint64_t size0,
+                                uint64_t epoch) {
   WaveRes r{0, kFailedPtr, 0, 0, 0};
   const uint32_t lane = lane_id();
   const uint32_t log2F = A.log2F;
@@ -213,13 +238,15 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
   uint64_t base = 0;
   bool stalled = false;
   if (t == 0) {
-    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStP, old_size + n_t));
+    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(epoch, kStP, n_t));
     base = old_size;
   } else {
-    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(I.epoch, kStA, n_t));
-    stalled = !lookback(A.status, tile, t, I.epoch, base);
+    uint64_t rel = 0;
+    if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(epoch, kStA, n_t));
+    stalled = !lookback(A.status, tile, t, epoch, rel);
     if (lane == 0 && !is_last && !stalled)
-      st_rlx(&A.status[tile], pack_status(I.epoch, kStP, base + n_t));
+      st_rlx(&A.status[tile], pack_status(epoch, kStP, rel + n_t));
+    base = old_size + rel;
   }
   if (stalled) {
     // Predecessors never published: leave the LFVector as it was and freeze it.
@@ -275,7 +302,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
   }
 
   if (is_last && lane == 0) {
-    const uint64_t old = (t == 0) ? old_size : ld_rlx(&A.size[v]);
+    const uint64_t old = old_size;
     const uint64_t nsize = base + n_t;
     const uint32_t others = nbuckets_for(log2F, nsize) - nbuckets_for(log2F, old) - n_alloc;
     uint32_t failed = n_fail;
@@ -307,11 +334,12 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
 
 // Block kernels: wave 0 resolves and leaves the result in LDS.
 __device__ __forceinline__ void resolve_tile(const ArrRef& A, const TileArgs& I, uint32_t v, uint64_t t,
-                                             uint64_t tile, bool is_last, uint32_t n_t, TileShared& sh) {
+                                             uint64_t tile, bool is_last, uint32_t n_t, uint64_t epoch,
+                                             TileShared& sh) {
   const uint32_t lane = lane_id();
   uint64_t size0 = 0;
-  if (t == 0 && lane == 0) size0 = ld_rlx(&A.size[v]);
-  const WaveRes r = resolve_wave(A, I, v, t, tile, is_last, n_t, __shfl(size0, 0, 64));
+  if (lane == 0) size0 = ld_rlx(&A.size[v]);
+  const WaveRes r = resolve_wave(A, I, v, t, tile, is_last, n_t, __shfl(size0, 0, 64), epoch);
   if (lane < r.nb) sh.bp[lane] = r.bp;
   if (lane == 0) {
     sh.base = r.base;
@@ -383,14 +411,17 @@ __device__ __forceinline__ void scatter_static(const StaticRef& S, const TileSha
   scatter_run<T>(reinterpret_cast<T*>(S.data) + sh.base + p0, stage, lim);
 }
 
-// Takes this block's ticket of LFVector v (thread 0 only; the result is waited
-// for later).  The LFVector's tpv blocks each take one; the last taker resets
-// the counter for the next launch.
+// Takes this block's ticket of LFVector v (one lane; the result is waited for
+// later).  The ticket word is epoch << 32 | count.  The LFVector's tpv blocks
+// each take one; the last taker resets the count and advances the epoch, so the
+// next launch's tiles tag their status words differently.  Every launch with
+// several tiles per LFVector advances every LFVector's epoch once, so all
+// LFVectors of an array share one epoch sequence.
 __device__ __forceinline__ uint64_t take_ticket(const ArrRef& A, uint32_t v) {
   return fetch_add(&A.vticket[v], 1);
 }
 __device__ __forceinline__ void settle_ticket(const ArrRef& A, uint32_t v, uint64_t k, uint64_t tpv) {
-  if (k == tpv - 1) st_rlx(&A.vticket[v], 0);
+  if ((k & 0xFFFFFFFFull) == tpv - 1) st_rlx(&A.vticket[v], ((k >> 32) + 1) << 32);
 }
 
 // Logical-thread range of tile t of LFVector v.
@@ -434,12 +465,15 @@ __device__ __forceinline__ uint64_t wave_flags(const Prod& prod, uint64_t g0, ui
   return bits;
 }
 
+// One wave, one tile; `block` is the wave's index among the launch's waves for
+// this array (the block index, or its offset inside a batch launch).
 template <typename T, class Prod, bool kStatic>
-__global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, TileArgs I, Prod prod) {
+__device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, const TileArgs& I,
+                                          const Prod& prod, uint64_t block) {
   const uint32_t lane = lane_id();
   const bool ticketed = !kStatic && I.tpv > 1;
-  const uint32_t v = kStatic ? 0u : (uint32_t)(blockIdx.x / I.tpv);
-  uint64_t t = kStatic ? blockIdx.x : blockIdx.x - (uint64_t)v * I.tpv;
+  const uint32_t v = kStatic ? 0u : (uint32_t)(block / I.tpv);
+  uint64_t t = kStatic ? block : block - (uint64_t)v * I.tpv;
   uint64_t k = 0, size0 = 0;
   if (ticketed && lane == 0) k = take_ticket(A, v);
   if (!kStatic && lane == 0) size0 = ld_rlx(&A.size[v]);  // needed if this is tile 0
@@ -451,9 +485,12 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
     tile_range(I, v, t, kWaveTile, g0, gend);
   }
   uint64_t bits = wave_flags<Prod>(prod, g0, gend);
+  uint64_t epoch = 0;
   if (ticketed) {
     if (lane == 0) settle_ticket(A, v, k, I.tpv);
     k = __shfl(k, 0, 64);
+    epoch = k >> 32;
+    k &= 0xFFFFFFFFull;
     if (k != t) {  // dispatched out of order: redo the first pass for the ticket
       t = k;
       tile_range(I, v, t, kWaveTile, g0, gend);
@@ -477,7 +514,7 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
     if (lane == 0 && lim < n_t) set_error(S.err, kErrRange);
     dst = reinterpret_cast<T*>(S.data) + base;
   } else {
-    r = resolve_wave(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, __shfl(size0, 0, 64));
+    r = resolve_wave(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, __shfl(size0, 0, 64), epoch);
     if (r.n_out == 0) return;
     const uint64_t p0 = __shfl(r.bp, 0, 64);
     dst = reinterpret_cast<T*>(p0) + (r.base - bucket_start(log2F, r.b_lo));
@@ -505,6 +542,30 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
     if (f && p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
     run += (uint32_t)__popcll(m);
   }
+}
+
+template <typename T, class Prod, bool kStatic>
+__global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, TileArgs I, Prod prod) {
+  wave_tile<T, Prod, kStatic>(A, S, I, prod, blockIdx.x);
+}
+
+// Batch launch: one insertion round of many arrays.  The waves of array i are
+// the blocks [begins[i], begins[i+1]); each wave finds its array with a 64-way
+// search and then runs exactly as in a single-array launch.
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void batch_insert_kernel(const BatchArr* items, const uint64_t* begins,
+                                                          uint32_t n, Prod prod) {
+  const uint64_t blk = blockIdx.x;
+  const uint32_t i = wave_search(begins, n, blk);
+  const BatchArr it = items[i];
+  TileArgs I;
+  I.n_threads = it.n_threads;
+  I.chunk = it.chunk;
+  I.tpv = it.tpv;
+  I.elem_log2 = it.elem_log2;
+  Prod p = prod;
+  p.bind(it);
+  wave_tile<T, Prod, false>(it.A, StaticRef{}, I, p, blk - begins[i]);
 }
 
 // --------------------------------------------- multi-element producer kernel --
@@ -549,8 +610,9 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
     settle_ticket(A, v, k, I.tpv);
   }
   __syncthreads();
-  if (ticketed && sh.tile != t) {  // dispatched out of order: produce for the ticket
-    t = sh.tile;
+  const uint64_t epoch = ticketed ? sh.tile >> 32 : 0;
+  if (ticketed && (sh.tile & 0xFFFFFFFFull) != t) {  // dispatched out of order: produce for the ticket
+    t = sh.tile & 0xFFFFFFFFull;
     tile_range(I, v, t, kCountTile, g0, gend);
     gt = g0 + (uint64_t)tid * kCountK;
     c = produce_counts<Prod>(prod, gt, gend, cnt);
@@ -573,7 +635,7 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
   if (kStatic) {
     resolve_static(S, n_t, sh);
   } else if (w == 0) {
-    resolve_tile(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, sh);
+    resolve_tile(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, epoch, sh);
   }
   __syncthreads();
   const uint32_t n_out = kStatic ? n_t : sh.n_tile;  // 0 if the tile stalled
@@ -622,6 +684,11 @@ int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const Inser
       hipLaunchKernelGGL((insert_wave_kernel<T, ProdRoundTag<T>, kStatic>), grid, dim3(64), 0, s, A, S, I, p);
       break;
     }
+    case kModeKeyed: {
+      ProdKeyed<T> p{d.seed, d.round, d.tag_shift, d.tag};
+      hipLaunchKernelGGL((insert_wave_kernel<T, ProdKeyed<T>, kStatic>), grid, dim3(64), 0, s, A, S, I, p);
+      break;
+    }
     case kModeCounts: {
       ProdCounts<T> p{static_cast<const T*>(d.values), d.flags, d.max_count};
       hipLaunchKernelGGL((insert_count_kernel<T, ProdCounts<T>, kStatic>), grid, block, 0, s, A, S, I, p);
@@ -644,6 +711,27 @@ int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const Inser
 
 bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePoisson; }
 
+// Look-back words (needed only when an LFVector spans several tiles): grown on
+// demand and zeroed when new (a zero word is never current).  Their epochs come
+// from the ticket words, so launches need no host-side state and a captured
+// graph can be replayed (capture after one eager launch of the same shape, so
+// that no allocation happens during capture).
+int ensure_status(ggarray* a, uint64_t ntiles, hipStream_t s) {
+  if (ntiles <= a->status_cap) return GGA_OK;
+  uint64_t cap = a->status_cap ? a->status_cap : 4096;
+  while (cap < ntiles) cap *= 2;
+  if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
+  a->ref.status = nullptr;
+  a->status_cap = 0;
+  void* p = nullptr;
+  if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+  if (hipMemsetAsync(p, 0, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+  a->ref.status = static_cast<uint64_t*>(p);
+  a->status_cap = cap;
+  return GGA_OK;
+}
+
+
 }  // namespace
 
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
@@ -653,36 +741,19 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   const uint64_t tpv = (chunk + tile - 1) / tile;
   const uint64_t ntiles = tpv * a->V;
   if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
+  // One round may add fewer than 2^32 elements to an LFVector (status words hold
+  // round-relative 32-bit values).
+  if (chunk * (multi_mode(d.mode) ? d.max_count : 1u) >= (1ull << 32)) return GGA_EINVAL;
 
-  // Look-back words (needed only when an LFVector spans several tiles): grown on
-  // demand; cleared when new or when the 24-bit epoch wraps.
   if (tpv > 1) {
-    if (ntiles > a->status_cap) {
-      uint64_t cap = a->status_cap ? a->status_cap : 4096;
-      while (cap < ntiles) cap *= 2;
-      if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
-      a->ref.status = nullptr;
-      a->status_cap = 0;
-      void* p = nullptr;
-      if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
-      if (hipMemsetAsync(p, 0, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
-      a->ref.status = static_cast<uint64_t*>(p);
-      a->status_cap = cap;
-      a->epoch = 0;
-    }
-    a->epoch += 1;
-    if (a->epoch >= (1ull << 24)) {
-      if (hipMemsetAsync(a->ref.status, 0, a->status_cap * sizeof(uint64_t), s) != hipSuccess)
-        return GGA_EHIP;
-      a->epoch = 1;
-    }
+    const int rc = ensure_status(a, ntiles, s);
+    if (rc) return rc;
   }
 
   TileArgs I;
   I.n_threads = d.n_threads;
   I.chunk = chunk;
   I.tpv = tpv;
-  I.epoch = a->epoch;
   I.elem_log2 = a->elem_log2;
   StaticRef S{};
   const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
@@ -706,6 +777,116 @@ int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
   const int rc = st->elem_bytes == 4 ? dispatch<uint32_t, true>(A, S, I, d, ntiles, s)
                                      : dispatch<uint64_t, true>(A, S, I, d, ntiles, s);
   return rc;
+}
+
+
+namespace {
+uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001B3ull;
+  return h;
+}
+}  // namespace
+
+int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,
+                       hipStream_t s) {
+  const uint64_t chunk = n ? (n + a->V - 1) / a->V : 0;
+  const uint64_t tpv = n ? (chunk + kFlagTile - 1) / kFlagTile : 0;
+  *ntiles = tpv * a->V;
+  if (chunk >= (1ull << 32)) return GGA_EINVAL;
+  if (tpv > 1) {
+    const int rc = ensure_status(a, *ntiles, s);
+    if (rc) return rc;
+  }
+  *item = BatchArr{a->ref, n, chunk, tpv, tag, index, a->elem_log2};
+  return GGA_OK;
+}
+
+int launch_keyed_items(const BatchArr* items, const uint64_t* begins, uint32_t n, uint64_t blocks,
+                       uint32_t elem_bytes, uint64_t seed, uint32_t round, uint32_t shift, hipStream_t s) {
+  if (!blocks) return GGA_OK;
+  if (blocks > 0x7FFFFFFFull) return GGA_EINVAL;
+  const dim3 grid((uint32_t)blocks), block(64);
+  if (elem_bytes == 4)
+    hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdKeyed<uint32_t>>), grid, block, 0, s, items, begins, n,
+                       ProdKeyed<uint32_t>{seed, round, shift, 0});
+  else
+    hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdKeyed<uint64_t>>), grid, block, 0, s, items, begins, n,
+                       ProdKeyed<uint64_t>{seed, round, shift, 0});
+  return hip_status(hipGetLastError());
+}
+
+int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_threads, hipStream_t s) {
+  if (d.mode != kModeRoundTag && d.mode != kModeBernoulli && d.mode != kModeKeyed) return GGA_EINVAL;
+  BatchArr* items = new (std::nothrow) BatchArr[b->n];
+  uint64_t* begins = new (std::nothrow) uint64_t[b->n + 1];
+  if (!items || !begins) {
+    delete[] items;
+    delete[] begins;
+    return GGA_EHIP;
+  }
+  int rc = GGA_OK;
+  uint64_t blocks = 0;
+  for (uint32_t i = 0; i < b->n && rc == GGA_OK; ++i) {
+    uint64_t ntiles = 0;
+    rc = prepare_round_item(b->arrays[i], n_threads[i], d.tag + i, i, &items[i], &ntiles, s);
+    if (rc == GGA_OK && blocks + ntiles > 0x7FFFFFFFull) rc = GGA_EINVAL;
+    begins[i] = blocks;
+    blocks += ntiles;
+  }
+  begins[b->n] = blocks;
+  gga_batch::Table* tab = nullptr;
+  if (rc == GGA_OK && blocks) {
+    const uint64_t key = fnv1a(begins, sizeof(uint64_t) * (b->n + 1),
+                               fnv1a(items, sizeof(BatchArr) * b->n, 0xCBF29CE484222325ull));
+    for (uint32_t k = 0; k < b->n_tables; ++k)
+      if (b->tables[k].key == key) tab = &b->tables[k];
+    if (!tab) {  // first time this round shape is seen: upload its table
+      if (b->n_tables == b->cap_tables) {
+        const uint32_t ncap = b->cap_tables ? 2 * b->cap_tables : 8;
+        gga_batch::Table* nt = new (std::nothrow) gga_batch::Table[ncap];
+        if (!nt) rc = GGA_EHIP;
+        else {
+          for (uint32_t k = 0; k < b->n_tables; ++k) nt[k] = b->tables[k];
+          delete[] b->tables;
+          b->tables = nt;
+          b->cap_tables = ncap;
+        }
+      }
+      if (rc == GGA_OK) {
+        gga_batch::Table t{key, blocks, nullptr, nullptr};
+        if (hipMalloc(&t.items, sizeof(BatchArr) * b->n) != hipSuccess ||
+            hipMalloc(&t.begins, sizeof(uint64_t) * (b->n + 1)) != hipSuccess ||
+            hipMemcpyAsync(t.items, items, sizeof(BatchArr) * b->n, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(t.begins, begins, sizeof(uint64_t) * (b->n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+          rc = GGA_EHIP;
+        } else {
+          b->tables[b->n_tables++] = t;
+          tab = &b->tables[b->n_tables - 1];
+        }
+      }
+    }
+  }
+  delete[] items;
+  delete[] begins;
+  if (rc != GGA_OK || !blocks) return rc;
+  const dim3 grid((uint32_t)blocks), block(64);
+  const bool u32 = b->elem_bytes == 4;
+  if (d.mode == kModeRoundTag) {
+    if (u32) hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdRoundTag<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint32_t>{d.round, d.tag_shift});
+    else hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdRoundTag<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint64_t>{d.round, d.tag_shift});
+  } else if (d.mode == kModeBernoulli) {
+    if (u32) hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdBernoulli<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdBernoulli<uint32_t>{d.seed, d.round});
+    else hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdBernoulli<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdBernoulli<uint64_t>{d.seed, d.round});
+  } else {
+    if (u32) hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdKeyed<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdKeyed<uint32_t>{d.seed, d.round, d.tag_shift, 0});
+    else hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdKeyed<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdKeyed<uint64_t>{d.seed, d.round, d.tag_shift, 0});
+  }
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess)
+    for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = false;
+  return hip_status(e);
 }
 
 }  // namespace gga

@@ -21,7 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libggarray.so")
 
 OK, EINVAL, ENOMEM, ERANGE, EHIP, EBUSY = 0, -1, -2, -3, -4, -5
 ADD1, MUL3ADD1, ADD1_X30 = 0, 1, 2
-GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON = 1, 2, 3
+GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON, GEN_KEYED = 1, 2, 3, 4
+REQ_APPEND, REQ_RW, REQ_FLATTEN = 0, 1, 2
+SERVE_BATCHED, SERVE_PER_REQUEST = 0, 1
 
 _u32, _u64, _i32, _vp = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p
 _P = ctypes.POINTER
@@ -29,7 +31,17 @@ _P = ctypes.POINTER
 
 class GenSpec(ctypes.Structure):
     _fields_ = [("kind", _u32), ("round", _u32), ("seed", _u64), ("tag_shift", _u32),
-                ("max_count", _u32), ("thresholds", _u64 * 16)]
+                ("max_count", _u32), ("thresholds", _u64 * 16), ("tag", _u64)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("cap_bytes", _u64), ("mode", _u32), ("lanes", _u32), ("max_step", _u32),
+                ("depth", _u32), ("seed", _u64), ("append_round", _u32), ("append_shift", _u32),
+                ("rw_op", _u32)]
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("n", _u64), ("arrival_ns", _vp), ("kind", _vp), ("target", _vp), ("length", _vp)]
 
 
 # name -> argtypes (every entry point returns int status unless listed in _RES)
@@ -60,6 +72,14 @@ _SIGS = {
     "gga_static_size": [_vp, _P(_u64), _vp],
     "gga_static_last_error": [_vp, _vp],
     "gga_static_clear": [_vp, _vp],
+    "gga_batch_create": [_P(_vp), _vp, _u32, _vp],
+    "gga_batch_destroy": [_vp, _vp],
+    "gga_batch_insert_gen": [_vp, _P(GenSpec), _vp, _vp],
+    "gga_batch_shrink": [_vp, _u32, _u32, _vp],
+    "gga_batch_rw": [_vp, _u32, _vp],
+    "gga_batch_flatten": [_vp, _vp, _u64, _vp],
+    "gga_batch_offsets": [_vp, _vp, _vp],
+    "gga_batch_last_error": [_vp, _vp],
     "gga_semi_create": [_P(_vp), _u32, _u64, _vp],
     "gga_semi_destroy": [_vp, _vp],
     "gga_semi_insert": [_vp, _vp, _vp, _u64, _vp],
@@ -68,6 +88,9 @@ _SIGS = {
     "gga_semi_size": [_vp, _P(_u64), _vp],
     "gga_semi_data": [_vp, _P(_vp), _P(_u64)],
     "gga_semi_resizes": [_vp, _P(_u64)],
+    "gga_server_create": [_P(_vp), _vp, _u32, _vp, _u64, _P(ServerConfig)],
+    "gga_server_destroy": [_vp],
+    "gga_server_run": [_vp, _P(Trace), _vp, _vp, _vp, _vp, _vp, _vp],
 }
 _RES = {"gga_strerror": ctypes.c_char_p}
 
@@ -136,10 +159,12 @@ def as_unsigned(t: torch.Tensor) -> np.ndarray:
     return a.view(np.uint32 if a.dtype == np.int32 else np.uint64)
 
 
-def make_gen(kind: int, seed: int = 0, round: int = 0, tag_shift: int = 0, max_count: int = 0,
-             thresholds=None) -> GenSpec:
+def make_gen(kind: int, seed: int = 0, round: int = 0, tag_shift: int | None = None, max_count: int = 0,
+             thresholds=None, tag: int = 0) -> GenSpec:
+    if tag_shift is None:
+        tag_shift = 32 if kind == GEN_KEYED else 0
     g = GenSpec()
-    g.kind, g.round, g.seed, g.tag_shift, g.max_count = kind, round, seed, tag_shift, max_count
+    g.kind, g.round, g.seed, g.tag_shift, g.max_count, g.tag = kind, round, seed, tag_shift, max_count, tag
     if thresholds is not None:
         thr = [int(x) for x in np.asarray(thresholds, dtype=np.uint64)]
         for k, x in enumerate(thr[:16]):
@@ -258,6 +283,101 @@ class GGArray:
     def close(self, stream=None):
         if self._h:
             _check(lib().ggarray_destroy(self._h, _stream(stream)), "ggarray_destroy")
+            self._h = _vp()
+
+
+class Batch:
+    """Many GGArrays driven with one launch per phase (see include/ggarray.h)."""
+
+    def __init__(self, arrays, stream=None):
+        self.arrays = list(arrays)
+        self.n = len(self.arrays)
+        handles = (_vp * self.n)(*[a._h.value for a in self.arrays])
+        self._h = _vp()
+        _check(lib().gga_batch_create(ctypes.byref(self._h), handles, self.n, _stream(stream)),
+               "gga_batch_create")
+        self._counts = {}
+
+    def insert_gen(self, gen: GenSpec, n_threads, stream=None):
+        key = tuple(int(x) for x in n_threads)
+        arr = self._counts.get(key)
+        if arr is None:  # keep the host array alive: a captured graph never reads it, but tidy
+            arr = (_u64 * self.n)(*key)
+            self._counts[key] = arr
+        _check(lib().gga_batch_insert_gen(self._h, ctypes.byref(gen), arr, _stream(stream)),
+               "gga_batch_insert_gen")
+
+    def shrink(self, num: int, den: int, stream=None):
+        _check(lib().gga_batch_shrink(self._h, num, den, _stream(stream)), "gga_batch_shrink")
+
+    def rw(self, op: int, stream=None):
+        _check(lib().gga_batch_rw(self._h, op, _stream(stream)), "gga_batch_rw")
+
+    def flatten_into(self, out: torch.Tensor, stream=None):
+        _check(lib().gga_batch_flatten(self._h, _dev_ptr(out, "out", 0, self.arrays[0].elem_bytes),
+                                       out.numel(), _stream(stream)), "gga_batch_flatten")
+
+    def offsets(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        _check(lib().gga_batch_offsets(self._h, _dev_ptr(out, "out"), _stream(stream)), "gga_batch_offsets")
+        return out
+
+    def last_error(self, stream=None) -> int:
+        return int(lib().gga_batch_last_error(self._h, _stream(stream)))
+
+    def close(self, stream=None):
+        if self._h:
+            _check(lib().gga_batch_destroy(self._h, _stream(stream)), "gga_batch_destroy")
+            self._h = _vp()
+
+
+class Server:
+    """Request loop over resident arrays (see include/ggarray.h, serving).
+
+    ``arena`` is a device tensor that receives flatten outputs (a ring)."""
+
+    STATS = ("steps", "largest_step", "issued", "rejected", "memory_waits", "peak_charged_bytes",
+             "elapsed_ns", "arena_wraps")
+
+    def __init__(self, arrays, arena: torch.Tensor, cap_bytes: int, mode: int = SERVE_BATCHED,
+                 lanes: int = 2, max_step: int = 1024, depth: int = 256, seed: int = 1,
+                 append_round: int = 0xA0, append_shift: int = 20, rw_op: int = ADD1):
+        self.arrays = list(arrays)
+        self.arena = arena
+        handles = (_vp * len(self.arrays))(*[a._h.value for a in self.arrays])
+        cfg = ServerConfig(int(cap_bytes), mode, lanes, max_step, depth, seed, append_round,
+                           append_shift, rw_op)
+        self._h = _vp()
+        nbytes = arena.numel() * arena.element_size()
+        _check(lib().gga_server_create(ctypes.byref(self._h), handles, len(self.arrays),
+                                       _dev_ptr(arena, "arena"), nbytes, ctypes.byref(cfg)),
+               "gga_server_create")
+
+    def run(self, arrival_ns, kind, target, length, out_len: torch.Tensor | None = None) -> dict:
+        """Replay a trace (numpy arrays); returns per-request host arrays and stats."""
+        arrival_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        kind = np.ascontiguousarray(kind, dtype=np.uint8)
+        target = np.ascontiguousarray(target, dtype=np.uint32)
+        length = np.ascontiguousarray(length, dtype=np.uint32)
+        n = arrival_ns.size
+        assert kind.size == n and target.size == n and length.size == n
+        tr = Trace(n, arrival_ns.ctypes.data, kind.ctypes.data, target.ctypes.data, length.ctypes.data)
+        t_issue = np.zeros(n, dtype=np.uint64)
+        t_done = np.zeros(n, dtype=np.uint64)
+        status = np.zeros(n, dtype=np.int32)
+        out_off = np.zeros(n, dtype=np.uint64)
+        stats = (_u64 * 8)()
+        dev_len = _dev_ptr(out_len, "out_len", n, 8)
+        _check(lib().gga_server_run(self._h, ctypes.byref(tr), t_issue.ctypes.data, t_done.ctypes.data,
+                                    status.ctypes.data, out_off.ctypes.data, dev_len, stats),
+               "gga_server_run")
+        res = dict(zip(self.STATS, (int(x) for x in stats)))
+        res.update(t_issue_ns=t_issue, t_done_ns=t_done, status=status, out_offset=out_off)
+        return res
+
+    def close(self):
+        if self._h:
+            _check(lib().gga_server_destroy(self._h), "gga_server_destroy")
             self._h = _vp()
 
 

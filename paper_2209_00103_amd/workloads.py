@@ -167,6 +167,80 @@ def cfg4_values(seed: int, a: int, r: int, n_threads: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
+# Configuration 5: served requests over resident arrays.
+# ---------------------------------------------------------------------------
+CFG5 = dict(n_arrays=4096, median_log2=16, sigma=1.0, size_cap_log2=24, n_requests=1 << 20,
+            append_median_log2=10, append_cap_log2=20, mix=(0.6, 0.3, 0.1), cap_bytes=64 << 30,
+            elem_bytes=4, fill_round=0xA1, append_round=0xA0, append_shift=20,
+            loads=(0.25, 0.5, 0.75, 0.9, 1.1))
+
+REQ_APPEND, REQ_RW, REQ_FLATTEN = 0, 1, 2
+
+
+def _unit(seed: int, a, b: int) -> np.ndarray:
+    """Uniform doubles in (0, 1): (top 53 bits of K + 1/2) / 2^53."""
+    return ((K(seed, a, b) >> _U64(11)).astype(np.float64) + 0.5) / float(1 << 53)
+
+
+def _normal(seed: int, a, b1: int, b2: int) -> np.ndarray:
+    """Standard normal by Box-Muller: sqrt(-2 ln u1) cos(2 pi u2)."""
+    u1, u2 = _unit(seed, a, b1), _unit(seed, a, b2)
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def cfg5_sizes(seed: int, n_arrays: int = 4096, median_log2: int = 16, sigma: float = 1.0,
+               cap_log2: int = 24) -> np.ndarray:
+    """Initial sizes s_a = round(2^median_log2 * e^(sigma z_a)), clipped to [1, 2^cap_log2]."""
+    z = _normal(seed, np.arange(n_arrays, dtype=np.uint64), 0xB0, 0xB1)
+    s = np.rint(float(1 << median_log2) * np.exp(sigma * z))
+    return np.clip(s, 1, 1 << cap_log2).astype(np.int64)
+
+
+def cfg5_first_bucket(n_a: int, V: int) -> int:
+    """First bucket of a served array: the largest power of two <= n_a / (8 V),
+    clamped to [64, 4096].  A fixed rule, never tuned."""
+    f = 64
+    while f * 2 <= min(4096, int(n_a) // (8 * V)):
+        f *= 2
+    return f
+
+
+def cfg5_fill_values(seed: int, a: int, n: int) -> np.ndarray:
+    """Initial contents of array a: one round where thread t inserts (u32) K(seed, (a << 32) | t, 0xA1)."""
+    return cfg4_values(seed, a, CFG5["fill_round"], n)
+
+
+def cfg5_trace(seed: int, n_requests: int, n_arrays: int, append_median_log2: int = 10,
+               append_cap_log2: int = 20, mix=(0.6, 0.3, 0.1)) -> dict:
+    """Request r: gap g_r ~ Exp(1) (in units of the mean inter-arrival time), type
+    append / r/w / flatten with probabilities mix, target uniform over the arrays,
+    append length round(2^append_median_log2 * e^z) clipped to [1, 2^append_cap_log2]."""
+    r = np.arange(n_requests, dtype=np.uint64)
+    gap = -np.log(_unit(seed, r, 0xC0))
+    u = _unit(seed, r, 0xC1)
+    kind = np.where(u < mix[0], REQ_APPEND, np.where(u < mix[0] + mix[1], REQ_RW, REQ_FLATTEN)).astype(np.uint8)
+    target = ((K(seed, r, 0xC2) >> _U64(11)) % _U64(n_arrays)).astype(np.uint32)
+    z = _normal(seed, r, 0xC3, 0xC4)
+    length = np.clip(np.rint(float(1 << append_median_log2) * np.exp(z)), 1, 1 << append_cap_log2)
+    length = np.where(kind == REQ_APPEND, length, 0).astype(np.uint32)
+    return dict(gap=gap, kind=kind, target=target, length=length)
+
+
+def cfg5_arrivals_ns(gap: np.ndarray, rate_per_s: float) -> np.ndarray:
+    """Arrival times in ns of a trace offered at rate_per_s requests per second
+    (rate 0 or inf: everything arrives at once)."""
+    if not rate_per_s or not np.isfinite(rate_per_s):
+        return np.zeros(gap.size, dtype=np.uint64)
+    return np.floor(np.cumsum(gap) * (1e9 / rate_per_s)).astype(np.uint64)
+
+
+def cfg5_append_values(seed: int, req: int, n: int) -> np.ndarray:
+    """Payload of append request req: element j is (u32) K(seed, (req << 20) | j, 0xA0)."""
+    j = np.arange(n, dtype=np.uint64)
+    return K(seed, (_U64(req) << _U64(CFG5["append_shift"])) | j, CFG5["append_round"]).astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
 # Generic random cases for property tests.
 # ---------------------------------------------------------------------------
 def random_round(rng: np.random.Generator, n_threads: int, p: float, elem_bytes: int):

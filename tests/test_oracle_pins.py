@@ -337,3 +337,31 @@ def test_cfg2_sizes_closed_form_and_growth_rounds():
     assert zero_growth == [1, 2]
     assert o.capacity() / o.size() <= 2.0
     assert o.check() == 0
+
+
+def test_gen_keyed_equals_buffer():
+    a, b = Oracle(4, 6, 32), Oracle(4, 6, 32)
+    for r, n in enumerate([1000, 37, 5000, 4097]):
+        a.insert_gen(oracle.GEN_KEYED, n, seed=7, round=r, tag=123)
+        b.insert(wl.cfg4_values(7, 123, r, n))
+    assert np.array_equal(a.flatten(), b.flatten())
+
+
+def test_gen_keyed_shift_equals_buffer():
+    # served appends: element j of request r is K(seed, (r << 20) | j, 0xA0)
+    a, b = Oracle(4, 3, 64), Oracle(4, 3, 64)
+    for req, n in [(0, 1), (5, 1000), (1 << 27, 4097), (77, 1 << 12)]:
+        a.insert_gen(oracle.GEN_KEYED, n, seed=9, round=0xA0, tag_shift=20, tag=req)
+        b.insert(wl.cfg5_append_values(9, req, n))
+    assert np.array_equal(a.flatten(), b.flatten())
+
+
+def test_gen_keyed_shift_limits():
+    a = Oracle(4, 2, 16)
+    a.insert_gen(oracle.GEN_KEYED, 1 << 4, seed=1, round=0, tag_shift=4, tag=(1 << 44) - 1)
+    for kw in (dict(tag_shift=0), dict(tag_shift=48), dict(tag_shift=4, tag=1 << 44)):
+        with pytest.raises(Exception):
+            a.insert_gen(oracle.GEN_KEYED, 16, seed=1, round=0, **kw)
+    with pytest.raises(Exception):  # more threads than the shift leaves room for
+        a.insert_gen(oracle.GEN_KEYED, 17, seed=1, round=0, tag_shift=4)
+    assert a.size() == 16
