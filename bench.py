@@ -187,6 +187,9 @@ def batched_leg(G, wl, torch, np, steps, warmup):
     b = G.Batch(arrays)
     out = torch.empty(total, dtype=torch.int32, device="cuda")
     out2 = torch.empty(total, dtype=torch.int32, device="cuda")
+    counts0 = [rounds[i][0] for i in range(n_arr)]
+    b.insert_gen(G.make_gen(G.GEN_KEYED, seed=1, round=0, tag=0), counts0)  # something to stream while tuning
+    grid = tuner.tune_grid(b, out, total)
     counts = [[rounds[i][r] for i in range(n_arr)] for r in range(4)]
     bgens = [G.make_gen(G.GEN_KEYED, seed=1, round=r, tag=0) for r in range(4)]
     agens = [[G.make_gen(G.GEN_KEYED, seed=1, round=r, tag=i) for r in range(4)] for i in range(n_arr)]
@@ -260,7 +263,7 @@ def batched_leg(G, wl, torch, np, steps, warmup):
     return {"workload": "512 arrays, sizes log-uniform 2^10..2^24 uint32, 4 keyed insertion rounds, "
                         "r/w x+1, flatten to per-array offsets",
             "elements": total, "lfvectors": sum(vecs), "timings": summary,
-            "capacity_over_live": cap / total, "first_bucket_choices": fhist,
+            "capacity_over_live": cap / total, "first_bucket_choices": fhist, "stream_grid": grid,
             "batched_equals_per_array": same}
 
 

@@ -208,6 +208,9 @@ int ggarray_last_error(ggarray *a, gga_stream s);
  *   array i starts at offset[i], the exclusive prefix of the array sizes.  If the
  *   total exceeds out_cap_elems nothing is written and the batch's sticky
  *   GGA_ERANGE is set.
+ * gga_batch_set_grid: workgroups of the persistent grid that r/w and flatten
+ *   launch (1..65536; 0 restores the default of 2048, 8 per compute unit).  A
+ *   launch-shape knob for tuning; results do not depend on it.
  * gga_batch_offsets: the n + 1 offsets (uint64, last = total) to dev_out.
  * gga_batch_last_error: the batch's sticky error.  Synchronises s. */
 int gga_batch_create(gga_batch **out, ggarray *const *arrays, uint32_t n, gga_stream s);
@@ -216,6 +219,7 @@ int gga_batch_insert_gen(gga_batch *b, const gga_gen *g, const uint64_t *n_threa
 int gga_batch_shrink(gga_batch *b, uint32_t num, uint32_t den, gga_stream s);
 int gga_batch_rw(gga_batch *b, uint32_t op, gga_stream s);
 int gga_batch_flatten(gga_batch *b, void *out, uint64_t out_cap_elems, gga_stream s);
+int gga_batch_set_grid(gga_batch *b, uint32_t stream_blocks);
 int gga_batch_offsets(gga_batch *b, uint64_t *dev_out, gga_stream s);
 int gga_batch_last_error(gga_batch *b, gga_stream s);
 

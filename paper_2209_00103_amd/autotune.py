@@ -10,8 +10,11 @@ candidate F in 2^6 .. 2^14 whose predicted capacity stays within twice the live
 elements, and keeps the fastest.  Results are cached as JSON keyed by
 (GPU architecture, element size, size class).
 
-The insertion kernel's launch shape is not a free knob here: one wavefront per
-4096-thread tile is the unit of work, so block size is fixed by design.
+The launch shape is tuned too, where it is a free knob: the insertion kernel's
+is fixed by design (one wavefront per 4096-thread tile is the unit of work,
+whatever the array), but the r/w and flatten launches run a persistent grid
+whose workgroup count (256 threads each) trades tail imbalance against
+per-workgroup overhead; ``tune_grid`` times the candidates on the batch itself.
 """
 from __future__ import annotations
 
@@ -19,6 +22,7 @@ import json
 import os
 
 CANDIDATES = tuple(1 << k for k in range(6, 15))
+GRID_CANDIDATES = (512, 1024, 2048, 4096, 8192)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ggarray", "autotune.json")
 
 
@@ -134,3 +138,38 @@ class AutoTuner:
         finally:
             pool.close()
         return best
+
+    def tune_grid(self, batch, out, total_elems: int) -> int:
+        """Workgroups of the batch's persistent r/w + flatten grid: the fastest of
+        GRID_CANDIDATES on this batch (r/w x+1 then flatten into out), cached by
+        (architecture, element size, octave of the batch's element count).  Leaves
+        the batch's contents changed by the r/w passes."""
+        import torch
+
+        from paper_2209_00103_amd import ggarray as G
+
+        key = self._key(size_class(total_elems)).replace("|c", "|grid") + f"|n{batch.n}"
+        if key not in self.cache:
+            best, best_ms = None, None
+            for g in GRID_CANDIDATES:
+                batch.set_grid(g)
+                batch.rw(G.ADD1)
+                batch.flatten_into(out)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                times = []
+                for _ in range(5):
+                    e0.record()
+                    batch.rw(G.ADD1)
+                    batch.flatten_into(out)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    times.append(e0.elapsed_time(e1))
+                ms = min(times)
+                if best_ms is None or ms < best_ms:
+                    best, best_ms = g, ms
+            self.cache[key] = best
+            self._save()
+        g = int(self.cache[key])
+        batch.set_grid(g)
+        return g

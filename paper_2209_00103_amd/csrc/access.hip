@@ -521,7 +521,7 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
 
 int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s) {
   const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
-  const dim3 grid(kStreamBlocks), block(kRwThreads);
+  const dim3 grid(b->stream_blocks ? b->stream_blocks : kStreamBlocks), block(kRwThreads);
   if (b->elem_bytes == 4) {
     if (flatten)
       hipLaunchKernelGGL((batch_stream_kernel<uint32_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,

@@ -452,6 +452,12 @@ int gga_batch_flatten(gga_batch* b, void* out, uint64_t out_cap_elems, gga_strea
   return rc ? rc : launch_batch_stream(b, 0, out, out_cap_elems, true, S(s));
 }
 
+int gga_batch_set_grid(gga_batch* b, uint32_t stream_blocks) {
+  if (!b || stream_blocks > 65536) return GGA_EINVAL;
+  b->stream_blocks = stream_blocks;
+  return GGA_OK;
+}
+
 int gga_batch_offsets(gga_batch* b, uint64_t* dev_out, gga_stream s) {
   if (!b || !dev_out) return GGA_EINVAL;
   int rc = launch_batch_scan(b, S(s));

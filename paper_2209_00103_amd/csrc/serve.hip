@@ -24,7 +24,9 @@ constexpr uint64_t kAlign = 256;
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
-// Flatten outputs: a ring over the arena; space comes back in allocation order.
+// Flatten outputs: a ring over the arena; space comes back in allocation order
+// and is handed out again only after the ring has gone all the way round, so an
+// output stays readable as long as the arena allows.
 struct Ring {
   struct Span {
     uint64_t off, bytes;
@@ -36,7 +38,11 @@ struct Ring {
   bool alloc(uint64_t n, uint64_t* off) {
     if (n > size) return false;
     if (q.empty()) {
-      *off = 0;
+      if (size - head >= n) *off = head;
+      else {
+        *off = 0;
+        ++wraps;
+      }
     } else {
       const uint64_t tail = q.front().off;
       if (head > tail) {  // live data in [tail, head): free space at the end, then at the start

@@ -78,6 +78,7 @@ _SIGS = {
     "gga_batch_shrink": [_vp, _u32, _u32, _vp],
     "gga_batch_rw": [_vp, _u32, _vp],
     "gga_batch_flatten": [_vp, _vp, _u64, _vp],
+    "gga_batch_set_grid": [_vp, _u32],
     "gga_batch_offsets": [_vp, _vp, _vp],
     "gga_batch_last_error": [_vp, _vp],
     "gga_semi_create": [_P(_vp), _u32, _u64, _vp],
@@ -316,6 +317,9 @@ class Batch:
     def flatten_into(self, out: torch.Tensor, stream=None):
         _check(lib().gga_batch_flatten(self._h, _dev_ptr(out, "out", 0, self.arrays[0].elem_bytes),
                                        out.numel(), _stream(stream)), "gga_batch_flatten")
+
+    def set_grid(self, stream_blocks: int):
+        _check(lib().gga_batch_set_grid(self._h, int(stream_blocks)), "gga_batch_set_grid")
 
     def offsets(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
