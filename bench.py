@@ -160,6 +160,17 @@ class _Null:
         return False
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def _pct(xs, q):
     xs = sorted(xs)
     return xs[min(len(xs) - 1, int(round(q / 100.0 * (len(xs) - 1))))]
@@ -327,6 +338,14 @@ def served_leg(G, wl, torch, np_, args):
     k_b = min(n, int(args.serve_baseline_requests))
     sat_pr = run(per_req, zeros, k_b)
     x = sat["req_per_s"]
+    # a load the per-request baseline can sustain: half its own saturation rate
+    low_rate = 0.5 * sat_pr["req_per_s"]
+    low_arrival = wl.cfg5_arrivals_ns(tr["gap"], low_rate)
+    low = {"offered_req_per_s": low_rate, "batched": run(batched, low_arrival, k_b),
+           "per_request": run(per_req, low_arrival, k_b)}
+    log(f"served at {low_rate:.3e} req/s: batched p50 {low['batched']['all']['p50_us']:.0f} us p99 "
+        f"{low['batched']['all']['p99_us']:.0f} us; per-request p50 {low['per_request']['all']['p50_us']:.0f} us "
+        f"p99 {low['per_request']['all']['p99_us']:.0f} us")
     loads = []
     for f in cfg["loads"]:
         arrival = wl.cfg5_arrivals_ns(tr["gap"], f * x)
@@ -351,7 +370,7 @@ def served_leg(G, wl, torch, np_, args):
             "resident_initial_GB": ELEM * sum(sizes) / 1e9, "appended_GB": ELEM * int(length.sum()) / 1e9,
             "lanes": args.serve_lanes, "max_step": args.serve_step,
             "baseline": f"one launch per request, in order, on the first {k_b} requests, at most 1024 in flight",
-            "saturation": sat, "saturation_per_request": sat_pr, "loads": loads}
+            "saturation": sat, "saturation_per_request": sat_pr, "low_load": low, "loads": loads}
 
 
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
@@ -398,10 +417,13 @@ def main():
     arr = G.GGArray(pool, ELEM, V, F)
     prefix_buf = torch.empty(V + 1, dtype=torch.int64, device="cuda")
 
-    # Size the flatten buffer with one untimed pass.
+    # Size the flatten buffer with one untimed pass; capacity / live after each round.
+    mem_rounds = []
     for r, n in enumerate(rounds):
         arr.insert_gen(gens[r], n)
         arr.shrink(1, 10)
+        live, cap = arr.size(), arr.capacity()
+        mem_rounds.append({"round": r, "live": live, "capacity": cap, "capacity_over_live": round(cap / live, 4)})
     final_size = arr.size()
     capacity = arr.capacity()
     pool_stats = pool.stats()
@@ -435,6 +457,27 @@ def main():
     torch.cuda.synchronize()
     assert arr.last_error() == 0, "device error during the per-kernel pass"
 
+    # Access by global index (rw_g, Sec. VI-B) on the final state: r/w x = 3x + 1 by
+    # global index beside the bucket-walk r/w, and a gather of 2^24 uniform indices.
+    for r, n in enumerate(rounds):
+        arr.insert_gen(gens[r], n)
+        arr.shrink(1, 10)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    n_gather = 1 << 24
+    gidx = torch.randint(0, final_size, (n_gather,), device="cuda", dtype=torch.int64, generator=gen)
+    gout = torch.empty(n_gather, dtype=torch.int32, device="cuda")
+    arr.rw_global(G.MUL3ADD1)
+    arr.gather(gidx, gout)
+    for _ in range(args.steps):
+        with timer.span("rw_global"):
+            arr.rw_global(G.MUL3ADD1)
+        with timer.span("gather"):
+            arr.gather(gidx, gout)
+    torch.cuda.synchronize()
+    assert arr.last_error() == 0, "device error during the global-index pass"
+    arr.shrink(1, 1)
+
     # Per-kernel figures (algorithmic bytes, SURVEY-style accounting in the design notes).
     ins_ms = [statistics.mean(timer.ms(f"insert{r}")) for r in range(len(rounds))]
     shr_ms = [statistics.mean(timer.ms(f"shrink{r}")) for r in range(len(rounds))]
@@ -460,6 +503,21 @@ def main():
         "shrink": {"launches_per_step": len(rounds) + 1, "avg_us": 1e3 * statistics.mean(shr_ms + [clr_ms])},
         "prefix_scan": {"launches_per_step": 1, "avg_us": 1e3 * pre_ms},
     }
+    rwg_ms = statistics.mean(timer.ms("rw_global"))
+    gat_ms = statistics.mean(timer.ms("gather"))
+    next_rows = {
+        "rw_global": {"avg_us": 1e3 * rwg_ms, "bytes_per_launch": rw_bytes, "GBps": gbps(rw_bytes, rwg_ms),
+                      "vs_rw": rw_ms / rwg_ms},
+        "gather": {"indices": n_gather, "avg_us": 1e3 * gat_ms, "Gelem_s": n_gather / (gat_ms * 1e-3) / 1e9,
+                   "bytes_per_launch": 16 * n_gather, "GBps": gbps(16 * n_gather, gat_ms),
+                   "note": "per index: 8 B index + 4 B element + 4 B output; the element read is random"},
+    }
+    for k, ts in (("insert_all_rounds", [sum(x) for x in zip(*[timer.ms(f"insert{r}") for r in range(len(rounds))])]),
+                  ("rw", timer.ms("rw")), ("flatten", timer.ms("flatten"))):
+        q = sorted(ts)
+        (kernels["insert"] if k == "insert_all_rounds" else kernels[k])["p10_p50_p90_us"] = [
+            round(1e3 * q[int(0.1 * (len(q) - 1))], 2), round(1e3 * statistics.median(q), 2),
+            round(1e3 * q[int(round(0.9 * (len(q) - 1)))], 2)]
     for k in ("insert", "rw", "flatten"):
         kernels[k]["frac"] = kernels[k]["GBps"] / HBM_PEAK_GBPS
     totals = {"insert": sum(ins_ms), "rw": rw_ms, "flatten": fl_ms}
@@ -547,7 +605,7 @@ def main():
         cpu = {"value": rate, "unit": "Gelem/s", "cores": 1, "kind": "oracle",
                "sample": f"the full workload (2^28 insertions, 12 rounds with shrink, r/w, flatten), "
                          f"single-threaded list-form oracle, median of {reps} passes of {secs:.2f} s",
-               "host_cpu": platform.processor() or platform.machine(), "host_nproc": os.cpu_count()}
+               "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
         log(f"cpu oracle {rate:.4f} Gelem/s ({secs:.2f} s/pass); flatten parity with oracle: {parity}")
 
     value = (1 << 28) / (ms_step * 1e-3) / 1e9
@@ -564,11 +622,13 @@ def main():
         "kernels": kernels,
         "baselines": baselines,
         "memory": {"capacity_elems": capacity, "live_elems": final_size, "capacity_over_live": capacity / final_size,
+                   "per_round": mem_rounds,
                    "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
         "parity_with_oracle": parity,
         "ms_per_step_wall": ms_step_wall,
         "batched": batched,
         "served": served,
+        "global_index_access": next_rows,
     }
     print(json.dumps(line), flush=True)
 

@@ -158,6 +158,19 @@ int ggarray_shrink(ggarray *a, uint32_t num, uint32_t den, gga_stream s);
  *   through the bucket tables (the per-block read/write rw_b of Sec. VI-B). */
 int ggarray_rw(ggarray *a, uint32_t op, gga_stream s);
 
+/* ggarray_rw_global: the same result as ggarray_rw, computed element by element
+ *   from the global index (the rw_g variant of Sec. VI-B): global index i lies in
+ *   the last LFVector v with P[v] <= i (P as for flatten, so empty LFVectors are
+ *   skipped), at local index i - P[v], whose bucket and offset follow from the
+ *   closed form of the bucket law (Alg. 2). */
+int ggarray_rw_global(ggarray *a, uint32_t op, gga_stream s);
+
+/* ggarray_gather: out[k] = element at global index idx[k] for k < n (idx and out
+ *   device memory, out of n elements; the order of the global index is the
+ *   flatten order).  An index at or past the size leaves out[k] unwritten and
+ *   sets the sticky GGA_ERANGE; the other entries are still written. */
+int ggarray_gather(ggarray *a, const uint64_t *idx, uint64_t n, void *out, gga_stream s);
+
 /* ggarray_flatten: copies LFVector 0, then 1, ... into out (device memory of
  *   out_cap_elems elements), element i of LFVector v landing at P[v] + i where P
  *   is the exclusive prefix sum of the LFVector sizes (Sec. IV).  The GGArray is

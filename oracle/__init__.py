@@ -68,6 +68,8 @@ def lib():
             "orc_alloc_count": (u64, [vp]),
             "orc_free_count": (u64, [vp]),
             "orc_flatten": (i32, [vp, vp, u64]),
+            "orc_at": (i32, [vp, u64, ctypes.POINTER(u64)]),
+            "orc_gather": (i32, [vp, vp, u64, vp]),
             "orc_check": (ctypes.c_int64, [vp]),
         }
         for name, (res, args) in sig.items():
@@ -209,6 +211,19 @@ class Oracle:
         out = np.zeros(max(cap, 1), dtype=self.dtype)
         self._chk(lib().orc_flatten(self._h, _ptr(out), cap), "flatten")
         return out[:n]
+
+    def at(self, i: int) -> int | None:
+        """Element at global index i (None past the end)."""
+        e = ctypes.c_uint64()
+        rc = int(lib().orc_at(self._h, i, ctypes.byref(e)))
+        return None if rc == ERANGE else e.value
+
+    def gather(self, idx: np.ndarray, fill: int = 0) -> tuple[np.ndarray, int]:
+        """(out, status): out[k] = element at idx[k]; out of range leaves fill."""
+        idx = np.ascontiguousarray(idx, dtype=np.uint64)
+        out = np.full(max(idx.size, 1), fill, dtype=self.dtype)
+        rc = int(lib().orc_gather(self._h, _ptr(idx), idx.size, _ptr(out)))
+        return out[:idx.size], rc
 
     def flatten_status(self, out: np.ndarray) -> int:
         return int(lib().orc_flatten(self._h, _ptr(out), out.size))

@@ -556,6 +556,52 @@ int orc_flatten(const orc_array *a, void *out, uint64_t out_cap)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Access by global index (rw_g of Sec. VI-B): global index i is found by       */
+/* walking the LFVectors in order and subtracting their sizes (no prefix, no    */
+/* search), then the element by the bucket walk (or the list).                  */
+/* ------------------------------------------------------------------------- */
+int orc_at(const orc_array *a, uint64_t i, uint64_t *out)
+{
+    if (!a || !out)
+        return ORC_EINVAL;
+    for (uint32_t v = 0; v < a->n_vectors; v++) {
+        uint64_t s = vsize(a, v);
+        if (i < s) {
+            if (a->lists) {
+                *out = a->lists[v].data[i];
+            } else {
+                uint32_t b;
+                uint64_t off;
+                orc_walk(a->first_bucket, i, &b, &off);
+                *out = a->vecs[v].bucket[b][off];
+            }
+            return ORC_OK;
+        }
+        i -= s;
+    }
+    return ORC_ERANGE;
+}
+
+/* out[k] = element at global index idx[k]; an index past the end leaves out[k]
+ * untouched and makes the call return ORC_ERANGE (the others are still read). */
+int orc_gather(const orc_array *a, const uint64_t *idx, uint64_t n, void *out)
+{
+    int rc = ORC_OK;
+    for (uint64_t k = 0; k < n; k++) {
+        uint64_t e;
+        if (orc_at(a, idx[k], &e) != ORC_OK) {
+            rc = ORC_ERANGE;
+            continue;
+        }
+        if (a->elem_bytes == 4)
+            ((uint32_t *)out)[k] = (uint32_t)e;
+        else
+            ((uint64_t *)out)[k] = e;
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Self-check: the two forms hold the same sizes and elements, and each bucketed */
 /* LFVector holds exactly the buckets that cover its live indices.              */
 /* Returns 0, or 1 + the first LFVector that disagrees.                         */

@@ -16,30 +16,6 @@ constexpr uint32_t kStreamBlocks = 2048;  // 8 workgroups per CU on 256 CUs
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
 
-// Tiles of an LFVector of s elements: every bucket below s contributes
-// ceil(live elements of the bucket / te) tiles.
-__device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
-  uint64_t n = 0;
-  const uint32_t nb = nbuckets_for(log2F, s);
-  for (uint32_t b = 0; b < nb; ++b) {
-    const uint64_t st = bucket_start(log2F, b);
-    uint64_t live = bucket_len(log2F, b);
-    if (s - st < live) live = s - st;
-    n += (live + (1ull << te_log2) - 1) >> te_log2;
-  }
-  return n;
-}
-
-__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
-  const uint32_t lane = threadIdx.x & 63u;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t y = __shfl_up(x, d, 64);
-    if (lane >= (uint32_t)d) x += y;
-  }
-  return x;
-}
-
 // Exclusive prefix sums of the LFVector sizes (element offsets, Sec. IV) and of
 // their tile counts, by one workgroup of kScanThreads; entry V holds the totals.
 __device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2) {
@@ -382,28 +358,58 @@ __global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr
 }
 
 // ---------------------------------------------------------- served steps --
-__global__ __launch_bounds__(kScanThreads) void serve_scan_kernel(const ServeItem* items, uint32_t te_log2) {
-  scan_array(items[blockIdx.x].A, te_log2);
+// Tile offsets of the step's items (exclusive prefix of their tile totals, entry
+// n the sum) into tb, by one workgroup.
+__device__ __forceinline__ void block_tile_offsets(const ServeItem* items, uint32_t n, uint64_t* tb) {
+  __shared__ uint64_t wsum[kRwThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t per = (n + kRwThreads - 1) / kRwThreads;
+  const uint32_t i0 = tid * per < n ? tid * per : n;
+  const uint32_t i1 = i0 + per < n ? i0 + per : n;
+  uint64_t t = 0;
+  for (uint32_t i = i0; i < i1; ++i) t += items[i].A.tprefix[items[i].A.V];
+  const uint64_t it = wave_incl_scan64(t);
+  if (lane == 63) wsum[w] = it;
+  __syncthreads();
+  uint64_t r = it - t, total = 0;
+  for (uint32_t k = 0; k < kRwThreads / 64; ++k) {
+    if (k < w) r += wsum[k];
+    total += wsum[k];
+  }
+  for (uint32_t i = i0; i < i1; ++i) {
+    tb[i] = r;
+    r += items[i].A.tprefix[items[i].A.V];
+  }
+  if (tid == 0) tb[n] = total;
+  __syncthreads();
 }
 
 // The r/w and flatten requests of one served step in one persistent grid: item i
 // is r/w'd in place, or flattened to its own destination (written only if its
-// reservation holds it).  Workgroup 0 also reports each
+// reservation holds it).  The step's front launch scanned the arrays.  With
+// kFused every workgroup forms the items' tile offsets in LDS itself; otherwise
+// they come from tile_begin (batch_top_kernel).  Workgroup 0 also reports each
 // flatten's length.
-template <typename T>
+template <typename T, bool kFused>
 __global__ __launch_bounds__(kRwThreads) void serve_stream_kernel(const ServeItem* items, const uint64_t* tile_begin,
                                                                  uint32_t n, uint32_t* err, uint32_t te_log2) {
+  extern __shared__ uint64_t lds_tb[];
   if (blockIdx.x == 0)
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x)
       if (items[i].len_out) items[i].len_out[0] = items[i].A.prefix[items[i].A.V];
-  const uint64_t total = tile_begin[n];
+  const uint64_t* tb = tile_begin;
+  if (kFused) {
+    block_tile_offsets(items, n, lds_tb);
+    tb = lds_tb;
+  }
+  const uint64_t total = tb[n];
   const uint64_t G = gridDim.x;
   uint64_t g0 = total * blockIdx.x / G;
   const uint64_t g1 = total * (blockIdx.x + 1) / G;
   if (g0 >= g1) return;
-  uint32_t i = wave_search(tile_begin, n, g0);
+  uint32_t i = wave_search(tb, n, g0);
   while (g0 < g1 && i < n) {
-    const uint64_t b0 = tile_begin[i], b1 = tile_begin[i + 1];
+    const uint64_t b0 = tb[i], b1 = tb[i + 1];
     const uint64_t hi = b1 < g1 ? b1 : g1;
     if (hi > g0) {
       const ServeItem& it = items[i];
@@ -427,15 +433,26 @@ int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin
   const uint32_t te_log2 = elem_bytes == 4 ? 12u : 11u;
   if (grid < 1) grid = 1;
   if (grid > kStreamBlocks) grid = kStreamBlocks;
-  hipLaunchKernelGGL(serve_scan_kernel, dim3(n), dim3(kScanThreads), 0, s, items, te_log2);
-  hipLaunchKernelGGL(batch_top_kernel<ServeItem>, dim3(1), dim3(kScanThreads), 0, s, items, n, tile_begin,
-                     elem_begin);
-  if (elem_bytes == 4)
-    hipLaunchKernelGGL(serve_stream_kernel<uint32_t>, dim3(grid), dim3(kRwThreads), 0, s, items, tile_begin, n, err,
-                       te_log2);
-  else
-    hipLaunchKernelGGL(serve_stream_kernel<uint64_t>, dim3(grid), dim3(kRwThreads), 0, s, items, tile_begin, n, err,
-                       te_log2);
+  const bool fused = n <= kServeFusedItems;
+  const size_t lds = fused ? (n + 1) * sizeof(uint64_t) : 0;
+  if (!fused)
+    hipLaunchKernelGGL(batch_top_kernel<ServeItem>, dim3(1), dim3(kScanThreads), 0, s, items, n, tile_begin,
+                       elem_begin);
+  if (elem_bytes == 4) {
+    if (fused)
+      hipLaunchKernelGGL((serve_stream_kernel<uint32_t, true>), dim3(grid), dim3(kRwThreads), lds, s, items,
+                         tile_begin, n, err, te_log2);
+    else
+      hipLaunchKernelGGL((serve_stream_kernel<uint32_t, false>), dim3(grid), dim3(kRwThreads), 0, s, items,
+                         tile_begin, n, err, te_log2);
+  } else {
+    if (fused)
+      hipLaunchKernelGGL((serve_stream_kernel<uint64_t, true>), dim3(grid), dim3(kRwThreads), lds, s, items,
+                         tile_begin, n, err, te_log2);
+    else
+      hipLaunchKernelGGL((serve_stream_kernel<uint64_t, false>), dim3(grid), dim3(kRwThreads), 0, s, items,
+                         tile_begin, n, err, te_log2);
+  }
   return hip_status(hipGetLastError());
 }
 

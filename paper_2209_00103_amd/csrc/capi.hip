@@ -203,6 +203,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   const size_t o_prefix = off;     off = align_up(off + 8 * (V + 1), 256);
   const size_t o_tprefix = off;    off = align_up(off + 8 * (V + 1), 256);
   const size_t o_vticket = off;    off = align_up(off + 8 * V, 256);
+  const size_t o_rbase = off;      off = align_up(off + 8 * V, 256);
   const size_t o_misc = off;       off = align_up(off + 64, 256);  // err, scratch
   if (hipMalloc(&a->meta, off) != hipSuccess) {
     delete f;
@@ -224,6 +225,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.tprefix = reinterpret_cast<uint64_t*>(m + o_tprefix);
   R.err = reinterpret_cast<uint32_t*>(m + o_misc);
   R.vticket = reinterpret_cast<uint64_t*>(m + o_vticket);
+  R.rbase = reinterpret_cast<uint64_t*>(m + o_rbase);
   f->x.d_scratch = reinterpret_cast<uint64_t*>(m + o_misc + 16);
   R.status = nullptr;
   R.pool = p->ref;
@@ -300,6 +302,18 @@ int ggarray_rw(ggarray* a, uint32_t op, gga_stream s) {
   return rc ? rc : launch_rw(a, op, S(s));
 }
 
+int ggarray_rw_global(ggarray* a, uint32_t op, gga_stream s) {
+  if (!a || op > GGA_ADD1_X30) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  return rc ? rc : launch_rw_global(a, op, S(s));
+}
+
+int ggarray_gather(ggarray* a, const uint64_t* idx, uint64_t n, void* out, gga_stream s) {
+  if (!a || (n && (!idx || !out))) return GGA_EINVAL;
+  int rc = ensure_prefix(a, S(s));
+  return rc ? rc : launch_gather(a, idx, n, out, S(s));
+}
+
 int ggarray_flatten(ggarray* a, void* out, uint64_t out_cap_elems, gga_stream s) {
   if (!a || (!out && out_cap_elems)) return GGA_EINVAL;
   int rc = ensure_prefix(a, S(s));
@@ -354,6 +368,7 @@ static void batch_free(gga_batch* b) {
   for (uint32_t k = 0; k < b->n_tables; ++k) {
     (void)hipFree(b->tables[k].items);
     (void)hipFree(b->tables[k].begins);
+    delete[] b->tables[k].host;
   }
   delete[] b->tables;
   delete[] b->arrays;

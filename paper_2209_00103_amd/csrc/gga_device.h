@@ -75,6 +75,7 @@ struct ArrRef {
   uint64_t* tprefix;
   uint32_t* err;
   uint64_t* vticket;     // per-LFVector tile tickets of the insertion kernel
+  uint64_t* rbase;       // per-LFVector size before the current dense round (grow -> store)
   uint64_t* status;
   PoolRef pool;
   uint32_t V;
@@ -206,17 +207,7 @@ __device__ __forceinline__ uint8_t* pool_pop(PoolRef P, uint32_t cls, uint32_t s
     const uint64_t off = ((h & kIdxMask) - 1) << kMinClassLog2;
     const uint64_t nxt = ld_rlx(reinterpret_cast<const uint64_t*>(P.base + off)) & kIdxMask;
     const uint64_t nh = (((h >> 40) + 1) << 40) | nxt;
-    if (cas_rlx(head, h, nh)) {
-      if (nxt == 0) {
-        // The shard looks empty now: clear its hint, and restore it if a push
-        // got in between.
-        uint64_t* m = &H->nonempty[cls][s >> 6];
-        __hip_atomic_fetch_and(m, ~(1ull << (s & 63)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ld_rlx(head) & kIdxMask)
-          __hip_atomic_fetch_or(m, 1ull << (s & 63), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      return P.base + off;
-    }
+    if (cas_rlx(head, h, nh)) return P.base + off;  // the shard's hint stays set (see pool_alloc)
   }
   return nullptr;
 }
@@ -231,9 +222,8 @@ __device__ __forceinline__ uint8_t* global_bump(PoolRef P, uint64_t bytes) {
   return P.base + old;
 }
 
-__device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t bytes) {
+__device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t bytes, uint32_t clog) {
   PoolHdr* H = P.hdr;
-  const uint32_t clog = (uint32_t)ld_rlx(&H->chunk_log2);
   const uint64_t units = bytes >> kMinClassLog2;
   const uint64_t cap = 1ull << (clog - kMinClassLog2);
   uint64_t* word = &H->shard[s].arena;
@@ -255,20 +245,34 @@ __device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t 
 __device__ __forceinline__ uint8_t* pool_alloc(PoolRef P, uint32_t cls, uint32_t fs) {
   PoolHdr* H = P.hdr;
   const uint64_t bytes = 1ull << cls;
-  if (ld_rlx(&H->fault_at)) {
+  // fault_at and chunk_log2 only change between launches (host writes), so plain
+  // loads see them and can issue together with the first atomic.
+  const uint64_t fault_at = H->fault_at;
+  const uint32_t clog = (uint32_t)H->chunk_log2;
+  if (fault_at) {
     const uint64_t n = fetch_add(&H->n_attempt, 1) + 1;
-    if (n == ld_rlx(&H->fault_at)) return nullptr;
+    if (n == fault_at) return nullptr;
   }
   if (cls > (uint32_t)kMaxClassLog2) return nullptr;
   const uint32_t as = arena_shard(fs);
   uint8_t* q = pool_pop(P, cls, fs);
-  if (!q && cls + 2 <= (uint32_t)ld_rlx(&H->chunk_log2)) q = arena_alloc(P, as, bytes);
+  if (!q && cls + 2 <= clog) q = arena_alloc(P, as, bytes, clog);
   if (!q) q = global_bump(P, bytes);
-  for (uint32_t wi = 0; !q && wi < (uint32_t)kFreeShards / 64; ++wi) {  // region exhausted: steal
+  // Region exhausted: steal from other shards.  A shard's hint bit is set by
+  // every push and cleared only here, when a steal finds the shard empty, so a
+  // pop costs no hint update and a set bit may be stale.
+  for (uint32_t wi = 0; !q && wi < (uint32_t)kFreeShards / 64; ++wi) {
     uint64_t mask = ld_rlx(&H->nonempty[cls][wi]);
     while (!q && mask) {
-      const uint32_t s = wi * 64 + (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+      const uint32_t b = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+      const uint32_t s = wi * 64 + b;
       q = pool_pop(P, cls, s);
+      if (!q) {
+        uint64_t* m = &H->nonempty[cls][wi];
+        __hip_atomic_fetch_and(m, ~(1ull << b), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ld_rlx(&H->heads[(uint64_t)cls * kFreeShards + s]) & kIdxMask)  // a push got in between
+          __hip_atomic_fetch_or(m, 1ull << b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       mask &= mask - 1;
     }
   }

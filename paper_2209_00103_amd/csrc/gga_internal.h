@@ -54,10 +54,11 @@ struct gga_batch {
   // Round tables uploaded so far (descriptors + block offsets), reused when the
   // same round shape comes again, so a captured graph always reads a stable table.
   struct Table {
-    uint64_t key;
+    uint64_t key;           // hash of the round's shape (look-back buffers excluded)
     uint64_t blocks;
-    gga::BatchArr* items;
-    uint64_t* begins;
+    gga::BatchArr* items;   // device
+    uint64_t* begins;       // device
+    gga::BatchArr* host;    // host copy of items
   };
   Table* tables;
   uint32_t n_tables;
@@ -111,6 +112,60 @@ struct ServeItem {
   uint32_t elem_log2;
 };
 
+// Tiles of an LFVector of s elements: every bucket below s contributes
+// ceil(live elements of the bucket / te) tiles.
+__device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
+  uint64_t n = 0;
+  const uint32_t nb = nbuckets_for(log2F, s);
+  for (uint32_t b = 0; b < nb; ++b) {
+    const uint64_t st = bucket_start(log2F, b);
+    uint64_t live = bucket_len(log2F, b);
+    if (s - st < live) live = s - st;
+    n += (live + (1ull << te_log2) - 1) >> te_log2;
+  }
+  return n;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  return x;
+}
+
+// Exclusive prefix sums of one array's LFVector sizes and tile counts (entry V
+// holds the totals), by one wave: lane l takes a contiguous run of LFVectors.
+__device__ __forceinline__ void scan_array_wave(const ArrRef& A, uint32_t te_log2) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t V = A.V;
+  const uint32_t per = (V + 63) / 64;
+  const uint32_t v0 = lane * per < V ? lane * per : V;
+  const uint32_t v1 = v0 + per < V ? v0 + per : V;
+  uint64_t e = 0, t = 0;
+  for (uint32_t v = v0; v < v1; ++v) {
+    const uint64_t s = A.size[v];
+    e += s;
+    t += tiles_for(A.log2F, s, te_log2);
+  }
+  const uint64_t ie = wave_incl_scan64(e), it = wave_incl_scan64(t);
+  uint64_t re = ie - e, rt = it - t;
+  for (uint32_t v = v0; v < v1; ++v) {
+    const uint64_t s = A.size[v];
+    A.prefix[v] = re;
+    A.tprefix[v] = rt;
+    re += s;
+    rt += tiles_for(A.log2F, s, te_log2);
+  }
+  const uint64_t te = __shfl(ie, 63, 64), tt = __shfl(it, 63, 64);
+  if (lane == 0) {
+    A.prefix[V] = te;
+    A.tprefix[V] = tt;
+  }
+}
+
 // How an insertion round produces its candidates.
 enum InsertMode : uint32_t {
   kModeBuffer = 0,   // values[gid], flags[gid]
@@ -134,6 +189,14 @@ struct InsertDesc {
   uint64_t tag;
 };
 
+// Insertion tile of the 0/1 producers: one wavefront, kInsertSlots candidate
+// slots per lane, so kInsertTile logical threads per tile.
+#ifndef GGA_INSERT_SLOTS
+#define GGA_INSERT_SLOTS 64
+#endif
+constexpr uint32_t kInsertSlots = GGA_INSERT_SLOTS;
+constexpr uint32_t kInsertTile = 64u * kInsertSlots;
+
 // Tile geometry of the element-streaming kernels (rw, flatten): 16 KiB per tile.
 constexpr uint32_t kRwThreads = 256;
 __host__ __device__ constexpr uint32_t rw_tile_elems(uint32_t elem_log2) {
@@ -146,6 +209,8 @@ int launch_scan(ggarray* a, hipStream_t s);
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s);
 int launch_rw(ggarray* a, uint32_t op, hipStream_t s);
 int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s);
+int launch_rw_global(ggarray* a, uint32_t op, hipStream_t s);
+int launch_gather(ggarray* a, const uint64_t* idx, uint64_t n, void* out, hipStream_t s);
 int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s);
 int launch_free_all(ggarray* a, hipStream_t s);
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s);
@@ -158,8 +223,14 @@ int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool
 // n threads on a (growing its look-back words on stream s) and returns its tiles.
 int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,
                        hipStream_t s);
-int launch_keyed_items(const BatchArr* items, const uint64_t* begins, uint32_t n, uint64_t blocks,
-                       uint32_t elem_bytes, uint64_t seed, uint32_t round, uint32_t shift, hipStream_t s);
+// launch_serve_front: the step's append rounds (keyed payloads) and the size
+// scans of the n_s arrays in sitems, one launch.  launch_serve_stream: the r/w
+// and flatten requests of sitems (scanned before), one streaming launch (plus one
+// prefix launch when n_s exceeds kServeFusedItems).
+constexpr uint32_t kServeFusedItems = 4096;
+int launch_serve_front(const BatchArr* items, const uint64_t* begins, uint32_t n_a, uint64_t blocks,
+                       const ServeItem* sitems, uint32_t n_s, uint32_t elem_bytes, uint64_t seed, uint32_t round,
+                       uint32_t shift, hipStream_t s);
 int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin, uint64_t* elem_begin,
                         uint32_t* err, uint32_t elem_bytes, uint32_t grid, hipStream_t s);
 

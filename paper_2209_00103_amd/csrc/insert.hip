@@ -1,28 +1,28 @@
 // Insertion rounds: block-cooperative push_back (Alg. 1) with in-kernel bucket
 // growth (Alg. 2), for the GGArray and for the static-array baseline.
 //
-// One workgroup handles one tile of logical threads.  Tiles are numbered in
-// (LFVector, position) order and handed out by a ticket counter, so a tile's
-// predecessors inside its LFVector always belong to workgroups already running;
-// that is what makes the waits below safe.  Per tile:
-//   1. each thread produces its candidates (loads or generates them);
-//   2. the block computes the exclusive prefix sum of the insertion counts
-//      (0/1 producers: one wave ballot + mbcnt per candidate slot and a 64-entry
-//      wave scan of the per-wave totals; multi-element producers: a wave scan of
-//      the per-thread counts) and stages the kept elements in LDS, compacted;
-//   3. wave 0 obtains the tile's first index in its LFVector: the first tile of
-//      the LFVector reads the LFVector size, later tiles use a decoupled
-//      look-back over the tiles before them (each tile publishes its count, then
-//      its inclusive prefix, in one tagged 64-bit word);
-//   4. wave 0 allocates every bucket whose first index falls in the tile's
-//      range (exactly one tile holds each bucket start, which makes it the
-//      Alg. 2 winner without a CAS) and waits for the buckets a predecessor
-//      allocates;
-//   5. the last tile of the LFVector commits the new size, or, if any bucket
+// The logical threads of a round are cut into tiles, numbered in (LFVector,
+// position) order.  For the 0/1 producers (at most one element per thread) one
+// wavefront handles one tile of kInsertTile threads; the multi-element producers
+// use 256-thread workgroups over 1024-thread tiles.  Per tile:
+//   1. the producer's flags (or counts) are evaluated and counted: a wave ballot
+//      per candidate slot (mbcnt gives each kept candidate its rank), or a scan
+//      of the per-thread counts;
+//   2. the tile's first index in its LFVector: the first tile of the LFVector
+//      reads the LFVector size, later tiles use a decoupled look-back over the
+//      tiles before them (each tile publishes its count, then its inclusive
+//      prefix, in one tagged 64-bit word); tiles take per-LFVector tickets, so
+//      every tile a tile waits for is held by a wave that is already running;
+//   3. the tile allocates every bucket whose first index falls in its range
+//      (exactly one tile holds each bucket start, which makes it the Alg. 2
+//      winner without a CAS) and waits for the buckets a predecessor allocates;
+//   4. the last tile of the LFVector commits the new size, or, if any bucket
 //      allocation of the round failed, leaves the size as it was and freezes
 //      the LFVector;
-//   6. the block scatters the staged elements to their buckets, coalesced.
-// The static baseline replaces 3-5 by one global atomicAdd per tile.
+//   5. the elements are stored at their positions: with 16-byte non-temporal
+//      stores when every thread of the tile inserts into one bucket, else one
+//      element per lane and slot, located by the closed form.
+// The static baseline replaces 2-4 by one global atomicAdd per tile.
 #include <new>
 
 #include "gga_internal.h"
@@ -32,13 +32,10 @@ namespace {
 
 constexpr int kB = 256;                  // threads per insertion workgroup
 constexpr int kW = kB / 64;              // waves per workgroup
-constexpr int kFlagK = 16;               // candidate slots per thread, 0/1 producers
-constexpr int kFlagTile = kB * kFlagK;   // 4096 logical threads per tile
+constexpr int kFlagTile = (int)kInsertTile;  // logical threads per tile, 0/1 producers (one wave)
 constexpr int kCountK = 4;               // candidates per thread, multi-element producers
 constexpr int kCountTile = kB * kCountK; // 1024 logical threads per tile
 constexpr int kStage = 4096;             // LDS staging capacity, elements
-static_assert(kFlagK * kW == 64, "one wave scans the per-(slot, wave) totals");
-static_assert(kFlagTile <= kStage, "a 0/1 tile stages in one pass");
 
 // Look-back status word: epoch (30 bits) | flag (2 bits) | value (32 bits).  The
 // value is a count or an inclusive prefix relative to the LFVector's size at the
@@ -106,6 +103,7 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
 template <typename T>
 struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
   static constexpr bool kMulti = false;
+  static constexpr bool kDense = false;
   const T* values;
   const uint8_t* flags;
   __device__ __forceinline__ bool flag(uint64_t g) const { return flags ? flags[g] != 0 : true; }
@@ -114,6 +112,7 @@ struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
 template <typename T>
 struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
   static constexpr bool kMulti = false;
+  static constexpr bool kDense = false;
   uint64_t seed;
   uint32_t round;
   __device__ __forceinline__ bool flag(uint64_t g) const { return (K(seed, g, round) >> 63) != 0; }
@@ -123,6 +122,7 @@ struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
 template <typename T>
 struct ProdRoundTag {  // insert (round << shift) | gid
   static constexpr bool kMulti = false;
+  static constexpr bool kDense = true;  // every thread inserts
   uint32_t round;
   uint32_t shift;
   __device__ __forceinline__ bool flag(uint64_t) const { return true; }
@@ -132,6 +132,7 @@ struct ProdRoundTag {  // insert (round << shift) | gid
 template <typename T>
 struct ProdKeyed {  // every thread inserts K(seed, (tag << shift) | gid, round)
   static constexpr bool kMulti = false;
+  static constexpr bool kDense = true;
   uint64_t seed;
   uint32_t round;
   uint32_t shift;
@@ -449,20 +450,60 @@ __device__ __forceinline__ void tile_range(const TileArgs& I, uint32_t v, uint64
 // that is already running.  Blocks are normally dispatched in index order, so
 // the first pass runs for the position the index suggests while the ticket is
 // in flight, and is redone in the rare case the ticket differs.
-constexpr int kWaveSlots = 64;
+constexpr int kWaveSlots = (int)kInsertSlots;
 constexpr int kWaveTile = 64 * kWaveSlots;
-static_assert(kWaveTile == kFlagTile, "0/1 tiles hold 4096 logical threads");
+constexpr int kMaskWords = kWaveSlots / 64;
+static_assert(kWaveSlots % 64 == 0 && kMaskWords >= 1, "whole 64-bit slot masks");
+
+struct SlotMask {  // bit j: slot j of this lane inserts
+  uint64_t w[kMaskWords];
+  __device__ __forceinline__ bool get(int j) const { return (w[j >> 6] >> (j & 63)) & 1u; }
+  __device__ __forceinline__ uint32_t count() const {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kMaskWords; ++k) c += (uint32_t)__popcll(w[k]);
+    return c;
+  }
+};
 
 template <class Prod>
-__device__ __forceinline__ uint64_t wave_flags(const Prod& prod, uint64_t g0, uint64_t gend) {
+__device__ __forceinline__ SlotMask wave_flags(const Prod& prod, uint64_t g0, uint64_t gend) {
   const uint32_t lane = lane_id();
-  uint64_t bits = 0;
+  SlotMask m;
+#pragma unroll
+  for (int k = 0; k < kMaskWords; ++k) m.w[k] = 0;
 #pragma unroll 16
   for (int j = 0; j < kWaveSlots; ++j) {
     const uint64_t g = g0 + (uint64_t)j * 64 + lane;
-    if (g < gend && prod.flag(g)) bits |= 1ull << j;
+    if (g < gend && prod.flag(g)) m.w[j >> 6] |= 1ull << (j & 63);
   }
-  return bits;
+  return m;
+}
+
+// Every thread of the tile inserts and the tile lies in one bucket: element i is
+// thread g0 + i at dst + i.  The wave writes the run with 16-byte non-temporal
+// stores on 16-byte boundaries (element stores for the ragged head and tail), a
+// quarter of the store instructions of one element per lane and slot.
+template <typename T, class Prod>
+__device__ __forceinline__ void dense_store(T* dst, const Prod& prod, uint64_t g0, uint32_t n) {
+  constexpr uint32_t VPL = 16 / sizeof(T);
+  const uint32_t lane = lane_id();
+  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst) & 15u) / sizeof(T));
+  uint32_t head = mis ? VPL - mis : 0u;
+  if (head > n) head = n;
+  if (lane < head) dst[lane] = prod.value(g0 + lane);
+  const uint32_t nv = (n - head) / VPL;
+  for (uint32_t q = lane; q < nv; q += 64) {
+    const uint32_t e = head + q * VPL;
+    T tmp[VPL];
+#pragma unroll
+    for (uint32_t k = 0; k < VPL; ++k) tmp[k] = prod.value(g0 + e + k);
+    u32x4 x;
+    __builtin_memcpy(&x, tmp, 16);
+    __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dst + e));
+  }
+  const uint32_t tail = head + nv * VPL + lane;
+  if (tail < n) dst[tail] = prod.value(g0 + tail);
 }
 
 // One wave, one tile; `block` is the wave's index among the launch's waves for
@@ -484,7 +525,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
   } else {
     tile_range(I, v, t, kWaveTile, g0, gend);
   }
-  uint64_t bits = wave_flags<Prod>(prod, g0, gend);
+  SlotMask bits = wave_flags<Prod>(prod, g0, gend);
   uint64_t epoch = 0;
   if (ticketed) {
     if (lane == 0) settle_ticket(A, v, k, I.tpv);
@@ -500,7 +541,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
   if (g0 >= gend) return;
   if (!kStatic && ld_rlx32(&A.dead[v])) return;
   const bool is_last = g0 + kWaveTile >= gend;
-  const uint32_t n_t = (uint32_t)wave_sum64((uint64_t)__popcll(bits));
+  const uint32_t n_t = (uint32_t)wave_sum64((uint64_t)bits.count());
 
   T* dst;
   uint64_t lim = n_t;
@@ -521,10 +562,14 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     if (r.nb == 1 && p0 <= kFailedPtr) return;
   }
   uint32_t run = 0;
+  if ((kStatic || r.nb == 1) && n_t == gend - g0 && lim == n_t) {
+    dense_store<T, Prod>(dst, prod, g0, n_t);
+    return;
+  }
   if (kStatic || r.nb == 1) {
 #pragma unroll 16
     for (int j = 0; j < kWaveSlots; ++j) {
-      const bool f = (bits >> j) & 1u;
+      const bool f = bits.get(j);
       const uint64_t m = __ballot(f);
       const uint32_t q = run + mbcnt(m);
       if (f && q < lim) dst[q] = prod.value(g0 + (uint64_t)j * 64 + lane);
@@ -534,7 +579,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
   }
   // The tile spans several buckets: locate each element by the closed form.
   for (int j = 0; j < kWaveSlots; ++j) {
-    const bool f = (bits >> j) & 1u;
+    const bool f = bits.get(j);
     const uint64_t m = __ballot(f);
     const uint64_t idx = r.base + run + mbcnt(m);
     const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
@@ -553,9 +598,8 @@ __global__ __launch_bounds__(64) void insert_wave_kernel(ArrRef A, StaticRef S, 
 // the blocks [begins[i], begins[i+1]); each wave finds its array with a 64-way
 // search and then runs exactly as in a single-array launch.
 template <typename T, class Prod>
-__global__ __launch_bounds__(64) void batch_insert_kernel(const BatchArr* items, const uint64_t* begins,
-                                                          uint32_t n, Prod prod) {
-  const uint64_t blk = blockIdx.x;
+__device__ __forceinline__ void batch_wave(const BatchArr* items, const uint64_t* begins, uint32_t n,
+                                           const Prod& prod, uint64_t blk) {
   const uint32_t i = wave_search(begins, n, blk);
   const BatchArr it = items[i];
   TileArgs I;
@@ -566,6 +610,92 @@ __global__ __launch_bounds__(64) void batch_insert_kernel(const BatchArr* items,
   Prod p = prod;
   p.bind(it);
   wave_tile<T, Prod, false>(it.A, StaticRef{}, I, p, blk - begins[i]);
+}
+
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void batch_insert_kernel(const BatchArr* items, const uint64_t* begins,
+                                                          uint32_t n, Prod prod) {
+  batch_wave<T, Prod>(items, begins, n, prod, blockIdx.x);
+}
+
+// Front half of a served step in one launch: waves [0, blocks) run the step's
+// append rounds exactly as batch_insert_kernel; the next waves, one per array,
+// scan the sizes of the arrays that the step's r/w and flatten requests read.
+template <typename T>
+__global__ __launch_bounds__(64) void serve_front_kernel(const BatchArr* items, const uint64_t* begins, uint32_t n_a,
+                                                         uint64_t blocks, const ServeItem* sitems, uint32_t te_log2,
+                                                         ProdKeyed<T> prod) {
+  const uint64_t blk = blockIdx.x;
+  if (blk >= blocks) {
+    scan_array_wave(sitems[blk - blocks].A, te_log2);
+    return;
+  }
+  batch_wave<T, ProdKeyed<T>>(items, begins, n_a, prod, blk);
+}
+
+// ------------------------------------------ dense rounds: grow, then store --
+// When every logical thread of a round inserts exactly one element, LFVector v
+// receives exactly the threads of its chunk, so its growth is known before any
+// element is produced.  Such a round runs as the two phases the paper times
+// separately (Table II: grow, then insert): grow_kernel allocates every bucket
+// the round reaches (one wave per LFVector, one lane per bucket) and moves the
+// size, keeping the old one in rbase; dense_insert_kernel then has one wave per
+// tile store its elements from rbase[v] + t * kInsertTile on.  No tile waits on
+// another and no atomic is taken outside the pool.  An LFVector whose growth
+// fails is frozen with its size unchanged (its round is dropped), as in the
+// single-kernel path.
+__global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (v >= A.V) return;
+  const uint32_t lane = lane_id();
+  const uint64_t c0 = (uint64_t)v * I.chunk;
+  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
+  if (cnt == 0 || A.dead[v]) return;
+  const uint64_t s0 = A.size[v];
+  const uint32_t lo = nbuckets_for(A.log2F, s0), hi = nbuckets_for(A.log2F, s0 + cnt);
+  const uint32_t b = lo + lane;
+  bool failed = false;
+  if (b < hi) {
+    if (b >= (uint32_t)kMaxBuckets) {
+      failed = true;
+    } else {
+      uint8_t* q = pool_alloc(A.pool, bucket_class(A.log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
+      A.bptr[(uint64_t)v * kMaxBuckets + b] = q ? (uint64_t)q : kFailedPtr;
+      failed = !q;
+    }
+  }
+  if (__ballot(failed)) {
+    if (lane == 0) {
+      set_error(A.err, kErrNoMem);
+      A.dead[v] = 1u;
+    }
+  } else if (lane == 0) {
+    A.rbase[v] = s0;
+    A.size[v] = s0 + cnt;
+  }
+}
+
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void dense_insert_kernel(ArrRef A, TileArgs I, Prod prod) {
+  const uint64_t block = blockIdx.x;
+  const uint32_t v = (uint32_t)(block / I.tpv);
+  const uint64_t t = block - (uint64_t)v * I.tpv;
+  uint64_t g0, gend;
+  tile_range(I, v, t, kWaveTile, g0, gend);
+  if (g0 >= gend || A.dead[v]) return;
+  const uint32_t n = gend - g0 < (uint64_t)kWaveTile ? (uint32_t)(gend - g0) : (uint32_t)kWaveTile;
+  const uint32_t log2F = A.log2F;
+  const uint64_t base = A.rbase[v] + t * (uint64_t)kWaveTile;
+  for (uint32_t i = 0; i < n;) {  // one run per bucket the tile reaches
+    const uint64_t idx = base + i;
+    const uint32_t b = bucket_of(log2F, idx);
+    const uint64_t bs = bucket_start(log2F, b);
+    const uint64_t room = bs + bucket_len(log2F, b) - idx;
+    const uint32_t run = (uint64_t)(n - i) < room ? n - i : (uint32_t)room;
+    T* dst = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + (idx - bs);
+    dense_store<T, Prod>(dst, prod, g0 + i, run);
+    i += run;
+  }
 }
 
 // --------------------------------------------- multi-element producer kernel --
@@ -711,6 +841,29 @@ int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const Inser
 
 bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePoisson; }
 
+template <typename T>
+int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(grow_kernel, dim3((A.V + 3) / 4), dim3(256), 0, s, A, I);
+  const dim3 grid((uint32_t)ntiles), block(64);
+  switch (d.mode) {
+    case kModeBuffer:
+      hipLaunchKernelGGL((dense_insert_kernel<T, ProdBuffer<T>>), grid, block, 0, s, A, I,
+                         ProdBuffer<T>{static_cast<const T*>(d.values), nullptr});
+      break;
+    case kModeRoundTag:
+      hipLaunchKernelGGL((dense_insert_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, A, I,
+                         ProdRoundTag<T>{d.round, d.tag_shift});
+      break;
+    case kModeKeyed:
+      hipLaunchKernelGGL((dense_insert_kernel<T, ProdKeyed<T>>), grid, block, 0, s, A, I,
+                         ProdKeyed<T>{d.seed, d.round, d.tag_shift, d.tag});
+      break;
+    default:
+      return GGA_EINVAL;
+  }
+  return hip_status(hipGetLastError());
+}
+
 // Look-back words (needed only when an LFVector spans several tiles): grown on
 // demand and zeroed when new (a zero word is never current).  Their epochs come
 // from the ticket words, so launches need no host-side state and a captured
@@ -745,16 +898,23 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   // round-relative 32-bit values).
   if (chunk * (multi_mode(d.mode) ? d.max_count : 1u) >= (1ull << 32)) return GGA_EINVAL;
 
-  if (tpv > 1) {
-    const int rc = ensure_status(a, ntiles, s);
-    if (rc) return rc;
-  }
-
   TileArgs I;
   I.n_threads = d.n_threads;
   I.chunk = chunk;
   I.tpv = tpv;
   I.elem_log2 = a->elem_log2;
+  const bool dense = d.mode == kModeRoundTag || d.mode == kModeKeyed || (d.mode == kModeBuffer && !d.flags);
+  if (dense) {
+    const int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
+                                      : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
+    if (st == GGA_OK) a->prefix_valid = false;
+    return st;
+  }
+
+  if (tpv > 1) {
+    const int rc = ensure_status(a, ntiles, s);
+    if (rc) return rc;
+  }
   StaticRef S{};
   const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
                                     : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
@@ -802,16 +962,19 @@ int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, Bat
   return GGA_OK;
 }
 
-int launch_keyed_items(const BatchArr* items, const uint64_t* begins, uint32_t n, uint64_t blocks,
-                       uint32_t elem_bytes, uint64_t seed, uint32_t round, uint32_t shift, hipStream_t s) {
-  if (!blocks) return GGA_OK;
-  if (blocks > 0x7FFFFFFFull) return GGA_EINVAL;
-  const dim3 grid((uint32_t)blocks), block(64);
+int launch_serve_front(const BatchArr* items, const uint64_t* begins, uint32_t n_a, uint64_t blocks,
+                       const ServeItem* sitems, uint32_t n_s, uint32_t elem_bytes, uint64_t seed, uint32_t round,
+                       uint32_t shift, hipStream_t s) {
+  const uint64_t waves = blocks + n_s;
+  if (!waves) return GGA_OK;
+  if (waves > 0x7FFFFFFFull) return GGA_EINVAL;
+  const uint32_t te_log2 = elem_bytes == 4 ? 12u : 11u;
+  const dim3 grid((uint32_t)waves), block(64);
   if (elem_bytes == 4)
-    hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdKeyed<uint32_t>>), grid, block, 0, s, items, begins, n,
+    hipLaunchKernelGGL(serve_front_kernel<uint32_t>, grid, block, 0, s, items, begins, n_a, blocks, sitems, te_log2,
                        ProdKeyed<uint32_t>{seed, round, shift, 0});
   else
-    hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdKeyed<uint64_t>>), grid, block, 0, s, items, begins, n,
+    hipLaunchKernelGGL(serve_front_kernel<uint64_t>, grid, block, 0, s, items, begins, n_a, blocks, sitems, te_log2,
                        ProdKeyed<uint64_t>{seed, round, shift, 0});
   return hip_status(hipGetLastError());
 }
@@ -827,18 +990,36 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   }
   int rc = GGA_OK;
   uint64_t blocks = 0;
+  bool grew = false;
   for (uint32_t i = 0; i < b->n && rc == GGA_OK; ++i) {
     uint64_t ntiles = 0;
+    const uint64_t* before = b->arrays[i]->ref.status;
     rc = prepare_round_item(b->arrays[i], n_threads[i], d.tag + i, i, &items[i], &ntiles, s);
+    grew = grew || b->arrays[i]->ref.status != before;
     if (rc == GGA_OK && blocks + ntiles > 0x7FFFFFFFull) rc = GGA_EINVAL;
     begins[i] = blocks;
     blocks += ntiles;
   }
   begins[b->n] = blocks;
+  // A table is keyed by the round's shape, without the look-back buffers; when an
+  // array's buffer moves (it grew), every cached table is patched and uploaded
+  // again now, so that a later capture of a known shape uploads nothing.
+  for (uint32_t k = 0; grew && rc == GGA_OK && k < b->n_tables; ++k) {
+    gga_batch::Table& t = b->tables[k];
+    for (uint32_t i = 0; i < b->n; ++i) t.host[i].A.status = b->arrays[i]->ref.status;
+    if (hipMemcpyAsync(t.items, t.host, sizeof(BatchArr) * b->n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = GGA_EHIP;
+  }
   gga_batch::Table* tab = nullptr;
   if (rc == GGA_OK && blocks) {
-    const uint64_t key = fnv1a(begins, sizeof(uint64_t) * (b->n + 1),
-                               fnv1a(items, sizeof(BatchArr) * b->n, 0xCBF29CE484222325ull));
+    uint64_t key = 0xCBF29CE484222325ull;
+    for (uint32_t i = 0; i < b->n; ++i) {
+      BatchArr shape = items[i];
+      shape.A.status = nullptr;
+      key = fnv1a(&shape, sizeof(BatchArr), key);
+    }
+    key = fnv1a(begins, sizeof(uint64_t) * (b->n + 1), key);
     for (uint32_t k = 0; k < b->n_tables; ++k)
       if (b->tables[k].key == key) tab = &b->tables[k];
     if (!tab) {  // first time this round shape is seen: upload its table
@@ -854,14 +1035,18 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
         }
       }
       if (rc == GGA_OK) {
-        gga_batch::Table t{key, blocks, nullptr, nullptr};
-        if (hipMalloc(&t.items, sizeof(BatchArr) * b->n) != hipSuccess ||
+        gga_batch::Table t{key, blocks, nullptr, nullptr, new (std::nothrow) BatchArr[b->n]};
+        if (!t.host || hipMalloc(&t.items, sizeof(BatchArr) * b->n) != hipSuccess ||
             hipMalloc(&t.begins, sizeof(uint64_t) * (b->n + 1)) != hipSuccess ||
             hipMemcpyAsync(t.items, items, sizeof(BatchArr) * b->n, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(t.begins, begins, sizeof(uint64_t) * (b->n + 1), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
+          if (t.items) (void)hipFree(t.items);
+          if (t.begins) (void)hipFree(t.begins);
+          delete[] t.host;
           rc = GGA_EHIP;
         } else {
+          for (uint32_t i = 0; i < b->n; ++i) t.host[i] = items[i];
           b->tables[b->n_tables++] = t;
           tab = &b->tables[b->n_tables - 1];
         }

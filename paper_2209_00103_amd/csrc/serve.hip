@@ -77,11 +77,14 @@ struct Ring {
 
 struct Lane {
   hipStream_t s = nullptr;
-  hipEvent_t ev = nullptr;
-  uint8_t* h_stage = nullptr;  // pinned staging of the step table
-  uint8_t* d_block = nullptr;  // device copy of the table, then the scan outputs
-  std::vector<uint32_t> reqs;  // requests of the step in flight
+  hipEvent_t ev_a = nullptr;     // the step's appends (and scans) are done
+  hipEvent_t ev = nullptr;       // the whole step is done
+  uint8_t* h_stage = nullptr;    // pinned staging of the step table
+  uint8_t* d_block = nullptr;    // device copy of the table, then the scan outputs
+  std::vector<uint32_t> a_reqs;  // appends of the step in flight
+  std::vector<uint32_t> reqs;    // its r/w and flatten requests
   bool busy = false;
+  bool a_done = false;
 };
 
 uint64_t now_ns(std::chrono::steady_clock::time_point t0) {
@@ -121,6 +124,7 @@ void destroy_server(gga_server* sv) {
   for (Lane& l : sv->lanes) {
     if (l.s) hipStreamSynchronize(l.s);
     if (l.ev) hipEventDestroy(l.ev);
+    if (l.ev_a) hipEventDestroy(l.ev_a);
     if (l.h_stage) hipHostFree(l.h_stage);
     if (l.d_block) hipFree(l.d_block);
     if (l.s) hipStreamDestroy(l.s);
@@ -219,7 +223,7 @@ int run_batched(RunState& R) {
   std::vector<BatchArr> items;
   std::vector<uint64_t> begins;
   std::vector<ServeItem> sitems;
-  std::vector<uint32_t> reqs;
+  std::vector<uint32_t> reqs, a_reqs;
   uint64_t next = 0;
   const uint64_t n = tr->n;
 
@@ -237,6 +241,20 @@ int run_batched(RunState& R) {
     }
     for (Lane& l : sv->lanes) {
       if (!l.busy) continue;
+      if (!l.a_done) {  // appends finish before the step's streaming launch
+        const hipError_t e = hipEventQuery(l.ev_a);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return GGA_EHIP;
+        const uint64_t tc = now_ns(R.t0);
+        for (uint32_t r : l.a_reqs) {
+          R.finish(r, tc);
+          const uint32_t a = tr->target[r];
+          busy[a] = 0;
+          requeue(a);
+        }
+        l.a_reqs.clear();
+        l.a_done = true;
+      }
       const hipError_t e = hipEventQuery(l.ev);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) return GGA_EHIP;
@@ -256,8 +274,9 @@ int run_batched(RunState& R) {
       begins.clear();
       sitems.clear();
       reqs.clear();
+      a_reqs.clear();
       uint64_t blocks = 0, grid = 0;
-      while (reqs.size() < sv->cfg.max_step && !ready.empty()) {
+      while (reqs.size() + a_reqs.size() < sv->cfg.max_step && !ready.empty()) {
         const Head h = ready.top();
         const uint32_t a = h.second;
         if (busy[a] || q[a].empty() || tr->arrival_ns[q[a].front()] != h.first) {
@@ -270,8 +289,8 @@ int run_batched(RunState& R) {
         if (tr->kind[r] == GGA_REQ_APPEND) {
           const uint64_t len = tr->length[r];
           const uint64_t chunk = (len + arr->V - 1) / arr->V;
-          ntiles = (chunk + 4095) / 4096 * arr->V;
-          if (!reqs.empty() && blocks + ntiles > 0x7FFFFFFFull) break;  // the step is full
+          ntiles = (chunk + kInsertTile - 1) / kInsertTile * arr->V;
+          if (!items.empty() && blocks + ntiles > 0x7FFFFFFFull - sv->cfg.max_step) break;  // the step is full
         }
         uint64_t off = kNone;
         const uint64_t s_before = R.size[a];
@@ -288,8 +307,8 @@ int run_batched(RunState& R) {
           continue;
         }
         busy[a] = 1;
-        reqs.push_back(r);
         const uint8_t kind = tr->kind[r];
+        (kind == GGA_REQ_APPEND ? a_reqs : reqs).push_back(r);
         if (kind == GGA_REQ_APPEND) {
           BatchArr it;
           const int rc = prepare_round_item(arr, tr->length[r], r, (uint32_t)items.size(), &it, &ntiles, l.s);
@@ -311,7 +330,7 @@ int run_batched(RunState& R) {
           arr->prefix_valid = true;
         }
       }
-      if (reqs.empty()) continue;
+      if (reqs.empty() && a_reqs.empty()) continue;
       begins.push_back(blocks);
       const uint32_t n_a = (uint32_t)items.size(), n_s = (uint32_t)sitems.size();
       const TableLayout L = layout(n_a, n_s);
@@ -325,21 +344,27 @@ int run_batched(RunState& R) {
       uint64_t* d_elem = d_tile + sv->cfg.max_step + 1;
       uint32_t* d_err = reinterpret_cast<uint32_t*>(d_elem + sv->cfg.max_step + 1);
       if (hipMemcpyAsync(d, l.h_stage, L.used, hipMemcpyHostToDevice, l.s) != hipSuccess) return GGA_EHIP;
-      int rc = launch_keyed_items(reinterpret_cast<const BatchArr*>(d), reinterpret_cast<const uint64_t*>(d + L.begins),
-                                  n_a, blocks, sv->elem_bytes, sv->cfg.seed, sv->cfg.append_round,
+      const ServeItem* d_sitems = reinterpret_cast<const ServeItem*>(d + L.sitems);
+      int rc = launch_serve_front(reinterpret_cast<const BatchArr*>(d), reinterpret_cast<const uint64_t*>(d + L.begins),
+                                  n_a, blocks, d_sitems, n_s, sv->elem_bytes, sv->cfg.seed, sv->cfg.append_round,
                                   sv->cfg.append_shift, l.s);
       if (rc) return rc;
-      rc = launch_serve_stream(reinterpret_cast<const ServeItem*>(d + L.sitems), n_s, d_tile, d_elem, d_err,
-                               sv->elem_bytes, (uint32_t)std::min<uint64_t>(grid, 1u << 20), l.s);
+      if (hipEventRecord(l.ev_a, l.s) != hipSuccess) return GGA_EHIP;
+      rc = launch_serve_stream(d_sitems, n_s, d_tile, d_elem, d_err, sv->elem_bytes,
+                               (uint32_t)std::min<uint64_t>(grid, 1u << 20), l.s);
       if (rc) return rc;
       if (hipEventRecord(l.ev, l.s) != hipSuccess) return GGA_EHIP;
       const uint64_t ti = now_ns(R.t0);
       for (uint32_t r : reqs) R.t_issue[r] = ti;
+      for (uint32_t r : a_reqs) R.t_issue[r] = ti;
+      const uint64_t in_step = reqs.size() + a_reqs.size();
       l.reqs.swap(reqs);
+      l.a_reqs.swap(a_reqs);
       l.busy = true;
+      l.a_done = false;
       ++R.steps;
-      R.issued += l.reqs.size();
-      if (l.reqs.size() > R.largest) R.largest = l.reqs.size();
+      R.issued += in_step;
+      if (in_step > R.largest) R.largest = in_step;
     }
   }
   return GGA_OK;
@@ -459,6 +484,7 @@ int gga_server_create(gga_server** out, ggarray* const* arrays, uint32_t n, void
     if (!ok) break;
     ok = hipStreamCreateWithFlags(&l.s, hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&l.ev, hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&l.ev_a, hipEventDisableTiming) == hipSuccess &&
          hipHostMalloc(reinterpret_cast<void**>(&l.h_stage), sv->table_bytes, hipHostMallocDefault) == hipSuccess &&
          hipMalloc(reinterpret_cast<void**>(&l.d_block), block) == hipSuccess &&
          hipMemset(l.d_block, 0, block) == hipSuccess;

@@ -59,6 +59,8 @@ _SIGS = {
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_rw": [_vp, _u32, _vp],
     "ggarray_flatten": [_vp, _vp, _u64, _vp],
+    "ggarray_rw_global": [_vp, _u32, _vp],
+    "ggarray_gather": [_vp, _vp, _u64, _vp, _vp],
     "ggarray_size": [_vp, _P(_u64), _vp],
     "ggarray_capacity": [_vp, _P(_u64), _vp],
     "ggarray_vector_sizes": [_vp, _vp, _vp],
@@ -237,6 +239,19 @@ class GGArray:
 
     def rw(self, op: int, stream=None):
         _check(lib().ggarray_rw(self._h, op, _stream(stream)), "ggarray_rw")
+
+    def rw_global(self, op: int, stream=None):
+        _check(lib().ggarray_rw_global(self._h, op, _stream(stream)), "ggarray_rw_global")
+
+    def gather(self, idx: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """out[k] = element at global index idx[k] (idx: device int64 tensor)."""
+        n = idx.numel()
+        if out is None:
+            out = torch.zeros(n, dtype=_dtype(self.elem_bytes), device=idx.device)
+        _check(lib().ggarray_gather(self._h, _dev_ptr(idx, "idx", n, 8), n,
+                                    _dev_ptr(out, "out", n, self.elem_bytes), _stream(stream)),
+               "ggarray_gather")
+        return out
 
     def flatten_into(self, out: torch.Tensor, stream=None):
         _check(lib().ggarray_flatten(self._h, _dev_ptr(out, "out", 0, self.elem_bytes), out.numel(),

@@ -313,3 +313,36 @@ def test_served_invalid_arguments():
             arr.close()
     finally:
         pool.close()
+
+
+def test_served_step_wider_than_fused_limit():
+    """A step with more r/w and flatten requests than one workgroup's offset table
+    holds (4096) takes the two-launch path; results equal the oracle."""
+    G = gg()
+    n_arr = 4500
+    sizes = np.array([1 + (a * 37) % 300 for a in range(n_arr)], dtype=np.int64)
+    kind = np.array([wl.REQ_RW] * n_arr + [wl.REQ_FLATTEN] * n_arr + [wl.REQ_APPEND] * n_arr, np.uint8)
+    target = np.tile(np.arange(n_arr, dtype=np.uint32), 3)
+    length = np.where(kind == wl.REQ_APPEND, 5, 0).astype(np.uint32)
+    tr = dict(kind=kind, target=target, length=length)
+    pool = G.Pool(256 * MiB)
+    try:
+        arrays = _resident(pool, sizes)
+        res = _run(arrays, tr, np.zeros(kind.size, np.uint64), _flatten_bytes(sizes, tr) + 4096, 1 << 40,
+                   mode=G.SERVE_BATCHED, lanes=2, max_step=8192)
+        assert (res["status"] == 0).all() and res["largest_step"] > 4096
+        outs = _outputs(res, tr)
+        fin = _finals(arrays)
+        for a in range(0, n_arr, 97):
+            o = Oracle(ELEM, *[x[a] for x in _shapes(sizes)], forms=oracle.FORM_LIST)
+            o.insert_gen(oracle.GEN_KEYED, int(sizes[a]), seed=SEED, round=wl.CFG5["fill_round"], tag=a)
+            o.rw(oracle.OP_ADD1)
+            assert np.array_equal(outs[n_arr + a], o.flatten()), f"flatten of array {a}"
+            o.insert_gen(oracle.GEN_KEYED, 5, seed=SEED, round=wl.CFG5["append_round"],
+                         tag_shift=wl.CFG5["append_shift"], tag=2 * n_arr + a)
+            assert np.array_equal(fin[a], o.flatten()), f"array {a}"
+            o.close()
+        for arr in arrays:
+            arr.close()
+    finally:
+        pool.close()

@@ -365,3 +365,24 @@ def test_gen_keyed_shift_limits():
     with pytest.raises(Exception):  # more threads than the shift leaves room for
         a.insert_gen(oracle.GEN_KEYED, 17, seed=1, round=0, tag_shift=4)
     assert a.size() == 16
+
+
+@pytest.mark.parametrize("forms", [oracle.FORM_LIST, oracle.FORM_BUCKETS])
+def test_at_equals_flatten_index(forms):
+    # access by global index is the element at that position of the flattened
+    # order; empty LFVectors (here most of them after a small round) are skipped
+    a = Oracle(4, 37, 4, forms=forms)
+    rng = np.random.default_rng(2)
+    for n in (20, 0, 3000, 777):
+        vals, flags = wl.random_round(rng, n, 0.6, 4)
+        a.insert(vals, flags)
+        a.shrink(1, 7)
+        flat = a.flatten()
+        assert [a.at(i) for i in range(flat.size)] == [int(x) for x in flat]
+        assert a.at(flat.size) is None and a.at(1 << 40) is None
+    idx = np.array([0, 5, flat.size - 1, flat.size, 2, 1 << 50], dtype=np.uint64)
+    out, rc = a.gather(idx, fill=0xDEAD)
+    assert rc == oracle.ERANGE
+    assert list(out) == [flat[0], flat[5], flat[-1], 0xDEAD, flat[2], 0xDEAD]
+    out, rc = a.gather(np.arange(flat.size, dtype=np.uint64))
+    assert rc == oracle.OK and np.array_equal(out, flat)
