@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg and its parity check")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (512-array) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served (4096-array request loop) leg")
+    ap.add_argument("--no-two-phase", action="store_true", help="skip the growth-then-work case study")
+    ap.add_argument("--no-shootout", action="store_true",
+                    help="skip the scan-vs-atomic insertion comparison and the memory model")
     ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
     ap.add_argument("--serve-lanes", type=int, default=2, help="served steps in flight")
     ap.add_argument("--serve-step", type=int, default=1024, help="requests per served step")
@@ -373,6 +376,149 @@ def served_leg(G, wl, torch, np_, args):
             "saturation": sat, "saturation_per_request": sat_pr, "low_load": low, "loads": loads}
 
 
+def mapped_baseline(G, torch, gens, rounds, steps):
+    """The mapped (memMap) array on the configuration-2 rounds (no shrink) and r/w."""
+    map_ins, map_rw, maps = [], [], 0
+    for rep in range(max(2, min(steps, 3)) + 1):
+        mp = G.MappedArray(ELEM, 1 << 28)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, n in enumerate(rounds):
+            mp.insert_gen(gens[r], n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mp.rw(G.MUL3ADD1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep > 0:
+            map_ins.append(t1 - t0)
+            map_rw.append(t2 - t1)
+        maps = mp.maps()
+        assert mp.size() == 1 << 28
+        mp.close()
+    return {"insert_Gelem_s": (1 << 28) / statistics.mean(map_ins) / 1e9,
+            "rw_GBps": 2 * ELEM * (1 << 28) / statistics.mean(map_rw) / 1e9,
+            "maps": maps, "timing": "host wall clock (growth synchronises)"}
+
+
+def two_phase_leg(G, torch, rounds, gens, V, ks=(1, 10, 100)):
+    """The two-phase pattern of Sec. VI-D: a growth phase (the configuration-2
+    rounds, 2^28 uint32 insertions with shrink 1/10) then a work phase of k passes
+    of x = x + 1 over the result.  Three ways: (a) GGArray, flatten, work on the
+    flat copy; (b) GGArray, work on the GGArray itself; (c) the mapped array, work
+    on it.  Device time of the whole pattern (HIP events), one run per k."""
+    out = {}
+    pool = G.Pool(8 << 30)
+    arr = G.GGArray(pool, ELEM, V, F)
+    flat = None
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def grow():
+        for r, n in enumerate(rounds):
+            arr.insert_gen(gens[r], n)
+            arr.shrink(1, 10)
+
+    grow()  # warm-up (sizes the flat buffer)
+    size = arr.size()
+    flat = torch.empty(size, dtype=torch.int32, device="cuda")
+    arr.shrink(1, 1)
+    for k in ks:
+        row = {}
+        for mode in ("flatten_then_static", "ggarray"):
+            torch.cuda.synchronize()
+            e0.record()
+            grow()
+            if mode == "flatten_then_static":
+                arr.flatten_into(flat)
+                for _ in range(k):
+                    flat.add_(1)
+            else:
+                for _ in range(k):
+                    arr.rw(G.ADD1)
+            e1.record()
+            torch.cuda.synchronize()
+            row[mode + "_ms"] = e0.elapsed_time(e1)
+            arr.shrink(1, 1)
+        mp = G.MappedArray(ELEM, 1 << 28)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r, n in enumerate(rounds):
+            mp.insert_gen(gens[r], n)
+        for _ in range(k):
+            mp.rw(G.ADD1)
+        torch.cuda.synchronize()
+        row["mapped_ms_wall"] = (time.perf_counter() - t0) * 1e3
+        mp.close()
+        row["speedup_flatten_vs_mapped"] = row["mapped_ms_wall"] / row["flatten_then_static_ms"]
+        out[str(k)] = row
+    arr.close()
+    pool.close()
+    return {"workload": "growth: configuration-2 rounds (2^28 uint32, shrink 1/10 per round; the mapped array "
+                        "has no shrink); work: k passes of x + 1", "k": out,
+            "note": "(a) and (b) device time between events; (c) host wall clock, since mapping synchronises; "
+                    "the flat copy's work pass is torch's in-place add"}
+
+
+def shootout_leg(G, torch, reps=3):
+    """The insertion-strategy comparison of Sec. VI-A on the static array: the
+    block scan (one atomic per tile of 4096 threads) against one atomic per
+    inserted element, for 2^20 .. 2^30 threads (10 doublings), every thread
+    inserting with probability 1/2 (generated payloads)."""
+    st = G.StaticArray(1 << 30, ELEM)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for k in range(11):
+        n = 1 << (20 + k)
+        row = {"threads": n}
+        for name, call in (("scan", st.insert_gen), ("atomic", st.insert_gen_atomic)):
+            ts = []
+            for rep in range(reps + 1):
+                st.clear()
+                g = G.make_gen(G.GEN_BERNOULLI, seed=1, round=rep)
+                torch.cuda.synchronize()
+                e0.record()
+                call(g, n)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep:
+                    ts.append(e0.elapsed_time(e1))
+            row[name + "_us"] = 1e3 * statistics.median(ts)
+            row[name + "_Gthreads_s"] = n / (statistics.median(ts) * 1e-3) / 1e9
+        assert st.last_error() == 0
+        row["scan_speedup"] = row["atomic_us"] / row["scan_us"]
+        rows.append(row)
+    st.close()
+    return {"workload": "static array, 2^20..2^30 threads, each inserting K(1,gid,r) with probability 1/2",
+            "rows": rows}
+
+
+def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=6):
+    """The memory comparison of Sec. V (Fig. 3), measured: a workload inserts
+    N * LogNormal(0, sigma) elements.  A static array must be sized in advance;
+    sized to fail at most 1% of the time it holds N * e^(2.326 sigma).  The
+    GGArray (V = 512, F = 1024) is grown to the drawn size and its capacity read
+    back.  Reported per sigma: mean allocated / live for both."""
+    rng = np_.random.default_rng(1)
+    pool = G.Pool(4 << 30)
+    rows = []
+    z99 = 2.3263478740408408
+    for sigma in [0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0]:
+        x = np_.maximum(1, np_.rint(N * np_.exp(sigma * rng.standard_normal(samples)))).astype(np_.int64)
+        static_cap = N * float(np_.exp(z99 * sigma))
+        gg_ratio, st_ratio = [], []
+        for n in x:
+            a = G.GGArray(pool, ELEM, V, F)
+            a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=0, tag_shift=40), int(n))
+            gg_ratio.append(a.capacity() / int(n))
+            st_ratio.append(static_cap / int(n))
+            a.close()
+        rows.append({"sigma": sigma, "ggarray_capacity_over_live": float(np_.mean(gg_ratio)),
+                     "static_1pct_capacity_over_live": float(np_.mean(st_ratio)),
+                     "static_fits_fraction": float(np_.mean(x <= static_cap))})
+    pool.close()
+    return {"workload": f"N = {N}, {samples} draws per sigma, GGArray V = {V}, F = {F}", "rows": rows}
+
+
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
     """The CPU oracle (list form, one thread) on the full workload, repeated until
     about min_seconds of work; returns (Gelem/s, seconds per pass, last flatten)."""
@@ -576,9 +722,15 @@ def main():
         baselines["semi_static"] = {"insert_Gelem_s": (1 << 28) / statistics.mean(sem_ins) / 1e9,
                                     "rw_GBps": 2 * ELEM * (1 << 28) / statistics.mean(sem_rw) / 1e9,
                                     "resizes": resizes, "timing": "host wall clock (resizes synchronise)"}
+        try:
+            baselines["mapped"] = mapped_baseline(G, torch, gens, rounds, args.steps)
+        except Exception as e:  # reported, never silently dropped
+            baselines["mapped"] = {"error": str(e)}
+            log(f"mapped baseline failed: {e}")
         log(f"static insert {baselines['static']['insert_Gelem_s']:.1f} Gelem/s rw "
             f"{baselines['static']['rw_GBps']:.0f} GB/s; semi-static insert "
-            f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s")
+            f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s; mapped "
+            f"{baselines['mapped'].get('insert_Gelem_s', baselines['mapped'].get('error'))}")
 
     arr.close()
     pool.close()
@@ -589,6 +741,33 @@ def main():
         log(f"batched: one launch per phase {t['batched']['mean_ms']:.3f} ms (graph {t['batched_graph']['mean_ms']:.3f}),"
             f" per-array launches {t['per_array']['mean_ms']:.3f} ms (graph {t['per_array_graph']['mean_ms']:.3f});"
             f" identical {batched['batched_equals_per_array']}")
+    shootout = memory_model = None
+    if not args.no_shootout:
+        try:
+            shootout = shootout_leg(G, torch)
+            log("shootout scan/atomic speedup: " + ", ".join(f"2^{20 + i}: {r['scan_speedup']:.2f}"
+                                                          for i, r in enumerate(shootout["rows"])))
+        except Exception as e:  # reported, never silently dropped
+            shootout = {"error": str(e)}
+            log(f"shootout failed: {e}")
+        try:
+            memory_model = memory_model_leg(G, torch, np)
+            log("memory model: " + ", ".join(f"s={r['sigma']}: gg {r['ggarray_capacity_over_live']:.2f} "
+                                             f"static {r['static_1pct_capacity_over_live']:.2f}"
+                                             for r in memory_model["rows"]))
+        except Exception as e:
+            memory_model = {"error": str(e)}
+            log(f"memory model failed: {e}")
+    two_phase = None
+    if not args.no_two_phase:
+        try:
+            two_phase = two_phase_leg(G, torch, rounds, gens, V)
+            log("two-phase: " + "; ".join(f"k={k}: flatten+static {r['flatten_then_static_ms']:.2f} ms, ggarray "
+                                          f"{r['ggarray_ms']:.2f} ms, mapped {r['mapped_ms_wall']:.2f} ms"
+                                          for k, r in two_phase["k"].items()))
+        except Exception as e:  # reported, never silently dropped
+            two_phase = {"error": str(e)}
+            log(f"two-phase leg failed: {e}")
     served = None
     if not args.no_served:
         served = served_leg(G, wl, torch, np, args)
@@ -629,6 +808,9 @@ def main():
         "batched": batched,
         "served": served,
         "global_index_access": next_rows,
+        "two_phase": two_phase,
+        "insertion_shootout": shootout,
+        "memory_model": memory_model,
     }
     print(json.dumps(line), flush=True)
 

@@ -58,6 +58,7 @@ typedef struct gga_pool gga_pool;
 typedef struct ggarray ggarray;
 typedef struct gga_static gga_static;
 typedef struct gga_semistatic gga_semistatic;
+typedef struct gga_mapped gga_mapped;
 typedef struct gga_batch gga_batch;
 
 /* r/w operations (Sec. VI-C times an operation over every element; the paper's
@@ -86,6 +87,10 @@ typedef struct {
     uint64_t tag;            /* KEYED: tag (+ batch position) < 2^(48 - tag_shift),
                                 gid < 2^tag_shift (so the key stays below 2^48) */
 } gga_gen;
+
+/* The last HIP call that failed in this thread (name and HIP error), after a
+ * GGA_EHIP; a static per-thread string. */
+const char *gga_last_hip_error(void);
 
 /* Human-readable name of a status code (static string). */
 const char *gga_strerror(int status);
@@ -197,6 +202,20 @@ int ggarray_prefix(ggarray *a, uint64_t *dev_out, gga_stream s);
 /* ggarray_last_error: the sticky device error of the array (GGA_OK if none).
  *   Synchronises s.  Does not clear it. */
 int ggarray_last_error(ggarray *a, gga_stream s);
+
+/* ------------------------------------------------------ device-side API --- */
+/* For user kernels that push elements themselves with gga::block_push_back
+ * (include/ggarray_device.h, the block-cooperative push_back of Alg. 1 used from
+ * inside any kernel, as the paper intends the structure to be used).
+ *
+ * ggarray_device_ref: copies the array's device descriptor (a gga::ArrRef,
+ *   `bytes` must equal its size) to the host memory at out; pass it to the user
+ *   kernel by value.  It stays valid until the array is destroyed.
+ * ggarray_device_done: declares that kernels queued on s may have changed the
+ *   array's sizes, so the next operation rescans them (call it after queueing
+ *   such kernels, before any other call on the array). */
+int ggarray_device_ref(ggarray *a, void *out, uint64_t bytes);
+int ggarray_device_done(ggarray *a, gga_stream s);
 
 /* ---------------------------------------------------------------- batches --- */
 /* A batch drives many GGArrays together: one launch inserts a round into every
@@ -327,6 +346,10 @@ int gga_static_destroy(gga_static *st, gga_stream s);
 int gga_static_insert(gga_static *st, const void *values, const uint8_t *flags,
                       uint64_t n_threads, gga_stream s);
 int gga_static_insert_gen(gga_static *st, const gga_gen *g, uint64_t n_threads, gga_stream s);
+/* The per-element strategy the paper compares against the scan (Sec. VI-A):
+ * every inserting thread takes its slot with its own atomic add on the size.
+ * Kinds BERNOULLI, ROUND_TAG and KEYED.  Order across threads not fixed. */
+int gga_static_insert_gen_atomic(gga_static *st, const gga_gen *g, uint64_t n_threads, gga_stream s);
 int gga_static_rw(gga_static *st, uint32_t op, gga_stream s);
 int gga_static_size(gga_static *st, uint64_t *out_host, gga_stream s); /* synchronises */
 int gga_static_last_error(gga_static *st, gga_stream s);                /* synchronises */
@@ -351,6 +374,28 @@ int gga_semi_size(gga_semistatic *ss, uint64_t *out_host, gga_stream s); /* sync
 int gga_semi_data(gga_semistatic *ss, void **dev_data, uint64_t *cap_elems);
 /* Number of host-driven resizes so far. */
 int gga_semi_resizes(gga_semistatic *ss, uint64_t *out_host);
+
+/* ------------------------------------------- mapped (memMap) array baseline --- */
+/* The host-grown array without copies that the paper measures beside the
+ * semi-static one (Table II, memMap): a virtual range for max_elems elements is
+ * reserved once; before each insertion round the host reads the size and, if
+ * the round's worst case does not fit, maps more physical memory (whole
+ * allocation-granularity chunks covering the shortfall) onto the end of the
+ * mapped part, so growing never moves elements.  Insertion and r/w then run as
+ * for the static array.  A round that could pass max_elems returns GGA_ERANGE
+ * before anything runs.  GGA_EHIP if the device lacks virtual memory management.
+ * Destroy synchronises s, unmaps and releases everything. */
+int gga_mapped_create(gga_mapped **out, uint32_t elem_bytes, uint64_t max_elems, gga_stream s);
+int gga_mapped_destroy(gga_mapped *m, gga_stream s);
+int gga_mapped_insert(gga_mapped *m, const void *values, const uint8_t *flags, uint64_t n_threads,
+                      gga_stream s);
+int gga_mapped_insert_gen(gga_mapped *m, const gga_gen *g, uint64_t n_threads, gga_stream s);
+int gga_mapped_rw(gga_mapped *m, uint32_t op, gga_stream s);
+int gga_mapped_size(gga_mapped *m, uint64_t *out_host, gga_stream s); /* synchronises */
+/* Base of the range and the elements mapped so far (the range never moves). */
+int gga_mapped_data(gga_mapped *m, void **dev_data, uint64_t *mapped_elems);
+/* Number of host-driven mappings so far. */
+int gga_mapped_maps(gga_mapped *m, uint64_t *out_host);
 
 #ifdef __cplusplus
 }

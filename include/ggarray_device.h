@@ -1,11 +1,13 @@
-// Device-side layout and primitives of the GGArray library (gfx950).
+// Device-side layout and primitives of the GGArray library (gfx950), and the
+// device API for user kernels: gga::block_push_back, the block-cooperative
+// push_back of Alg. 1 callable from any HIP kernel (see the end of this file).
 //
 // Layout in HBM
 //   pool:   [PoolHdr | pad to 2 MiB | bucket region ...]   (caller-owned memory)
 //   array:  size[V] u64 | bptr[V][kMaxBuckets] u64 | dead[V] u32 |
 //           alloc_done[V] u32 | prefix[V+1] u64 | tprefix[V+1] u64 |
-//           vticket[V] u64 | err u32 | status[...] u64 (look-back words, grown
-//           on demand)
+//           vticket[V] u64 | rbase[V] u64 | err u32 | status[...] u64
+//           (look-back words, grown on demand)
 //
 // Bucket law (Alg. 2): bucket b of an LFVector holds F * 2^b elements, F a power
 // of two, so bucket b starts at local index F * (2^b - 1).  For local index i,
@@ -321,6 +323,93 @@ __device__ __forceinline__ T apply_op(uint32_t op, T x) {
   if (op == 0) return x + (T)1;
   if (op == 1) return x * (T)3 + (T)1;
   return x + (T)30;  // thirty increments by one, folded
+}
+
+// ------------------------------------------------------- device-side API --
+// Block-cooperative push_back (Alg. 1) for user kernels: the "fully in GPU" use
+// the paper designs the structure for.  Obtain the array's ArrRef on the host
+// with ggarray_device_ref, pass it to the kernel by value, and call
+// ggarray_device_done after the kernel is queued (the next size, r/w or flatten
+// then rescans the sizes).
+//
+// Every thread of the block must call block_push_back, the same number of times,
+// with the same LFVector v (the paper assigns one LFVector per block); thread t
+// inserts `value` iff keep.  The block's kept elements land at the end of
+// LFVector v in thread order; blocks that push to one LFVector concurrently get
+// disjoint ranges in the order of their single atomic add on its size, as in
+// the paper.  The bucket whose first index falls in a block's range is
+// allocated by that block (the Alg. 2 winner); blocks needing it wait for its
+// pointer.  Returns the element's local index in v, or ~0 for a thread that
+// does not insert.  If a bucket cannot be allocated the elements that would go
+// there are dropped, the LFVector is frozen and the array's sticky GGA_ENOMEM
+// is set (its contents past the failure are then unspecified).
+template <typename T>
+__device__ uint64_t block_push_back(const ArrRef& A, uint32_t v, bool keep, T value) {
+  __shared__ uint32_t s_wave[16];  // kept elements per wave (up to 1024 threads)
+  __shared__ uint64_t s_base;
+  __shared__ uint64_t s_bp[64];
+  __shared__ uint32_t s_blo;
+  const uint32_t tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const uint32_t nthreads = blockDim.x * blockDim.y * blockDim.z;
+  const uint32_t lane = tid & 63u, w = tid >> 6, nw = (nthreads + 63u) / 64u;
+  const uint64_t m = __ballot(keep);
+  const uint32_t rank_w = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  if (lane == 0) s_wave[w] = (uint32_t)__popcll(m);
+  __syncthreads();
+  uint32_t before = 0, n = 0;
+  for (uint32_t k = 0; k < nw; ++k) {
+    if (k < w) before += s_wave[k];
+    n += s_wave[k];
+  }
+  if (tid < 64) {  // wave 0: reserve the range, then allocate or wait for its buckets
+    uint64_t base = ~0ull;
+    if (tid == 0 && n && !ld_rlx32(&A.dead[v])) base = fetch_add(&A.size[v], n);
+    base = __shfl(base, 0, 64);
+    uint32_t b_lo = 0;
+    if (base != ~0ull) {
+      b_lo = bucket_of(A.log2F, base);
+      const uint32_t b = b_lo + tid;
+      uint64_t p = kFailedPtr;
+      if (b <= bucket_of(A.log2F, base + n - 1)) {
+        if (b < (uint32_t)kMaxBuckets) {
+          uint64_t* slot = &A.bptr[(uint64_t)v * kMaxBuckets + b];
+          if (bucket_start(A.log2F, b) >= base) {
+            uint8_t* q = pool_alloc(A.pool, bucket_class(A.log2F, sizeof(T) == 4 ? 2u : 3u, b),
+                                    pool_shard(v, b, A.salt));
+            p = q ? (uint64_t)q : kFailedPtr;
+            st_rlx(slot, p);
+          } else {
+            uint32_t spins = 0;
+            while ((p = ld_rlx(slot)) == 0 && spins < kSpinLimit) {
+              ++spins;
+              spin_pause();
+            }
+            if (p == 0) {
+              p = kFailedPtr;
+              set_error(A.err, kErrStall);
+            }
+          }
+        }
+        s_bp[tid] = p;
+        if (p <= kFailedPtr) {
+          set_error(A.err, kErrNoMem);
+          st_rlx32(&A.dead[v], 1u);
+        }
+      }
+    }
+    if (tid == 0) {
+      s_base = base;
+      s_blo = b_lo;
+    }
+  }
+  __syncthreads();
+  const uint64_t base = s_base;
+  if (!keep || base == ~0ull) return ~0ull;
+  const uint64_t idx = base + before + rank_w;
+  const uint32_t b = bucket_of(A.log2F, idx);
+  const uint64_t p = s_bp[b - s_blo];
+  if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(A.log2F, idx, b)] = value;
+  return idx;
 }
 
 }  // namespace gga

@@ -52,5 +52,20 @@ def build(extra: list[str] | None = None, verbose: bool = False) -> str:
     return LIB
 
 
+def build_test_kernels(verbose: bool = False) -> str:
+    """The test suite's user kernels for the device-side API (tests/device)."""
+    src = os.path.join(ROOT, "tests", "device", "push_kernels.hip")
+    lib = os.path.join(ROOT, "tests", "device", "libggtest.so")
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *CFLAGS, "-shared", src, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, lib)
+    if verbose:
+        print("built", lib)
+    return lib
+
+
 if __name__ == "__main__":
     build(sys.argv[1:], verbose=True)

@@ -3,6 +3,9 @@
 #include <cstddef>
 #include <new>
 
+#include <cstdio>
+#include <cstring>
+
 #include "gga_internal.h"
 
 using namespace gga;
@@ -21,6 +24,14 @@ int map_device_error(uint32_t e) {
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) & ~(a - 1); }
+
+// The last failing HIP call of this thread, for gga_last_hip_error.
+thread_local char g_hip_error[192] = "";
+int hip_fail(hipError_t e, const char* what) {
+  std::snprintf(g_hip_error, sizeof(g_hip_error), "%s: %s (%d)", what, hipGetErrorName(e), (int)e);
+  (void)hipGetLastError();  // clear it, so that a later launch check does not report it again
+  return GGA_EHIP;
+}
 
 // Per-array host scratch for synchronising reads (pinned, so copies are async).
 struct Pinned {
@@ -90,6 +101,8 @@ struct ggarray_full {
 };
 
 extern "C" {
+
+const char* gga_last_hip_error(void) { return g_hip_error; }
 
 const char* gga_strerror(int status) {
   switch (status) {
@@ -360,6 +373,20 @@ int ggarray_last_error(ggarray* a, gga_stream s) {
   return read_back(a, nullptr, nullptr, S(s));
 }
 
+// ------------------------------------------------------------ device API --
+int ggarray_device_ref(ggarray* a, void* out, uint64_t bytes) {
+  if (!a || !out || bytes != sizeof(ArrRef)) return GGA_EINVAL;
+  std::memcpy(out, &a->ref, sizeof(ArrRef));
+  return GGA_OK;
+}
+
+int ggarray_device_done(ggarray* a, gga_stream s) {
+  (void)s;
+  if (!a) return GGA_EINVAL;
+  a->prefix_valid = false;
+  return GGA_OK;
+}
+
 // ------------------------------------------------------------------- batches --
 static void batch_free(gga_batch* b) {
   if (b->d_arrays) (void)hipFree(b->d_arrays);
@@ -560,6 +587,15 @@ int gga_static_insert_gen(gga_static* st, const gga_gen* g, uint64_t n_threads, 
   return launch_static_insert(st, gen_desc(g, mode, n_threads), S(s));
 }
 
+int gga_static_insert_gen_atomic(gga_static* st, const gga_gen* g, uint64_t n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!st) return GGA_EINVAL;
+  const int rc = check_gen(g, n_threads, &mode, &maxc);
+  if (rc) return rc;
+  if (maxc != 1) return GGA_EINVAL;  // 0/1 producers only
+  return launch_static_insert_atomic(st, gen_desc(g, mode, n_threads), S(s));
+}
+
 int gga_static_rw(gga_static* st, uint32_t op, gga_stream s) {
   if (!st || op > GGA_ADD1_X30) return GGA_EINVAL;
   return launch_static_rw(st, op, S(s));
@@ -670,6 +706,171 @@ int gga_semi_data(gga_semistatic* ss, void** dev_data, uint64_t* cap_elems) {
 int gga_semi_resizes(gga_semistatic* ss, uint64_t* out_host) {
   if (!ss || !out_host) return GGA_EINVAL;
   *out_host = ss->resizes;
+  return GGA_OK;
+}
+
+// ----------------------------------------------------- mapped (memMap) array --
+static hipMemAllocationProp mapped_prop(int device) {
+  hipMemAllocationProp prop{};
+  prop.type = hipMemAllocationTypePinned;
+  prop.location.type = hipMemLocationTypeDevice;
+  prop.location.id = device;
+  return prop;
+}
+
+static void mapped_release(gga_mapped* m) {
+  uint64_t off = 0;
+  for (uint64_t k = 0; k < m->n_handles; ++k) {
+    (void)hipMemUnmap(static_cast<uint8_t*>(m->st.data) + off, m->handle_bytes[k]);
+    (void)hipMemRelease(m->handles[k]);
+    off += m->handle_bytes[k];
+  }
+  if (m->st.data) (void)hipMemAddressFree(m->st.data, m->va_bytes);
+  if (m->st.meta) (void)hipFree(m->st.meta);
+  delete[] m->handles;
+  delete[] m->handle_bytes;
+  delete m;
+}
+
+int gga_mapped_create(gga_mapped** out, uint32_t elem_bytes, uint64_t max_elems, gga_stream s) {
+  if (!out) return GGA_EINVAL;
+  *out = nullptr;
+  if ((elem_bytes != 4 && elem_bytes != 8) || max_elems == 0 || max_elems > (1ull << 40)) return GGA_EINVAL;
+  int dev = 0, vmm = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  e = hipDeviceGetAttribute(&vmm, hipDeviceAttributeVirtualMemoryManagementSupported, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  if (!vmm) return hip_fail(hipErrorNotSupported, "virtual memory management");
+  gga_mapped* m = new (std::nothrow) gga_mapped();
+  if (!m) return GGA_EHIP;
+  m->device = dev;
+  const hipMemAllocationProp prop = mapped_prop(dev);
+  size_t gran = 0;
+  e = hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityRecommended);
+  if (e != hipSuccess || !gran) {
+    delete m;
+    return hip_fail(e, "hipMemGetAllocationGranularity");
+  }
+  m->gran = gran;
+  m->va_bytes = align_up(max_elems * elem_bytes, gran);
+  void* va = nullptr;
+  e = hipMemAddressReserve(&va, m->va_bytes, gran, nullptr, 0);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "hipMemAddressReserve");
+  }
+  const int rc = static_init(&m->st, va, 0, elem_bytes, S(s));
+  if (rc) {
+    m->st.meta = nullptr;
+    mapped_release(m);
+    return rc;
+  }
+  *out = m;
+  return GGA_OK;
+}
+
+int gga_mapped_destroy(gga_mapped* m, gga_stream s) {
+  if (!m) return GGA_EINVAL;
+  const int rc = hip_status(hipStreamSynchronize(S(s)));
+  mapped_release(m);
+  return rc;
+}
+
+// Maps chunks onto the end of the mapped part until `worst` more elements fit.
+static int mapped_reserve(gga_mapped* m, uint64_t worst, hipStream_t s) {
+  uint64_t size = 0;
+  int rc = static_read(&m->st, &size, s);
+  if (rc) return rc;
+  const uint64_t need = (size + worst) * m->st.elem_bytes;
+  if (need <= m->mapped_bytes) return GGA_OK;
+  if (need > m->va_bytes) return GGA_ERANGE;
+  const uint64_t bytes = align_up(need - m->mapped_bytes, m->gran);
+  if (m->n_handles == m->cap_handles) {
+    const uint64_t nc = m->cap_handles ? 2 * m->cap_handles : 16;
+    auto* nh = new (std::nothrow) hipMemGenericAllocationHandle_t[nc];
+    auto* nb = new (std::nothrow) uint64_t[nc];
+    if (!nh || !nb) {
+      delete[] nh;
+      delete[] nb;
+      return GGA_EHIP;
+    }
+    for (uint64_t k = 0; k < m->n_handles; ++k) {
+      nh[k] = m->handles[k];
+      nb[k] = m->handle_bytes[k];
+    }
+    delete[] m->handles;
+    delete[] m->handle_bytes;
+    m->handles = nh;
+    m->handle_bytes = nb;
+    m->cap_handles = nc;
+  }
+  const hipMemAllocationProp prop = mapped_prop(m->device);
+  hipMemGenericAllocationHandle_t h;
+  hipError_t e = hipMemCreate(&h, bytes, &prop, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipMemCreate");
+  uint8_t* at = static_cast<uint8_t*>(m->st.data) + m->mapped_bytes;
+  e = hipMemMap(at, bytes, 0, h, 0);
+  if (e != hipSuccess) {
+    (void)hipMemRelease(h);
+    return hip_fail(e, "hipMemMap");
+  }
+  hipMemAccessDesc desc{};
+  desc.location = prop.location;
+  desc.flags = hipMemAccessFlagsProtReadWrite;
+  // Access is granted over the whole mapped prefix of the range: on this runtime
+  // a multi-granule chunk mapped past the start of a reservation rejects an
+  // access call that covers only itself, while one from the start succeeds.
+  e = hipMemSetAccess(m->st.data, m->mapped_bytes + bytes, &desc, 1);
+  if (e != hipSuccess) {
+    (void)hipMemUnmap(at, bytes);
+    (void)hipMemRelease(h);
+    return hip_fail(e, "hipMemSetAccess");
+  }
+  m->handles[m->n_handles] = h;
+  m->handle_bytes[m->n_handles] = bytes;
+  m->n_handles += 1;
+  m->mapped_bytes += bytes;
+  m->st.cap = m->mapped_bytes / m->st.elem_bytes;
+  m->maps += 1;
+  return GGA_OK;
+}
+
+int gga_mapped_insert(gga_mapped* m, const void* values, const uint8_t* flags, uint64_t n_threads, gga_stream s) {
+  if (!m || (n_threads && !values)) return GGA_EINVAL;
+  int rc = mapped_reserve(m, n_threads, S(s));
+  return rc ? rc : gga_static_insert(&m->st, values, flags, n_threads, s);
+}
+
+int gga_mapped_insert_gen(gga_mapped* m, const gga_gen* g, uint64_t n_threads, gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!m) return GGA_EINVAL;
+  int rc = check_gen(g, n_threads, &mode, &maxc);
+  if (rc) return rc;
+  rc = mapped_reserve(m, n_threads * maxc, S(s));
+  return rc ? rc : launch_static_insert(&m->st, gen_desc(g, mode, n_threads), S(s));
+}
+
+int gga_mapped_rw(gga_mapped* m, uint32_t op, gga_stream s) {
+  if (!m) return GGA_EINVAL;
+  return gga_static_rw(&m->st, op, s);
+}
+
+int gga_mapped_size(gga_mapped* m, uint64_t* out_host, gga_stream s) {
+  if (!m || !out_host) return GGA_EINVAL;
+  return static_read(&m->st, out_host, S(s));
+}
+
+int gga_mapped_data(gga_mapped* m, void** dev_data, uint64_t* mapped_elems) {
+  if (!m || !dev_data || !mapped_elems) return GGA_EINVAL;
+  *dev_data = m->st.data;
+  *mapped_elems = m->st.cap;
+  return GGA_OK;
+}
+
+int gga_mapped_maps(gga_mapped* m, uint64_t* out_host) {
+  if (!m || !out_host) return GGA_EINVAL;
+  *out_host = m->maps;
   return GGA_OK;
 }
 

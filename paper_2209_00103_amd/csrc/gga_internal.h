@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ggarray.h"
-#include "gga_device.h"
+#include "ggarray_device.h"
 
 struct gga_pool {
   gga::PoolRef ref;
@@ -68,6 +68,18 @@ struct gga_batch {
 struct gga_semistatic {
   gga_static st;      // current buffer, resized by the host
   uint64_t resizes;
+};
+
+struct gga_mapped {
+  gga_static st;                    // data = start of the reserved range, cap = mapped elements
+  uint64_t va_bytes;                // reserved range
+  uint64_t mapped_bytes;
+  uint64_t gran;                    // allocation granularity
+  int device;
+  uint64_t maps;
+  uint64_t n_handles, cap_handles;
+  hipMemGenericAllocationHandle_t* handles;
+  uint64_t* handle_bytes;
 };
 
 namespace gga {
@@ -205,6 +217,7 @@ __host__ __device__ constexpr uint32_t rw_tile_elems(uint32_t elem_log2) {
 
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s);
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
+int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_scan(ggarray* a, hipStream_t s);
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s);
 int launch_rw(ggarray* a, uint32_t op, hipStream_t s);

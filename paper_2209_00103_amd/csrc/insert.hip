@@ -698,6 +698,25 @@ __global__ __launch_bounds__(64) void dense_insert_kernel(ArrRef A, TileArgs I, 
   }
 }
 
+// ------------------------------------ static array, one atomic per element --
+// The other insertion strategy the paper compares (Sec. VI-A): every inserting
+// thread takes its own slot with an atomic add on the size, so the order across
+// threads is not fixed.  (The compiler may combine the atomics of a wavefront
+// that target one address into one; that is the strategy as the hardware runs
+// it.)
+template <typename T, class Prod>
+__global__ __launch_bounds__(256) void static_atomic_kernel(StaticRef S, uint64_t n, Prod prod) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  bool over = false;
+  for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+    if (!prod.flag(g)) continue;
+    const uint64_t pos = fetch_add(S.size, 1);
+    if (pos < S.cap) reinterpret_cast<T*>(S.data)[pos] = prod.value(g);
+    else over = true;
+  }
+  if (over) set_error(S.err, kErrRange);
+}
+
 // --------------------------------------------- multi-element producer kernel --
 // Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
 // plain scan of per-thread counts orders the elements.  A tile may emit up to
@@ -922,6 +941,32 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
     a->prefix_valid = false;
   }
   return st;
+}
+
+int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {
+  if (d.n_threads == 0) return GGA_OK;
+  StaticRef S{st->data, st->cap, st->d_size, st->d_err};
+  uint64_t blocks = (d.n_threads + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  const dim3 grid((uint32_t)blocks), block(256);
+  const bool u32 = st->elem_bytes == 4;
+  switch (d.mode) {
+    case kModeBernoulli:
+      if (u32) hipLaunchKernelGGL((static_atomic_kernel<uint32_t, ProdBernoulli<uint32_t>>), grid, block, 0, s, S, d.n_threads, ProdBernoulli<uint32_t>{d.seed, d.round});
+      else hipLaunchKernelGGL((static_atomic_kernel<uint64_t, ProdBernoulli<uint64_t>>), grid, block, 0, s, S, d.n_threads, ProdBernoulli<uint64_t>{d.seed, d.round});
+      break;
+    case kModeRoundTag:
+      if (u32) hipLaunchKernelGGL((static_atomic_kernel<uint32_t, ProdRoundTag<uint32_t>>), grid, block, 0, s, S, d.n_threads, ProdRoundTag<uint32_t>{d.round, d.tag_shift});
+      else hipLaunchKernelGGL((static_atomic_kernel<uint64_t, ProdRoundTag<uint64_t>>), grid, block, 0, s, S, d.n_threads, ProdRoundTag<uint64_t>{d.round, d.tag_shift});
+      break;
+    case kModeKeyed:
+      if (u32) hipLaunchKernelGGL((static_atomic_kernel<uint32_t, ProdKeyed<uint32_t>>), grid, block, 0, s, S, d.n_threads, ProdKeyed<uint32_t>{d.seed, d.round, d.tag_shift, d.tag});
+      else hipLaunchKernelGGL((static_atomic_kernel<uint64_t, ProdKeyed<uint64_t>>), grid, block, 0, s, S, d.n_threads, ProdKeyed<uint64_t>{d.seed, d.round, d.tag_shift, d.tag});
+      break;
+    default:
+      return GGA_EINVAL;
+  }
+  return hip_status(hipGetLastError());
 }
 
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {

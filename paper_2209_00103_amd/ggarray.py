@@ -46,6 +46,7 @@ class Trace(ctypes.Structure):
 
 # name -> argtypes (every entry point returns int status unless listed in _RES)
 _SIGS = {
+    "gga_last_hip_error": [],
     "gga_strerror": [_i32],
     "gga_pool_create": [_P(_vp), _vp, _u64, _vp],
     "gga_pool_destroy": [_vp],
@@ -60,6 +61,8 @@ _SIGS = {
     "ggarray_rw": [_vp, _u32, _vp],
     "ggarray_flatten": [_vp, _vp, _u64, _vp],
     "ggarray_rw_global": [_vp, _u32, _vp],
+    "ggarray_device_ref": [_vp, _vp, _u64],
+    "ggarray_device_done": [_vp, _vp],
     "ggarray_gather": [_vp, _vp, _u64, _vp, _vp],
     "ggarray_size": [_vp, _P(_u64), _vp],
     "ggarray_capacity": [_vp, _P(_u64), _vp],
@@ -70,6 +73,7 @@ _SIGS = {
     "gga_static_destroy": [_vp, _vp],
     "gga_static_insert": [_vp, _vp, _vp, _u64, _vp],
     "gga_static_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
+    "gga_static_insert_gen_atomic": [_vp, _P(GenSpec), _u64, _vp],
     "gga_static_rw": [_vp, _u32, _vp],
     "gga_static_size": [_vp, _P(_u64), _vp],
     "gga_static_last_error": [_vp, _vp],
@@ -91,11 +95,19 @@ _SIGS = {
     "gga_semi_size": [_vp, _P(_u64), _vp],
     "gga_semi_data": [_vp, _P(_vp), _P(_u64)],
     "gga_semi_resizes": [_vp, _P(_u64)],
+    "gga_mapped_create": [_P(_vp), _u32, _u64, _vp],
+    "gga_mapped_destroy": [_vp, _vp],
+    "gga_mapped_insert": [_vp, _vp, _vp, _u64, _vp],
+    "gga_mapped_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
+    "gga_mapped_rw": [_vp, _u32, _vp],
+    "gga_mapped_size": [_vp, _P(_u64), _vp],
+    "gga_mapped_data": [_vp, _P(_vp), _P(_u64)],
+    "gga_mapped_maps": [_vp, _P(_u64)],
     "gga_server_create": [_P(_vp), _vp, _u32, _vp, _u64, _P(ServerConfig)],
     "gga_server_destroy": [_vp],
     "gga_server_run": [_vp, _P(Trace), _vp, _vp, _vp, _vp, _vp, _vp],
 }
-_RES = {"gga_strerror": ctypes.c_char_p}
+_RES = {"gga_strerror": ctypes.c_char_p, "gga_last_hip_error": ctypes.c_char_p}
 
 _lib = None
 
@@ -118,6 +130,10 @@ def lib() -> ctypes.CDLL:
 class GGAError(RuntimeError):
     def __init__(self, status: int, what: str):
         msg = lib().gga_strerror(status).decode()
+        if status == EHIP:
+            detail = lib().gga_last_hip_error().decode()
+            if detail:
+                msg += f" [{detail}]"
         super().__init__(f"{what}: {msg} ({status})")
         self.status = status
 
@@ -239,6 +255,15 @@ class GGArray:
 
     def rw(self, op: int, stream=None):
         _check(lib().ggarray_rw(self._h, op, _stream(stream)), "ggarray_rw")
+
+    def device_ref(self, nbytes: int) -> bytes:
+        """The array's device descriptor (for user kernels that push elements)."""
+        buf = ctypes.create_string_buffer(nbytes)
+        _check(lib().ggarray_device_ref(self._h, buf, nbytes), "ggarray_device_ref")
+        return buf.raw
+
+    def device_done(self, stream=None):
+        _check(lib().ggarray_device_done(self._h, _stream(stream)), "ggarray_device_done")
 
     def rw_global(self, op: int, stream=None):
         _check(lib().ggarray_rw_global(self._h, op, _stream(stream)), "ggarray_rw_global")
@@ -421,6 +446,11 @@ class StaticArray:
         _check(lib().gga_static_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
                "gga_static_insert_gen")
 
+    def insert_gen_atomic(self, gen: GenSpec, n_threads: int, stream=None):
+        """Per-element atomic strategy (the scan's comparison point)."""
+        _check(lib().gga_static_insert_gen_atomic(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
+               "gga_static_insert_gen_atomic")
+
     def rw(self, op: int, stream=None):
         _check(lib().gga_static_rw(self._h, op, _stream(stream)), "gga_static_rw")
 
@@ -491,6 +521,56 @@ class SemiStaticArray:
     def close(self, stream=None):
         if self._h:
             _check(lib().gga_semi_destroy(self._h, _stream(stream)), "gga_semi_destroy")
+            self._h = _vp()
+
+
+class MappedArray:
+    """Host-grown array over a reserved virtual range (memMap baseline)."""
+
+    def __init__(self, elem_bytes: int, max_elems: int, stream=None):
+        self.elem_bytes = elem_bytes
+        self.dtype = _dtype(elem_bytes)
+        self._h = _vp()
+        _check(lib().gga_mapped_create(ctypes.byref(self._h), elem_bytes, int(max_elems), _stream(stream)),
+               "gga_mapped_create")
+
+    def insert(self, values, flags=None, stream=None):
+        n = values.numel()
+        _check(lib().gga_mapped_insert(self._h, _dev_ptr(values, "values", n, self.elem_bytes),
+                                       _dev_ptr(flags, "flags", n, 1), n, _stream(stream)),
+               "gga_mapped_insert")
+
+    def insert_gen(self, gen: GenSpec, n_threads: int, stream=None):
+        _check(lib().gga_mapped_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
+               "gga_mapped_insert_gen")
+
+    def rw(self, op: int, stream=None):
+        _check(lib().gga_mapped_rw(self._h, op, _stream(stream)), "gga_mapped_rw")
+
+    def size(self, stream=None) -> int:
+        v = _u64()
+        _check(lib().gga_mapped_size(self._h, ctypes.byref(v), _stream(stream)), "gga_mapped_size")
+        return int(v.value)
+
+    def maps(self) -> int:
+        v = _u64()
+        _check(lib().gga_mapped_maps(self._h, ctypes.byref(v)), "gga_mapped_maps")
+        return int(v.value)
+
+    def data(self, stream=None) -> torch.Tensor:
+        """Copy of the live elements (device tensor)."""
+        n = self.size(stream)
+        p, cap = _vp(), _u64()
+        _check(lib().gga_mapped_data(self._h, ctypes.byref(p), ctypes.byref(cap)), "gga_mapped_data")
+        out = torch.empty(max(n, 1), dtype=self.dtype, device="cuda")
+        if n:
+            torch.cuda.current_stream().synchronize()
+            _copy_from_ptr(out, p.value, n * self.elem_bytes)
+        return out[:n]
+
+    def close(self, stream=None):
+        if self._h:
+            _check(lib().gga_mapped_destroy(self._h, _stream(stream)), "gga_mapped_destroy")
             self._h = _vp()
 
 
