@@ -418,10 +418,17 @@ def two_phase_leg(G, torch, rounds, gens, V, ks=(1, 10, 100)):
             arr.insert_gen(gens[r], n)
             arr.shrink(1, 10)
 
-    grow()  # warm-up (sizes the flat buffer)
+    grow()  # warm-up (sizes the flat buffer, loads every kernel once)
     size = arr.size()
     flat = torch.empty(size, dtype=torch.int32, device="cuda")
+    arr.flatten_into(flat)
+    flat.add_(1)
+    arr.rw(G.ADD1)
     arr.shrink(1, 1)
+    mp = G.MappedArray(ELEM, 1 << 28)
+    mp.insert_gen(gens[0], rounds[0])
+    mp.rw(G.ADD1)
+    mp.close()
     for k in ks:
         row = {}
         for mode in ("flatten_then_static", "ggarray"):
@@ -595,6 +602,36 @@ def main():
     assert arr.last_error() == 0, "device error during the timed steps"
     ms_step = ev0.elapsed_time(ev1) / args.steps
     ms_step_wall = wall * 1e3 / args.steps
+
+    # The same step captured once as a HIP graph and replayed K times (one
+    # submission per step instead of ~40 launches).
+    graph_ms = None
+    try:
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(gs):
+            ggarray_step(G, arr, gens, rounds, out, prefix_buf)  # eager on the capture stream first
+        gs.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gs):
+            ggarray_step(G, arr, gens, rounds, out, prefix_buf)
+        for _ in range(max(1, args.warmup)):
+            graph.replay()
+        torch.cuda.synchronize()
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(gs):
+            g0.record()
+            for _ in range(args.steps):
+                graph.replay()
+            g1.record()
+        torch.cuda.synchronize()
+        assert arr.last_error() == 0, "device error during the graph replays"
+        graph_ms = g0.elapsed_time(g1) / args.steps
+        del graph
+    except Exception as e:  # reported, never silently dropped
+        log(f"graph replay failed: {e}")
+    log(f"graph replay: {graph_ms} ms/step")
 
     # Per-kernel durations: the same K steps again with events around every call.
     timer = Timer(torch)
@@ -805,6 +842,7 @@ def main():
                    "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
         "parity_with_oracle": parity,
         "ms_per_step_wall": ms_step_wall,
+        "ms_per_step_graph": graph_ms,
         "batched": batched,
         "served": served,
         "global_index_access": next_rows,
