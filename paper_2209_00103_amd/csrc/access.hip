@@ -11,7 +11,25 @@ namespace gga {
 namespace {
 
 constexpr uint32_t kScanThreads = 1024;
-constexpr uint32_t kStreamBlocks = 2048;  // 8 workgroups per CU on 256 CUs
+// Persistent grids of the streaming kernels (256-thread workgroups; 256 CUs).
+// Measured on configuration 2: r/w peaks at 4096-8192 workgroups, flatten keeps
+// gaining up to 16384 (its destination stream benefits from more stores in
+// flight).
+constexpr uint32_t kRwBlocks = 8192;
+constexpr uint32_t kFlattenBlocks = 16384;
+// The static-array baseline streams a flat buffer; it measured best with
+// non-temporal loads and 2048 workgroups (5.04 TB/s), and runs that way.
+constexpr uint32_t kStaticBlocks = 2048;
+
+// Workgroups for one array's r/w or flatten: enough for the tiles the array can
+// hold (the host's upper bound of its size), at most `cap`, so a small array
+// does not pay for dispatching a grid sized for the largest ones.
+inline uint32_t stream_grid(const ggarray* a, uint32_t cap) {
+  const uint32_t te_log2 = 14u - a->elem_log2;
+  const uint64_t tiles = (a->size_ub >> te_log2) + 2ull * a->V;
+  const uint64_t g = (tiles + 1) / 2;
+  return (uint32_t)(g < 1 ? 1 : (g > cap ? cap : g));
+}
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
@@ -138,9 +156,11 @@ __device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
 
 // One tile: cnt (<= te) elements at src (16-byte aligned); rw in place, or copy
 // to dst (element aligned) for flatten.  Lane i of slot k handles the 16 bytes
-// at element k * (256 * VPL) + i * VPL.  Every byte is touched once, so loads and
-// stores are non-temporal.
-template <typename T, bool kFlatten>
+// at element k * (256 * VPL) + i * VPL.  Every byte is touched once, so stores
+// are non-temporal; so are flatten's loads, while r/w loads through the cache,
+// which lets its non-temporal stores find the lines they overwrite (measured:
+// r/w 4.80 -> 5.31 TB/s, flatten slower with cached loads).
+template <typename T, bool kFlatten, bool kNtLoad = kFlatten>
 __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32_t op) {
   constexpr uint32_t VPL = 16 / sizeof(T);
   constexpr uint32_t kSlots = 4;
@@ -150,7 +170,8 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
     u32x4 r[kSlots];
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k)
-      r[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL));
+      r[k] = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL))
+                      : *reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL);
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k) {
       if (kFlatten)
@@ -163,7 +184,8 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
   for (uint32_t k = 0; k < kSlots; ++k) {
     const uint32_t e = k * kSpan + tid * VPL;
     if (e + VPL <= cnt) {
-      const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + e));
+      const u32x4 x = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + e))
+                               : *reinterpret_cast<const u32x4*>(src + e);
       if (kFlatten)
         __builtin_nontemporal_store(x, reinterpret_cast<u32x4_a4*>(dst + e));
       else
@@ -265,7 +287,7 @@ __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const ui
   for (uint64_t t = t0; t < t1; ++t) {
     const uint64_t e0 = t << te_log2;
     const uint64_t rem = n - e0;
-    stream_tile<T, false>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
+    stream_tile<T, false, true>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
   }
 }
 
@@ -432,7 +454,7 @@ int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin
   if (n == 0) return GGA_OK;
   const uint32_t te_log2 = elem_bytes == 4 ? 12u : 11u;
   if (grid < 1) grid = 1;
-  if (grid > kStreamBlocks) grid = kStreamBlocks;
+  if (grid > kRwBlocks) grid = kRwBlocks;
   const bool fused = n <= kServeFusedItems;
   const size_t lds = fused ? (n + 1) * sizeof(uint64_t) : 0;
   if (!fused)
@@ -465,6 +487,7 @@ int launch_scan(ggarray* a, hipStream_t s) {
 }
 
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s) {
+  if (num == den) a->size_ub = 0;
   const uint32_t blocks = (a->V + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(shrink_kernel, dim3(blocks), dim3(256), 0, s, a->ref, num, den, a->elem_log2);
   a->prefix_valid = false;
@@ -487,10 +510,10 @@ int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s) {
 int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
   const uint32_t te_log2 = 14u - a->elem_log2;
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL((stream_kernel<uint32_t, false>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((stream_kernel<uint32_t, false>), dim3(stream_grid(a, kRwBlocks)), dim3(kRwThreads), 0, s,
                        a->ref, op, (uint32_t*)nullptr, (uint64_t)0, te_log2);
   else
-    hipLaunchKernelGGL((stream_kernel<uint64_t, false>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((stream_kernel<uint64_t, false>), dim3(stream_grid(a, kRwBlocks)), dim3(kRwThreads), 0, s,
                        a->ref, op, (uint64_t*)nullptr, (uint64_t)0, te_log2);
   return hip_status(hipGetLastError());
 }
@@ -498,20 +521,20 @@ int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
 int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
   const uint32_t te_log2 = 14u - a->elem_log2;
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL((stream_kernel<uint32_t, true>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((stream_kernel<uint32_t, true>), dim3(stream_grid(a, kFlattenBlocks)), dim3(kRwThreads), 0, s,
                        a->ref, 0u, static_cast<uint32_t*>(out), cap, te_log2);
   else
-    hipLaunchKernelGGL((stream_kernel<uint64_t, true>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((stream_kernel<uint64_t, true>), dim3(stream_grid(a, kFlattenBlocks)), dim3(kRwThreads), 0, s,
                        a->ref, 0u, static_cast<uint64_t*>(out), cap, te_log2);
   return hip_status(hipGetLastError());
 }
 
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
   if (st->elem_bytes == 4)
-    hipLaunchKernelGGL((static_rw_kernel<uint32_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((static_rw_kernel<uint32_t>), dim3(kStaticBlocks), dim3(kRwThreads), 0, s,
                        static_cast<uint32_t*>(st->data), st->d_size, st->cap, op, 12u);
   else
-    hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStreamBlocks), dim3(kRwThreads), 0, s,
+    hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStaticBlocks), dim3(kRwThreads), 0, s,
                        static_cast<uint64_t*>(st->data), st->d_size, st->cap, op, 11u);
   return hip_status(hipGetLastError());
 }
@@ -529,6 +552,8 @@ int launch_batch_scan(gga_batch* b, hipStream_t s) {
 }
 
 int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s) {
+  if (num == den)
+    for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->size_ub = 0;
   const uint64_t blocks = (b->total_vectors + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(batch_shrink_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, b->d_arrays, b->d_vbegin,
                      b->n, num, den);
@@ -538,7 +563,7 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
 
 int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s) {
   const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
-  const dim3 grid(b->stream_blocks ? b->stream_blocks : kStreamBlocks), block(kRwThreads);
+  const dim3 grid(b->stream_blocks ? b->stream_blocks : (flatten ? kFlattenBlocks : kRwBlocks)), block(kRwThreads);
   if (b->elem_bytes == 4) {
     if (flatten)
       hipLaunchKernelGGL((batch_stream_kernel<uint32_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,

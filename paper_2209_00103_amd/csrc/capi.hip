@@ -247,6 +247,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.salt = (uint32_t)((reinterpret_cast<uintptr_t>(a->meta) >> 8) * 2654435761u) & (kFreeShards - 1);
   a->status_cap = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
+  a->size_ub = 0;
   p->n_arrays += 1;
   *out = a;
   return GGA_OK;
@@ -384,6 +385,7 @@ int ggarray_device_done(ggarray* a, gga_stream s) {
   (void)s;
   if (!a) return GGA_EINVAL;
   a->prefix_valid = false;
+  a->size_ub = ~0ull >> 2;  // sizes unknown to the host now
   return GGA_OK;
 }
 

@@ -23,6 +23,7 @@ struct ggarray {
   gga::ArrRef ref;
   uint64_t status_cap;    // look-back words available
   bool prefix_valid;      // prefix / tprefix match the current sizes
+  uint64_t size_ub;       // host upper bound of the size (sets launch shapes only)
 };
 
 struct gga_static {
@@ -233,9 +234,10 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
 int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s);
 
 // Served steps.  prepare_round_item fills the descriptor of one insertion round of
-// n threads on a (growing its look-back words on stream s) and returns its tiles.
+// n threads on a (growing its look-back words on stream s when the round's kernel
+// uses them) and returns its tiles.
 int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,
-                       hipStream_t s);
+                       hipStream_t s, bool lookback);
 // launch_serve_front: the step's append rounds (keyed payloads) and the size
 // scans of the n_s arrays in sitems, one launch.  launch_serve_stream: the r/w
 // and flatten requests of sitems (scanned before), one streaming launch (plus one
@@ -248,5 +250,12 @@ int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin
                         uint32_t* err, uint32_t elem_bytes, uint32_t grid, hipStream_t s);
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? GGA_OK : GGA_EHIP; }
+
+// Host upper bound of an array's size: raised by the elements a round may add,
+// dropped to zero by a full shrink, unknown (maximal) after user kernels.
+inline void grow_bound(ggarray* a, uint64_t n) {
+  const uint64_t lim = ~0ull >> 2;
+  a->size_ub = n > lim - a->size_ub ? lim : a->size_ub + n;
+}
 
 }  // namespace gga

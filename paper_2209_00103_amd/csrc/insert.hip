@@ -648,9 +648,7 @@ __global__ __launch_bounds__(64) void serve_front_kernel(const BatchArr* items, 
 // another and no atomic is taken outside the pool.  An LFVector whose growth
 // fails is frozen with its size unchanged (its round is dropped), as in the
 // single-kernel path.
-__global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
-  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
-  if (v >= A.V) return;
+__device__ __forceinline__ void grow_vector(const ArrRef& A, const TileArgs& I, uint32_t v) {
   const uint32_t lane = lane_id();
   const uint64_t c0 = (uint64_t)v * I.chunk;
   const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
@@ -680,8 +678,7 @@ __global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
 }
 
 template <typename T, class Prod>
-__global__ __launch_bounds__(64) void dense_insert_kernel(ArrRef A, TileArgs I, Prod prod) {
-  const uint64_t block = blockIdx.x;
+__device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, const Prod& prod, uint64_t block) {
   const uint32_t v = (uint32_t)(block / I.tpv);
   const uint64_t t = block - (uint64_t)v * I.tpv;
   uint64_t g0, gend;
@@ -700,6 +697,47 @@ __global__ __launch_bounds__(64) void dense_insert_kernel(ArrRef A, TileArgs I, 
     dense_store<T, Prod>(dst, prod, g0 + i, run);
     i += run;
   }
+}
+
+__global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (v < A.V) grow_vector(A, I, v);
+}
+
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void dense_insert_kernel(ArrRef A, TileArgs I, Prod prod) {
+  store_tile<T, Prod>(A, I, prod, blockIdx.x);
+}
+
+// The same two phases for one round of many arrays: wave w of the grow launch is
+// LFVector w - vbegin[i] of array i, wave w of the store launch is tile
+// w - begins[i] of array i.
+__device__ __forceinline__ TileArgs item_args(const BatchArr& it) {
+  TileArgs I;
+  I.n_threads = it.n_threads;
+  I.chunk = it.chunk;
+  I.tpv = it.tpv;
+  I.elem_log2 = it.elem_log2;
+  return I;
+}
+
+__global__ __launch_bounds__(256) void batch_grow_kernel(const BatchArr* items, const uint64_t* vbegin, uint32_t n) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (w >= vbegin[n]) return;
+  const uint32_t i = wave_search(vbegin, n, w);
+  const BatchArr it = items[i];
+  if (it.n_threads) grow_vector(it.A, item_args(it), (uint32_t)(w - vbegin[i]));
+}
+
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void batch_dense_kernel(const BatchArr* items, const uint64_t* begins, uint32_t n,
+                                                         Prod prod) {
+  const uint64_t blk = blockIdx.x;
+  const uint32_t i = wave_search(begins, n, blk);
+  const BatchArr it = items[i];
+  Prod p = prod;
+  p.bind(it);
+  store_tile<T, Prod>(it.A, item_args(it), p, blk - begins[i]);
 }
 
 // ------------------------------------ static array, one atomic per element --
@@ -926,6 +964,7 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   I.chunk = chunk;
   I.tpv = tpv;
   I.elem_log2 = a->elem_log2;
+  grow_bound(a, d.n_threads * (multi_mode(d.mode) ? d.max_count : 1u));
   const bool dense = d.mode == kModeRoundTag || d.mode == kModeKeyed || (d.mode == kModeBuffer && !d.flags);
   if (dense) {
     const int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
@@ -998,12 +1037,12 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
 }  // namespace
 
 int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,
-                       hipStream_t s) {
+                       hipStream_t s, bool lookback) {
   const uint64_t chunk = n ? (n + a->V - 1) / a->V : 0;
   const uint64_t tpv = n ? (chunk + kFlagTile - 1) / kFlagTile : 0;
   *ntiles = tpv * a->V;
   if (chunk >= (1ull << 32)) return GGA_EINVAL;
-  if (tpv > 1) {
+  if (lookback && tpv > 1) {
     const int rc = ensure_status(a, *ntiles, s);
     if (rc) return rc;
   }
@@ -1030,6 +1069,7 @@ int launch_serve_front(const BatchArr* items, const uint64_t* begins, uint32_t n
 
 int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_threads, hipStream_t s) {
   if (d.mode != kModeRoundTag && d.mode != kModeBernoulli && d.mode != kModeKeyed) return GGA_EINVAL;
+  const bool dense = d.mode != kModeBernoulli;  // every thread inserts: grow, then store
   BatchArr* items = new (std::nothrow) BatchArr[b->n];
   uint64_t* begins = new (std::nothrow) uint64_t[b->n + 1];
   if (!items || !begins) {
@@ -1043,7 +1083,8 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   for (uint32_t i = 0; i < b->n && rc == GGA_OK; ++i) {
     uint64_t ntiles = 0;
     const uint64_t* before = b->arrays[i]->ref.status;
-    rc = prepare_round_item(b->arrays[i], n_threads[i], d.tag + i, i, &items[i], &ntiles, s);
+    rc = prepare_round_item(b->arrays[i], n_threads[i], d.tag + i, i, &items[i], &ntiles, s, !dense);
+    grow_bound(b->arrays[i], n_threads[i]);
     grew = grew || b->arrays[i]->ref.status != before;
     if (rc == GGA_OK && blocks + ntiles > 0x7FFFFFFFull) rc = GGA_EINVAL;
     begins[i] = blocks;
@@ -1107,7 +1148,17 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   if (rc != GGA_OK || !blocks) return rc;
   const dim3 grid((uint32_t)blocks), block(64);
   const bool u32 = b->elem_bytes == 4;
-  if (d.mode == kModeRoundTag) {
+  if (dense) {
+    hipLaunchKernelGGL(batch_grow_kernel, dim3((uint32_t)((b->total_vectors + 3) / 4)), dim3(256), 0, s, tab->items,
+                       b->d_vbegin, b->n);
+    if (d.mode == kModeRoundTag) {
+      if (u32) hipLaunchKernelGGL((batch_dense_kernel<uint32_t, ProdRoundTag<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint32_t>{d.round, d.tag_shift});
+      else hipLaunchKernelGGL((batch_dense_kernel<uint64_t, ProdRoundTag<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint64_t>{d.round, d.tag_shift});
+    } else {
+      if (u32) hipLaunchKernelGGL((batch_dense_kernel<uint32_t, ProdKeyed<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdKeyed<uint32_t>{d.seed, d.round, d.tag_shift, 0});
+      else hipLaunchKernelGGL((batch_dense_kernel<uint64_t, ProdKeyed<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdKeyed<uint64_t>{d.seed, d.round, d.tag_shift, 0});
+    }
+  } else if (d.mode == kModeRoundTag) {
     if (u32) hipLaunchKernelGGL((batch_insert_kernel<uint32_t, ProdRoundTag<uint32_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint32_t>{d.round, d.tag_shift});
     else hipLaunchKernelGGL((batch_insert_kernel<uint64_t, ProdRoundTag<uint64_t>>), grid, block, 0, s, tab->items, tab->begins, b->n, ProdRoundTag<uint64_t>{d.round, d.tag_shift});
   } else if (d.mode == kModeBernoulli) {

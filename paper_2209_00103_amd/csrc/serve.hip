@@ -311,12 +311,13 @@ int run_batched(RunState& R) {
         (kind == GGA_REQ_APPEND ? a_reqs : reqs).push_back(r);
         if (kind == GGA_REQ_APPEND) {
           BatchArr it;
-          const int rc = prepare_round_item(arr, tr->length[r], r, (uint32_t)items.size(), &it, &ntiles, l.s);
+          const int rc = prepare_round_item(arr, tr->length[r], r, (uint32_t)items.size(), &it, &ntiles, l.s, true);
           if (rc) return rc;
           items.push_back(it);
           begins.push_back(blocks);
           blocks += ntiles;
           arr->prefix_valid = false;
+          grow_bound(arr, tr->length[r]);
         } else {
           const bool flat = kind == GGA_REQ_FLATTEN;
           if (flat) {
