@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (512-array) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served (4096-array request loop) leg")
     ap.add_argument("--no-two-phase", action="store_true", help="skip the growth-then-work case study")
+    ap.add_argument("--no-config3", action="store_true", help="skip the irregular-insertion (configuration 3) leg")
     ap.add_argument("--no-shootout", action="store_true",
                     help="skip the scan-vs-atomic insertion comparison and the memory model")
     ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
@@ -526,6 +527,53 @@ def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=6):
     return {"workload": f"N = {N}, {samples} draws per sigma, GGArray V = {V}, F = {F}", "rows": rows}
 
 
+def config3_leg(G, wl, torch, steps=3):
+    """Configuration 3 at full size (irregular insertion): uint64, V = 65536,
+    F = 1024, 2^26 threads with Poisson(3) counts capped at 16 (thresholds from the
+    host), 4 insert phases each followed by r/w x + 1, then flatten.  Device time
+    per phase (HIP events), median over `steps` passes from an empty array."""
+    thr = wl.poisson_thresholds(3, 16)
+    n, V = 1 << 26, 65536
+    pool = G.Pool(16 << 30)
+    a = G.GGArray(pool, 8, V, 1024)
+    gens = [G.make_gen(G.GEN_POISSON, seed=1, round=i, max_count=16, thresholds=thr) for i in range(4)]
+    sizes = []
+    for i in range(4):  # sizing pass
+        a.insert_gen(gens[i], n)
+        a.rw(G.ADD1)
+        sizes.append(a.size())
+    out = torch.empty(sizes[-1], dtype=torch.int64, device="cuda")
+    a.shrink(1, 1)
+    timer = Timer(torch)
+    for rep in range(steps + 1):
+        t = timer if rep else Timer(torch)
+        for i in range(4):
+            with t.span(f"ins{i}"):
+                a.insert_gen(gens[i], n)
+            with t.span(f"rw{i}"):
+                a.rw(G.ADD1)
+        with t.span("flatten"):
+            a.flatten_into(out)
+        a.shrink(1, 1)
+    torch.cuda.synchronize()
+    assert a.last_error() == 0
+    a.close()
+    pool.close()
+    prev, phases = 0, []
+    for i in range(4):
+        ins = statistics.median(timer.ms(f"ins{i}"))
+        rw = statistics.median(timer.ms(f"rw{i}"))
+        added = sizes[i] - prev
+        prev = sizes[i]
+        phases.append({"inserted": added, "insert_us": 1e3 * ins, "insert_Gelem_s": added / (ins * 1e-3) / 1e9,
+                       "insert_GBps": 8 * added / (ins * 1e-3) / 1e9, "rw_us": 1e3 * rw,
+                       "rw_GBps": 16 * sizes[i] / (rw * 1e-3) / 1e9})
+    fl = statistics.median(timer.ms("flatten"))
+    return {"workload": "2^26 threads, Poisson(3) counts capped at 16, uint64 K(1,gid,16i+j), V = 65536, "
+                        "4 x (insert, r/w x+1), flatten", "final_size": sizes[-1], "phases": phases,
+            "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9}
+
+
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
     """The CPU oracle (list form, one thread) on the full workload, repeated until
     about min_seconds of work; returns (Gelem/s, seconds per pass, last flatten)."""
@@ -795,6 +843,15 @@ def main():
         except Exception as e:
             memory_model = {"error": str(e)}
             log(f"memory model failed: {e}")
+    config3 = None
+    if not args.no_config3:
+        try:
+            config3 = config3_leg(G, wl, torch)
+            log("configuration 3: insert " + ", ".join(f"{p['insert_Gelem_s']:.1f}" for p in config3["phases"])
+                + f" Gelem/s; flatten {config3['flatten_GBps']:.0f} GB/s")
+        except Exception as e:  # reported, never silently dropped
+            config3 = {"error": str(e)}
+            log(f"configuration-3 leg failed: {e}")
     two_phase = None
     if not args.no_two_phase:
         try:
@@ -847,6 +904,7 @@ def main():
         "served": served,
         "global_index_access": next_rows,
         "two_phase": two_phase,
+        "config3": config3,
         "insertion_shootout": shootout,
         "memory_model": memory_model,
     }
