@@ -699,6 +699,55 @@ __device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, c
   }
 }
 
+// Small rounds (one tile per LFVector): one wave per LFVector grows it and then
+// stores its elements, in one launch.  The new bucket pointers stay in the
+// lanes that allocated them; a bucket that existed before the round is read
+// from the table, written by an earlier launch.
+template <typename T, class Prod>
+__global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, Prod prod) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (v >= A.V) return;
+  const uint32_t lane = lane_id();
+  const uint64_t c0 = (uint64_t)v * I.chunk;
+  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
+  if (cnt == 0 || A.dead[v]) return;
+  const uint32_t log2F = A.log2F;
+  const uint64_t s0 = A.size[v];
+  const uint32_t lo = nbuckets_for(log2F, s0), hi = nbuckets_for(log2F, s0 + cnt);
+  const uint32_t b = lo + lane;
+  uint64_t q = 0;
+  bool failed = false;
+  if (b < hi) {
+    if (b >= (uint32_t)kMaxBuckets) {
+      failed = true;
+    } else {
+      uint8_t* p = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
+      q = p ? (uint64_t)p : kFailedPtr;
+      A.bptr[(uint64_t)v * kMaxBuckets + b] = q;
+      failed = !p;
+    }
+  }
+  if (__ballot(failed)) {
+    if (lane == 0) {
+      set_error(A.err, kErrNoMem);
+      A.dead[v] = 1u;
+    }
+    return;
+  }
+  if (lane == 0) A.size[v] = s0 + cnt;
+  const uint32_t n = (uint32_t)cnt;
+  for (uint32_t i = 0; i < n;) {
+    const uint64_t idx = s0 + i;
+    const uint32_t bk = bucket_of(log2F, idx);
+    const uint64_t bs = bucket_start(log2F, bk);
+    const uint64_t room = bs + bucket_len(log2F, bk) - idx;
+    const uint32_t run = (uint64_t)(n - i) < room ? n - i : (uint32_t)room;
+    const uint64_t p = bk >= lo ? __shfl(q, (int)(bk - lo), 64) : A.bptr[(uint64_t)v * kMaxBuckets + bk];
+    dense_store<T, Prod>(reinterpret_cast<T*>(p) + (idx - bs), prod, c0 + i, run);
+    i += run;
+  }
+}
+
 __global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
   const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
   if (v < A.V) grow_vector(A, I, v);
@@ -904,6 +953,26 @@ bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePois
 
 template <typename T>
 int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
+  if (I.tpv == 1) {  // one tile per LFVector: grow and store in one launch
+    const dim3 grid((A.V + 3) / 4), block(256);
+    switch (d.mode) {
+      case kModeBuffer:
+        hipLaunchKernelGGL((grow_store_kernel<T, ProdBuffer<T>>), grid, block, 0, s, A, I,
+                           ProdBuffer<T>{static_cast<const T*>(d.values), nullptr});
+        break;
+      case kModeRoundTag:
+        hipLaunchKernelGGL((grow_store_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, A, I,
+                           ProdRoundTag<T>{d.round, d.tag_shift});
+        break;
+      case kModeKeyed:
+        hipLaunchKernelGGL((grow_store_kernel<T, ProdKeyed<T>>), grid, block, 0, s, A, I,
+                           ProdKeyed<T>{d.seed, d.round, d.tag_shift, d.tag});
+        break;
+      default:
+        return GGA_EINVAL;
+    }
+    return hip_status(hipGetLastError());
+  }
   hipLaunchKernelGGL(grow_kernel, dim3((A.V + 3) / 4), dim3(256), 0, s, A, I);
   const dim3 grid((uint32_t)ntiles), block(64);
   switch (d.mode) {
