@@ -35,7 +35,6 @@ constexpr int kW = kB / 64;              // waves per workgroup
 constexpr int kFlagTile = (int)kInsertTile;  // logical threads per tile, 0/1 producers (one wave)
 constexpr int kCountK = 4;               // candidates per thread, multi-element producers
 constexpr int kCountTile = kB * kCountK; // 1024 logical threads per tile
-constexpr int kStage = 4096;             // LDS staging capacity, elements
 
 // Look-back status word: epoch (30 bits) | flag (2 bits) | value (32 bits).  The
 // value is a count or an inclusive prefix relative to the LFVector's size at the
@@ -360,56 +359,6 @@ __device__ void resolve_static(const StaticRef& S, uint32_t n_t, TileShared& sh)
     sh.base = base;
     sh.writable = (uint32_t)fit;
   }
-}
-
-// Copy n staged elements to dst, which is element aligned: element stores for the
-// ragged head and tail, 16-byte stores for the aligned middle.
-template <typename T>
-__device__ __forceinline__ void scatter_run(T* dst, const T* stage, uint32_t n) {
-  constexpr uint32_t VPL = 16 / sizeof(T);
-  const uint32_t tid = threadIdx.x;
-  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst) & 15u) / sizeof(T));
-  uint32_t head = mis ? VPL - mis : 0u;
-  if (head > n) head = n;
-  const uint32_t nv = (n - head) / VPL;
-  if (tid < head) dst[tid] = stage[tid];
-  for (uint32_t q = tid; q < nv; q += kB) {
-    const uint32_t e = head + q * VPL;
-    T tmp[VPL];
-#pragma unroll
-    for (uint32_t k = 0; k < VPL; ++k) tmp[k] = stage[e + k];
-    u32x4 x;
-    __builtin_memcpy(&x, tmp, 16);
-    *reinterpret_cast<u32x4*>(dst + e) = x;
-  }
-  const uint32_t tail = head + nv * VPL + tid;
-  if (tail < n) dst[tail] = stage[tail];
-}
-
-// Scatter staged elements [0, n) (tile positions p0 + i) to their buckets, one
-// contiguous run per bucket the range touches.
-template <typename T>
-__device__ __forceinline__ void scatter(const ArrRef& A, const TileShared& sh, const T* stage,
-                                        uint64_t p0, uint32_t n) {
-  const uint32_t log2F = A.log2F;
-  const uint64_t first = sh.base + p0, last = first + n;
-  for (uint32_t i = 0; i < sh.nb; ++i) {
-    const uint32_t b = sh.b_lo + i;
-    const uint64_t bs = bucket_start(log2F, b), be = bs + bucket_len(log2F, b);
-    const uint64_t lo = first > bs ? first : bs, hi = last < be ? last : be;
-    if (lo >= hi) continue;
-    const uint64_t p = sh.bp[i];
-    if (p <= kFailedPtr) continue;
-    scatter_run<T>(reinterpret_cast<T*>(p) + (lo - bs), stage + (lo - first), (uint32_t)(hi - lo));
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void scatter_static(const StaticRef& S, const TileShared& sh,
-                                               const T* stage, uint64_t p0, uint32_t n) {
-  uint32_t lim = sh.writable > p0 ? (uint32_t)(sh.writable - p0) : 0u;
-  if (lim > n) lim = n;
-  scatter_run<T>(reinterpret_cast<T*>(S.data) + sh.base + p0, stage, lim);
 }
 
 // Takes this block's ticket of LFVector v (one lane; the result is waited for
@@ -810,8 +759,12 @@ __global__ __launch_bounds__(256) void static_atomic_kernel(StaticRef S, uint64_
 
 // --------------------------------------------- multi-element producer kernel --
 // Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
-// plain scan of per-thread counts orders the elements.  A tile may emit up to
-// 16384 elements; they are staged and scattered in passes of kStage.
+// plain scan of per-thread counts orders the elements.  Once the tile's first
+// index is known, the block expands the elements directly: output q (consecutive
+// across lanes, so stores coalesce) belongs to the last thread whose exclusive
+// prefix is <= q (a binary search over the 256 prefixes in LDS), and to that
+// thread's logical thread and element by its four counts; the element is then
+// produced and stored.  Nothing is staged, so the block needs 2 KiB of LDS.
 template <typename Prod>
 __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt, uint64_t gend,
                                                    uint32_t* cnt) {
@@ -827,7 +780,8 @@ __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt
 template <typename T, class Prod, bool kStatic>
 __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S, TileArgs I,
                                                           Prod prod) {
-  __shared__ T stage[kStage];
+  __shared__ uint32_t s_excl[kB + 1];
+  __shared__ uint32_t s_cnt[kB];  // the thread's four counts, 8 bits each
   __shared__ TileShared sh;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const bool ticketed = !kStatic && I.tpv > 1;
@@ -872,34 +826,41 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
     n_t += x;
   }
   const uint32_t excl = before + incl - c;
+  s_excl[tid] = excl;
+  s_cnt[tid] = cnt[0] | (cnt[1] << 8) | (cnt[2] << 16) | (cnt[3] << 24);
+  if (tid == 0) s_excl[kB] = n_t;
   if (kStatic) {
     resolve_static(S, n_t, sh);
   } else if (w == 0) {
     resolve_tile(A, I, v, t, (uint64_t)v * I.tpv + t, is_last, n_t, epoch, sh);
   }
   __syncthreads();
-  const uint32_t n_out = kStatic ? n_t : sh.n_tile;  // 0 if the tile stalled
-  for (uint32_t p0 = 0; p0 < n_out; p0 += kStage) {
-    const uint32_t p1 = p0 + kStage;
-    uint32_t run = excl;
-#pragma unroll
-    for (int j = 0; j < kCountK; ++j) {
-      const uint32_t cj = cnt[j];
-      if (run < p1 && run + cj > p0) {
-        for (uint32_t r = 0; r < cj; ++r) {
-          const uint32_t q = run + r;
-          if (q >= p0 && q < p1) stage[q - p0] = prod.value(gt + j, r);
-        }
-      }
-      run += cj;
+  const uint32_t n_out = kStatic ? (sh.writable < n_t ? sh.writable : n_t) : sh.n_tile;  // 0 if stalled
+  const uint32_t log2F = A.log2F;
+  for (uint32_t q = tid; q < n_out; q += kB) {
+    uint32_t lo = 0, hi = kB;  // s_excl[lo] <= q < s_excl[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_excl[mid] <= q) lo = mid;
+      else hi = mid;
     }
-    __syncthreads();
-    const uint32_t n = (n_out - p0) < (uint32_t)kStage ? (n_out - p0) : (uint32_t)kStage;
-    if (kStatic)
-      scatter_static<T>(S, sh, stage, p0, n);
-    else
-      scatter<T>(A, sh, stage, p0, n);
-    __syncthreads();
+    uint32_t rem = q - s_excl[lo];
+    const uint32_t packed = s_cnt[lo];
+    uint32_t j = 0;
+    for (; j < (uint32_t)kCountK - 1; ++j) {
+      const uint32_t cj = (packed >> (8 * j)) & 0xFFu;
+      if (rem < cj) break;
+      rem -= cj;
+    }
+    const T val = prod.value(g0 + (uint64_t)lo * kCountK + j, rem);
+    if (kStatic) {
+      reinterpret_cast<T*>(S.data)[sh.base + q] = val;
+    } else {
+      const uint64_t idx = sh.base + q;
+      const uint32_t b = bucket_of(log2F, idx);
+      const uint64_t p = sh.bp[b - sh.b_lo];
+      if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = val;
+    }
   }
 }
 
