@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-shootout", action="store_true",
                     help="skip the scan-vs-atomic insertion comparison and the memory model")
     ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
-    ap.add_argument("--serve-lanes", type=int, default=2, help="served steps in flight")
+    ap.add_argument("--serve-lanes", type=int, default=3, help="served steps in flight")
     ap.add_argument("--serve-step", type=int, default=1024, help="requests per served step")
     ap.add_argument("--serve-baseline-requests", type=int, default=1 << 14,
                     help="trace prefix replayed with one launch per request")
