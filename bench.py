@@ -709,7 +709,7 @@ def main():
     assert arr.last_error() == 0, "device error during the global-index pass"
     arr.shrink(1, 1)
 
-    # Per-kernel figures (algorithmic bytes, SURVEY-style accounting in the design notes).
+    # Per-kernel figures: algorithmic bytes per launch over the measured duration.
     ins_ms = [statistics.mean(timer.ms(f"insert{r}")) for r in range(len(rounds))]
     shr_ms = [statistics.mean(timer.ms(f"shrink{r}")) for r in range(len(rounds))]
     rw_ms = statistics.mean(timer.ms("rw"))
