@@ -241,7 +241,7 @@ int ggarray_device_done(ggarray *a, gga_stream s);
  *   total exceeds out_cap_elems nothing is written and the batch's sticky
  *   GGA_ERANGE is set.
  * gga_batch_set_grid: workgroups of the persistent grid that r/w and flatten
- *   launch (1..65536; 0 restores the defaults, 8192 for r/w and 32768 for
+ *   launch (1..65536; 0 restores the defaults, 8192 for r/w and 65536 for
  *   flatten).  A launch-shape knob for tuning; results do not depend on it.
  * gga_batch_offsets: the n + 1 offsets (uint64, last = total) to dev_out.
  * gga_batch_last_error: the batch's sticky error.  Synchronises s. */

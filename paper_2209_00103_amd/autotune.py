@@ -22,7 +22,7 @@ import json
 import os
 
 CANDIDATES = tuple(1 << k for k in range(6, 15))
-GRID_CANDIDATES = (2048, 4096, 8192, 16384, 32768)
+GRID_CANDIDATES = (4096, 8192, 16384, 32768, 65536)
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ggarray", "autotune.json")
 
 

@@ -13,9 +13,10 @@ namespace {
 constexpr uint32_t kScanThreads = 1024;
 // Persistent grids of the streaming kernels (256-thread workgroups; 256 CUs).
 // Measured on configuration 2: r/w peaks at 4096-8192 workgroups, flatten keeps
-// gaining up to 32768 (4.47 TB/s at 2048, 4.70 at 16384, 5.08 at 32768).
+// gaining up to 65536 (4.47 TB/s at 2048, 4.70 at 16384, 5.13 at 32768, 5.27 at
+// 65536).
 constexpr uint32_t kRwBlocks = 8192;
-constexpr uint32_t kFlattenBlocks = 32768;
+constexpr uint32_t kFlattenBlocks = 65536;
 // The static-array baseline streams a flat buffer; it measured best with
 // non-temporal loads and 2048 workgroups (5.04 TB/s), and runs that way.
 constexpr uint32_t kStaticBlocks = 2048;
@@ -25,8 +26,7 @@ constexpr uint32_t kStaticBlocks = 2048;
 // does not pay for dispatching a grid sized for the largest ones.
 inline uint32_t stream_grid(const ggarray* a, uint32_t cap) {
   const uint32_t te_log2 = 14u - a->elem_log2;
-  const uint64_t tiles = (a->size_ub >> te_log2) + 2ull * a->V;
-  const uint64_t g = (tiles + 1) / 2;
+  const uint64_t g = (a->size_ub >> te_log2) + 2ull * a->V;
   return (uint32_t)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 

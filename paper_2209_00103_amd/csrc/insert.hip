@@ -648,9 +648,11 @@ __device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, c
   }
 }
 
-// Small rounds (up to 8 tiles per LFVector, measured faster than two launches on
-// configuration 2): one wave per LFVector grows it and then stores its
-// elements, in one launch.  The new bucket pointers stay in the
+// One wave per LFVector grows it and then stores its elements, in one launch.
+// Used when that still fills the GPU: rounds of up to 8 tiles per LFVector, or
+// arrays of 512 or more LFVectors (on configuration 2, 512 waves writing up to
+// 1 MiB each reach 4.8 TB/s, against 4.5 for a grow launch plus a store launch
+// of one wave per tile).  Fewer, longer LFVectors take the two-launch form.  The new bucket pointers stay in the
 // lanes that allocated them; a bucket that existed before the round is read
 // from the table, written by an earlier launch.
 template <typename T, class Prod>
@@ -915,7 +917,7 @@ bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePois
 
 template <typename T>
 int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
-  if (I.tpv <= 8) {  // up to 8 tiles per LFVector: one wave grows and stores it, in one launch
+  if (I.tpv <= 8 || A.V >= 512) {  // one wave per LFVector grows and stores it, in one launch
     const dim3 grid((A.V + 3) / 4), block(256);
     switch (d.mode) {
       case kModeBuffer:
