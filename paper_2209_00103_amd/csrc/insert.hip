@@ -656,9 +656,7 @@ __device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, c
 // lanes that allocated them; a bucket that existed before the round is read
 // from the table, written by an earlier launch.
 template <typename T, class Prod>
-__global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, Prod prod) {
-  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
-  if (v >= A.V) return;
+__device__ __forceinline__ void grow_store_vector(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v) {
   const uint32_t lane = lane_id();
   const uint64_t c0 = (uint64_t)v * I.chunk;
   const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
@@ -700,6 +698,12 @@ __global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, P
   }
 }
 
+template <typename T, class Prod>
+__global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, Prod prod) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (v < A.V) grow_store_vector<T, Prod>(A, I, prod, v);
+}
+
 __global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
   const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
   if (v < A.V) grow_vector(A, I, v);
@@ -728,6 +732,21 @@ __global__ __launch_bounds__(256) void batch_grow_kernel(const BatchArr* items, 
   const uint32_t i = wave_search(vbegin, n, w);
   const BatchArr it = items[i];
   if (it.n_threads) grow_vector(it.A, item_args(it), (uint32_t)(w - vbegin[i]));
+}
+
+// The one-launch form for a round of many arrays: wave w is LFVector
+// w - vbegin[i] of array i.
+template <typename T, class Prod>
+__global__ __launch_bounds__(256) void batch_grow_store_kernel(const BatchArr* items, const uint64_t* vbegin,
+                                                               uint32_t n, Prod prod) {
+  const uint64_t w = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (w >= vbegin[n]) return;
+  const uint32_t i = wave_search(vbegin, n, w);
+  const BatchArr it = items[i];
+  if (!it.n_threads) return;
+  Prod p = prod;
+  p.bind(it);
+  grow_store_vector<T, Prod>(it.A, item_args(it), p, (uint32_t)(w - vbegin[i]));
 }
 
 template <typename T, class Prod>
@@ -1112,11 +1131,13 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   }
   int rc = GGA_OK;
   uint64_t blocks = 0;
+  uint64_t max_tpv = 0;
   bool grew = false;
   for (uint32_t i = 0; i < b->n && rc == GGA_OK; ++i) {
     uint64_t ntiles = 0;
     const uint64_t* before = b->arrays[i]->ref.status;
     rc = prepare_round_item(b->arrays[i], n_threads[i], d.tag + i, i, &items[i], &ntiles, s, !dense);
+    if (rc == GGA_OK && n_threads[i] && items[i].tpv > max_tpv) max_tpv = items[i].tpv;
     grow_bound(b->arrays[i], n_threads[i]);
     grew = grew || b->arrays[i]->ref.status != before;
     if (rc == GGA_OK && blocks + ntiles > 0x7FFFFFFFull) rc = GGA_EINVAL;
@@ -1181,7 +1202,16 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   if (rc != GGA_OK || !blocks) return rc;
   const dim3 grid((uint32_t)blocks), block(64);
   const bool u32 = b->elem_bytes == 4;
-  if (dense) {
+  if (dense && (max_tpv <= 8 || b->total_vectors >= 512)) {  // one wave per LFVector, as for one array
+    const dim3 vgrid((uint32_t)((b->total_vectors + 3) / 4)), vblock(256);
+    if (d.mode == kModeRoundTag) {
+      if (u32) hipLaunchKernelGGL((batch_grow_store_kernel<uint32_t, ProdRoundTag<uint32_t>>), vgrid, vblock, 0, s, tab->items, b->d_vbegin, b->n, ProdRoundTag<uint32_t>{d.round, d.tag_shift});
+      else hipLaunchKernelGGL((batch_grow_store_kernel<uint64_t, ProdRoundTag<uint64_t>>), vgrid, vblock, 0, s, tab->items, b->d_vbegin, b->n, ProdRoundTag<uint64_t>{d.round, d.tag_shift});
+    } else {
+      if (u32) hipLaunchKernelGGL((batch_grow_store_kernel<uint32_t, ProdKeyed<uint32_t>>), vgrid, vblock, 0, s, tab->items, b->d_vbegin, b->n, ProdKeyed<uint32_t>{d.seed, d.round, d.tag_shift, 0});
+      else hipLaunchKernelGGL((batch_grow_store_kernel<uint64_t, ProdKeyed<uint64_t>>), vgrid, vblock, 0, s, tab->items, b->d_vbegin, b->n, ProdKeyed<uint64_t>{d.seed, d.round, d.tag_shift, 0});
+    }
+  } else if (dense) {
     hipLaunchKernelGGL(batch_grow_kernel, dim3((uint32_t)((b->total_vectors + 3) / 4)), dim3(256), 0, s, tab->items,
                        b->d_vbegin, b->n);
     if (d.mode == kModeRoundTag) {

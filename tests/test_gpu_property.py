@@ -1,0 +1,89 @@
+"""Property-based GPU parity: random shapes (V, F, element size), random rounds of
+every producer kind (buffer with and without flags, Bernoulli, round-tag, keyed,
+per-thread counts, Poisson), random shrinks and r/w passes, drawn by Hypothesis;
+after every operation the GPU array must equal the CPU oracle bit for bit."""
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+import oracle
+from oracle import Oracle
+from paper_2209_00103_amd import workloads as wl
+from tests.gpu_util import assert_same, gg
+
+pytestmark = pytest.mark.gpu
+MiB = 1 << 20
+
+OPS = st.one_of(
+    st.tuples(st.just("buffer"), st.integers(0, 70000), st.floats(0.0, 1.0), st.booleans()),
+    st.tuples(st.just("bernoulli"), st.integers(0, 70000), st.integers(0, 255)),
+    st.tuples(st.just("round_tag"), st.integers(0, 70000), st.integers(0, 255)),
+    st.tuples(st.just("keyed"), st.integers(0, 70000), st.integers(0, 255)),
+    st.tuples(st.just("counts"), st.integers(0, 20000), st.integers(1, 16)),
+    st.tuples(st.just("poisson"), st.integers(0, 20000), st.integers(0, 7)),
+    st.tuples(st.just("shrink"), st.integers(0, 7), st.integers(1, 7)),
+    st.tuples(st.just("rw"), st.integers(0, 2)),
+)
+
+
+@pytest.fixture(scope="module")
+def pool():
+    p = gg().Pool(1024 * MiB)
+    yield p
+    p.close()
+
+
+@settings(max_examples=25, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(elem=st.sampled_from([4, 8]), V=st.sampled_from([1, 2, 5, 64, 300, 512, 1024]),
+       F_log2=st.integers(0, 12), ops=st.lists(OPS, min_size=1, max_size=6), seed=st.integers(0, 2 ** 31))
+def test_random_operation_sequences_match_oracle(pool, elem, V, F_log2, ops, seed):
+    G = gg()
+    F = 1 << F_log2
+    a, o = G.GGArray(pool, elem, V, F), Oracle(elem, V, F)
+    rng = np.random.default_rng(seed)
+    thr = wl.poisson_thresholds(3, 16)
+    try:
+        for step, op in enumerate(ops):
+            kind = op[0]
+            if kind == "buffer":
+                n, p, with_flags = op[1], op[2], op[3]
+                vals, flags = wl.random_round(rng, n, p, elem)
+                if with_flags:
+                    a.insert(G.to_device(vals), G.to_device(flags))
+                    o.insert(vals, flags)
+                else:
+                    a.insert(G.to_device(vals))
+                    o.insert(vals, np.ones(n, np.uint8))
+            elif kind == "bernoulli":
+                a.insert_gen(G.make_gen(G.GEN_BERNOULLI, seed=op[2], round=step), op[1])
+                o.insert_gen(oracle.GEN_BERNOULLI, op[1], seed=op[2], round=step)
+            elif kind == "round_tag":
+                a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=op[2], tag_shift=20), op[1])
+                o.insert_gen(oracle.GEN_ROUND_TAG, op[1], round=op[2], tag_shift=20)
+            elif kind == "keyed":
+                a.insert_gen(G.make_gen(G.GEN_KEYED, seed=op[2] & 255, round=step, tag=op[2]), op[1])
+                o.insert_gen(oracle.GEN_KEYED, op[1], seed=op[2] & 255, round=step, tag=op[2])
+            elif kind == "counts":
+                n, mx = op[1], op[2]
+                counts = rng.integers(0, mx + 1, size=n).astype(np.uint8)
+                if elem == 4:
+                    vals = rng.integers(0, 1 << 32, size=n * mx, dtype=np.uint64).astype(np.uint32)
+                else:
+                    vals = rng.integers(0, np.iinfo(np.uint64).max, size=n * mx, dtype=np.uint64)
+                a.insert_counts(G.to_device(vals), G.to_device(counts), mx)
+                o.insert_counts(vals, counts, mx)
+            elif kind == "poisson":
+                a.insert_gen(G.make_gen(G.GEN_POISSON, seed=1, round=op[2], max_count=16, thresholds=thr), op[1])
+                o.insert_gen(oracle.GEN_POISSON, op[1], seed=1, round=op[2], max_count=16, thresholds=thr)
+            elif kind == "shrink":
+                num, den = min(op[1], op[2]), op[2]
+                a.shrink(num, den)
+                o.shrink(num, den)
+            else:
+                a.rw(op[1])
+                o.rw(op[1])
+            assert_same(a, o, f"step {step} {op}")
+    finally:
+        a.close()
+        o.close()
