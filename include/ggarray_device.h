@@ -305,6 +305,19 @@ __device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls,
   add_nr(&H->shard[arena_shard(s)].n_free, 1ull);
 }
 
+// -------------------------------------------------------- element pointers --
+// Bucket pointers are kept as integers, so the compiler cannot tell that they
+// address device memory and would access elements with flat instructions, whose
+// completion the hardware counts together with LDS and scalar loads: a wait for
+// an LDS read would then also wait for earlier element stores.  Element accesses
+// go through this global-memory view instead.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------------ payloads --
 // SplitMix64 output for generator state x (Steele, Lea, Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -408,7 +421,7 @@ __device__ uint64_t block_push_back(const ArrRef& A, uint32_t v, bool keep, T va
   const uint64_t idx = base + before + rank_w;
   const uint32_t b = bucket_of(A.log2F, idx);
   const uint64_t p = s_bp[b - s_blo];
-  if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(A.log2F, idx, b)] = value;
+  if (p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(A.log2F, idx, b)] = value;
   return idx;
 }
 

@@ -160,7 +160,8 @@ __device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
 // which lets its non-temporal stores find the lines they overwrite (measured:
 // r/w 4.80 -> 5.31 TB/s, flatten slower with cached loads).
 template <typename T, bool kFlatten, bool kNtLoad = kFlatten>
-__device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32_t op) {
+__device__ __forceinline__ void stream_tile(T* src_, T* dst_, uint32_t cnt, uint32_t op) {
+  const gptr<T> src = gmem(src_), dst = gmem(dst_);
   constexpr uint32_t VPL = 16 / sizeof(T);
   constexpr uint32_t kSlots = 4;
   constexpr uint32_t kSpan = kRwThreads * VPL;
@@ -171,14 +172,14 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
     // instruction of a wave covering complete lines (flatten 4.51 -> 4.70 TB/s;
     // taking the misalignment on the global loads instead was slower).
     __shared__ u32x4 stage[kSlots * kRwThreads];
-    const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst) & 127u) / sizeof(T));
+    const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst_) & 127u) / sizeof(T));
     if (mis) {
       const uint32_t nsrc = (cnt + VPL - 1) / VPL;
       for (uint32_t k = 0; k < kSlots; ++k) {
         const uint32_t q = k * kRwThreads + tid;
         if (q < nsrc) {
           if ((q + 1) * VPL <= cnt)
-            stage[q] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + q * VPL));
+            stage[q] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(src + q * VPL));
           else {
             T tmp[VPL] = {};
             for (uint32_t e = 0; e < VPL && q * VPL + e < cnt; ++e) tmp[e] = src[q * VPL + e];
@@ -190,7 +191,7 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
       }
       __syncthreads();
       const T* st = reinterpret_cast<const T*>(stage);
-      T* dal = dst - mis;
+      const gptr<T> dal = dst - mis;
       const uint32_t nvec = (cnt + mis + VPL - 1) / VPL;
       for (uint32_t j = tid; j < nvec; j += kRwThreads) {
         const int64_t e0 = (int64_t)j * VPL - (int64_t)mis;
@@ -199,7 +200,7 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
           for (uint32_t e = 0; e < VPL; ++e) tmp[e] = st[e0 + e];
           u32x4 x;
           __builtin_memcpy(&x, tmp, 16);
-          __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dal + (uint64_t)j * VPL));
+          __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dal + (uint64_t)j * VPL));
         } else {
           for (uint32_t e = 0; e < VPL; ++e) {
             const int64_t i = e0 + e;
@@ -215,26 +216,26 @@ __device__ __forceinline__ void stream_tile(T* src, T* dst, uint32_t cnt, uint32
     u32x4 r[kSlots];
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k)
-      r[k] = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL))
-                      : *reinterpret_cast<const u32x4*>(src + k * kSpan + tid * VPL);
+      r[k] = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(src + k * kSpan + tid * VPL))
+                      : *reinterpret_cast<gptr<const u32x4>>(src + k * kSpan + tid * VPL);
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k) {
       if (kFlatten)
-        __builtin_nontemporal_store(r[k], reinterpret_cast<u32x4_a4*>(dst + k * kSpan + tid * VPL));
+        __builtin_nontemporal_store(r[k], reinterpret_cast<gptr<u32x4_a4>>(dst + k * kSpan + tid * VPL));
       else
-        __builtin_nontemporal_store(op_vec<T>(op, r[k]), reinterpret_cast<u32x4*>(src + k * kSpan + tid * VPL));
+        __builtin_nontemporal_store(op_vec<T>(op, r[k]), reinterpret_cast<gptr<u32x4>>(src + k * kSpan + tid * VPL));
     }
     return;
   }
   for (uint32_t k = 0; k < kSlots; ++k) {
     const uint32_t e = k * kSpan + tid * VPL;
     if (e + VPL <= cnt) {
-      const u32x4 x = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src + e))
-                               : *reinterpret_cast<const u32x4*>(src + e);
+      const u32x4 x = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(src + e))
+                               : *reinterpret_cast<gptr<const u32x4>>(src + e);
       if (kFlatten)
-        __builtin_nontemporal_store(x, reinterpret_cast<u32x4_a4*>(dst + e));
+        __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4_a4>>(dst + e));
       else
-        __builtin_nontemporal_store(op_vec<T>(op, x), reinterpret_cast<u32x4*>(src + e));
+        __builtin_nontemporal_store(op_vec<T>(op, x), reinterpret_cast<gptr<u32x4>>(src + e));
     } else {
       for (uint32_t q = e; q < cnt && q < e + VPL; ++q) {
         if (kFlatten)

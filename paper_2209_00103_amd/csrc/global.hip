@@ -24,11 +24,11 @@ __device__ __forceinline__ uint32_t vector_of(const uint64_t* prefix, uint32_t V
 }
 
 template <typename T>
-__device__ __forceinline__ T* element_at(const ArrRef& A, uint64_t i) {
+__device__ __forceinline__ gptr<T> element_at(const ArrRef& A, uint64_t i) {
   const uint32_t v = vector_of(A.prefix, A.V, i);
   const uint64_t j = i - A.prefix[v];
   const uint32_t b = bucket_of(A.log2F, j);
-  return reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + offset_in(A.log2F, j, b);
+  return gmem(reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b])) + offset_in(A.log2F, j, b);
 }
 
 template <typename T>
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kGlobalThreads) void rw_global_kernel(ArrRef A, uin
   const uint64_t n = A.prefix[A.V];
   const uint64_t stride = (uint64_t)gridDim.x * kGlobalThreads;
   for (uint64_t i = (uint64_t)blockIdx.x * kGlobalThreads + threadIdx.x; i < n; i += stride) {
-    T* p = element_at<T>(A, i);
+    const gptr<T> p = element_at<T>(A, i);
     *p = apply_op<T>(op, *p);
   }
 }

@@ -444,7 +444,8 @@ __device__ __forceinline__ void dense_store(T* dst, const Prod& prod, uint64_t g
   const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst) & 127u) / sizeof(T));
   uint32_t head = mis ? kLine - mis : 0u;
   if (head > n) head = n;
-  if (lane < head) dst[lane] = prod.value(g0 + lane);
+  const gptr<T> d = gmem(dst);
+  if (lane < head) d[lane] = prod.value(g0 + lane);
   const uint32_t nv = (n - head) / VPL;
   for (uint32_t q = lane; q < nv; q += 64) {
     const uint32_t e = head + q * VPL;
@@ -453,10 +454,10 @@ __device__ __forceinline__ void dense_store(T* dst, const Prod& prod, uint64_t g
     for (uint32_t k = 0; k < VPL; ++k) tmp[k] = prod.value(g0 + e + k);
     u32x4 x;
     __builtin_memcpy(&x, tmp, 16);
-    __builtin_nontemporal_store(x, reinterpret_cast<u32x4*>(dst + e));
+    __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(d + e));
   }
   const uint32_t tail = head + nv * VPL + lane;
-  if (tail < n) dst[tail] = prod.value(g0 + tail);
+  if (tail < n) d[tail] = prod.value(g0 + tail);
 }
 
 // One wave, one tile; `block` is the wave's index among the launch's waves for
@@ -525,7 +526,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
       const bool f = bits.get(j);
       const uint64_t m = __ballot(f);
       const uint32_t q = run + mbcnt(m);
-      if (f && q < lim) dst[q] = prod.value(g0 + (uint64_t)j * 64 + lane);
+      if (f && q < lim) gmem(dst)[q] = prod.value(g0 + (uint64_t)j * 64 + lane);
       run += (uint32_t)__popcll(m);
     }
     return;
@@ -537,7 +538,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     const uint64_t idx = r.base + run + mbcnt(m);
     const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
     const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
-    if (f && p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
+    if (f && p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
     run += (uint32_t)__popcll(m);
   }
 }
@@ -773,7 +774,7 @@ __global__ __launch_bounds__(256) void static_atomic_kernel(StaticRef S, uint64_
   for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
     if (!prod.flag(g)) continue;
     const uint64_t pos = fetch_add(S.size, 1);
-    if (pos < S.cap) reinterpret_cast<T*>(S.data)[pos] = prod.value(g);
+    if (pos < S.cap) gmem(reinterpret_cast<T*>(S.data))[pos] = prod.value(g);
     else over = true;
   }
   if (over) set_error(S.err, kErrRange);
@@ -860,12 +861,10 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
   const uint32_t n_out = kStatic ? (sh.writable < n_t ? sh.writable : n_t) : sh.n_tile;  // 0 if stalled
   const uint32_t log2F = A.log2F;
   for (uint32_t q = tid; q < n_out; q += kB) {
-    uint32_t lo = 0, hi = kB;  // s_excl[lo] <= q < s_excl[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (s_excl[mid] <= q) lo = mid;
-      else hi = mid;
-    }
+    uint32_t lo = 0;  // the last thread whose exclusive prefix is <= q
+#pragma unroll
+    for (uint32_t step = kB / 2; step; step >>= 1)
+      if (s_excl[lo + step] <= q) lo += step;
     uint32_t rem = q - s_excl[lo];
     const uint32_t packed = s_cnt[lo];
     uint32_t j = 0;
@@ -876,12 +875,12 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
     }
     const T val = prod.value(g0 + (uint64_t)lo * kCountK + j, rem);
     if (kStatic) {
-      reinterpret_cast<T*>(S.data)[sh.base + q] = val;
+      gmem(reinterpret_cast<T*>(S.data))[sh.base + q] = val;
     } else {
       const uint64_t idx = sh.base + q;
       const uint32_t b = bucket_of(log2F, idx);
       const uint64_t p = sh.bp[b - sh.b_lo];
-      if (p > kFailedPtr) reinterpret_cast<T*>(p)[offset_in(log2F, idx, b)] = val;
+      if (p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val;
     }
   }
 }
