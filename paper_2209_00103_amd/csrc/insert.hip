@@ -35,6 +35,7 @@ constexpr int kW = kB / 64;              // waves per workgroup
 constexpr int kFlagTile = (int)kInsertTile;  // logical threads per tile, 0/1 producers (one wave)
 constexpr int kCountK = 4;               // candidates per thread, multi-element producers
 constexpr int kCountTile = kB * kCountK; // 1024 logical threads per tile
+constexpr uint32_t kOwnWindow = 4096;     // outputs per owner-map pass
 
 // Look-back status word: epoch (30 bits) | flag (2 bits) | value (32 bits).  The
 // value is a count or an inclusive prefix relative to the LFVector's size at the
@@ -783,11 +784,12 @@ __global__ __launch_bounds__(256) void static_atomic_kernel(StaticRef S, uint64_
 // --------------------------------------------- multi-element producer kernel --
 // Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
 // plain scan of per-thread counts orders the elements.  Once the tile's first
-// index is known, the block expands the elements directly: output q (consecutive
-// across lanes, so stores coalesce) belongs to the last thread whose exclusive
-// prefix is <= q (a binary search over the 256 prefixes in LDS), and to that
-// thread's logical thread and element by its four counts; the element is then
-// produced and stored.  Nothing is staged, so the block needs 2 KiB of LDS.
+// index is known, each thread writes, for each of its outputs, who produces it
+// (thread, logical thread, element number) into an LDS owner map; output q
+// (consecutive across lanes, so stores coalesce) then reads its entry, produces
+// the element and stores it.  One LDS write and one read per element replace a
+// binary search over the 256 prefixes per element; the map covers 4096 outputs
+// at a time (16 KiB), more rarely needing further passes.
 template <typename Prod>
 __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt, uint64_t gend,
                                                    uint32_t* cnt) {
@@ -803,8 +805,7 @@ __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt
 template <typename T, class Prod, bool kStatic>
 __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S, TileArgs I,
                                                           Prod prod) {
-  __shared__ uint32_t s_excl[kB + 1];
-  __shared__ uint32_t s_cnt[kB];  // the thread's four counts, 8 bits each
+  __shared__ uint32_t s_own[kOwnWindow];  // output -> (thread, logical thread, element)
   __shared__ TileShared sh;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const bool ticketed = !kStatic && I.tpv > 1;
@@ -849,9 +850,6 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
     n_t += x;
   }
   const uint32_t excl = before + incl - c;
-  s_excl[tid] = excl;
-  s_cnt[tid] = cnt[0] | (cnt[1] << 8) | (cnt[2] << 16) | (cnt[3] << 24);
-  if (tid == 0) s_excl[kB] = n_t;
   if (kStatic) {
     resolve_static(S, n_t, sh);
   } else if (w == 0) {
@@ -860,27 +858,28 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
   __syncthreads();
   const uint32_t n_out = kStatic ? (sh.writable < n_t ? sh.writable : n_t) : sh.n_tile;  // 0 if stalled
   const uint32_t log2F = A.log2F;
-  for (uint32_t q = tid; q < n_out; q += kB) {
-    uint32_t lo = 0;  // the last thread whose exclusive prefix is <= q
+  const uint64_t base = sh.base;
+  for (uint32_t w0 = 0; w0 < n_out; w0 += kOwnWindow) {
+    const uint32_t w1 = n_out - w0 < kOwnWindow ? n_out : w0 + kOwnWindow;
+    if (w0) __syncthreads();  // the previous window has been read
+    // Each thread names itself as the owner of its outputs in this window.
+    uint32_t e = excl - w0;  // wraps for outputs before the window, which fail the test
 #pragma unroll
-    for (uint32_t step = kB / 2; step; step >>= 1)
-      if (s_excl[lo + step] <= q) lo += step;
-    uint32_t rem = q - s_excl[lo];
-    const uint32_t packed = s_cnt[lo];
-    uint32_t j = 0;
-    for (; j < (uint32_t)kCountK - 1; ++j) {
-      const uint32_t cj = (packed >> (8 * j)) & 0xFFu;
-      if (rem < cj) break;
-      rem -= cj;
-    }
-    const T val = prod.value(g0 + (uint64_t)lo * kCountK + j, rem);
-    if (kStatic) {
-      gmem(reinterpret_cast<T*>(S.data))[sh.base + q] = val;
-    } else {
-      const uint64_t idx = sh.base + q;
-      const uint32_t b = bucket_of(log2F, idx);
-      const uint64_t p = sh.bp[b - sh.b_lo];
-      if (p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val;
+    for (uint32_t j = 0; j < (uint32_t)kCountK; ++j)
+      for (uint32_t r = 0; r < cnt[j]; ++r, ++e)
+        if (e < kOwnWindow) s_own[e] = (tid << 10) | (j << 8) | r;
+    __syncthreads();
+    for (uint32_t q = w0 + tid; q < w1; q += kB) {
+      const uint32_t o = s_own[q - w0];
+      const T val = prod.value(g0 + (uint64_t)(o >> 10) * kCountK + ((o >> 8) & 3u), o & 0xFFu);
+      if (kStatic) {
+        gmem(reinterpret_cast<T*>(S.data))[base + q] = val;
+      } else {
+        const uint64_t idx = base + q;
+        const uint32_t b = bucket_of(log2F, idx);
+        const uint64_t p = sh.bp[b - sh.b_lo];
+        if (p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val;
+      }
     }
   }
 }
