@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true", help="skip the served (4096-array request loop) leg")
     ap.add_argument("--no-two-phase", action="store_true", help="skip the growth-then-work case study")
     ap.add_argument("--no-config3", action="store_true", help="skip the irregular-insertion (configuration 3) leg")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the plain fill / copy rate measurement")
     ap.add_argument("--no-shootout", action="store_true",
                     help="skip the scan-vs-atomic insertion comparison and the memory model")
     ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
@@ -79,6 +80,36 @@ def copy_calibration():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def ceiling_leg(torch, reps=10):
+    """Achievable streaming rates on this GPU with plain PyTorch kernels over 4 GiB:
+    a write-only fill, a copy (4 GiB read, 4 GiB written) and an in-place add (the
+    same 4 GiB read and written, the access pattern of r/w).  Context for the
+    roofline fractions, which stay against the 8 TB/s specification."""
+    n = 1 << 30  # int32 words: 4 GiB per buffer
+    a = torch.empty(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+
+    def rate(fn, moved):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return {"GBps": moved / (ms * 1e-3) / 1e9, "ms": ms}
+
+    res = {"fill": rate(lambda: a.fill_(7), 4 * n), "copy": rate(lambda: b.copy_(a), 8 * n),
+           "inplace_add": rate(lambda: a.add_(1), 8 * n), "bytes_per_buffer": 4 * n,
+           "note": "torch fill_, copy_ and add_ over 4 GiB int32 buffers; bytes moved per call / time"}
+    del a, b
+    torch.cuda.empty_cache()
+    return res
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cfg2_hbm_traffic.md")
@@ -760,6 +791,15 @@ def main():
     log(f"ms/step {ms_step:.3f} (wall {ms_step_wall:.3f}); insert {kernels['insert']['Gelem_s']:.1f} Gelem/s "
         f"rw {kernels['rw']['GBps']:.0f} GB/s flatten {kernels['flatten']['GBps']:.0f} GB/s")
 
+    ceilings = None
+    if not args.no_ceiling:
+        ceilings = ceiling_leg(torch)
+        ceilings["flatten_over_copy"] = kernels["flatten"]["GBps"] / ceilings["copy"]["GBps"]
+        ceilings["rw_over_inplace_add"] = kernels["rw"]["GBps"] / ceilings["inplace_add"]["GBps"]
+        log(f"plain kernels: fill {ceilings['fill']['GBps']:.0f} GB/s, copy {ceilings['copy']['GBps']:.0f} GB/s, "
+            f"in-place add {ceilings['inplace_add']['GBps']:.0f} GB/s; flatten / copy "
+            f"{ceilings['flatten_over_copy']:.2f}, rw / in-place add {ceilings['rw_over_inplace_add']:.2f}")
+
     # Baselines beside it: the static array (pre-allocated for 2^28) and the
     # host-resized array, same insertion rounds (they have no shrink) and r/w.
     baselines = None
@@ -897,6 +937,7 @@ def main():
         "memory": {"capacity_elems": capacity, "live_elems": final_size, "capacity_over_live": capacity / final_size,
                    "per_round": mem_rounds,
                    "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
+        "ceilings": ceilings,
         "parity_with_oracle": parity,
         "ms_per_step_wall": ms_step_wall,
         "ms_per_step_graph": graph_ms,

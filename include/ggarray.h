@@ -35,6 +35,13 @@
  *    the elements land in thread-rank order, a thread's own elements contiguous
  *    and in their order.  The result is therefore a pure function of the inputs,
  *    V and first_bucket; block size and launch shape never change it.
+ *  - HIP graphs: the single-array calls may be captured on `s`.  During capture
+ *    nothing is allocated: an insertion round needing more look-back words than
+ *    an earlier eager round of the array left returns GGA_EINVAL (run the same
+ *    round once eagerly first).  The size prefix and the tile table that r/w and
+ *    flatten read are recomputed inside the graph, so a replay sees the sizes of
+ *    its own moment.  Internal buffers an array outgrows are kept until
+ *    ggarray_destroy, so a graph captured earlier stays valid.
  */
 #ifndef GGARRAY_H
 #define GGARRAY_H

@@ -1,25 +1,38 @@
 // Size/prefix scan, shrink, regular read/write, flatten and bucket release.
 //
 // Regular access walks the LFVectors bucket by bucket (the per-block access rw_b
-// of Sec. VI-B), but the work is cut into bucket-aligned tiles of at most 16 KiB
-// that are spread evenly over a persistent grid, so the number of LFVectors and
-// their uneven sizes do not set the parallelism.  A tile lies inside one bucket,
-// so it costs one bucket-pointer load and streams 16-byte vectors.
+// of Sec. VI-B), but the work is cut into bucket-aligned tiles of at most 16 KiB,
+// so the number of LFVectors and their uneven sizes do not set the parallelism.
+// A tile lies inside one bucket and streams 16-byte vectors.  For one array the
+// tiles are listed once per state of the sizes in a tile table and each
+// workgroup streams one tile; batches and served steps spread the tiles over a
+// persistent grid that locates its share by a search of the tile prefix.
 #include "gga_internal.h"
 
 namespace gga {
 namespace {
 
 constexpr uint32_t kScanThreads = 1024;
-// Persistent grids of the streaming kernels (256-thread workgroups; 256 CUs).
-// Measured on configuration 2: r/w peaks at 4096-8192 workgroups, flatten keeps
-// gaining up to 65536 (4.47 TB/s at 2048, 4.70 at 16384, 5.13 at 32768, 5.27 at
-// 65536).
+// Persistent grids of the batched and served streaming kernels (256-thread
+// workgroups; 256 CUs).  Measured on configuration 2 with the search-located
+// shares: r/w peaks at 4096-8192 workgroups, flatten keeps gaining up to 65536
+// (4.47 TB/s at 2048, 4.70 at 16384, 5.13 at 32768, 5.27 at 65536).
 constexpr uint32_t kRwBlocks = 8192;
 constexpr uint32_t kFlattenBlocks = 65536;
 // The static-array baseline streams a flat buffer; it measured best with
 // non-temporal loads and 2048 workgroups (5.04 TB/s), and runs that way.
 constexpr uint32_t kStaticBlocks = 2048;
+// Table-driven r/w and flatten of one array: one workgroup per tile, up to this
+// many workgroups, looping beyond (configuration 2: flatten 5.33 -> 5.7 TB/s
+// against the search-located persistent grid).
+constexpr uint32_t kTableBlocks = 131072;
+// Largest tile table kept per array (32 MiB, arrays up to 32 GiB of elements);
+// a larger array walks its buckets instead.  Arrays the host knows to hold fewer
+// than kTableMinTiles tiles (32 MiB of elements) walk their buckets too: for them
+// the table's extra launch costs more than it saves.
+constexpr uint64_t kTableMaxTiles = 1ull << 21;
+constexpr uint64_t kTableMinTiles = 2048;
+
 
 // Workgroups for one array's r/w or flatten: enough for the tiles the array can
 // hold (the host's upper bound of its size), at most `cap`, so a small array
@@ -305,17 +318,64 @@ __device__ __forceinline__ void stream_range(const ArrRef& A, uint64_t t0, uint6
   }
 }
 
-// Persistent grid over one array: workgroup w takes the w-th contiguous share.
+// Tile table of one array, built once per state of the sizes (after the prefix
+// scan): tile t, in the order of the tile prefix, gets the address of its first
+// element and its destination offset in a flatten, with its element count in the
+// top 16 bits.  One wave per LFVector, lanes over the tiles of each bucket.
+// Entries from `cap` on are not written; the streaming kernels then walk the
+// buckets instead.
+__global__ __launch_bounds__(256) void tile_table_kernel(ArrRef A, uint64_t* tab, uint64_t cap, uint32_t te_log2,
+                                                         uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  if (v >= A.V) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t s = A.size[v];
+  uint64_t t = A.tprefix[v];
+  const uint64_t pv = A.prefix[v];
+  const uint32_t log2F = A.log2F;
+  const uint64_t te = 1ull << te_log2;
+  typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+  for (uint32_t b = 0; b < (uint32_t)kMaxBuckets; ++b) {
+    const uint64_t st = bucket_start(log2F, b);
+    if (st >= s) break;
+    uint64_t live = bucket_len(log2F, b);
+    if (s - st < live) live = s - st;
+    const uint64_t nt = (live + te - 1) >> te_log2;
+    const uint64_t base = A.bptr[(uint64_t)v * kMaxBuckets + b];
+    for (uint64_t i = lane; i < nt; i += 64) {
+      const uint64_t e0 = i << te_log2;
+      const uint64_t cnt = live - e0 < te ? live - e0 : te;
+      if (t + i < cap) {
+        const u64x2 d = {base + (e0 << elem_log2), (pv + st + e0) | (cnt << 48)};
+        gmem(reinterpret_cast<u64x2*>(tab))[t + i] = d;
+      }
+    }
+    t += nt;
+  }
+}
+
+// r/w or flatten of one array through its tile table: workgroup w takes tiles
+// w, w + G, ...  (one each when the grid covers the array).  Without a table
+// for the current state (more tiles than it holds) the grid walks the buckets.
 template <typename T, bool kFlatten>
-__global__ __launch_bounds__(kRwThreads) void stream_kernel(ArrRef A, uint32_t op, T* out,
-                                                           uint64_t out_cap, uint32_t te_log2) {
+__global__ __launch_bounds__(kRwThreads) void stream_table_kernel(ArrRef A, const uint64_t* __restrict__ tab,
+                                                                 uint64_t cap, uint32_t op, T* out,
+                                                                 uint64_t out_cap, uint32_t te_log2) {
   const uint64_t total = A.tprefix[A.V];
   if (kFlatten && A.prefix[A.V] > out_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) set_error(A.err, kErrRange);
     return;
   }
   const uint64_t G = gridDim.x;
-  stream_range<T, kFlatten>(A, total * blockIdx.x / G, total * (blockIdx.x + 1) / G, op, out, te_log2);
+  if (total > cap) {
+    stream_range<T, kFlatten>(A, total * blockIdx.x / G, total * (blockIdx.x + 1) / G, op, out, te_log2);
+    return;
+  }
+  for (uint64_t t = blockIdx.x; t < total; t += G) {
+    const uint64_t src = tab[2 * t], w = tab[2 * t + 1];
+    stream_tile<T, kFlatten>(reinterpret_cast<T*>(src), kFlatten ? out + (w & 0xFFFFFFFFFFFFull) : nullptr,
+                             (uint32_t)(w >> 48), op);
+  }
 }
 
 // Static / semi-static array r/w: the flat array cut into 16 KiB tiles, each
@@ -536,7 +596,7 @@ int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s) {
   if (num == den) a->size_ub = 0;
   const uint32_t blocks = (a->V + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(shrink_kernel, dim3(blocks), dim3(256), 0, s, a->ref, num, den, a->elem_log2);
-  a->prefix_valid = false;
+  sizes_changed(a);
   return hip_status(hipGetLastError());
 }
 
@@ -553,25 +613,83 @@ int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s) {
   return hip_status(hipGetLastError());
 }
 
-int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
+// Builds the tile table for the current sizes (the prefix must be current).
+// Under graph capture it is always rebuilt, inside the graph, and never grown.
+static int ensure_table(ggarray* a, hipStream_t s) {
+  const bool cap_mode = stream_capturing(s);
+  if (a->tab_gen == a->sizes_gen && !cap_mode) return GGA_OK;
   const uint32_t te_log2 = 14u - a->elem_log2;
+  const uint64_t ub = a->size_ub;
+  // Tiles of an LFVector of s elements: at most s / te + one partial tile per bucket.
+  // With the sizes unknown to the host (after device-side pushes) the table is not grown.
+  uint64_t need = a->tab_cap;
+  if (ub < (1ull << 40)) {
+    need = (ub >> te_log2) + (uint64_t)a->V * (nbuckets_for(a->log2F, ub) + 1);
+    if (need > kTableMaxTiles) need = kTableMaxTiles;
+  }
+  if (need > a->tab_cap && !cap_mode) {
+    uint64_t ncap = a->tab_cap * 2 > need ? a->tab_cap * 2 : need;
+    if (ncap > kTableMaxTiles) ncap = kTableMaxTiles;
+    void* p = nullptr;
+    if (hipMallocAsync(&p, 16 * ncap, s) == hipSuccess) {
+      if (retire_buffer(a, a->tile_tab, s) != GGA_OK) return GGA_EHIP;
+      a->tile_tab = static_cast<uint64_t*>(p);
+      a->tab_cap = ncap;
+    } else {
+      (void)hipGetLastError();  // keep the smaller table; a larger array walks its buckets
+    }
+  }
+  if (a->tab_cap) {
+    hipLaunchKernelGGL(tile_table_kernel, dim3((a->V + kVecPerBlock - 1) / kVecPerBlock), dim3(256), 0, s, a->ref,
+                       a->tile_tab, a->tab_cap, te_log2, a->elem_log2);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_status(e);
+  }
+  a->tab_gen = a->sizes_gen;
+  return GGA_OK;
+}
+
+// The table to stream through (its capacity 0: walk the buckets), built if needed.
+static int stream_source(ggarray* a, hipStream_t s, const uint64_t** tab, uint64_t* cap) {
+  *tab = nullptr;
+  *cap = 0;
+  if ((a->size_ub >> (14u - a->elem_log2)) < kTableMinTiles) return GGA_OK;
+  const int rc = ensure_table(a, s);
+  if (rc) return rc;
+  *tab = a->tile_tab;
+  *cap = a->tab_cap;
+  return GGA_OK;
+}
+
+int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
+  const uint64_t* tab;
+  uint64_t tcap;
+  const int rc = stream_source(a, s, &tab, &tcap);
+  if (rc) return rc;
+  const uint32_t te_log2 = 14u - a->elem_log2;
+  const dim3 grid(stream_grid(a, tcap ? kTableBlocks : kRwBlocks)), block(kRwThreads);
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL((stream_kernel<uint32_t, false>), dim3(stream_grid(a, kRwBlocks)), dim3(kRwThreads), 0, s,
-                       a->ref, op, (uint32_t*)nullptr, (uint64_t)0, te_log2);
+    hipLaunchKernelGGL((stream_table_kernel<uint32_t, false>), grid, block, 0, s, a->ref, tab, tcap, op,
+                       (uint32_t*)nullptr, (uint64_t)0, te_log2);
   else
-    hipLaunchKernelGGL((stream_kernel<uint64_t, false>), dim3(stream_grid(a, kRwBlocks)), dim3(kRwThreads), 0, s,
-                       a->ref, op, (uint64_t*)nullptr, (uint64_t)0, te_log2);
+    hipLaunchKernelGGL((stream_table_kernel<uint64_t, false>), grid, block, 0, s, a->ref, tab, tcap, op,
+                       (uint64_t*)nullptr, (uint64_t)0, te_log2);
   return hip_status(hipGetLastError());
 }
 
 int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
+  const uint64_t* tab;
+  uint64_t tcap;
+  const int rc = stream_source(a, s, &tab, &tcap);
+  if (rc) return rc;
   const uint32_t te_log2 = 14u - a->elem_log2;
+  const dim3 grid(stream_grid(a, tcap ? kTableBlocks : kFlattenBlocks)), block(kRwThreads);
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL((stream_kernel<uint32_t, true>), dim3(stream_grid(a, kFlattenBlocks)), dim3(kRwThreads), 0, s,
-                       a->ref, 0u, static_cast<uint32_t*>(out), cap, te_log2);
+    hipLaunchKernelGGL((stream_table_kernel<uint32_t, true>), grid, block, 0, s, a->ref, tab, tcap, 0u,
+                       static_cast<uint32_t*>(out), cap, te_log2);
   else
-    hipLaunchKernelGGL((stream_kernel<uint64_t, true>), dim3(stream_grid(a, kFlattenBlocks)), dim3(kRwThreads), 0, s,
-                       a->ref, 0u, static_cast<uint64_t*>(out), cap, te_log2);
+    hipLaunchKernelGGL((stream_table_kernel<uint64_t, true>), grid, block, 0, s, a->ref, tab, tcap, 0u,
+                       static_cast<uint64_t*>(out), cap, te_log2);
   return hip_status(hipGetLastError());
 }
 
@@ -603,7 +721,7 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
   const uint64_t blocks = (b->total_vectors + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(batch_shrink_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, b->d_arrays, b->d_vbegin,
                      b->n, num, den);
-  for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = false;
+  for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i]);
   return hip_status(hipGetLastError());
 }
 

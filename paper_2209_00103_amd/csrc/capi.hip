@@ -248,6 +248,11 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->status_cap = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
   a->size_ub = 0;
+  a->tile_tab = nullptr;
+  a->tab_cap = 0;
+  a->sizes_gen = 0;
+  a->tab_gen = ~0ull;
+  a->n_retired = 0;
   p->n_arrays += 1;
   *out = a;
   return GGA_OK;
@@ -258,6 +263,9 @@ int ggarray_destroy(ggarray* a, gga_stream s) {
   ggarray_full* f = reinterpret_cast<ggarray_full*>(a);
   int rc = launch_free_all(a, S(s));
   if (a->ref.status && hipFreeAsync(a->ref.status, S(s)) != hipSuccess) rc = GGA_EHIP;
+  if (a->tile_tab && hipFreeAsync(a->tile_tab, S(s)) != hipSuccess) rc = GGA_EHIP;
+  for (uint32_t i = 0; i < a->n_retired; ++i)
+    if (hipFreeAsync(a->retired[i], S(s)) != hipSuccess) rc = GGA_EHIP;
   if (hipStreamSynchronize(S(s)) != hipSuccess) rc = GGA_EHIP;
   if (hipFree(a->meta) != hipSuccess) rc = GGA_EHIP;
   f->x.pin.release();
@@ -306,8 +314,10 @@ int ggarray_shrink(ggarray* a, uint32_t num, uint32_t den, gga_stream s) {
   return launch_shrink(a, num, den, S(s));
 }
 
+// Under graph capture the scan is always recorded, so that a replay never reads
+// a prefix left over from before the capture.
 static int ensure_prefix(ggarray* a, hipStream_t s) {
-  return a->prefix_valid ? GGA_OK : launch_scan(a, s);
+  return a->prefix_valid && !stream_capturing(s) ? GGA_OK : launch_scan(a, s);
 }
 
 int ggarray_rw(ggarray* a, uint32_t op, gga_stream s) {
@@ -384,7 +394,7 @@ int ggarray_device_ref(ggarray* a, void* out, uint64_t bytes) {
 int ggarray_device_done(ggarray* a, gga_stream s) {
   (void)s;
   if (!a) return GGA_EINVAL;
-  a->prefix_valid = false;
+  sizes_changed(a);
   a->size_ub = ~0ull >> 2;  // sizes unknown to the host now
   return GGA_OK;
 }

@@ -24,7 +24,41 @@ struct ggarray {
   uint64_t status_cap;    // look-back words available
   bool prefix_valid;      // prefix / tprefix match the current sizes
   uint64_t size_ub;       // host upper bound of the size (sets launch shapes only)
+  uint64_t* tile_tab;     // device: per tile, its first element's address and its
+                          // destination offset | element count << 48 (r/w, flatten)
+  uint64_t tab_cap;       // tiles the table holds
+  uint64_t sizes_gen;     // advanced whenever the LFVector sizes may change
+  uint64_t tab_gen;       // sizes_gen the table was built for
+  // Device buffers the array has outgrown (look-back words, tile tables): kept
+  // until the array is destroyed, so that a HIP graph captured earlier never
+  // reads freed memory.  Both grow at least twofold, so few are retired.
+  void* retired[64];
+  uint32_t n_retired;
 };
+
+// Hands an outgrown device buffer to the array, to be freed with it.
+inline int retire_buffer(ggarray* a, void* p, hipStream_t s) {
+  if (!p) return GGA_OK;
+  if (a->n_retired < sizeof(a->retired) / sizeof(a->retired[0])) {
+    a->retired[a->n_retired++] = p;
+    return GGA_OK;
+  }
+  return hipFreeAsync(p, s) == hipSuccess ? GGA_OK : GGA_EHIP;
+}
+
+// The LFVector sizes are about to change (insertion, shrink, device-side use):
+// the prefix and the tile table must be rebuilt before the next walk.
+inline void sizes_changed(ggarray* a) {
+  a->prefix_valid = false;
+  ++a->sizes_gen;
+}
+
+// True while `s` records into a HIP graph (or when that cannot be told): then
+// nothing may be allocated, and derived state is rebuilt inside the graph.
+inline bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
 
 struct gga_static {
   void* data;

@@ -978,13 +978,15 @@ int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64
 // Look-back words (needed only when an LFVector spans several tiles): grown on
 // demand and zeroed when new (a zero word is never current).  Their epochs come
 // from the ticket words, so launches need no host-side state and a captured
-// graph can be replayed (capture after one eager launch of the same shape, so
-// that no allocation happens during capture).
+// graph can be replayed.  Nothing is allocated while the stream is capturing
+// (run the same round eagerly first); an outgrown buffer is retired, not freed,
+// so graphs that use it stay valid.
 int ensure_status(ggarray* a, uint64_t ntiles, hipStream_t s) {
   if (ntiles <= a->status_cap) return GGA_OK;
+  if (stream_capturing(s)) return GGA_EINVAL;  // nothing is allocated inside a graph
   uint64_t cap = a->status_cap ? a->status_cap : 4096;
   while (cap < ntiles) cap *= 2;
-  if (a->ref.status && hipFreeAsync(a->ref.status, s) != hipSuccess) return GGA_EHIP;
+  if (retire_buffer(a, a->ref.status, s) != GGA_OK) return GGA_EHIP;
   a->ref.status = nullptr;
   a->status_cap = 0;
   void* p = nullptr;
@@ -1019,7 +1021,7 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   if (dense) {
     const int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
                                       : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
-    if (st == GGA_OK) a->prefix_valid = false;
+    if (st == GGA_OK) sizes_changed(a);
     return st;
   }
 
@@ -1031,7 +1033,7 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
                                     : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
   if (st == GGA_OK) {
-    a->prefix_valid = false;
+    sizes_changed(a);
   }
   return st;
 }
@@ -1231,7 +1233,7 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess)
-    for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = false;
+    for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i]);
   return hip_status(e);
 }
 

@@ -316,7 +316,7 @@ int run_batched(RunState& R) {
           items.push_back(it);
           begins.push_back(blocks);
           blocks += ntiles;
-          arr->prefix_valid = false;
+          sizes_changed(arr);
           grow_bound(arr, tr->length[r]);
         } else {
           const bool flat = kind == GGA_REQ_FLATTEN;

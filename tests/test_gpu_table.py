@@ -1,0 +1,126 @@
+"""The tile table that r/w and flatten of a large array (2^23 elements or more)
+stream through: results equal the oracle whether the table covers the array or
+not (graphs captured before the array outgrew it), and graphs captured earlier
+stay correct after the library outgrows and retires its buffers."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import Oracle
+from paper_2209_00103_amd import workloads as wl
+from tests.gpu_util import gg
+
+pytestmark = pytest.mark.gpu
+MiB = 1 << 20
+BIG = 1 << 23  # elements from which r/w and flatten use a tile table (2048 tiles of 16 KiB, u32)
+
+
+@pytest.fixture
+def pool():
+    p = gg().Pool(2048 * MiB)
+    yield p
+    p.close()
+
+
+def _check(G, out, o, what):
+    ref = o.flatten()
+    got = G.as_unsigned(out[:ref.size])
+    assert np.array_equal(got, ref), f"{what}: {np.count_nonzero(got != ref)} elements differ"
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_graph_growing_past_the_table_it_was_captured_with(pool, elem):
+    """The table is sized eagerly for a small array; the captured step grows the
+    array far past it on every replay, so the replays stream without a table."""
+    G = gg()
+    V, F = 6, 16
+    a, o = G.GGArray(pool, elem, V, F), Oracle(elem, V, F)
+    dt = torch.int32 if elem == 4 else torch.int64
+    a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=0, tag_shift=26), BIG + 300)
+    o.insert_gen(oracle.GEN_ROUND_TAG, BIG + 300, round=0, tag_shift=26)
+    big = BIG
+    out = torch.zeros(BIG + 300 + 3 * big, dtype=dt, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.rw(G.ADD1)  # eager: builds a table for this size
+        a.flatten_into(out)
+    s.synchronize()
+    o.rw(oracle.OP_ADD1)
+    _check(G, out, o, "eager")
+    gen = G.make_gen(G.GEN_ROUND_TAG, round=1, tag_shift=26)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.insert_gen(gen, big)
+        a.rw(G.MUL3ADD1)
+        a.flatten_into(out)
+    for rep in range(3):
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o.insert_gen(oracle.GEN_ROUND_TAG, big, round=1, tag_shift=26)
+        o.rw(oracle.OP_MUL3ADD1)
+        _check(G, out, o, f"replay {rep}")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
+
+
+def test_graph_of_rw_alone_sees_later_eager_growth(pool):
+    """A graph of r/w + flatten captured on an array of 2^23 elements, replayed
+    after eager insertions (and eager calls that grow, and retire, the tile table)."""
+    G = gg()
+    V, F = 5, 64
+    a, o = G.GGArray(pool, 4, V, F), Oracle(4, V, F)
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=3, round=0, tag=1), BIG)
+    o.insert_gen(oracle.GEN_KEYED, BIG, seed=3, round=0, tag=1)
+    out = torch.zeros(BIG + (1 << 24) + 5000 + 400000 + 3000000, dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.rw(G.ADD1)
+    s.synchronize()
+    o.rw(oracle.OP_ADD1)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.rw(G.ADD1_X30)
+        a.flatten_into(out)
+    for rep, n in enumerate((0, 5000, 3000000, 1 << 24)):
+        if n:
+            a.insert_gen(G.make_gen(G.GEN_KEYED, seed=3, round=rep, tag=1), n)
+            o.insert_gen(oracle.GEN_KEYED, n, seed=3, round=rep, tag=1)
+            a.rw(G.ADD1)  # eager: rebuilds (and grows) the table
+            o.rw(oracle.OP_ADD1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o.rw(oracle.OP_ADD1_X30)
+        _check(G, out, o, f"replay after {n} more")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
+
+
+def test_tile_table_on_many_small_and_empty_vectors(pool):
+    """3000 LFVectors with first bucket 2 (many partial tiles per LFVector), buffer
+    rounds of 2^22 threads with random flags, shrinks, r/w and flatten."""
+    G = gg()
+    V, F = 3000, 2
+    a, o = G.GGArray(pool, 4, V, F), Oracle(4, V, F)
+    rng = np.random.default_rng(11)
+    out = torch.zeros(1 << 24, dtype=torch.int32, device="cuda")
+    for r in range(4):
+        n = (1 << 22) - int(rng.integers(0, 1000))
+        vals, flags = wl.random_round(rng, n, float(rng.uniform(0.5, 0.95)), 4)
+        a.insert(G.to_device(vals), G.to_device(flags))
+        o.insert(vals, flags)
+        a.rw(G.MUL3ADD1)
+        o.rw(oracle.OP_MUL3ADD1)
+        a.flatten_into(out)
+        _check(G, out, o, f"round {r}")
+        a.shrink(1, 5)
+        o.shrink(1, 5)
+    a.flatten_into(out)
+    _check(G, out, o, "after the last shrink")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
