@@ -113,6 +113,7 @@ def ceiling_leg(torch, reps=10):
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cfg2_hbm_traffic.md")
+VALU_SUMMARY = os.path.join(ROOT, "profiles", "cfg3_insert_alu.md")
 
 
 def kernel_source_digest() -> str:
@@ -127,18 +128,24 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path: str, kernel: str):
-    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary, or None
-    when there is none or the kernels changed since it was taken."""
+def measured_counter(path: str, key: str, kernel: str):
+    """A per-launch counter figure of `kernel` from a rocprofv3 summary (its line
+    `key: {json}`), or None when there is none or the kernels changed since."""
     if not path or not os.path.exists(path):
         return None
     with open(path) as f:
         for line in f:
-            if line.startswith("traffic_bytes_per_launch:"):
+            if line.startswith(key + ":"):
                 d = json.loads(line.split(":", 1)[1])
                 if d.get("digest") == kernel_source_digest():
                     return d.get(kernel)
     return None
+
+
+def measured_traffic(path: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summary, or None
+    when there is none or the kernels changed since it was taken."""
+    return measured_counter(path, "traffic_bytes_per_launch", kernel)
 
 
 class Timer:
@@ -600,9 +607,21 @@ def config3_leg(G, wl, torch, steps=3):
                        "insert_GBps": 8 * added / (ins * 1e-3) / 1e9, "rw_us": 1e3 * rw,
                        "rw_GBps": 16 * sizes[i] / (rw * 1e-3) / 1e9})
     fl = statistics.median(timer.ms("flatten"))
+    # The insertion is bound by vector-ALU issue (SplitMix64 per element): its roofline
+    # is the VALU instruction rate, from the committed counter summary (VALU wave
+    # instructions per launch, valid while the kernel sources are unchanged) over the
+    # live launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+    ins_us = statistics.median(p["insert_us"] for p in phases)
+    valu = measured_counter(VALU_SUMMARY, "valu_per_launch", "insert")
+    peak = 256 * 4 * 16 * 2.4e9 / 1e12
+    roof = {"kernel": "insert_count_kernel (Poisson counts)", "bound": "alu", "unit": "T lane-instr/s",
+            "peak": peak, "achieved": None, "frac": None, "valu_insts_per_launch": valu, "avg_launch_us": ins_us}
+    if valu:
+        roof["achieved"] = valu * 64 / (ins_us * 1e-6) / 1e12
+        roof["frac"] = roof["achieved"] / peak
     return {"workload": "2^26 threads, Poisson(3) counts capped at 16, uint64 K(1,gid,16i+j), V = 65536, "
                         "4 x (insert, r/w x+1), flatten", "final_size": sizes[-1], "phases": phases,
-            "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9}
+            "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9, "insert_roofline": roof}
 
 
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
@@ -887,8 +906,11 @@ def main():
     if not args.no_config3:
         try:
             config3 = config3_leg(G, wl, torch)
+            r3 = config3["insert_roofline"]
             log("configuration 3: insert " + ", ".join(f"{p['insert_Gelem_s']:.1f}" for p in config3["phases"])
-                + f" Gelem/s; flatten {config3['flatten_GBps']:.0f} GB/s")
+                + f" Gelem/s (VALU issue {r3['frac'] if r3['frac'] is None else round(r3['frac'], 2)} of peak); "
+                + "r/w " + ", ".join(f"{p['rw_GBps']:.0f}" for p in config3["phases"])
+                + f" GB/s; flatten {config3['flatten_GBps']:.0f} GB/s")
         except Exception as e:  # reported, never silently dropped
             config3 = {"error": str(e)}
             log(f"configuration-3 leg failed: {e}")

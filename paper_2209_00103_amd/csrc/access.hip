@@ -26,11 +26,11 @@ constexpr uint32_t kStaticBlocks = 2048;
 // many workgroups, looping beyond (configuration 2: flatten 5.33 -> 5.7 TB/s
 // against the search-located persistent grid).
 constexpr uint32_t kTableBlocks = 131072;
-// Largest tile table kept per array (32 MiB, arrays up to 32 GiB of elements);
+// Largest tile table kept per array (128 MiB, arrays up to 128 GiB of elements);
 // a larger array walks its buckets instead.  Arrays the host knows to hold fewer
 // than kTableMinTiles tiles (32 MiB of elements) walk their buckets too: for them
 // the table's extra launch costs more than it saves.
-constexpr uint64_t kTableMaxTiles = 1ull << 21;
+constexpr uint64_t kTableMaxTiles = 1ull << 23;
 constexpr uint64_t kTableMinTiles = 2048;
 
 
@@ -92,6 +92,73 @@ __device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2) {
 
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2) {
   scan_array(A, te_log2);
+}
+
+// The same prefix sums for many LFVectors, over many workgroups in two passes.
+// Pass 1: workgroup c scans LFVectors [1024 c, 1024 c + 1024) (one per thread,
+// coalesced), writes their prefixes within the chunk and the chunk's totals.
+__global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(ArrRef A, uint64_t* tot, uint32_t te_log2) {
+  __shared__ uint64_t wsum_e[kScanThreads / 64], wsum_t[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t v = blockIdx.x * kScanThreads + tid;
+  const uint64_t e = v < A.V ? A.size[v] : 0;
+  const uint64_t t = tiles_for(A.log2F, e, te_log2);
+  const uint64_t ie = wave_incl_scan64(e), it = wave_incl_scan64(t);
+  if (lane == 63) {
+    wsum_e[w] = ie;
+    wsum_t[w] = it;
+  }
+  __syncthreads();
+  uint64_t be = 0, bt = 0, ce = 0, ct = 0;
+  for (uint32_t k = 0; k < kScanThreads / 64; ++k) {
+    if (k < w) {
+      be += wsum_e[k];
+      bt += wsum_t[k];
+    }
+    ce += wsum_e[k];
+    ct += wsum_t[k];
+  }
+  if (v < A.V) {
+    A.prefix[v] = be + ie - e;
+    A.tprefix[v] = bt + it - t;
+  }
+  if (tid == 0) {
+    tot[2 * blockIdx.x] = ce;
+    tot[2 * blockIdx.x + 1] = ct;
+  }
+}
+
+// Pass 2: workgroup c adds the totals of the chunks before it; the last chunk's
+// workgroup writes entry V.
+__global__ __launch_bounds__(kScanThreads) void scan_fix_kernel(ArrRef A, const uint64_t* tot, uint32_t nchunks) {
+  __shared__ uint64_t red_e[kScanThreads / 64], red_t[kScanThreads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  uint64_t e = 0, t = 0;
+  for (uint32_t c = tid; c < blockIdx.x; c += kScanThreads) {
+    e += tot[2 * c];
+    t += tot[2 * c + 1];
+  }
+  e = wave_incl_scan64(e);
+  t = wave_incl_scan64(t);
+  if (lane == 63) {
+    red_e[w] = e;
+    red_t[w] = t;
+  }
+  __syncthreads();
+  uint64_t oe = 0, ot = 0;
+  for (uint32_t k = 0; k < kScanThreads / 64; ++k) {
+    oe += red_e[k];
+    ot += red_t[k];
+  }
+  const uint32_t v = blockIdx.x * kScanThreads + tid;
+  if (v < A.V) {
+    A.prefix[v] += oe;
+    A.tprefix[v] += ot;
+  }
+  if (blockIdx.x == nchunks - 1 && tid == 0) {
+    A.prefix[A.V] = oe + tot[2 * blockIdx.x];
+    A.tprefix[A.V] = ot + tot[2 * blockIdx.x + 1];
+  }
 }
 
 // Shrink (pop floor(s num / den) per LFVector) and bucket release: one wave per
@@ -585,8 +652,14 @@ int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin
 }
 
 int launch_scan(ggarray* a, hipStream_t s) {
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref,
-                     14u - a->elem_log2);
+  const uint32_t te_log2 = 14u - a->elem_log2;
+  if (a->V <= 4 * kScanThreads) {  // one workgroup, a few LFVectors per thread
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref, te_log2);
+  } else {  // one workgroup per 1024 LFVectors, two passes
+    const uint32_t chunks = (a->V + kScanThreads - 1) / kScanThreads;
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, te_log2);
+    hipLaunchKernelGGL(scan_fix_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, chunks);
+  }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) a->prefix_valid = true;
   return hip_status(e);

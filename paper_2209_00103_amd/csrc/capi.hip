@@ -218,6 +218,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   const size_t o_vticket = off;    off = align_up(off + 8 * V, 256);
   const size_t o_rbase = off;      off = align_up(off + 8 * V, 256);
   const size_t o_misc = off;       off = align_up(off + 64, 256);  // err, scratch
+  const size_t o_stot = off;       off = align_up(off + 16 * ((V + 1023) / 1024), 256);  // scan chunk totals
   if (hipMalloc(&a->meta, off) != hipSuccess) {
     delete f;
     return GGA_EHIP;
@@ -240,6 +241,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.vticket = reinterpret_cast<uint64_t*>(m + o_vticket);
   R.rbase = reinterpret_cast<uint64_t*>(m + o_rbase);
   f->x.d_scratch = reinterpret_cast<uint64_t*>(m + o_misc + 16);
+  a->scan_tot = reinterpret_cast<uint64_t*>(m + o_stot);
   R.status = nullptr;
   R.pool = p->ref;
   R.V = n_vectors;

@@ -34,6 +34,7 @@ struct ggarray {
   // reads freed memory.  Both grow at least twofold, so few are retired.
   void* retired[64];
   uint32_t n_retired;
+  uint64_t* scan_tot;     // device: per 1024 LFVectors, their total size and tiles
 };
 
 // Hands an outgrown device buffer to the array, to be freed with it.
@@ -160,17 +161,17 @@ struct ServeItem {
 };
 
 // Tiles of an LFVector of s elements: every bucket below s contributes
-// ceil(live elements of the bucket / te) tiles.
-__device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
-  uint64_t n = 0;
+// ceil(live elements of the bucket / te) tiles.  In closed form: the nb - 1 full
+// buckets hold F 2^b elements, one tile each while F 2^b <= te and F 2^b / te
+// tiles after that (a geometric sum), and the last bucket holds the rest.
+__host__ __device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
   const uint32_t nb = nbuckets_for(log2F, s);
-  for (uint32_t b = 0; b < nb; ++b) {
-    const uint64_t st = bucket_start(log2F, b);
-    uint64_t live = bucket_len(log2F, b);
-    if (s - st < live) live = s - st;
-    n += (live + (1ull << te_log2) - 1) >> te_log2;
-  }
-  return n;
+  if (nb == 0) return 0;
+  const uint32_t full = nb - 1;
+  const uint32_t small = te_log2 > log2F ? (te_log2 - log2F < full ? te_log2 - log2F : full) : 0u;
+  uint64_t n = small;
+  if (full > small) n += (1ull << (log2F + full - te_log2)) - (1ull << (log2F + small - te_log2));
+  return n + ((s - bucket_start(log2F, full) + (1ull << te_log2) - 1) >> te_log2);
 }
 
 __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t x) {

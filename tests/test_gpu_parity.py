@@ -55,6 +55,8 @@ CASES = [  # elem, V, F, n_threads, p
     (8, 300, 16, 257, 0.5),             # fewer threads than LFVectors
     (4, 5, 8, 0, 0.5),                  # empty round
     (4, 1, 4096, 1 << 22, 0.3),          # 1024 tiles in one LFVector
+    (4, 4097, 8, 300000, 0.6),          # prefix over several workgroups, last chunk of one LFVector
+    (8, 70000, 1, 500000, 0.4),         # 69 chunks of the multi-workgroup prefix, many empty LFVectors
 ]
 
 
