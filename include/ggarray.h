@@ -247,9 +247,10 @@ int ggarray_device_done(ggarray *a, gga_stream s);
  *   array i starts at offset[i], the exclusive prefix of the array sizes.  If the
  *   total exceeds out_cap_elems nothing is written and the batch's sticky
  *   GGA_ERANGE is set.
- * gga_batch_set_grid: workgroups of the persistent grid that r/w and flatten
- *   launch (1..65536; 0 restores the defaults, 8192 for r/w and 65536 for
- *   flatten).  A launch-shape knob for tuning; results do not depend on it.
+ * gga_batch_set_grid: workgroups that r/w and flatten launch (1..2^20; 0
+ *   restores the defaults: one per tile of the batch's tile table, at most
+ *   131072, or 8192 for r/w and 65536 for flatten when the batch streams
+ *   without a table).  A launch-shape knob for tuning; results do not depend on it.
  * gga_batch_offsets: the n + 1 offsets (uint64, last = total) to dev_out.
  * gga_batch_last_error: the batch's sticky error.  Synchronises s. */
 int gga_batch_create(gga_batch **out, ggarray *const *arrays, uint32_t n, gga_stream s);

@@ -22,7 +22,7 @@ import json
 import os
 
 CANDIDATES = tuple(1 << k for k in range(6, 15))
-GRID_CANDIDATES = (4096, 8192, 16384, 32768, 65536)
+GRID_CANDIDATES = (0, 8192, 16384, 32768, 65536, 131072)  # 0: the library's default shape
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ggarray", "autotune.json")
 
 
@@ -140,10 +140,11 @@ class AutoTuner:
         return best
 
     def tune_grid(self, batch, out, total_elems: int) -> int:
-        """Workgroups of the batch's persistent r/w + flatten grid: the fastest of
-        GRID_CANDIDATES on this batch (r/w x+1 then flatten into out), cached by
-        (architecture, element size, octave of the batch's element count).  Leaves
-        the batch's contents changed by the r/w passes."""
+        """Workgroups of the batch's r/w + flatten launches: the fastest of
+        GRID_CANDIDATES on this batch (r/w x+1 then flatten into out; 0 is the
+        library's default shape), cached by (architecture, element size, octave of
+        the batch's element count).  Leaves the batch's contents changed by the r/w
+        passes."""
         import torch
 
         from paper_2209_00103_amd import ggarray as G

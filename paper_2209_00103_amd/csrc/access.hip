@@ -391,14 +391,13 @@ __device__ __forceinline__ void stream_range(const ArrRef& A, uint64_t t0, uint6
 // top 16 bits.  One wave per LFVector, lanes over the tiles of each bucket.
 // Entries from `cap` on are not written; the streaming kernels then walk the
 // buckets instead.
-__global__ __launch_bounds__(256) void tile_table_kernel(ArrRef A, uint64_t* tab, uint64_t cap, uint32_t te_log2,
-                                                         uint32_t elem_log2) {
-  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
-  if (v >= A.V) return;
+__device__ __forceinline__ void table_vector(const ArrRef& A, uint32_t v, uint64_t* tab, uint64_t cap,
+                                             uint32_t te_log2, uint32_t elem_log2, uint64_t t_base,
+                                             uint64_t e_base) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint64_t s = A.size[v];
-  uint64_t t = A.tprefix[v];
-  const uint64_t pv = A.prefix[v];
+  uint64_t t = t_base + A.tprefix[v];
+  const uint64_t pv = e_base + A.prefix[v];
   const uint32_t log2F = A.log2F;
   const uint64_t te = 1ull << te_log2;
   typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
@@ -419,6 +418,26 @@ __global__ __launch_bounds__(256) void tile_table_kernel(ArrRef A, uint64_t* tab
     }
     t += nt;
   }
+}
+
+__global__ __launch_bounds__(256) void tile_table_kernel(ArrRef A, uint64_t* tab, uint64_t cap, uint32_t te_log2,
+                                                         uint32_t elem_log2) {
+  const uint32_t v = blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  if (v < A.V) table_vector(A, v, tab, cap, te_log2, elem_log2, 0, 0);
+}
+
+// The tile table of a batch: the tiles of array i follow those of arrays before
+// it (tile_begin), and destination offsets are positions in the batch flatten
+// (elem_begin).  Wave w is LFVector w - vbegin[i] of array i.
+__global__ __launch_bounds__(256) void batch_table_kernel(const BatchArr* items, const uint64_t* vbegin,
+                                                          const uint64_t* tile_begin, const uint64_t* elem_begin,
+                                                          uint32_t n, uint64_t* tab, uint64_t cap,
+                                                          uint32_t te_log2) {
+  const uint64_t w = (uint64_t)blockIdx.x * kVecPerBlock + (threadIdx.x >> 6);
+  if (w >= vbegin[n]) return;
+  const uint32_t i = wave_search(vbegin, n, w);
+  table_vector(items[i].A, (uint32_t)(w - vbegin[i]), tab, cap, te_log2, items[i].elem_log2, tile_begin[i],
+               elem_begin[i]);
 }
 
 // r/w or flatten of one array through its tile table: workgroup w takes tiles
@@ -524,12 +543,14 @@ __global__ __launch_bounds__(256) void batch_shrink_kernel(const BatchArr* items
   shrink_vector(items[i].A, (uint32_t)(w - vbegin[i]), num, den, items[i].elem_log2);
 }
 
-// Persistent grid over the tiles of every array of the batch: workgroup w takes
-// the w-th contiguous share and walks it array by array.  Flatten writes array i
-// at out + elem_begin[i].
+// r/w or flatten of every array of the batch.  With a tile table covering the
+// batch, workgroup w takes tiles w, w + G, ...; otherwise a persistent grid:
+// workgroup w takes the w-th contiguous share of the tiles and walks it array by
+// array.  Flatten writes array i at out + elem_begin[i].
 template <typename T, bool kFlatten>
 __global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr* items, const uint64_t* tile_begin,
                                                                  const uint64_t* elem_begin, uint32_t n,
+                                                                 const uint64_t* __restrict__ tab, uint64_t tcap,
                                                                  uint32_t op, T* out, uint64_t cap,
                                                                  uint32_t* err, uint32_t te_log2) {
   const uint64_t total = tile_begin[n];
@@ -538,6 +559,14 @@ __global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr
     return;
   }
   const uint64_t G = gridDim.x;
+  if (total <= tcap) {
+    for (uint64_t t = blockIdx.x; t < total; t += G) {
+      const uint64_t src = tab[2 * t], w = tab[2 * t + 1];
+      stream_tile<T, kFlatten>(reinterpret_cast<T*>(src), kFlatten ? out + (w & 0xFFFFFFFFFFFFull) : nullptr,
+                               (uint32_t)(w >> 48), op);
+    }
+    return;
+  }
   uint64_t g0 = total * blockIdx.x / G;
   const uint64_t g1 = total * (blockIdx.x + 1) / G;
   if (g0 >= g1) return;
@@ -777,15 +806,80 @@ int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
 }
 
 
+// Sum of the member arrays' size generations: unchanged exactly when no member's
+// sizes can have changed since it was last taken.
+static uint64_t batch_gen(const gga_batch* b) {
+  uint64_t g = 0;
+  for (uint32_t i = 0; i < b->n; ++i) g += b->arrays[i]->sizes_gen;
+  return g;
+}
+
 int launch_batch_scan(gga_batch* b, hipStream_t s) {
+  const uint64_t gen = batch_gen(b);
+  if (b->scan_valid && b->scan_gen == gen && !stream_capturing(s)) return GGA_OK;
   const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
   hipLaunchKernelGGL(batch_scan_kernel, dim3(b->n), dim3(kScanThreads), 0, s, b->d_arrays, te_log2);
   hipLaunchKernelGGL(batch_top_kernel<BatchArr>, dim3(1), dim3(kScanThreads), 0, s, b->d_arrays, b->n,
                      b->d_tile_begin, b->d_elem_begin);
   const hipError_t e = hipGetLastError();
-  if (e == hipSuccess)
+  if (e == hipSuccess) {
     for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = true;
+    b->scan_valid = true;
+    b->scan_gen = gen;
+  }
   return hip_status(e);
+}
+
+// The batch's tile table for the current sizes (after launch_batch_scan); like
+// the single-array table it is grown only outside graph capture, retired rather
+// than freed, and always rebuilt under capture.  *tab / *tcap: what to stream
+// through (capacity 0: the persistent walk).
+static int ensure_batch_table(gga_batch* b, hipStream_t s, const uint64_t** tab, uint64_t* tcap, uint64_t* bound) {
+  const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
+  uint64_t need = 0;
+  bool known = true;
+  for (uint32_t i = 0; i < b->n; ++i) {
+    const ggarray* a = b->arrays[i];
+    if (a->size_ub >= (1ull << 40)) known = false;
+    else need += (a->size_ub >> te_log2) + (uint64_t)a->V * (nbuckets_for(a->log2F, a->size_ub) + 1);
+  }
+  *bound = known ? need : kTableMaxTiles;
+  *tab = nullptr;
+  *tcap = 0;
+  if (known && need < kTableMinTiles) return GGA_OK;
+  if (!known) need = b->tab_cap;
+  if (need > kTableMaxTiles) need = kTableMaxTiles;
+  const bool cap_mode = stream_capturing(s);
+  const uint64_t gen = batch_gen(b);
+  if (!(b->tab_valid && b->tab_gen == gen && !cap_mode)) {
+    if (need > b->tab_cap && !cap_mode) {
+      uint64_t ncap = b->tab_cap * 2 > need ? b->tab_cap * 2 : need;
+      if (ncap > kTableMaxTiles) ncap = kTableMaxTiles;
+      void* p = nullptr;
+      if (hipMallocAsync(&p, 16 * ncap, s) == hipSuccess) {
+        if (b->tile_tab) {
+          if (b->n_retired < sizeof(b->retired) / sizeof(b->retired[0])) b->retired[b->n_retired++] = b->tile_tab;
+          else if (hipFreeAsync(b->tile_tab, s) != hipSuccess) return GGA_EHIP;
+        }
+        b->tile_tab = static_cast<uint64_t*>(p);
+        b->tab_cap = ncap;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    if (b->tab_cap) {
+      hipLaunchKernelGGL(batch_table_kernel, dim3((uint32_t)((b->total_vectors + kVecPerBlock - 1) / kVecPerBlock)),
+                         dim3(256), 0, s, b->d_arrays, b->d_vbegin, b->d_tile_begin, b->d_elem_begin, b->n,
+                         b->tile_tab, b->tab_cap, te_log2);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return hip_status(e);
+    }
+    b->tab_valid = true;
+    b->tab_gen = gen;
+  }
+  *tab = b->tile_tab;
+  *tcap = b->tab_cap;
+  return GGA_OK;
 }
 
 int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s) {
@@ -800,21 +894,27 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
 
 int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s) {
   const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
-  const dim3 grid(b->stream_blocks ? b->stream_blocks : (flatten ? kFlattenBlocks : kRwBlocks)), block(kRwThreads);
+  const uint64_t* tab;
+  uint64_t tcap, bound;
+  const int rc = ensure_batch_table(b, s, &tab, &tcap, &bound);
+  if (rc) return rc;
+  uint64_t g = b->stream_blocks;
+  if (!g) g = tcap ? (bound < kTableBlocks ? (bound ? bound : 1) : kTableBlocks) : (flatten ? kFlattenBlocks : kRwBlocks);
+  const dim3 grid((uint32_t)g), block(kRwThreads);
   if (b->elem_bytes == 4) {
     if (flatten)
       hipLaunchKernelGGL((batch_stream_kernel<uint32_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
-                         b->d_elem_begin, b->n, 0u, static_cast<uint32_t*>(out), cap, b->d_err, te_log2);
+                         b->d_elem_begin, b->n, tab, tcap, 0u, static_cast<uint32_t*>(out), cap, b->d_err, te_log2);
     else
       hipLaunchKernelGGL((batch_stream_kernel<uint32_t, false>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
-                         b->d_elem_begin, b->n, op, (uint32_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
+                         b->d_elem_begin, b->n, tab, tcap, op, (uint32_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
   } else {
     if (flatten)
       hipLaunchKernelGGL((batch_stream_kernel<uint64_t, true>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
-                         b->d_elem_begin, b->n, 0u, static_cast<uint64_t*>(out), cap, b->d_err, te_log2);
+                         b->d_elem_begin, b->n, tab, tcap, 0u, static_cast<uint64_t*>(out), cap, b->d_err, te_log2);
     else
       hipLaunchKernelGGL((batch_stream_kernel<uint64_t, false>), grid, block, 0, s, b->d_arrays, b->d_tile_begin,
-                         b->d_elem_begin, b->n, op, (uint64_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
+                         b->d_elem_begin, b->n, tab, tcap, op, (uint64_t*)nullptr, (uint64_t)0, b->d_err, te_log2);
   }
   return hip_status(hipGetLastError());
 }

@@ -412,6 +412,8 @@ static void batch_free(gga_batch* b) {
     delete[] b->tables[k].host;
   }
   delete[] b->tables;
+  if (b->tile_tab) (void)hipFree(b->tile_tab);  // hipFree waits for the device
+  for (uint32_t k = 0; k < b->n_retired; ++k) (void)hipFree(b->retired[k]);
   delete[] b->arrays;
   delete b;
 }
@@ -509,7 +511,7 @@ int gga_batch_flatten(gga_batch* b, void* out, uint64_t out_cap_elems, gga_strea
 }
 
 int gga_batch_set_grid(gga_batch* b, uint32_t stream_blocks) {
-  if (!b || stream_blocks > 65536) return GGA_EINVAL;
+  if (!b || stream_blocks > (1u << 20)) return GGA_EINVAL;
   b->stream_blocks = stream_blocks;
   return GGA_OK;
 }

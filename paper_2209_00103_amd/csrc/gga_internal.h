@@ -99,6 +99,16 @@ struct gga_batch {
   Table* tables;
   uint32_t n_tables;
   uint32_t cap_tables;
+  // Prefix scans and tile table of the batch, valid for the member arrays' size
+  // generations they were built for (see batch_gen).
+  bool scan_valid;
+  uint64_t scan_gen;
+  uint64_t* tile_tab;      // device: two words per tile of the whole batch
+  uint64_t tab_cap;
+  bool tab_valid;
+  uint64_t tab_gen;
+  void* retired[64];       // outgrown tables, freed with the batch
+  uint32_t n_retired;
 };
 
 struct gga_semistatic {

@@ -124,3 +124,62 @@ def test_tile_table_on_many_small_and_empty_vectors(pool):
     assert a.last_error() == 0
     a.close()
     o.close()
+
+
+def test_batch_table_and_its_graph(pool):
+    """A batch above the table threshold (three arrays, 2^23 + elements in all):
+    batched r/w and flatten against the oracles, eagerly and as a graph whose
+    replays grow the batch past the table it was captured with."""
+    G = gg()
+    shapes = [(64, 1024), (3, 16), (700, 2)]
+    arrays = [G.GGArray(pool, 4, V, F) for V, F in shapes]
+    oracles = [Oracle(4, V, F) for V, F in shapes]
+    b = G.Batch(arrays)
+    first = [BIG // 2, 3 * BIG // 8, BIG // 4]
+    b.insert_gen(G.make_gen(G.GEN_KEYED, seed=9, round=0, tag=4), first)
+    for i, o in enumerate(oracles):
+        o.insert_gen(oracle.GEN_KEYED, first[i], seed=9, round=0, tag=4 + i)
+    grow = [1 << 20, 1 << 19, 3 << 19]
+    total = sum(first) + 4 * sum(grow)
+    out = torch.zeros(total, dtype=torch.int32, device="cuda")
+    grow_gen = G.make_gen(G.GEN_KEYED, seed=9, round=1, tag=4)
+
+    def grow_oracles():
+        for i, o in enumerate(oracles):
+            o.insert_gen(oracle.GEN_KEYED, grow[i], seed=9, round=1, tag=4 + i)
+
+    def check(what):
+        torch.cuda.synchronize()
+        offs = b.offsets().cpu().numpy()
+        got = G.as_unsigned(out)
+        for i, o in enumerate(oracles):
+            ref = o.flatten()
+            assert offs[i + 1] - offs[i] == ref.size, f"{what}: array {i} size"
+            assert np.array_equal(got[offs[i]:offs[i + 1]], ref), f"{what}: array {i} differs"
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        b.rw(G.ADD1)
+        b.flatten_into(out)
+    for o in oracles:
+        o.rw(oracle.OP_ADD1)
+    check("eager")
+    with torch.cuda.stream(s):
+        b.insert_gen(grow_gen, grow)  # eager round of this shape: its launch table exists before capture
+    grow_oracles()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.insert_gen(grow_gen, grow)
+        b.rw(G.MUL3ADD1)
+        b.flatten_into(out)
+    for rep in range(3):
+        g.replay()
+        grow_oracles()
+        for o in oracles:
+            o.rw(oracle.OP_MUL3ADD1)
+        check(f"replay {rep}")
+    assert b.last_error() == 0
+    b.close()
+    for a, o in zip(arrays, oracles):
+        a.close()
+        o.close()
