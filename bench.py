@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (512-array) leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served (4096-array request loop) leg")
     ap.add_argument("--no-two-phase", action="store_true", help="skip the growth-then-work case study")
+    ap.add_argument("--no-config1", action="store_true", help="skip the small launch-bound (configuration 1) leg")
     ap.add_argument("--no-config3", action="store_true", help="skip the irregular-insertion (configuration 3) leg")
     ap.add_argument("--no-ceiling", action="store_true", help="skip the plain fill / copy rate measurement")
     ap.add_argument("--no-shootout", action="store_true",
@@ -565,6 +566,76 @@ def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=6):
     return {"workload": f"N = {N}, {samples} draws per sigma, GGArray V = {V}, F = {F}", "rows": rows}
 
 
+def config1_leg(G, wl, torch, reps=50):
+    """Configuration 1 (small, launch-bound, cache-resident): 256 LFVectors, first
+    bucket 1024, uint32, 2^18 threads per round inserting K(1, gid, r) with
+    probability 1/2 over 4 rounds, r/w x + 1, flatten (about 2 MiB live).  Reported
+    as latency: per-operation device time (HIP events; median and p10/p90 over
+    `reps` steps) and the whole step eager and replayed as a HIP graph."""
+    cfg = wl.CFG1
+    pool = G.Pool(256 << 20)
+    a = G.GGArray(pool, 4, cfg["V"], cfg["F"])
+    gens = [G.make_gen(G.GEN_BERNOULLI, seed=1, round=r) for r in range(cfg["rounds"])]
+    n = cfg["n_threads"]
+    for g in gens:
+        a.insert_gen(g, n)
+    size = a.size()
+    out = torch.empty(size, dtype=torch.int32, device="cuda")
+
+    def step(t=None):
+        a.shrink(1, 1)
+        for r, g in enumerate(gens):
+            with (t.span(f"insert{r}") if t else _Null()):
+                a.insert_gen(g, n)
+        with (t.span("rw") if t else _Null()):
+            a.rw(G.ADD1)
+        with (t.span("flatten") if t else _Null()):
+            a.flatten_into(out)
+
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        for _ in range(5):
+            step()
+        timer = Timer(torch)
+        for _ in range(reps):
+            step(timer)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+    s.synchronize()
+    eager_us = 1e3 * e0.elapsed_time(e1) / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        step()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_us = 1e3 * e0.elapsed_time(e1) / reps
+    assert a.last_error() == 0 and a.size() == size
+    a.close()
+    pool.close()
+
+    def pct(xs):
+        q = sorted(xs)
+        return {"p10_us": round(1e3 * q[int(0.1 * (len(q) - 1))], 2), "p50_us": round(1e3 * statistics.median(q), 2),
+                "p90_us": round(1e3 * q[int(round(0.9 * (len(q) - 1)))], 2)}
+
+    ops = {f"insert{r}": pct(timer.ms(f"insert{r}")) for r in range(len(gens))}
+    ops["rw"] = pct(timer.ms("rw"))
+    ops["flatten"] = pct(timer.ms("flatten"))
+    return {"workload": "256 LFVectors, first bucket 1024, uint32, 4 rounds of 2^18 threads inserting "
+                        "K(1,gid,r) with probability 1/2, r/w x+1, flatten", "final_size": size,
+            "ops": ops, "step_us_eager": eager_us, "step_us_graph": graph_us, "reps": reps}
+
+
 def config3_leg(G, wl, torch, steps=3):
     """Configuration 3 at full size (irregular insertion): uint64, V = 65536,
     F = 1024, 2^26 threads with Poisson(3) counts capped at 16 (thresholds from the
@@ -902,6 +973,17 @@ def main():
         except Exception as e:
             memory_model = {"error": str(e)}
             log(f"memory model failed: {e}")
+    config1 = None
+    if not args.no_config1:
+        try:
+            config1 = config1_leg(G, wl, torch)
+            o1 = config1["ops"]
+            log(f"configuration 1: step {config1['step_us_eager']:.1f} us eager, {config1['step_us_graph']:.1f} us "
+                f"as a graph; insert p50 " + ", ".join(f"{o1[f'insert{r}']['p50_us']:.1f}" for r in range(4))
+                + f" us, r/w {o1['rw']['p50_us']:.1f} us, flatten {o1['flatten']['p50_us']:.1f} us")
+        except Exception as e:  # reported, never silently dropped
+            config1 = {"error": str(e)}
+            log(f"configuration-1 leg failed: {e}")
     config3 = None
     if not args.no_config3:
         try:
@@ -967,6 +1049,7 @@ def main():
         "served": served,
         "global_index_access": next_rows,
         "two_phase": two_phase,
+        "config1": config1,
         "config3": config3,
         "insertion_shootout": shootout,
         "memory_model": memory_model,
