@@ -118,14 +118,21 @@ VALU_SUMMARY = os.path.join(ROOT, "profiles", "cfg3_insert_alu.md")
 
 
 def kernel_source_digest() -> str:
-    """Digest of the HIP sources; a traffic figure counts only if it was measured on them."""
+    """Digest of the HIP sources and the device header, comments and blank space
+    removed; a counter figure counts only if it was measured on the same code."""
     import hashlib
+    import re
     csrc = os.path.join(ROOT, "paper_2209_00103_amd", "csrc")
+    files = [os.path.join(csrc, n) for n in sorted(os.listdir(csrc)) if n.endswith((".hip", ".h"))]
+    files.append(os.path.join(ROOT, "include", "ggarray_device.h"))
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for path in files:
+        with open(path) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = " ".join(text.split())
+        h.update(os.path.basename(path).encode() + b"\0" + text.encode())
     return h.hexdigest()[:16]
 
 

@@ -3,10 +3,11 @@
 // Regular access walks the LFVectors bucket by bucket (the per-block access rw_b
 // of Sec. VI-B), but the work is cut into bucket-aligned tiles of at most 16 KiB,
 // so the number of LFVectors and their uneven sizes do not set the parallelism.
-// A tile lies inside one bucket and streams 16-byte vectors.  For one array the
-// tiles are listed once per state of the sizes in a tile table and each
-// workgroup streams one tile; batches and served steps spread the tiles over a
-// persistent grid that locates its share by a search of the tile prefix.
+// A tile lies inside one bucket and streams 16-byte vectors.  For an array (or a
+// batch) of at least 2048 tiles the tiles are listed once per state of the sizes
+// in a tile table and workgroups take table entries; smaller arrays and served
+// steps spread the tiles over a persistent grid that locates its share by a
+// search of the tile prefix.
 #include "gga_internal.h"
 
 namespace gga {

@@ -85,7 +85,7 @@ struct gga_batch {
   uint32_t* d_err;           // device: sticky batch error (flatten output too small)
   uint64_t* d_vbegin;        // device: n + 1 exclusive prefix of the arrays' LFVector counts
   uint64_t total_vectors;
-  uint32_t stream_blocks;    // persistent grid of the r/w and flatten launches (0: default)
+  uint32_t stream_blocks;    // workgroups of the r/w and flatten launches (0: default)
   uint64_t* h_pin;           // pinned host scratch
   // Round tables uploaded so far (descriptors + block offsets), reused when the
   // same round shape comes again, so a captured graph always reads a stable table.
