@@ -49,7 +49,7 @@ typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
 
 // Exclusive prefix sums of the LFVector sizes (element offsets, Sec. IV) and of
 // their tile counts, by one workgroup of kScanThreads; entry V holds the totals.
-__device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2) {
+__device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2, uint64_t* copy = nullptr) {
   __shared__ uint64_t wsum_e[kScanThreads / 64], wsum_t[kScanThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const uint32_t V = A.V;
@@ -81,18 +81,21 @@ __device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2) {
   for (uint32_t v = v0; v < v1; ++v) {
     const uint64_t s = A.size[v];
     A.prefix[v] = re;
+    if (copy) copy[v] = re;
     A.tprefix[v] = rt;
     re += s;
     rt += tiles_for(A.log2F, s, te_log2);
   }
   if (tid == 0) {
     A.prefix[V] = te;
+    if (copy) copy[V] = te;
     A.tprefix[V] = tt;
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2) {
-  scan_array(A, te_log2);
+// `copy`, if not null, receives the V + 1 prefix entries too (ggarray_prefix).
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(ArrRef A, uint32_t te_log2, uint64_t* copy) {
+  scan_array(A, te_log2, copy);
 }
 
 // The same prefix sums for many LFVectors, over many workgroups in two passes.
@@ -131,7 +134,8 @@ __global__ __launch_bounds__(kScanThreads) void scan_chunks_kernel(ArrRef A, uin
 
 // Pass 2: workgroup c adds the totals of the chunks before it; the last chunk's
 // workgroup writes entry V.
-__global__ __launch_bounds__(kScanThreads) void scan_fix_kernel(ArrRef A, const uint64_t* tot, uint32_t nchunks) {
+__global__ __launch_bounds__(kScanThreads) void scan_fix_kernel(ArrRef A, const uint64_t* tot, uint32_t nchunks,
+                                                             uint64_t* copy) {
   __shared__ uint64_t red_e[kScanThreads / 64], red_t[kScanThreads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   uint64_t e = 0, t = 0;
@@ -154,10 +158,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_fix_kernel(ArrRef A, const 
   const uint32_t v = blockIdx.x * kScanThreads + tid;
   if (v < A.V) {
     A.prefix[v] += oe;
+    if (copy) copy[v] = A.prefix[v];
     A.tprefix[v] += ot;
   }
   if (blockIdx.x == nchunks - 1 && tid == 0) {
     A.prefix[A.V] = oe + tot[2 * blockIdx.x];
+    if (copy) copy[A.V] = oe + tot[2 * blockIdx.x];
     A.tprefix[A.V] = ot + tot[2 * blockIdx.x + 1];
   }
 }
@@ -681,14 +687,14 @@ int launch_serve_stream(const ServeItem* items, uint32_t n, uint64_t* tile_begin
   return hip_status(hipGetLastError());
 }
 
-int launch_scan(ggarray* a, hipStream_t s) {
+int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy) {
   const uint32_t te_log2 = 14u - a->elem_log2;
   if (a->V <= 4 * kScanThreads) {  // one workgroup, a few LFVectors per thread
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref, te_log2);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, s, a->ref, te_log2, copy);
   } else {  // one workgroup per 1024 LFVectors, two passes
     const uint32_t chunks = (a->V + kScanThreads - 1) / kScanThreads;
     hipLaunchKernelGGL(scan_chunks_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, te_log2);
-    hipLaunchKernelGGL(scan_fix_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, chunks);
+    hipLaunchKernelGGL(scan_fix_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, chunks, copy);
   }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) a->prefix_valid = true;
@@ -857,10 +863,10 @@ static int ensure_batch_table(gga_batch* b, hipStream_t s, const uint64_t** tab,
       uint64_t ncap = b->tab_cap * 2 > need ? b->tab_cap * 2 : need;
       if (ncap > kTableMaxTiles) ncap = kTableMaxTiles;
       void* p = nullptr;
-      if (hipMallocAsync(&p, 16 * ncap, s) == hipSuccess) {
+      if (hipMalloc(&p, 16 * ncap) == hipSuccess) {  // freed with hipFree when the batch is destroyed
         if (b->tile_tab) {
           if (b->n_retired < sizeof(b->retired) / sizeof(b->retired[0])) b->retired[b->n_retired++] = b->tile_tab;
-          else if (hipFreeAsync(b->tile_tab, s) != hipSuccess) return GGA_EHIP;
+          else if (hipFree(b->tile_tab) != hipSuccess) return GGA_EHIP;  // waits for the device
         }
         b->tile_tab = static_cast<uint64_t*>(p);
         b->tab_cap = ncap;

@@ -376,8 +376,7 @@ int ggarray_vector_sizes(ggarray* a, uint64_t* dev_out, gga_stream s) {
 
 int ggarray_prefix(ggarray* a, uint64_t* dev_out, gga_stream s) {
   if (!a || !dev_out) return GGA_EINVAL;
-  int rc = ensure_prefix(a, S(s));
-  if (rc) return rc;
+  if (!a->prefix_valid || stream_capturing(S(s))) return launch_scan(a, S(s), dev_out);  // scan writes both
   return hip_status(hipMemcpyAsync(dev_out, a->ref.prefix, 8ull * (a->V + 1), hipMemcpyDeviceToDevice, S(s)));
 }
 
