@@ -298,7 +298,8 @@ int orc_insert(orc_array *a, const void *values, const uint8_t *flags, uint64_t 
 }
 
 /* Buffer mode with several elements per thread: thread gid inserts
- * values[gid * max_count + j] for j < counts[gid]. */
+ * values[gid * max_count + j] for j < min(counts[gid], max_count) (the library's
+ * contract clamps larger counts). */
 int orc_insert_counts(orc_array *a, const void *values, const uint8_t *counts, uint32_t max_count,
                       uint64_t n_threads)
 {
@@ -311,9 +312,8 @@ int orc_insert_counts(orc_array *a, const void *values, const uint8_t *counts, u
         uint64_t g0 = (uint64_t)v * chunk;
         uint64_t g1 = g0 + chunk < n_threads ? g0 + chunk : n_threads;
         for (uint64_t gid = g0; gid < g1; gid++) {
-            if (counts[gid] > max_count)
-                return ORC_EINVAL;
-            for (uint32_t j = 0; j < counts[gid]; j++) {
+            const uint32_t c = counts[gid] < max_count ? counts[gid] : max_count;
+            for (uint32_t j = 0; j < c; j++) {
                 int st = push(a, v, load_elem(values, a->elem_bytes, gid * max_count + j));
                 if (st)
                     return st;

@@ -118,6 +118,7 @@ def test_insert_counts(pool, elem):
         n = 5000 + 777 * r
         mc = [16, 5, 1][r]
         counts = rng.integers(0, mc + 1, size=n, dtype=np.uint8)
+        counts[::97] = 255  # above max_count: clamped to it
         vals, _ = wl.random_round(rng, n * mc, 1.0, elem)
         a.insert_counts(dev(vals), dev(counts), mc)
         o.insert_counts(vals, counts, mc)

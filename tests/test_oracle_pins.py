@@ -200,6 +200,14 @@ def test_insert_counts_order():
     assert o.flatten().tolist() == [0, 1, 6, 7, 8, 9]
 
 
+def test_insert_counts_clamps_to_max_count():
+    """A count above max_count inserts max_count elements (the C-ABI contract)."""
+    o = Oracle(4, 1, 4)
+    vals = np.arange(6, dtype=np.uint32)  # 2 threads x 3 slots
+    o.insert_counts(vals, np.array([7, 255], dtype=np.uint8), 3)
+    assert o.flatten().tolist() == [0, 1, 2, 3, 4, 5]
+
+
 # ---------------------------------------------------------------------------
 # Generated workloads: gen mode equals buffer mode built by the numpy generator.
 # ---------------------------------------------------------------------------
