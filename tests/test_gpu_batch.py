@@ -166,3 +166,42 @@ def test_single_array_graph_replays_equal_eager(pool):
         np.testing.assert_array_equal(G.as_unsigned(out), ref, err_msg=f"replay {rep}")
     assert a.last_error() == 0
     a.close()
+
+
+def test_results_do_not_depend_on_launch_shape(pool):
+    """The same batched rounds, r/w and flatten under every streaming grid (1
+    workgroup up to 131072, and the default) give identical outputs; so do single
+    arrays that differ only in their first-bucket size."""
+    G = gg()
+    rng = np.random.default_rng(5)
+    rounds = [_sizes(rng, len(SHAPES)) for _ in range(3)]
+    total = sum(sum(r[i] for r in rounds) for i in range(len(SHAPES)))
+    ref = None
+    for grid in (0, 1, 3, 4096, 131072):
+        arrays = [G.GGArray(pool, 4, V, F) for V, F in SHAPES]
+        b = G.Batch(arrays)
+        b.set_grid(grid)
+        for r, n in enumerate(rounds):
+            b.insert_gen(G.make_gen(G.GEN_KEYED, seed=2, round=r, tag=7), n)
+        b.rw(G.MUL3ADD1)
+        out = torch.zeros(total, dtype=torch.int32, device="cuda")
+        b.flatten_into(out)
+        got = G.as_unsigned(out).copy()
+        assert b.last_error() == 0
+        if ref is None:
+            ref = got
+        else:
+            assert np.array_equal(got, ref), f"grid {grid}"
+        b.close()
+        for a in arrays:
+            a.close()
+    flats = []
+    for F in (1, 64, 4096):
+        a = G.GGArray(pool, 8, 9, F)
+        for r in range(3):
+            a.insert_gen(G.make_gen(G.GEN_BERNOULLI, seed=4, round=r), 70001)
+        a.shrink(2, 7)
+        a.rw(G.ADD1)
+        flats.append(gpu_flat(a))
+        a.close()
+    assert all(np.array_equal(flats[0], f) for f in flats[1:])
