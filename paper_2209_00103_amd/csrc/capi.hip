@@ -255,6 +255,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->sizes_gen = 0;
   a->tab_gen = ~0ull;
   a->n_retired = 0;
+  a->last_rw_gen = 0;
   p->n_arrays += 1;
   *out = a;
   return GGA_OK;

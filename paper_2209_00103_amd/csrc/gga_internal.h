@@ -35,6 +35,7 @@ struct ggarray {
   void* retired[64];
   uint32_t n_retired;
   uint64_t* scan_tot;     // device: per 1024 LFVectors, their total size and tiles
+  uint64_t last_rw_gen;   // sizes_gen + 1 when the last streaming call was an r/w (0: not)
 };
 
 // Hands an outgrown device buffer to the array, to be freed with it.

@@ -183,3 +183,32 @@ def test_batch_table_and_its_graph(pool):
     for a, o in zip(arrays, oracles):
         a.close()
         o.close()
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_repeated_rw_through_the_table(pool, elem):
+    """r/w directly after r/w (streamed with non-temporal loads), then after a
+    flatten and after an insertion (loads through the cache), on an array above
+    the table threshold."""
+    G = gg()
+    a, o = G.GGArray(pool, elem, 32, 1024), Oracle(elem, 32, 1024)
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=6, round=0, tag=2), BIG + 12345)
+    o.insert_gen(oracle.GEN_KEYED, BIG + 12345, seed=6, round=0, tag=2)
+    dt = torch.int32 if elem == 4 else torch.int64
+    out = torch.zeros(BIG + 12345 + 999, dtype=dt, device="cuda")
+    for op in (G.ADD1, G.MUL3ADD1, G.ADD1_X30):
+        a.rw(op)
+        o.rw(op)
+    a.flatten_into(out)
+    _check(G, out, o, "after three r/w")
+    a.rw(G.MUL3ADD1)
+    o.rw(oracle.OP_MUL3ADD1)
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=6, round=1, tag=2), 999)
+    o.insert_gen(oracle.GEN_KEYED, 999, seed=6, round=1, tag=2)
+    a.rw(G.ADD1)
+    o.rw(oracle.OP_ADD1)
+    a.flatten_into(out)
+    _check(G, out, o, "after flatten, r/w, insertion, r/w")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
