@@ -756,6 +756,7 @@ def main():
     final_size = arr.size()
     capacity = arr.capacity()
     pool_stats = pool.stats()
+    footprint = arr.footprint()
     arr.shrink(1, 1)
     out = torch.empty(final_size, dtype=torch.int32, device="cuda")
     log(f"final size {final_size}, capacity {capacity} ({capacity / final_size:.3f} x live)")
@@ -854,6 +855,9 @@ def main():
                    "GBps": gbps(sum(ins_bytes), sum(ins_ms)),
                    "Gelem_s": (1 << 28) / (sum(ins_ms) * 1e-3) / 1e9,
                    "per_round_us": [round(1e3 * x, 2) for x in ins_ms],
+                   "per_round_GBps": [round(gbps(b, ms)) for b, ms in zip(ins_bytes, ins_ms)],
+                   # rounds writing less than the 256 MiB Infinity Cache may be served by it
+                   "cache_assisted_rounds": [r for r, b in enumerate(ins_bytes) if b < (256 << 20)],
                    "last_round_GBps": gbps(ins_bytes[-1], ins_ms[-1])},
         "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,
                "GBps": gbps(rw_bytes, rw_ms)},
@@ -954,6 +958,7 @@ def main():
             f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s; mapped "
             f"{baselines['mapped'].get('insert_Gelem_s', baselines['mapped'].get('error'))}")
 
+    footprint_end = arr.footprint()  # after the timed steps: the tile table has been built
     arr.close()
     pool.close()
     batched = None
@@ -1047,7 +1052,9 @@ def main():
         "baselines": baselines,
         "memory": {"capacity_elems": capacity, "live_elems": final_size, "capacity_over_live": capacity / final_size,
                    "per_round": mem_rounds,
-                   "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"]},
+                   "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"],
+                   "metadata_bytes": footprint["metadata"], "lookback_bytes": footprint["lookback"],
+                   "tile_table_bytes": footprint_end["tile_tables"]},
         "ceilings": ceilings,
         "parity_with_oracle": parity,
         "ms_per_step_wall": ms_step_wall,

@@ -199,6 +199,12 @@ int ggarray_size(ggarray *a, uint64_t *out_host, gga_stream s);
  *   Synchronises s. */
 int ggarray_capacity(ggarray *a, uint64_t *out_host, gga_stream s);
 
+/* ggarray_footprint: device bytes the array holds besides its buckets, from host
+ *   state (no synchronisation): out[0] metadata (sizes, bucket tables, prefixes,
+ *   tickets), out[1] look-back words, out[2] tile tables (current and outgrown
+ *   ones kept for captured graphs).  Bucket bytes: ggarray_capacity x elem_bytes. */
+int ggarray_footprint(ggarray *a, uint64_t out[3]);
+
 /* ggarray_vector_sizes: copies the V LFVector sizes (uint64) to dev_out. Queued. */
 int ggarray_vector_sizes(ggarray *a, uint64_t *dev_out, gga_stream s);
 

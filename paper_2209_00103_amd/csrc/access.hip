@@ -746,6 +746,7 @@ static int ensure_table(ggarray* a, hipStream_t s) {
     void* p = nullptr;
     if (hipMallocAsync(&p, 16 * ncap, s) == hipSuccess) {
       if (retire_buffer(a, a->tile_tab, s) != GGA_OK) return GGA_EHIP;
+      a->retired_tab_bytes += 16 * a->tab_cap;
       a->tile_tab = static_cast<uint64_t*>(p);
       a->tab_cap = ncap;
     } else {

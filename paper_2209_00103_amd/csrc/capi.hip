@@ -256,6 +256,8 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->tab_gen = ~0ull;
   a->n_retired = 0;
   a->last_rw_gen = 0;
+  a->meta_bytes = off;
+  a->retired_tab_bytes = 0;
   p->n_arrays += 1;
   *out = a;
   return GGA_OK;
@@ -368,6 +370,14 @@ int ggarray_capacity(ggarray* a, uint64_t* out_host, gga_stream s) {
   ggarray_full* f = reinterpret_cast<ggarray_full*>(a);
   int rc = launch_capacity(a, f->x.d_scratch, S(s));
   return rc ? rc : read_back(a, f->x.d_scratch, out_host, S(s));
+}
+
+int ggarray_footprint(ggarray* a, uint64_t out[3]) {
+  if (!a || !out) return GGA_EINVAL;
+  out[0] = a->meta_bytes;
+  out[1] = a->status_cap * sizeof(uint64_t);
+  out[2] = 16 * a->tab_cap + a->retired_tab_bytes;
+  return GGA_OK;
 }
 
 int ggarray_vector_sizes(ggarray* a, uint64_t* dev_out, gga_stream s) {

@@ -36,6 +36,8 @@ struct ggarray {
   uint32_t n_retired;
   uint64_t* scan_tot;     // device: per 1024 LFVectors, their total size and tiles
   uint64_t last_rw_gen;   // sizes_gen + 1 when the last streaming call was an r/w (0: not)
+  uint64_t meta_bytes;    // size of the metadata allocation
+  uint64_t retired_tab_bytes;  // outgrown tile tables kept until destroy
 };
 
 // Hands an outgrown device buffer to the array, to be freed with it.

@@ -66,6 +66,7 @@ _SIGS = {
     "ggarray_gather": [_vp, _vp, _u64, _vp, _vp],
     "ggarray_size": [_vp, _P(_u64), _vp],
     "ggarray_capacity": [_vp, _P(_u64), _vp],
+    "ggarray_footprint": [_vp, _P(_u64)],
     "ggarray_vector_sizes": [_vp, _vp, _vp],
     "ggarray_prefix": [_vp, _vp, _vp],
     "ggarray_last_error": [_vp, _vp],
@@ -302,6 +303,12 @@ class GGArray:
         v = _u64()
         _check(lib().ggarray_capacity(self._h, ctypes.byref(v), _stream(stream)), "ggarray_capacity")
         return int(v.value)
+
+    def footprint(self) -> dict:
+        """Device bytes besides the buckets (host state, no synchronisation)."""
+        out = (_u64 * 3)()
+        _check(lib().ggarray_footprint(self._h, out), "ggarray_footprint")
+        return {"metadata": int(out[0]), "lookback": int(out[1]), "tile_tables": int(out[2])}
 
     def vector_sizes(self, stream=None) -> torch.Tensor:
         out = torch.empty(self.n_vectors, dtype=torch.int64, device=self.pool.mem.device)

@@ -212,3 +212,18 @@ def test_repeated_rw_through_the_table(pool, elem):
     assert a.last_error() == 0
     a.close()
     o.close()
+
+
+def test_footprint_reports_metadata_lookback_and_tables(pool):
+    G = gg()
+    a = G.GGArray(pool, 4, 8, 1024)
+    fp = a.footprint()
+    assert fp["metadata"] >= 8 * (8 + 8 * 40) and fp["lookback"] == 0 and fp["tile_tables"] == 0
+    vals = torch.zeros(40000, dtype=torch.int32, device="cuda")
+    a.insert(vals, torch.ones(40000, dtype=torch.uint8, device="cuda"))  # 5000 threads per LFVector: look-back
+    assert a.footprint()["lookback"] > 0
+    a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=1, tag_shift=24), BIG)
+    a.rw(G.ADD1)  # above the threshold: builds a tile table
+    assert a.footprint()["tile_tables"] >= 16 * (BIG // 4096)
+    assert a.last_error() == 0
+    a.close()
