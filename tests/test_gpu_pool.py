@@ -1,0 +1,69 @@
+"""The device bucket pool alone, under a user kernel: 16384 threads allocate 8
+blocks each of random size classes (256 B .. 8 KiB) from random free-list shards,
+free half, allocate them again, check that every live block still carries its own
+signature at both ends and that no two live blocks overlap, then free all and find
+the pool empty."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from tests.conftest import ROOT
+from tests.gpu_util import gg
+
+pytestmark = pytest.mark.gpu
+KLIB = os.path.join(ROOT, "tests", "device", "libggtest.so")
+
+
+def test_pool_concurrent_alloc_free_no_overlap():
+    assert os.path.exists(KLIB), f"{KLIB} missing: run __graft_entry__.build()"
+    K = ctypes.CDLL(KLIB)
+    K.ggt_pool_stress.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    K.ggt_pool_stress.restype = ctypes.c_int
+    K.ggt_ref_bytes.restype = ctypes.c_uint64
+    G = gg()
+    pool = G.Pool(4 << 30)
+    a = G.GGArray(pool, 4, 1, 1)  # an empty array, for its device descriptor (which holds the pool's)
+    nb = int(K.ggt_ref_bytes())
+    ref = a.device_ref(nb)
+    threads, k, nclass = 16384, 8, 6
+    ptr = torch.zeros(threads * k, dtype=torch.int64, device="cuda")
+    cls = torch.zeros(threads * k, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    before = pool.stats()
+
+    def phase(p):
+        assert K.ggt_pool_stress(ref, nb, threads, k, p, 7, nclass, ptr.data_ptr(), cls.data_ptr(),
+                                 err.data_ptr(), s) == 0
+
+    for p in (0, 1, 2, 3):
+        phase(p)
+    torch.cuda.synchronize()
+    e = int(err.item())
+    assert e & 0xFFFF == 0, f"{e & 0xFFFF} allocations failed"
+    assert e >> 16 == 0, f"{e >> 16} blocks lost their signature"
+    P = ptr.cpu().numpy().view(np.uint64)
+    C = cls.cpu().numpy().astype(np.uint64)
+    assert np.all(P != 0)
+    base, end = pool.mem.data_ptr(), pool.mem.data_ptr() + pool.mem.numel()
+    assert np.all(P >= base) and np.all(P + (np.uint64(1) << C) <= end)
+    order = np.argsort(P)
+    lo, hi = P[order], P[order] + (np.uint64(1) << C[order])
+    assert np.all(hi[:-1] <= lo[1:]), "two live blocks overlap"
+    assert np.all(P % np.uint64(256) == 0)
+    live = int(sum(1 << int(c) for c in C))
+    st = pool.stats()
+    assert st["in_use"] - before["in_use"] == live
+    assert st["allocs"] - before["allocs"] == threads * k + threads * k // 2
+    phase(4)
+    torch.cuda.synchronize()
+    st = pool.stats()
+    assert st["in_use"] == before["in_use"]
+    assert st["frees"] - before["frees"] == threads * k + threads * k // 2
+    a.close()
+    pool.close()
