@@ -817,6 +817,26 @@ def main():
     torch.cuda.synchronize()
     assert arr.last_error() == 0, "device error during the per-kernel pass"
 
+    # The same r/w and flatten with the caches cold: before each, 1 GiB of unrelated
+    # data is read (clean lines), evicting the array from L2 and the 256 MB Infinity
+    # Cache, so no byte of it is served from there.
+    scratch = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    for _ in range(args.steps):
+        arr.shrink(1, 1)
+        for r, n in enumerate(rounds):
+            arr.insert_gen(gens[r], n)
+            arr.shrink(1, 10)
+        arr.prefix_into(prefix_buf)
+        scratch.sum()
+        with timer.span("rw_cold"):
+            arr.rw(G.MUL3ADD1)
+        scratch.sum()
+        with timer.span("flatten_cold"):
+            arr.flatten_into(out)
+    torch.cuda.synchronize()
+    del scratch
+    assert arr.last_error() == 0, "device error during the cold-cache pass"
+
     # Access by global index (rw_g, Sec. VI-B) on the final state: r/w x = 3x + 1 by
     # global index beside the bucket-walk r/w, and a gather of 2^24 uniform indices.
     for r, n in enumerate(rounds):
@@ -860,9 +880,11 @@ def main():
                    "cache_assisted_rounds": [r for r, b in enumerate(ins_bytes) if b < (256 << 20)],
                    "last_round_GBps": gbps(ins_bytes[-1], ins_ms[-1])},
         "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,
-               "GBps": gbps(rw_bytes, rw_ms)},
+               "GBps": gbps(rw_bytes, rw_ms),
+               "cold_cache_GBps": gbps(rw_bytes, statistics.mean(timer.ms("rw_cold")))},
         "flatten": {"launches_per_step": 1, "avg_us": 1e3 * fl_ms, "bytes_per_launch": fl_bytes,
-                    "GBps": gbps(fl_bytes, fl_ms)},
+                    "GBps": gbps(fl_bytes, fl_ms),
+                    "cold_cache_GBps": gbps(fl_bytes, statistics.mean(timer.ms("flatten_cold")))},
         "shrink": {"launches_per_step": len(rounds) + 1, "avg_us": 1e3 * statistics.mean(shr_ms + [clr_ms])},
         "prefix_scan": {"launches_per_step": 1, "avg_us": 1e3 * pre_ms},
     }
@@ -890,7 +912,8 @@ def main():
                 "unit": "GB/s", "frac": kernels[dom]["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
                 "avg_launch_us": kernels[dom]["avg_us"], "bytes_per_launch": kernels[dom]["bytes_per_launch"]}
     log(f"ms/step {ms_step:.3f} (wall {ms_step_wall:.3f}); insert {kernels['insert']['Gelem_s']:.1f} Gelem/s "
-        f"rw {kernels['rw']['GBps']:.0f} GB/s flatten {kernels['flatten']['GBps']:.0f} GB/s")
+        f"rw {kernels['rw']['GBps']:.0f} GB/s flatten {kernels['flatten']['GBps']:.0f} GB/s "
+        f"(cold caches: rw {kernels['rw']['cold_cache_GBps']:.0f}, flatten {kernels['flatten']['cold_cache_GBps']:.0f})")
 
     ceilings = None
     if not args.no_ceiling:
