@@ -448,7 +448,7 @@ def mapped_baseline(G, torch, gens, rounds, steps):
             "maps": maps, "timing": "host wall clock (growth synchronises)"}
 
 
-def two_phase_leg(G, torch, rounds, gens, V, ks=(1, 10, 100)):
+def two_phase_leg(G, torch, rounds, gens, V, ks=(1, 10, 100, 1000)):
     """The two-phase pattern of Sec. VI-D: a growth phase (the configuration-2
     rounds, 2^28 uint32 insertions with shrink 1/10) then a work phase of k passes
     of x = x + 1 over the result.  Three ways: (a) GGArray, flatten, work on the
