@@ -87,3 +87,79 @@ def test_random_operation_sequences_match_oracle(pool, elem, V, F_log2, ops, see
     finally:
         a.close()
         o.close()
+
+
+BATCH_OPS = st.one_of(
+    st.tuples(st.just("keyed"), st.lists(st.integers(0, 40000), min_size=8, max_size=8), st.integers(0, 255)),
+    st.tuples(st.just("round_tag"), st.lists(st.integers(0, 40000), min_size=8, max_size=8), st.integers(0, 255)),
+    st.tuples(st.just("bernoulli"), st.lists(st.integers(0, 40000), min_size=8, max_size=8), st.integers(0, 255)),
+    st.tuples(st.just("shrink"), st.integers(0, 5), st.integers(1, 5)),
+    st.tuples(st.just("rw"), st.integers(0, 2)),
+    st.tuples(st.just("single"), st.integers(0, 7), st.integers(0, 30000)),  # one member alone, then batch again
+)
+
+
+@settings(max_examples=15, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(elem=st.sampled_from([4, 8]),
+       shapes=st.lists(st.tuples(st.sampled_from([1, 3, 16, 200, 1024]), st.integers(0, 11)), min_size=1, max_size=8),
+       ops=st.lists(BATCH_OPS, min_size=1, max_size=6), grid=st.sampled_from([0, 1, 5, 4096]))
+def test_random_batch_sequences_match_oracle(pool, elem, shapes, ops, grid):
+    """Batches of up to 8 arrays of random shapes through random sequences of batched
+    rounds, shrinks and r/w passes (and single-array calls on members in between);
+    after each operation every array, and the batch flatten with its offsets, must
+    equal the oracles."""
+    import torch
+
+    G = gg()
+    arrays = [G.GGArray(pool, elem, V, 1 << f) for V, f in shapes]
+    oracles = [Oracle(elem, V, 1 << f) for V, f in shapes]
+    b = G.Batch(arrays)
+    b.set_grid(grid)
+    n = len(arrays)
+    dt = torch.int32 if elem == 4 else torch.int64
+    try:
+        for step, op in enumerate(ops):
+            kind = op[0]
+            if kind in ("keyed", "round_tag", "bernoulli"):
+                counts = [int(c) for c in op[1][:n]]
+                if kind == "keyed":
+                    b.insert_gen(G.make_gen(G.GEN_KEYED, seed=op[2], round=step, tag=3), counts)
+                    for i, o in enumerate(oracles):
+                        o.insert_gen(oracle.GEN_KEYED, counts[i], seed=op[2], round=step, tag=3 + i)
+                elif kind == "round_tag":
+                    b.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=op[2], tag_shift=20), counts)
+                    for i, o in enumerate(oracles):
+                        o.insert_gen(oracle.GEN_ROUND_TAG, counts[i], round=op[2], tag_shift=20)
+                else:
+                    b.insert_gen(G.make_gen(G.GEN_BERNOULLI, seed=op[2], round=step), counts)
+                    for i, o in enumerate(oracles):
+                        o.insert_gen(oracle.GEN_BERNOULLI, counts[i], seed=op[2], round=step)
+            elif kind == "shrink":
+                num, den = min(op[1], op[2]), op[2]
+                b.shrink(num, den)
+                for o in oracles:
+                    o.shrink(num, den)
+            elif kind == "rw":
+                b.rw(op[1])
+                for o in oracles:
+                    o.rw(op[1])
+            else:
+                i = op[1] % n
+                arrays[i].insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=200 + step, tag_shift=20), op[2])
+                oracles[i].insert_gen(oracle.GEN_ROUND_TAG, op[2], round=200 + step, tag_shift=20)
+            total = sum(int(o.size()) for o in oracles)
+            out = torch.zeros(max(total, 1), dtype=dt, device="cuda")
+            b.flatten_into(out)
+            offs = b.offsets().cpu().numpy()
+            got = G.as_unsigned(out)
+            assert b.last_error() == 0, f"step {step} {kind}: batch error"
+            for i, o in enumerate(oracles):
+                ref = o.flatten()
+                assert offs[i + 1] - offs[i] == ref.size, f"step {step} {kind}: array {i} size"
+                assert np.array_equal(got[offs[i]:offs[i + 1]], ref), f"step {step} {kind}: array {i}"
+                assert_same(arrays[i], o, f"step {step} {kind}: array {i}")
+    finally:
+        b.close()
+        for a, o in zip(arrays, oracles):
+            a.close()
+            o.close()
