@@ -160,6 +160,16 @@ int ggarray_insert_counts(ggarray *a, const void *values, const uint8_t *counts,
  *   device by g (see GGA_GEN_*); `g` is a host pointer read before returning. */
 int ggarray_insert_gen(ggarray *a, const gga_gen *g, uint64_t n_threads, gga_stream s);
 
+/* ggarray_insert_segments: LFVector v appends values[prefix[v] .. prefix[v + 1])
+ *   in order, for every v (values: n_values elements, prefix: V + 1 uint64, both
+ *   device memory).  With ggarray_prefix and ggarray_flatten this restores an
+ *   array from a flat snapshot: the flatten of the Sec. VI-C two-phase use, run
+ *   backwards.  An LFVector whose pair decreases, runs past n_values or spans 2^32
+ *   elements or more is left unchanged and the sticky GGA_ERANGE is set.  Buckets
+ *   are allocated on the device as for ggarray_insert. */
+int ggarray_insert_segments(ggarray *a, const void *values, const uint64_t *prefix, uint64_t n_values,
+                            gga_stream s);
+
 /* ggarray_shrink: every LFVector pops floor(s_v * num / den) trailing elements
  *   and returns each bucket that starts at or past its new size to the pool.
  *   0 <= num <= den, den > 0.  (The paper studies growth only; shrinking follows

@@ -57,6 +57,7 @@ def lib():
             "orc_destroy": (None, [vp]),
             "orc_insert": (i32, [vp, vp, vp, u64]),
             "orc_insert_counts": (i32, [vp, vp, vp, u32, u64]),
+            "orc_insert_segments": (i32, [vp, vp, vp, u64]),
             "orc_insert_gen": (i32, [vp, u32, u64, u32, u32, u32, vp, u64, u64]),
             "orc_shrink": (i32, [vp, u32, u32]),
             "orc_rw": (i32, [vp, u32]),
@@ -162,6 +163,14 @@ class Oracle:
         assert values.size == counts.size * max_count
         self._chk(lib().orc_insert_counts(self._h, _ptr(values), _ptr(counts), max_count,
                                           counts.size), "insert_counts")
+
+    def insert_segments(self, values: np.ndarray, prefix: np.ndarray) -> int:
+        """LFVector v appends values[prefix[v]:prefix[v + 1]]; returns the status
+        (ERANGE for an invalid segment, whose LFVector is left unchanged)."""
+        values = np.ascontiguousarray(values, dtype=self.dtype)
+        prefix = np.ascontiguousarray(prefix, dtype=np.uint64)
+        assert prefix.size == self.n_vectors + 1
+        return int(lib().orc_insert_segments(self._h, _ptr(values), _ptr(prefix), values.size))
 
     def insert_gen(self, kind: int, n_threads: int, seed: int = 0, round: int = 0,
                    tag_shift: int | None = None, max_count: int = 0,

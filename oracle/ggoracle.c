@@ -323,6 +323,30 @@ int orc_insert_counts(orc_array *a, const void *values, const uint8_t *counts, u
     return ORC_OK;
 }
 
+/* Segment append (restoring a flat snapshot): LFVector v appends
+ * values[prefix[v] .. prefix[v + 1]).  An LFVector whose pair decreases, runs past
+ * n_values or spans 2^32 elements or more keeps its contents and the call returns
+ * ORC_ERANGE after the other LFVectors have appended theirs. */
+int orc_insert_segments(orc_array *a, const void *values, const uint64_t *prefix, uint64_t n_values)
+{
+    if (!a || !prefix || (n_values && !values))
+        return ORC_EINVAL;
+    int rc = ORC_OK;
+    for (uint32_t v = 0; v < a->n_vectors; v++) {
+        const uint64_t lo = prefix[v], hi = prefix[v + 1];
+        if (hi < lo || hi > n_values || hi - lo >= (1ull << 32)) {
+            rc = ORC_ERANGE;
+            continue;
+        }
+        for (uint64_t i = lo; i < hi; i++) {
+            int st = push(a, v, load_elem(values, a->elem_bytes, i));
+            if (st)
+                return st;
+        }
+    }
+    return rc;
+}
+
 /* Generated payloads (the benchmark workloads):
  *   BERNOULLI: h = K(seed, gid, round); insert h iff its top bit is set;
  *   ROUND_TAG: insert (round << tag_shift) | gid;

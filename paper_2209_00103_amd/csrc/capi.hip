@@ -313,6 +313,12 @@ int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_str
   return launch_insert(a, d, S(s));
 }
 
+int ggarray_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
+                            gga_stream s) {
+  if (!a || !prefix || (n_values && !values)) return GGA_EINVAL;
+  return launch_insert_segments(a, values, prefix, n_values, S(s));
+}
+
 int ggarray_shrink(ggarray* a, uint32_t num, uint32_t den, gga_stream s) {
   if (!a || den == 0 || num > den) return GGA_EINVAL;
   if (num == 0) return GGA_OK;

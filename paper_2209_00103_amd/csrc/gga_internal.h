@@ -267,7 +267,9 @@ __host__ __device__ constexpr uint32_t rw_tile_elems(uint32_t elem_log2) {
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s);
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
-int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);  // copy: also write the prefix there
+int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);
+int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
+                           hipStream_t s);  // copy: also write the prefix there
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s);
 int launch_rw(ggarray* a, uint32_t op, hipStream_t s);
 int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s);

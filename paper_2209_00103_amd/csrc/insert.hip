@@ -657,11 +657,11 @@ __device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, c
 // of one wave per tile).  Fewer, longer LFVectors take the two-launch form.  The new bucket pointers stay in the
 // lanes that allocated them; a bucket that existed before the round is read
 // from the table, written by an earlier launch.
+// LFVector v appends the elements the producer gives for g = c0 .. c0 + cnt - 1.
 template <typename T, class Prod>
-__device__ __forceinline__ void grow_store_vector(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v) {
+__device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v,
+                                                 uint64_t c0, uint64_t cnt) {
   const uint32_t lane = lane_id();
-  const uint64_t c0 = (uint64_t)v * I.chunk;
-  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
   if (cnt == 0 || A.dead[v]) return;
   const uint32_t log2F = A.log2F;
   const uint64_t s0 = A.size[v];
@@ -700,10 +700,34 @@ __device__ __forceinline__ void grow_store_vector(const ArrRef& A, const TileArg
   }
 }
 
+// The round's share of LFVector v: logical threads [v chunk, v chunk + chunk).
+template <typename T, class Prod>
+__device__ __forceinline__ void grow_store_vector(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v) {
+  const uint64_t c0 = (uint64_t)v * I.chunk;
+  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
+  grow_store_range<T, Prod>(A, I, prod, v, c0, cnt);
+}
+
 template <typename T, class Prod>
 __global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, Prod prod) {
   const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
   if (v < A.V) grow_store_vector<T, Prod>(A, I, prod, v);
+}
+
+// Segment append: LFVector v appends values[prefix[v] .. prefix[v + 1]).  A
+// decreasing pair, a segment past n_values or one of 2^32 elements or more sets
+// GGA_ERANGE and leaves the LFVector unchanged.
+template <typename T>
+__global__ __launch_bounds__(256) void segments_kernel(ArrRef A, TileArgs I, const T* values, const uint64_t* prefix,
+                                                       uint64_t n_values) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (v >= A.V) return;
+  const uint64_t lo = prefix[v], hi = prefix[v + 1];
+  if (hi < lo || hi > n_values || hi - lo >= (1ull << 32)) {
+    if (lane_id() == 0) set_error(A.err, kErrRange);
+    return;
+  }
+  grow_store_range<T, ProdBuffer<T>>(A, I, ProdBuffer<T>{values, nullptr}, v, lo, hi - lo);
 }
 
 __global__ __launch_bounds__(256) void grow_kernel(ArrRef A, TileArgs I) {
@@ -1036,6 +1060,23 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
     sizes_changed(a);
   }
   return st;
+}
+
+int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
+                           hipStream_t s) {
+  TileArgs I{};
+  I.elem_log2 = a->elem_log2;
+  grow_bound(a, n_values);
+  const dim3 grid((a->V + 3) / 4), block(256);
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL(segments_kernel<uint32_t>, grid, block, 0, s, a->ref, I, static_cast<const uint32_t*>(values),
+                       prefix, n_values);
+  else
+    hipLaunchKernelGGL(segments_kernel<uint64_t>, grid, block, 0, s, a->ref, I, static_cast<const uint64_t*>(values),
+                       prefix, n_values);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) sizes_changed(a);
+  return hip_status(e);
 }
 
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {

@@ -67,6 +67,7 @@ _SIGS = {
     "ggarray_size": [_vp, _P(_u64), _vp],
     "ggarray_capacity": [_vp, _P(_u64), _vp],
     "ggarray_footprint": [_vp, _P(_u64)],
+    "ggarray_insert_segments": [_vp, _vp, _vp, _u64, _vp],
     "ggarray_vector_sizes": [_vp, _vp, _vp],
     "ggarray_prefix": [_vp, _vp, _vp],
     "ggarray_last_error": [_vp, _vp],
@@ -303,6 +304,15 @@ class GGArray:
         v = _u64()
         _check(lib().ggarray_capacity(self._h, ctypes.byref(v), _stream(stream)), "ggarray_capacity")
         return int(v.value)
+
+    def insert_segments(self, values: torch.Tensor, prefix: torch.Tensor, stream=None):
+        """LFVector v appends values[prefix[v]:prefix[v + 1]] (prefix: V + 1 int64 on
+        the device); with prefix_into and flatten_into, restores a flat snapshot."""
+        if prefix.numel() != self.n_vectors + 1:
+            raise ValueError(f"prefix needs {self.n_vectors + 1} entries")
+        _check(lib().ggarray_insert_segments(self._h, _dev_ptr(values, "values", 0, self.elem_bytes) if values.numel() else None,
+                                             _dev_ptr(prefix, "prefix", 0, 8), values.numel(), _stream(stream)),
+               "ggarray_insert_segments")
 
     def footprint(self) -> dict:
         """Device bytes besides the buckets (host state, no synchronisation)."""

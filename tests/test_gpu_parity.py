@@ -357,3 +357,43 @@ def test_invalid_arguments_with_gpu(pool):
     with pytest.raises(G.GGAError):
         G.GGArray(pool, 4, 4, 3)
     a.close()
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_insert_segments_and_snapshot_restore(pool, elem):
+    """Segment append against the oracle (appending to non-empty LFVectors, empty
+    segments, segments crossing many buckets), a flat snapshot (flatten + prefix)
+    restored into an empty array, and invalid segments reported with ERANGE."""
+    G = gg()
+    rng = np.random.default_rng(17)
+    V, F = 37, 8
+    a, o = both(elem, V, F, pool)
+    for r in range(2):
+        vals, flags = wl.random_round(rng, 30000, 0.6, elem)
+        a.insert(dev(vals), dev(flags))
+        o.insert(vals, flags)
+    lens = rng.integers(0, 3000, size=V)
+    lens[::5] = 0
+    prefix = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+    seg, _ = wl.random_round(rng, int(prefix[-1]), 1.0, elem)
+    a.insert_segments(dev(seg), dev(prefix))
+    assert o.insert_segments(seg, prefix) == oracle.OK
+    assert_same(a, o, "segments appended")
+    # restore: flatten + prefix of a, appended to an empty array of the same shape
+    flat = gpu_flat(a)
+    pre = a.prefix().cpu().numpy().astype(np.uint64)
+    b, ob = both(elem, V, F, pool)
+    b.insert_segments(dev(flat), dev(pre))
+    assert ob.insert_segments(o.flatten(), o.prefix()) == oracle.OK
+    assert_same(b, ob, "restored")
+    assert np.array_equal(gpu_flat(b), gpu_flat(a)) and b.capacity() == a.capacity()
+    # an invalid pair: that LFVector is unchanged, the others append, ERANGE is sticky
+    c, oc = both(elem, 4, F, pool)
+    bad = np.array([0, 5, 3, 9, 12], dtype=np.uint64)
+    vals, _ = wl.random_round(rng, 12, 1.0, elem)
+    c.insert_segments(dev(vals), dev(bad))
+    assert oc.insert_segments(vals, bad) == oracle.ERANGE
+    assert c.last_error() == G.ERANGE
+    assert gpu_sizes(c).tolist() == oc.vector_sizes().tolist() == [5, 0, 6, 3]
+    for x in (a, b, c):
+        x.close()

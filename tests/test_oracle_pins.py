@@ -394,3 +394,31 @@ def test_at_equals_flatten_index(forms):
     assert list(out) == [flat[0], flat[5], flat[-1], 0xDEAD, flat[2], 0xDEAD]
     out, rc = a.gather(np.arange(flat.size, dtype=np.uint64))
     assert rc == oracle.OK and np.array_equal(out, flat)
+
+
+def test_insert_segments_appends_each_lfvector_its_slice():
+    """LFVector v appends values[prefix[v]:prefix[v + 1]] after what it holds; a bad
+    pair leaves its LFVector unchanged and reports ERANGE."""
+    o = Oracle(4, 3, 2)
+    o.insert(np.array([100, 101, 102], dtype=np.uint32), np.ones(3, np.uint8))  # one element each
+    vals = np.arange(10, dtype=np.uint32)
+    assert o.insert_segments(vals, np.array([0, 4, 4, 10], dtype=np.uint64)) == oracle.OK
+    assert o.vector_sizes().tolist() == [5, 1, 7]
+    assert o.flatten().tolist() == [100, 0, 1, 2, 3, 101, 102, 4, 5, 6, 7, 8, 9]
+    assert o.insert_segments(vals, np.array([0, 2, 1, 11], dtype=np.uint64)) == oracle.ERANGE
+    assert o.vector_sizes().tolist() == [7, 1, 7]  # v1 decreases, v2 runs past the values
+    assert o.check() == 0
+
+
+def test_flat_snapshot_restores_an_array():
+    """flatten + prefix of an array, appended as segments to an empty array of the
+    same shape, give the same sizes, contents and capacity."""
+    o = Oracle(8, 7, 4)
+    for r in range(3):
+        o.insert_gen(oracle.GEN_BERNOULLI, 5000, seed=3, round=r)
+    o.shrink(1, 3)
+    o2 = Oracle(8, 7, 4)
+    assert o2.insert_segments(o.flatten(), o.prefix()) == oracle.OK
+    assert o2.vector_sizes().tolist() == o.vector_sizes().tolist()
+    assert o2.flatten().tolist() == o.flatten().tolist()
+    assert o2.capacity() == o.capacity()
