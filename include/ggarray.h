@@ -39,9 +39,14 @@
  *    nothing is allocated: an insertion round needing more look-back words than
  *    an earlier eager round of the array left returns GGA_EINVAL (run the same
  *    round once eagerly first).  The size prefix and the tile table that r/w and
- *    flatten read are recomputed inside the graph, so a replay sees the sizes of
- *    its own moment.  Internal buffers an array outgrows are kept until
- *    ggarray_destroy, so a graph captured earlier stays valid.
+ *    flatten read are recomputed inside the graph (once per size change within
+ *    one capture), so a replay sees the sizes of its own moment.  Once a
+ *    captured call changes an array's sizes, every later eager r/w, flatten or
+ *    prefix call on it recomputes them too, since replays change the sizes
+ *    without the library seeing it.  Calls on one array must be
+ *    ordered on one stream, in a graph as outside it.  Internal buffers an array
+ *    outgrows are kept until ggarray_destroy, so a graph captured earlier stays
+ *    valid.
  */
 #ifndef GGARRAY_H
 #define GGARRAY_H

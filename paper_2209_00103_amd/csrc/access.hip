@@ -701,7 +701,10 @@ int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy) {
     hipLaunchKernelGGL(scan_fix_kernel, dim3(chunks), dim3(kScanThreads), 0, s, a->ref, a->scan_tot, chunks, copy);
   }
   const hipError_t e = hipGetLastError();
-  if (e == hipSuccess) a->prefix_valid = true;
+  if (e == hipSuccess) {
+    a->prefix_valid = true;
+    a->scan_tag = stream_capture_tag(s);
+  }
   return hip_status(e);
 }
 
@@ -709,7 +712,7 @@ int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s) {
   if (num == den) a->size_ub = 0;
   const uint32_t blocks = (a->V + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(shrink_kernel, dim3(blocks), dim3(256), 0, s, a->ref, num, den, a->elem_log2);
-  sizes_changed(a);
+  sizes_changed(a, s);
   return hip_status(hipGetLastError());
 }
 
@@ -729,8 +732,9 @@ int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s) {
 // Builds the tile table for the current sizes (the prefix must be current).
 // Under graph capture it is always rebuilt, inside the graph, and never grown.
 static int ensure_table(ggarray* a, hipStream_t s) {
-  const bool cap_mode = stream_capturing(s);
-  if (a->tab_gen == a->sizes_gen && !cap_mode) return GGA_OK;
+  const uint64_t tag = stream_capture_tag(s);
+  const bool cap_mode = tag != 0;
+  if (a->tab_gen == a->sizes_gen && capture_reuse(a, a->tab_tag, tag)) return GGA_OK;
   const uint32_t te_log2 = 14u - a->elem_log2;
   const uint64_t ub = a->size_ub;
   // Tiles of an LFVector of s elements: at most s / te + one partial tile per bucket.
@@ -760,6 +764,7 @@ static int ensure_table(ggarray* a, hipStream_t s) {
     if (e != hipSuccess) return hip_status(e);
   }
   a->tab_gen = a->sizes_gen;
+  a->tab_tag = tag;
   return GGA_OK;
 }
 
@@ -838,18 +843,33 @@ static uint64_t batch_gen(const gga_batch* b) {
   return g;
 }
 
+// capture_reuse for a batch: eager reuse also needs that no graph changes the
+// sizes of any member.
+static bool batch_reuse(const gga_batch* b, uint64_t built, uint64_t now) {
+  if (built != now || now == ~0ull) return false;
+  if (now == 0)
+    for (uint32_t i = 0; i < b->n; ++i)
+      if (b->arrays[i]->graph_sized) return false;
+  return true;
+}
+
 int launch_batch_scan(gga_batch* b, hipStream_t s) {
   const uint64_t gen = batch_gen(b);
-  if (b->scan_valid && b->scan_gen == gen && !stream_capturing(s)) return GGA_OK;
+  const uint64_t tag = stream_capture_tag(s);
+  if (b->scan_valid && b->scan_gen == gen && batch_reuse(b, b->scan_tag, tag)) return GGA_OK;
   const uint32_t te_log2 = b->elem_bytes == 4 ? 12u : 11u;
   hipLaunchKernelGGL(batch_scan_kernel, dim3(b->n), dim3(kScanThreads), 0, s, b->d_arrays, te_log2);
   hipLaunchKernelGGL(batch_top_kernel<BatchArr>, dim3(1), dim3(kScanThreads), 0, s, b->d_arrays, b->n,
                      b->d_tile_begin, b->d_elem_begin);
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
-    for (uint32_t i = 0; i < b->n; ++i) b->arrays[i]->prefix_valid = true;
+    for (uint32_t i = 0; i < b->n; ++i) {
+      b->arrays[i]->prefix_valid = true;
+      b->arrays[i]->scan_tag = tag;
+    }
     b->scan_valid = true;
     b->scan_gen = gen;
+    b->scan_tag = tag;
   }
   return hip_status(e);
 }
@@ -873,9 +893,10 @@ static int ensure_batch_table(gga_batch* b, hipStream_t s, const uint64_t** tab,
   if (known && need < kTableMinTiles) return GGA_OK;
   if (!known) need = b->tab_cap;
   if (need > kTableMaxTiles) need = kTableMaxTiles;
-  const bool cap_mode = stream_capturing(s);
+  const uint64_t tag = stream_capture_tag(s);
+  const bool cap_mode = tag != 0;
   const uint64_t gen = batch_gen(b);
-  if (!(b->tab_valid && b->tab_gen == gen && !cap_mode)) {
+  if (!(b->tab_valid && b->tab_gen == gen && batch_reuse(b, b->tab_tag, tag))) {
     if (need > b->tab_cap && !cap_mode) {
       uint64_t ncap = b->tab_cap * 2 > need ? b->tab_cap * 2 : need;
       if (ncap > kTableMaxTiles) ncap = kTableMaxTiles;
@@ -900,6 +921,7 @@ static int ensure_batch_table(gga_batch* b, hipStream_t s, const uint64_t** tab,
     }
     b->tab_valid = true;
     b->tab_gen = gen;
+    b->tab_tag = tag;
   }
   *tab = b->tile_tab;
   *tcap = b->tab_cap;
@@ -912,7 +934,7 @@ int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s)
   const uint64_t blocks = (b->total_vectors + kVecPerBlock - 1) / kVecPerBlock;
   hipLaunchKernelGGL(batch_shrink_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, b->d_arrays, b->d_vbegin,
                      b->n, num, den);
-  for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i]);
+  for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i], s);
   return hip_status(hipGetLastError());
 }
 

@@ -256,6 +256,9 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->tab_gen = ~0ull;
   a->n_retired = 0;
   a->last_rw_gen = 0;
+  a->scan_tag = 0;
+  a->tab_tag = 0;
+  a->graph_sized = false;
   a->meta_bytes = off;
   a->retired_tab_bytes = 0;
   p->n_arrays += 1;
@@ -325,10 +328,11 @@ int ggarray_shrink(ggarray* a, uint32_t num, uint32_t den, gga_stream s) {
   return launch_shrink(a, num, den, S(s));
 }
 
-// Under graph capture the scan is always recorded, so that a replay never reads
-// a prefix left over from before the capture.
+// A prefix is reused only where it was built: eagerly for eager calls, in the
+// same capture for captured calls, so that a replay never reads a prefix left
+// over from before its capture.
 static int ensure_prefix(ggarray* a, hipStream_t s) {
-  return a->prefix_valid && !stream_capturing(s) ? GGA_OK : launch_scan(a, s);
+  return a->prefix_valid && capture_reuse(a, a->scan_tag, stream_capture_tag(s)) ? GGA_OK : launch_scan(a, s);
 }
 
 int ggarray_rw(ggarray* a, uint32_t op, gga_stream s) {
@@ -393,7 +397,8 @@ int ggarray_vector_sizes(ggarray* a, uint64_t* dev_out, gga_stream s) {
 
 int ggarray_prefix(ggarray* a, uint64_t* dev_out, gga_stream s) {
   if (!a || !dev_out) return GGA_EINVAL;
-  if (!a->prefix_valid || stream_capturing(S(s))) return launch_scan(a, S(s), dev_out);  // scan writes both
+  if (!a->prefix_valid || !capture_reuse(a, a->scan_tag, stream_capture_tag(S(s))))
+    return launch_scan(a, S(s), dev_out);  // the scan writes both
   return hip_status(hipMemcpyAsync(dev_out, a->ref.prefix, 8ull * (a->V + 1), hipMemcpyDeviceToDevice, S(s)));
 }
 
@@ -410,9 +415,8 @@ int ggarray_device_ref(ggarray* a, void* out, uint64_t bytes) {
 }
 
 int ggarray_device_done(ggarray* a, gga_stream s) {
-  (void)s;
   if (!a) return GGA_EINVAL;
-  sizes_changed(a);
+  sizes_changed(a, S(s));
   a->size_ub = ~0ull >> 2;  // sizes unknown to the host now
   return GGA_OK;
 }

@@ -36,6 +36,9 @@ struct ggarray {
   uint32_t n_retired;
   uint64_t* scan_tot;     // device: per 1024 LFVectors, their total size and tiles
   uint64_t last_rw_gen;   // sizes_gen + 1 when the last streaming call was an r/w (0: not)
+  uint64_t scan_tag;      // capture tag (stream_capture_tag) the current prefix was built under
+  uint64_t tab_tag;       // capture tag the current tile table was built under
+  bool graph_sized;       // a captured call changes the sizes (replays do so unseen)
   uint64_t meta_bytes;    // size of the metadata allocation
   uint64_t retired_tab_bytes;  // outgrown tile tables kept until destroy
 };
@@ -50,18 +53,40 @@ inline int retire_buffer(ggarray* a, void* p, hipStream_t s) {
   return hipFreeAsync(p, s) == hipSuccess ? GGA_OK : GGA_EHIP;
 }
 
-// The LFVector sizes are about to change (insertion, shrink, device-side use):
-// the prefix and the tile table must be rebuilt before the next walk.
-inline void sizes_changed(ggarray* a) {
-  a->prefix_valid = false;
-  ++a->sizes_gen;
-}
-
 // True while `s` records into a HIP graph (or when that cannot be told): then
 // nothing may be allocated, and derived state is rebuilt inside the graph.
 inline bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
+
+// The LFVector sizes are about to change (insertion, shrink, device-side use) by
+// work issued on `s`: the prefix and the tile table must be rebuilt before the
+// next walk.  When that work goes into a graph, every replay changes the sizes
+// without the host seeing it, so from then on eager calls rebuild them each time.
+inline void sizes_changed(ggarray* a, hipStream_t s) {
+  a->prefix_valid = false;
+  ++a->sizes_gen;
+  if (stream_capturing(s)) a->graph_sized = true;
+}
+
+// 0 when `s` is not capturing; otherwise 1 + the capture's id, or ~0 when the id
+// cannot be told.  Derived state (prefix, tile table) recorded earlier in the same
+// capture is reused by later calls of that capture, never by other graphs.
+inline uint64_t stream_capture_tag(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  unsigned long long id = 0;
+  if (hipStreamGetCaptureInfo(s, &st, &id) != hipSuccess) return ~0ull;
+  if (st == hipStreamCaptureStatusNone) return 0;
+  return st == hipStreamCaptureStatusActive ? (uint64_t)id + 1 : ~0ull;
+}
+
+// Whether derived state built under capture tag `built` may serve a call under
+// capture tag `now` (the same sizes assumed): eagerly built state serves eager
+// calls unless a graph changes the sizes, state recorded in a capture serves
+// later calls of that capture.
+inline bool capture_reuse(const ggarray* a, uint64_t built, uint64_t now) {
+  return built == now && now != ~0ull && (now != 0 || !a->graph_sized);
 }
 
 struct gga_static {
@@ -106,6 +131,8 @@ struct gga_batch {
   // generations they were built for (see batch_gen).
   bool scan_valid;
   uint64_t scan_gen;
+  uint64_t scan_tag;       // capture tags the scans and the table were built under
+  uint64_t tab_tag;
   uint64_t* tile_tab;      // device: two words per tile of the whole batch
   uint64_t tab_cap;
   bool tab_valid;

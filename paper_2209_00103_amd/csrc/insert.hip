@@ -1045,7 +1045,7 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   if (dense) {
     const int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
                                       : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
-    if (st == GGA_OK) sizes_changed(a);
+    if (st == GGA_OK) sizes_changed(a, s);
     return st;
   }
 
@@ -1056,9 +1056,7 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   StaticRef S{};
   const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
                                     : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
-  if (st == GGA_OK) {
-    sizes_changed(a);
-  }
+  if (st == GGA_OK) sizes_changed(a, s);
   return st;
 }
 
@@ -1075,7 +1073,7 @@ int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefi
     hipLaunchKernelGGL(segments_kernel<uint64_t>, grid, block, 0, s, a->ref, I, static_cast<const uint64_t*>(values),
                        prefix, n_values);
   const hipError_t e = hipGetLastError();
-  if (e == hipSuccess) sizes_changed(a);
+  if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);
 }
 
@@ -1274,7 +1272,7 @@ int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_thr
   }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess)
-    for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i]);
+    for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i], s);
   return hip_status(e);
 }
 

@@ -316,7 +316,7 @@ int run_batched(RunState& R) {
           items.push_back(it);
           begins.push_back(blocks);
           blocks += ntiles;
-          sizes_changed(arr);
+          sizes_changed(arr, l.s);
           grow_bound(arr, tr->length[r]);
         } else {
           const bool flat = kind == GGA_REQ_FLATTEN;
@@ -329,6 +329,7 @@ int run_batched(RunState& R) {
                                      flat ? kOpFlatten : sv->cfg.rw_op, arr->elem_log2});
           grid += (s_before >> te_log2) + 2ull * arr->V;
           arr->prefix_valid = true;
+          arr->scan_tag = 0;  // the server runs eagerly
         }
       }
       if (reqs.empty() && a_reqs.empty()) continue;

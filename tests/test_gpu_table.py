@@ -227,3 +227,150 @@ def test_footprint_reports_metadata_lookback_and_tables(pool):
     assert a.footprint()["tile_tables"] >= 16 * (BIG // 4096)
     assert a.last_error() == 0
     a.close()
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_one_capture_reuses_its_prefix_and_table(pool, elem):
+    """A captured step that calls r/w, flatten and prefix several times around an
+    insertion: each replay's results equal the oracle, and eager calls made before
+    the first replay and between replays see the array as it really is then."""
+    G = gg()
+    V, F = 7, 32
+    a, o = G.GGArray(pool, elem, V, F), Oracle(elem, V, F)
+    dt = torch.int32 if elem == 4 else torch.int64
+    n_small = 70000
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=5, round=0, tag=2), BIG + 123)
+    o.insert_gen(oracle.GEN_KEYED, BIG + 123, seed=5, round=0, tag=2)
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=5, round=1, tag=2), n_small)  # sizes the look-back eagerly
+    o.insert_gen(oracle.GEN_KEYED, n_small, seed=5, round=1, tag=2)
+    cap = BIG + 123 + 5 * n_small
+    out1 = torch.zeros(cap, dtype=dt, device="cuda")
+    out2 = torch.zeros(cap, dtype=dt, device="cuda")
+    pre = torch.zeros(V + 1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.rw(G.ADD1)  # eager prefix and table
+    s.synchronize()
+    o.rw(oracle.OP_ADD1)
+    gen = G.make_gen(G.GEN_ROUND_TAG, round=9, tag_shift=26)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.rw(G.MUL3ADD1)
+        a.flatten_into(out1)
+        a.insert_gen(gen, n_small)
+        a.rw(G.ADD1)
+        a.rw(G.ADD1_X30)
+        a.prefix_into(pre)
+        a.flatten_into(out2)
+    torch.cuda.synchronize()
+    _check(G, a.flatten(), o, "eager flatten after capture, before any replay")
+    for rep in range(3):
+        if rep == 1:
+            a.rw(G.ADD1)  # eager work between replays
+            o.rw(oracle.OP_ADD1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o.rw(oracle.OP_MUL3ADD1)
+        _check(G, out1, o, f"replay {rep}: first flatten")
+        o.insert_gen(oracle.GEN_ROUND_TAG, n_small, round=9, tag_shift=26)
+        o.rw(oracle.OP_ADD1)
+        o.rw(oracle.OP_ADD1_X30)
+        assert np.array_equal(pre.cpu().numpy().astype(np.uint64), o.prefix().astype(np.uint64)), f"replay {rep}: prefix"
+        _check(G, out2, o, f"replay {rep}: second flatten")
+        _check(G, a.flatten(), o, f"replay {rep}: eager flatten")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
+
+
+@pytest.mark.parametrize("base", [1000, BIG])
+def test_graph_of_insertion_alone_then_eager_calls(pool, base):
+    """A graph that only inserts changes the sizes on every replay behind the
+    host's back: eager r/w, flatten and prefix calls between replays (each
+    following an eager call that left a valid prefix and table) see them."""
+    G = gg()
+    V, F = 9, 64
+    a, o = G.GGArray(pool, 4, V, F), Oracle(4, V, F)
+    n = 30000
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=1, round=0, tag=7), base)
+    o.insert_gen(oracle.GEN_KEYED, base, seed=1, round=0, tag=7)
+    gen = G.make_gen(G.GEN_BERNOULLI, seed=4, round=2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.insert_gen(gen, n)  # eager round of this shape: its look-back exists before capture
+    s.synchronize()
+    o.insert_gen(oracle.GEN_BERNOULLI, n, seed=4, round=2)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.insert_gen(gen, n)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        a.rw(G.ADD1)
+        o.rw(oracle.OP_ADD1)
+        _check(G, a.flatten(), o, f"before replay {rep}")
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o.insert_gen(oracle.GEN_BERNOULLI, n, seed=4, round=2)
+        assert np.array_equal(a.prefix().cpu().numpy().astype(np.uint64), o.prefix()), f"replay {rep}: prefix"
+        a.rw(G.MUL3ADD1)
+        o.rw(oracle.OP_MUL3ADD1)
+        _check(G, a.flatten(), o, f"after replay {rep}")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
+
+
+def test_batch_graph_of_insertion_alone_then_eager_calls(pool):
+    """The same for a batch: eager batched r/w and flatten between replays of a
+    graph holding only a batched insertion round."""
+    G = gg()
+    shapes = [(64, 1024), (3, 16), (700, 2)]
+    arrays = [G.GGArray(pool, 4, V, F) for V, F in shapes]
+    oracles = [Oracle(4, V, F) for V, F in shapes]
+    b = G.Batch(arrays)
+    first = [BIG // 2, 3 * BIG // 8, BIG // 4]
+    grow = [40000, 3, 70000]
+    gen = G.make_gen(G.GEN_KEYED, seed=2, round=1, tag=1)
+    b.insert_gen(G.make_gen(G.GEN_KEYED, seed=2, round=0, tag=1), first)
+    b.insert_gen(gen, grow)
+    for i, o in enumerate(oracles):
+        o.insert_gen(oracle.GEN_KEYED, first[i], seed=2, round=0, tag=1 + i)
+        o.insert_gen(oracle.GEN_KEYED, grow[i], seed=2, round=1, tag=1 + i)
+    out = torch.zeros(sum(first) + 5 * sum(grow), dtype=torch.int32, device="cuda")
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.insert_gen(gen, grow)
+
+    def check(what):
+        torch.cuda.synchronize()
+        offs = b.offsets().cpu().numpy()
+        got = G.as_unsigned(out)
+        for i, o in enumerate(oracles):
+            ref = o.flatten()
+            assert offs[i + 1] - offs[i] == ref.size, f"{what}: array {i} size"
+            assert np.array_equal(got[offs[i]:offs[i + 1]], ref), f"{what}: array {i} differs"
+
+    for rep in range(3):
+        b.rw(G.ADD1)
+        b.flatten_into(out)
+        for o in oracles:
+            o.rw(oracle.OP_ADD1)
+        check(f"before replay {rep}")
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, o in enumerate(oracles):
+            o.insert_gen(oracle.GEN_KEYED, grow[i], seed=2, round=1, tag=1 + i)
+        b.rw(G.MUL3ADD1)
+        b.flatten_into(out)
+        for o in oracles:
+            o.rw(oracle.OP_MUL3ADD1)
+        check(f"after replay {rep}")
+    assert b.last_error() == 0
+    b.close()
+    for a, o in zip(arrays, oracles):
+        a.close()
+        o.close()
