@@ -181,6 +181,18 @@ int ggarray_insert_segments(ggarray *a, const void *values, const uint64_t *pref
  *   the generic vector interface it names in Sec. I.) */
 int ggarray_shrink(ggarray *a, uint32_t num, uint32_t den, gga_stream s);
 
+/* ggarray_insert_gen_shrink: ggarray_insert_gen(a, g, n_threads) followed by
+ *   ggarray_shrink(a, num, den), with the same results (sizes, contents,
+ *   capacity, pool counts, errors; an LFVector whose growth fails in the round is
+ *   still shrunk).  A round of round-tag or keyed payloads that runs one wave per
+ *   LFVector (at most 8 tiles of 4096 threads per LFVector, or 512 LFVectors or
+ *   more) does both in one launch: the wave stores its elements, sets the size
+ *   the shrink leaves and releases the buckets past it.  Other rounds take two
+ *   launches.  den == 0 or num > den: GGA_EINVAL, nothing
+ *   launched. */
+int ggarray_insert_gen_shrink(ggarray *a, const gga_gen *g, uint64_t n_threads, uint32_t num, uint32_t den,
+                              gga_stream s);
+
 /* ggarray_rw: x = op(x) for every live element, in place, LFVector by LFVector
  *   through the bucket tables (the per-block read/write rw_b of Sec. VI-B). */
 int ggarray_rw(ggarray *a, uint32_t op, gga_stream s);

@@ -168,28 +168,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_fix_kernel(ArrRef A, const 
   }
 }
 
-// Shrink (pop floor(s num / den) per LFVector) and bucket release: one wave per
-// LFVector, lane b looks after bucket b, so the releases of one LFVector run in
-// parallel and go to different pool shards.
-constexpr uint32_t kVecPerBlock = 4;  // 256 threads = 4 waves = 4 LFVectors
-
-__device__ __forceinline__ void shrink_vector(const ArrRef& A, uint32_t v, uint32_t num, uint32_t den,
-                                              uint32_t elem_log2) {
-  const uint32_t b = threadIdx.x & 63u;
-  const uint64_t s = A.size[v];
-  const uint64_t ns = s - ((s / den) * num + ((s % den) * num) / den);
-  const uint32_t lo = nbuckets_for(A.log2F, ns);
-  uint32_t hi = A.dead[v] ? (uint32_t)kMaxBuckets : nbuckets_for(A.log2F, s);
-  if (hi > (uint32_t)kMaxBuckets) hi = kMaxBuckets;
-  if (b >= lo && b < hi) {
-    uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
-    const uint64_t p = *slot;
-    if (p > kFailedPtr)
-      pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b, A.salt));
-    if (p) *slot = 0;
-  }
-  if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
-}
+constexpr uint32_t kVecPerBlock = 4;  // shrink: 256 threads = 4 waves = 4 LFVectors
 
 __global__ __launch_bounds__(256) void shrink_kernel(ArrRef A, uint32_t num, uint32_t den,
                                                      uint32_t elem_log2) {

@@ -316,6 +316,16 @@ int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_str
   return launch_insert(a, d, S(s));
 }
 
+int ggarray_insert_gen_shrink(ggarray* a, const gga_gen* g, uint64_t n_threads, uint32_t num, uint32_t den,
+                              gga_stream s) {
+  uint32_t mode = 0, maxc = 0;
+  if (!a || den == 0 || num > den) return GGA_EINVAL;
+  const int rc = check_gen(g, n_threads, &mode, &maxc);
+  if (rc) return rc;
+  const InsertDesc d = gen_desc(g, mode, n_threads);
+  return launch_insert(a, d, S(s), num, den);
+}
+
 int ggarray_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
                             gga_stream s) {
   if (!a || !prefix || (n_values && !values)) return GGA_EINVAL;

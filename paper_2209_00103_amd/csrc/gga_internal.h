@@ -204,6 +204,40 @@ struct ServeItem {
 // ceil(live elements of the bucket / te) tiles.  In closed form: the nb - 1 full
 // buckets hold F 2^b elements, one tile each while F 2^b <= te and F 2^b / te
 // tiles after that (a geometric sum), and the last bucket holds the rest.
+// Elements an LFVector of s elements keeps when a shrink pops floor(s num / den)
+// of them (num <= den; the product is split so that it cannot overflow).
+__host__ __device__ __forceinline__ uint64_t shrink_keep(uint64_t s, uint32_t num, uint32_t den) {
+  return s - ((s / den) * num + ((s % den) * num) / den);
+}
+
+// Lane b of a wave releases bucket b of LFVector v when keep <= b < hi: a live
+// bucket goes back to the pool and its slot is cleared (a failed-allocation
+// marker is only cleared).  With `held` the caller passes the slot's value in
+// `cur` (a bucket it allocated itself), otherwise it is read.
+__device__ __forceinline__ void release_bucket(const ArrRef& A, uint32_t v, uint32_t b, uint32_t keep, uint32_t hi,
+                                               bool held, uint64_t cur, uint32_t elem_log2) {
+  if (b < keep || b >= hi) return;
+  uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
+  const uint64_t p = held ? cur : *slot;
+  if (p > kFailedPtr)
+    pool_free(A.pool, reinterpret_cast<uint8_t*>(p), bucket_class(A.log2F, elem_log2, b), pool_shard(v, b, A.salt));
+  if (p) *slot = 0;
+}
+
+// Shrink (pop floor(s num / den) per LFVector) and bucket release: one wave per
+// LFVector, lane b looks after bucket b, so the releases of one LFVector run in
+// parallel and go to different pool shards.
+__device__ __forceinline__ void shrink_vector(const ArrRef& A, uint32_t v, uint32_t num, uint32_t den,
+                                              uint32_t elem_log2) {
+  const uint32_t b = threadIdx.x & 63u;
+  const uint64_t s = A.size[v];
+  const uint64_t ns = shrink_keep(s, num, den);
+  uint32_t hi = A.dead[v] ? (uint32_t)kMaxBuckets : nbuckets_for(A.log2F, s);
+  if (hi > (uint32_t)kMaxBuckets) hi = kMaxBuckets;
+  release_bucket(A, v, b, nbuckets_for(A.log2F, ns), hi, false, 0, elem_log2);
+  if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
+}
+
 __host__ __device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
   const uint32_t nb = nbuckets_for(log2F, s);
   if (nb == 0) return 0;
@@ -291,7 +325,9 @@ __host__ __device__ constexpr uint32_t rw_tile_elems(uint32_t elem_log2) {
   return 16384u >> elem_log2;
 }
 
-int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s);
+// An insertion round, then (sh_den != 0) a shrink sh_num / sh_den fused into the
+// same launch where the round runs one wave per LFVector, else launched after it.
+int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_num = 0, uint32_t sh_den = 0);
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);

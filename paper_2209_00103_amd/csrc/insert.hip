@@ -52,6 +52,8 @@ struct TileArgs {
   uint64_t chunk;        // logical threads per LFVector, ceil(n / V)
   uint64_t tpv;          // tiles per LFVector
   uint32_t elem_log2;
+  uint32_t sh_num = 0;   // a shrink num / den fused after the round (sh_den 0: none;
+  uint32_t sh_den = 0;   // honoured by the one-wave-per-LFVector grow + store only)
 };
 
 struct StaticRef {
@@ -662,7 +664,10 @@ template <typename T, class Prod>
 __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v,
                                                  uint64_t c0, uint64_t cnt) {
   const uint32_t lane = lane_id();
-  if (cnt == 0 || A.dead[v]) return;
+  if (cnt == 0 || A.dead[v]) {
+    if (I.sh_den) shrink_vector(A, v, I.sh_num, I.sh_den, I.elem_log2);
+    return;
+  }
   const uint32_t log2F = A.log2F;
   const uint64_t s0 = A.size[v];
   const uint32_t lo = nbuckets_for(log2F, s0), hi = nbuckets_for(log2F, s0 + cnt);
@@ -679,14 +684,24 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
       failed = !p;
     }
   }
+  // Bucket `lane`'s pointer when this round allocated it (lane lo + k holds bucket lo + k).
+  const uint64_t mine = I.sh_den ? __shfl(q, (int)((lane - lo) & 63u), 64) : 0;
+  const bool held = lane >= lo && lane < hi;
   if (__ballot(failed)) {
     if (lane == 0) {
       set_error(A.err, kErrNoMem);
       A.dead[v] = 1u;
     }
+    if (I.sh_den) {  // the shrink of an LFVector that has just failed: it keeps shrink_keep(s0) and no bucket
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the slot stores above land before they are cleared
+      release_bucket(A, v, lane, nbuckets_for(log2F, shrink_keep(s0, I.sh_num, I.sh_den)), kMaxBuckets, held, mine,
+                     I.elem_log2);
+      if (lane == 0) A.size[v] = shrink_keep(s0, I.sh_num, I.sh_den);
+    }
     return;
   }
-  if (lane == 0) A.size[v] = s0 + cnt;
+  const uint64_t fin = I.sh_den ? shrink_keep(s0 + cnt, I.sh_num, I.sh_den) : s0 + cnt;
+  if (lane == 0) A.size[v] = fin;
   const uint32_t n = (uint32_t)cnt;
   for (uint32_t i = 0; i < n;) {
     const uint64_t idx = s0 + i;
@@ -697,6 +712,13 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
     const uint64_t p = bk >= lo ? __shfl(q, (int)(bk - lo), 64) : A.bptr[(uint64_t)v * kMaxBuckets + bk];
     dense_store<T, Prod>(reinterpret_cast<T*>(p) + (idx - bs), prod, c0 + i, run);
     i += run;
+  }
+  if (I.sh_den) {  // the fused shrink: release the buckets past the kept elements
+    const uint32_t keep = nbuckets_for(log2F, fin);
+    if (keep < hi) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the element stores land before a bucket is handed back
+      release_bucket(A, v, lane, keep, hi, held, mine, I.elem_log2);
+    }
   }
 }
 
@@ -956,9 +978,13 @@ int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const Inser
 
 bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePoisson; }
 
+// Whether a dense round runs as one launch in which one wave per LFVector grows
+// and stores it (else a grow launch, then one workgroup per tile).
+inline bool wave_per_vector(const TileArgs& I, uint32_t V) { return I.tpv <= 8 || V >= 512; }
+
 template <typename T>
 int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
-  if (I.tpv <= 8 || A.V >= 512) {  // one wave per LFVector grows and stores it, in one launch
+  if (wave_per_vector(I, A.V)) {
     const dim3 grid((A.V + 3) / 4), block(256);
     switch (d.mode) {
       case kModeBuffer:
@@ -1024,8 +1050,9 @@ int ensure_status(ggarray* a, uint64_t ntiles, hipStream_t s) {
 
 }  // namespace
 
-int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
-  if (d.n_threads == 0) return GGA_OK;
+int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_num, uint32_t sh_den) {
+  if (sh_num == 0) sh_den = 0;  // a shrink that pops nothing
+  if (d.n_threads == 0) return sh_den ? launch_shrink(a, sh_num, sh_den, s) : GGA_OK;
   const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
   const uint64_t chunk = (d.n_threads + a->V - 1) / a->V;
   const uint64_t tpv = (chunk + tile - 1) / tile;
@@ -1043,9 +1070,16 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
   grow_bound(a, d.n_threads * (multi_mode(d.mode) ? d.max_count : 1u));
   const bool dense = d.mode == kModeRoundTag || d.mode == kModeKeyed || (d.mode == kModeBuffer && !d.flags);
   if (dense) {
-    const int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
-                                      : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
+    const bool fused = sh_den && wave_per_vector(I, a->V);
+    if (fused) {
+      I.sh_num = sh_num;
+      I.sh_den = sh_den;
+    }
+    int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
+                                : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
     if (st == GGA_OK) sizes_changed(a, s);
+    if (fused && st == GGA_OK && sh_num == sh_den) a->size_ub = 0;
+    if (!fused && sh_den && st == GGA_OK) st = launch_shrink(a, sh_num, sh_den, s);
     return st;
   }
 
@@ -1054,9 +1088,10 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s) {
     if (rc) return rc;
   }
   StaticRef S{};
-  const int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
-                                    : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
+  int st = a->elem_bytes == 4 ? dispatch<uint32_t, false>(a->ref, S, I, d, ntiles, s)
+                              : dispatch<uint64_t, false>(a->ref, S, I, d, ntiles, s);
   if (st == GGA_OK) sizes_changed(a, s);
+  if (sh_den && st == GGA_OK) st = launch_shrink(a, sh_num, sh_den, s);
   return st;
 }
 

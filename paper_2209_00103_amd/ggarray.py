@@ -58,6 +58,7 @@ _SIGS = {
     "ggarray_insert_counts": [_vp, _vp, _vp, _u32, _u64, _vp],
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
+    "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
     "ggarray_rw": [_vp, _u32, _vp],
     "ggarray_flatten": [_vp, _vp, _u64, _vp],
     "ggarray_rw_global": [_vp, _u32, _vp],
@@ -254,6 +255,11 @@ class GGArray:
 
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().ggarray_shrink(self._h, num, den, _stream(stream)), "ggarray_shrink")
+
+    def insert_gen_shrink(self, gen: GenSpec, n_threads: int, num: int, den: int, stream=None):
+        """insert_gen then shrink(num, den), as one launch where the round allows it."""
+        _check(lib().ggarray_insert_gen_shrink(self._h, ctypes.byref(gen), int(n_threads), num, den,
+                                               _stream(stream)), "ggarray_insert_gen_shrink")
 
     def rw(self, op: int, stream=None):
         _check(lib().ggarray_rw(self._h, op, _stream(stream)), "ggarray_rw")
