@@ -184,13 +184,15 @@ class Timer:
         return [a.elapsed_time(b) for a, b in self.marks.get(name, [])]
 
 
-def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None):
+def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None, round_ms=None):
     def span(name):
         return timer.span(name) if timer else _Null()
 
     for r, n in enumerate(rounds):
         with span(f"insert{r}"):
             arr.insert_gen_shrink(gens[r], n, 1, 10)  # the round, then its shrink 1/10, in one launch
+        if round_ms is not None:  # kernel timing on: the launch's own start / end events
+            round_ms[r].append(arr.kernel_ms(2))
     with span("prefix"):
         arr.prefix_into(prefix_buf)
     with span("rw"):
@@ -808,10 +810,18 @@ def main():
         log(f"graph replay failed: {e}")
     log(f"graph replay: {graph_ms} ms/step")
 
-    # Per-kernel durations: the same K steps again with events around every call.
+    # Per-kernel durations: the same K steps again with events around every call, and
+    # the r/w and flatten kernels timed by events their own dispatches record at the
+    # kernel's start and end (the spans around those calls also hold the tile-table
+    # launch and the dispatch).
     timer = Timer(torch)
+    arr.kernel_timing(True)
+    k_rw, k_fl = [], []
+    k_ins = [[] for _ in rounds]
     for _ in range(args.steps):
-        ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer)
+        ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer, k_ins)
+        k_rw.append(arr.kernel_ms(0))
+        k_fl.append(arr.kernel_ms(1))
     torch.cuda.synchronize()
     assert arr.last_error() == 0, "device error during the per-kernel pass"
 
@@ -819,6 +829,7 @@ def main():
     # data is read (clean lines), evicting the array from L2 and the 256 MB Infinity
     # Cache, so no byte of it is served from there.
     scratch = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    k_rw_cold, k_fl_cold = [], []
     for _ in range(args.steps):
         arr.shrink(1, 1)
         for r, n in enumerate(rounds):
@@ -826,12 +837,13 @@ def main():
             arr.shrink(1, 10)
         arr.prefix_into(prefix_buf)
         scratch.sum()
-        with timer.span("rw_cold"):
-            arr.rw(G.MUL3ADD1)
+        arr.rw(G.MUL3ADD1)
+        k_rw_cold.append(arr.kernel_ms(0))
         scratch.sum()
-        with timer.span("flatten_cold"):
-            arr.flatten_into(out)
+        arr.flatten_into(out)
+        k_fl_cold.append(arr.kernel_ms(1))
     torch.cuda.synchronize()
+    arr.kernel_timing(False)
     del scratch
     assert arr.last_error() == 0, "device error during the cold-cache pass"
 
@@ -857,9 +869,10 @@ def main():
     arr.shrink(1, 1)
 
     # Per-kernel figures: algorithmic bytes per launch over the measured duration.
-    ins_ms = [statistics.mean(timer.ms(f"insert{r}")) for r in range(len(rounds))]
-    rw_ms = statistics.mean(timer.ms("rw"))
-    fl_ms = statistics.mean(timer.ms("flatten"))
+    ins_ms = [statistics.mean(k) for k in k_ins]
+    ins_span_ms = [statistics.mean(timer.ms(f"insert{r}")) for r in range(len(rounds))]
+    rw_ms = statistics.mean(k_rw)
+    fl_ms = statistics.mean(k_fl)
     pre_ms = statistics.mean(timer.ms("prefix"))
     clr_ms = statistics.mean(timer.ms("clear"))
     ins_bytes = [ELEM * n for n in rounds]
@@ -876,13 +889,19 @@ def main():
                    # rounds writing less than the 256 MiB Infinity Cache may be served by it
                    "cache_assisted_rounds": [r for r, b in enumerate(ins_bytes) if b < (256 << 20)],
                    "last_round_GBps": gbps(ins_bytes[-1], ins_ms[-1]),
-                   "fused": "each launch also applies its round's shrink 1/10 (pops and bucket releases)"},
+                   "fused": "each launch also applies its round's shrink 1/10 (pops and bucket releases)",
+                   "span_us": round(1e3 * sum(ins_span_ms) / len(rounds), 2),
+                   "timing": "events recorded by each launch's own dispatch; span_us: events around the call"},
         "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,
                "GBps": gbps(rw_bytes, rw_ms),
-               "cold_cache_GBps": gbps(rw_bytes, statistics.mean(timer.ms("rw_cold")))},
+               "cold_cache_GBps": gbps(rw_bytes, statistics.mean(k_rw_cold)),
+               "span_us": 1e3 * statistics.mean(timer.ms("rw")),
+               "timing": "events recorded by the kernel's own dispatch; span_us: events around the call "
+                         "(tile-table launch and dispatch included)"},
         "flatten": {"launches_per_step": 1, "avg_us": 1e3 * fl_ms, "bytes_per_launch": fl_bytes,
                     "GBps": gbps(fl_bytes, fl_ms),
-                    "cold_cache_GBps": gbps(fl_bytes, statistics.mean(timer.ms("flatten_cold")))},
+                    "cold_cache_GBps": gbps(fl_bytes, statistics.mean(k_fl_cold)),
+                    "span_us": 1e3 * statistics.mean(timer.ms("flatten"))},
         "shrink": {"launches_per_step": 1, "avg_us": 1e3 * clr_ms,
                    "note": "the clear (shrink 1/1); the rounds' shrinks run inside their insertion launches"},
         "prefix_scan": {"launches_per_step": 1, "avg_us": 1e3 * pre_ms},
@@ -896,8 +915,8 @@ def main():
                    "bytes_per_launch": 16 * n_gather, "GBps": gbps(16 * n_gather, gat_ms),
                    "note": "per index: 8 B index + 4 B element + 4 B output; the element read is random"},
     }
-    for k, ts in (("insert_all_rounds", [sum(x) for x in zip(*[timer.ms(f"insert{r}") for r in range(len(rounds))])]),
-                  ("rw", timer.ms("rw")), ("flatten", timer.ms("flatten"))):
+    for k, ts in (("insert_all_rounds", [sum(x) for x in zip(*k_ins)]),
+                  ("rw", k_rw), ("flatten", k_fl)):
         q = sorted(ts)
         (kernels["insert"] if k == "insert_all_rounds" else kernels[k])["p10_p50_p90_us"] = [
             round(1e3 * q[int(0.1 * (len(q) - 1))], 2), round(1e3 * statistics.median(q), 2),

@@ -239,6 +239,19 @@ int ggarray_vector_sizes(ggarray *a, uint64_t *dev_out, gga_stream s);
  *   LFVector sizes (uint64; the last entry is the global size) to dev_out. Queued. */
 int ggarray_prefix(ggarray *a, uint64_t *dev_out, gga_stream s);
 
+/* ggarray_kernel_timing: a measurement aid.  With on != 0 the array's r/w and
+ *   flatten kernels, and its insertion rounds that run as one launch (rounds of
+ *   round-tag or keyed payloads, or of a buffer without flags, with one wave per
+ *   LFVector), when not captured in a graph, are dispatched with a pair of HIP
+ *   events that the dispatch itself records at the kernel's start and end (the
+ *   library creates and owns them; on == 0 destroys them).
+ * ggarray_kernel_ms: the duration in milliseconds of the array's last timed r/w
+ *   (kind 0) or flatten (kind 1) kernel, or of its last insertion round (kind 2)
+ *   if that round was timed; waits for it to end.  GGA_EINVAL when there is no
+ *   such timed kernel. */
+int ggarray_kernel_timing(ggarray *a, uint32_t on);
+int ggarray_kernel_ms(ggarray *a, uint32_t kind, float *ms);
+
 /* ggarray_last_error: the sticky device error of the array (GGA_OK if none).
  *   Synchronises s.  Does not clear it. */
 int ggarray_last_error(ggarray *a, gga_stream s);

@@ -8,6 +8,8 @@
 // in a tile table and workgroups take table entries; smaller arrays and served
 // steps spread the tiles over a persistent grid that locates its share by a
 // search of the tile prefix.
+#include <hip/hip_ext.h>
+
 #include "gga_internal.h"
 
 namespace gga {
@@ -759,6 +761,21 @@ static int stream_source(ggarray* a, hipStream_t s, const uint64_t** tab, uint64
   return GGA_OK;
 }
 
+// Launches an r/w (kind 0) or flatten (kind 1) kernel.  With kernel timing on and
+// the stream not capturing, the dispatch itself records the array's start and end
+// events of that kind, so they bracket the kernel alone.
+template <typename... Args, typename F>
+static void launch_streaming(ggarray* a, uint32_t kind, F kernel, dim3 grid, dim3 block, hipStream_t s,
+                             Args... args) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (a->tev[kind][0] && !stream_capturing(s)) {
+    e0 = a->tev[kind][0];
+    e1 = a->tev[kind][1];
+    a->tev_set |= 1u << kind;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+}
+
 int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
   const uint64_t* tab;
   uint64_t tcap;
@@ -769,18 +786,18 @@ int launch_rw(ggarray* a, uint32_t op, hipStream_t s) {
   const bool nt = a->last_rw_gen == a->sizes_gen + 1;  // the array's previous streaming call was an r/w
   if (a->elem_bytes == 4) {
     if (nt)
-      hipLaunchKernelGGL((stream_table_kernel<uint32_t, false, true>), grid, block, 0, s, a->ref, tab, tcap, op,
-                         (uint32_t*)nullptr, (uint64_t)0, te_log2);
+      launch_streaming(a, 0, stream_table_kernel<uint32_t, false, true>, grid, block, s, a->ref, tab, tcap, op,
+                       (uint32_t*)nullptr, (uint64_t)0, te_log2);
     else
-      hipLaunchKernelGGL((stream_table_kernel<uint32_t, false>), grid, block, 0, s, a->ref, tab, tcap, op,
-                         (uint32_t*)nullptr, (uint64_t)0, te_log2);
+      launch_streaming(a, 0, stream_table_kernel<uint32_t, false>, grid, block, s, a->ref, tab, tcap, op,
+                       (uint32_t*)nullptr, (uint64_t)0, te_log2);
   } else {
     if (nt)
-      hipLaunchKernelGGL((stream_table_kernel<uint64_t, false, true>), grid, block, 0, s, a->ref, tab, tcap, op,
-                         (uint64_t*)nullptr, (uint64_t)0, te_log2);
+      launch_streaming(a, 0, stream_table_kernel<uint64_t, false, true>, grid, block, s, a->ref, tab, tcap, op,
+                       (uint64_t*)nullptr, (uint64_t)0, te_log2);
     else
-      hipLaunchKernelGGL((stream_table_kernel<uint64_t, false>), grid, block, 0, s, a->ref, tab, tcap, op,
-                         (uint64_t*)nullptr, (uint64_t)0, te_log2);
+      launch_streaming(a, 0, stream_table_kernel<uint64_t, false>, grid, block, s, a->ref, tab, tcap, op,
+                       (uint64_t*)nullptr, (uint64_t)0, te_log2);
   }
   a->last_rw_gen = a->sizes_gen + 1;
   return hip_status(hipGetLastError());
@@ -795,11 +812,11 @@ int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
   const uint32_t te_log2 = 14u - a->elem_log2;
   const dim3 grid(stream_grid(a, tcap ? kTableBlocks : kFlattenBlocks)), block(kRwThreads);
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL((stream_table_kernel<uint32_t, true>), grid, block, 0, s, a->ref, tab, tcap, 0u,
-                       static_cast<uint32_t*>(out), cap, te_log2);
+    launch_streaming(a, 1, stream_table_kernel<uint32_t, true>, grid, block, s, a->ref, tab, tcap, 0u,
+                     static_cast<uint32_t*>(out), cap, te_log2);
   else
-    hipLaunchKernelGGL((stream_table_kernel<uint64_t, true>), grid, block, 0, s, a->ref, tab, tcap, 0u,
-                       static_cast<uint64_t*>(out), cap, te_log2);
+    launch_streaming(a, 1, stream_table_kernel<uint64_t, true>, grid, block, s, a->ref, tab, tcap, 0u,
+                     static_cast<uint64_t*>(out), cap, te_log2);
   return hip_status(hipGetLastError());
 }
 

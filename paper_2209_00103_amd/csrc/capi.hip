@@ -259,6 +259,8 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->scan_tag = 0;
   a->tab_tag = 0;
   a->graph_sized = false;
+  for (auto& k : a->tev) k[0] = k[1] = nullptr;
+  a->tev_set = 0;
   a->meta_bytes = off;
   a->retired_tab_bytes = 0;
   p->n_arrays += 1;
@@ -276,6 +278,9 @@ int ggarray_destroy(ggarray* a, gga_stream s) {
     if (hipFreeAsync(a->retired[i], S(s)) != hipSuccess) rc = GGA_EHIP;
   if (hipStreamSynchronize(S(s)) != hipSuccess) rc = GGA_EHIP;
   if (hipFree(a->meta) != hipSuccess) rc = GGA_EHIP;
+  for (auto& k : a->tev)
+    for (hipEvent_t& e : k)
+      if (e && hipEventDestroy(e) != hipSuccess) rc = GGA_EHIP;
   f->x.pin.release();
   a->pool->n_arrays -= 1;
   delete f;
@@ -314,6 +319,29 @@ int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_str
   if (rc) return rc;
   const InsertDesc d = gen_desc(g, mode, n_threads);
   return launch_insert(a, d, S(s));
+}
+
+int ggarray_kernel_timing(ggarray* a, uint32_t on) {
+  if (!a) return GGA_EINVAL;
+  if (!on) {
+    for (auto& k : a->tev)
+      for (hipEvent_t& e : k) {
+        if (e && hipEventDestroy(e) != hipSuccess) return GGA_EHIP;
+        e = nullptr;
+      }
+    a->tev_set = 0;
+    return GGA_OK;
+  }
+  for (auto& k : a->tev)
+    for (hipEvent_t& e : k)
+      if (!e && hipEventCreate(&e) != hipSuccess) return GGA_EHIP;
+  return GGA_OK;
+}
+
+int ggarray_kernel_ms(ggarray* a, uint32_t kind, float* ms) {
+  if (!a || kind > 2 || !ms || !(a->tev_set >> kind & 1u)) return GGA_EINVAL;
+  if (hipEventSynchronize(a->tev[kind][1]) != hipSuccess) return GGA_EHIP;
+  return hip_status(hipEventElapsedTime(ms, a->tev[kind][0], a->tev[kind][1]));
 }
 
 int ggarray_insert_gen_shrink(ggarray* a, const gga_gen* g, uint64_t n_threads, uint32_t num, uint32_t den,

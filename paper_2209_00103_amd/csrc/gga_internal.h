@@ -39,6 +39,8 @@ struct ggarray {
   uint64_t scan_tag;      // capture tag (stream_capture_tag) the current prefix was built under
   uint64_t tab_tag;       // capture tag the current tile table was built under
   bool graph_sized;       // a captured call changes the sizes (replays do so unseen)
+  hipEvent_t tev[3][2];   // kernel timing: start / end events of the last r/w (0), flatten (1), round (2)
+  uint32_t tev_set;       // bit k: events of kind k were recorded by a dispatch
   uint64_t meta_bytes;    // size of the metadata allocation
   uint64_t retired_tab_bytes;  // outgrown tile tables kept until destroy
 };

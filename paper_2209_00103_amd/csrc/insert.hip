@@ -25,6 +25,8 @@
 // The static baseline replaces 2-4 by one global atomicAdd per tile.
 #include <new>
 
+#include <hip/hip_ext.h>
+
 #include "gga_internal.h"
 
 namespace gga {
@@ -983,20 +985,21 @@ bool multi_mode(uint32_t mode) { return mode == kModeCounts || mode == kModePois
 inline bool wave_per_vector(const TileArgs& I, uint32_t V) { return I.tpv <= 8 || V >= 512; }
 
 template <typename T>
-int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
+int launch_dense(const ArrRef& A, const TileArgs& I, const InsertDesc& d, uint64_t ntiles, hipStream_t s,
+                 hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (wave_per_vector(I, A.V)) {
     const dim3 grid((A.V + 3) / 4), block(256);
     switch (d.mode) {
       case kModeBuffer:
-        hipLaunchKernelGGL((grow_store_kernel<T, ProdBuffer<T>>), grid, block, 0, s, A, I,
+        hipExtLaunchKernelGGL(grow_store_kernel<T, ProdBuffer<T>>, grid, block, 0, s, e0, e1, 0, A, I,
                            ProdBuffer<T>{static_cast<const T*>(d.values), nullptr});
         break;
       case kModeRoundTag:
-        hipLaunchKernelGGL((grow_store_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, A, I,
+        hipExtLaunchKernelGGL(grow_store_kernel<T, ProdRoundTag<T>>, grid, block, 0, s, e0, e1, 0, A, I,
                            ProdRoundTag<T>{d.round, d.tag_shift});
         break;
       case kModeKeyed:
-        hipLaunchKernelGGL((grow_store_kernel<T, ProdKeyed<T>>), grid, block, 0, s, A, I,
+        hipExtLaunchKernelGGL(grow_store_kernel<T, ProdKeyed<T>>, grid, block, 0, s, e0, e1, 0, A, I,
                            ProdKeyed<T>{d.seed, d.round, d.tag_shift, d.tag});
         break;
       default:
@@ -1052,6 +1055,7 @@ int ensure_status(ggarray* a, uint64_t ntiles, hipStream_t s) {
 
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_num, uint32_t sh_den) {
   if (sh_num == 0) sh_den = 0;  // a shrink that pops nothing
+  a->tev_set &= ~4u;            // set again below if this round is timed
   if (d.n_threads == 0) return sh_den ? launch_shrink(a, sh_num, sh_den, s) : GGA_OK;
   const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
   const uint64_t chunk = (d.n_threads + a->V - 1) / a->V;
@@ -1075,8 +1079,15 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_nu
       I.sh_num = sh_num;
       I.sh_den = sh_den;
     }
-    int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s)
-                                : launch_dense<uint64_t>(a->ref, I, d, ntiles, s);
+    // Kernel timing: a round that is one launch records the array's round events.
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (a->tev[2][0] && wave_per_vector(I, a->V) && !stream_capturing(s)) {
+      e0 = a->tev[2][0];
+      e1 = a->tev[2][1];
+      a->tev_set |= 4u;
+    }
+    int st = a->elem_bytes == 4 ? launch_dense<uint32_t>(a->ref, I, d, ntiles, s, e0, e1)
+                                : launch_dense<uint64_t>(a->ref, I, d, ntiles, s, e0, e1);
     if (st == GGA_OK) sizes_changed(a, s);
     if (fused && st == GGA_OK && sh_num == sh_den) a->size_ub = 0;
     if (!fused && sh_den && st == GGA_OK) st = launch_shrink(a, sh_num, sh_den, s);
@@ -1099,6 +1110,7 @@ int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefi
                            hipStream_t s) {
   TileArgs I{};
   I.elem_log2 = a->elem_log2;
+  a->tev_set &= ~4u;  // not a timed round
   grow_bound(a, n_values);
   const dim3 grid((a->V + 3) / 4), block(256);
   if (a->elem_bytes == 4)

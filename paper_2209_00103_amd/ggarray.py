@@ -59,6 +59,8 @@ _SIGS = {
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
+    "ggarray_kernel_timing": [_vp, _u32],
+    "ggarray_kernel_ms": [_vp, _u32, _P(ctypes.c_float)],
     "ggarray_rw": [_vp, _u32, _vp],
     "ggarray_flatten": [_vp, _vp, _u64, _vp],
     "ggarray_rw_global": [_vp, _u32, _vp],
@@ -255,6 +257,16 @@ class GGArray:
 
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().ggarray_shrink(self._h, num, den, _stream(stream)), "ggarray_shrink")
+
+    def kernel_timing(self, on: bool):
+        """Measurement aid: r/w and flatten dispatches record events at their own start and end."""
+        _check(lib().ggarray_kernel_timing(self._h, 1 if on else 0), "ggarray_kernel_timing")
+
+    def kernel_ms(self, kind: int) -> float:
+        """Duration of the last timed r/w (0) or flatten (1) kernel, in ms."""
+        ms = ctypes.c_float()
+        _check(lib().ggarray_kernel_ms(self._h, int(kind), ctypes.byref(ms)), "ggarray_kernel_ms")
+        return float(ms.value)
 
     def insert_gen_shrink(self, gen: GenSpec, n_threads: int, num: int, den: int, stream=None):
         """insert_gen then shrink(num, den), as one launch where the round allows it."""

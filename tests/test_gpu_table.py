@@ -374,3 +374,42 @@ def test_batch_graph_of_insertion_alone_then_eager_calls(pool):
     for a, o in zip(arrays, oracles):
         a.close()
         o.close()
+
+
+def test_kernel_timing_events(pool):
+    """The measurement aid: r/w and flatten dispatches record events at the kernel's
+    own start and end; results are unchanged, durations are positive, and asking
+    before any timed kernel (or after timing is switched off) is an error."""
+    G = gg()
+    a, o = G.GGArray(pool, 4, 16, 1024), Oracle(4, 16, 1024)
+    a.insert_gen(G.make_gen(G.GEN_KEYED, seed=1, round=0, tag=1), BIG)
+    o.insert_gen(oracle.GEN_KEYED, BIG, seed=1, round=0, tag=1)
+    with pytest.raises(G.GGAError):
+        a.kernel_ms(0)
+    a.kernel_timing(True)
+    with pytest.raises(G.GGAError):
+        a.kernel_ms(1)
+    a.rw(G.ADD1)
+    o.rw(oracle.OP_ADD1)
+    out = torch.zeros(BIG, dtype=torch.int32, device="cuda")
+    a.flatten_into(out)
+    rw_ms, fl_ms = a.kernel_ms(0), a.kernel_ms(1)
+    assert 0.0 < rw_ms < 1000.0 and 0.0 < fl_ms < 1000.0
+    _check(G, out, o, "timed r/w and flatten")
+    # a round of 8 tiles per LFVector is one launch and is timed; one of 128 tiles is not
+    a.insert_gen_shrink(G.make_gen(G.GEN_ROUND_TAG, round=1, tag_shift=26), 16 * 4096 * 8, 1, 10)
+    o.insert_gen(oracle.GEN_ROUND_TAG, 16 * 4096 * 8, round=1, tag_shift=26)
+    o.shrink(1, 10)
+    assert 0.0 < a.kernel_ms(2) < 1000.0
+    a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=2, tag_shift=26), BIG)
+    o.insert_gen(oracle.GEN_ROUND_TAG, BIG, round=2, tag_shift=26)
+    with pytest.raises(G.GGAError):
+        a.kernel_ms(2)
+    out = torch.zeros(o.flatten().size, dtype=torch.int32, device="cuda")
+    a.flatten_into(out)
+    _check(G, out, o, "after timed and untimed rounds")
+    a.kernel_timing(False)
+    with pytest.raises(G.GGAError):
+        a.kernel_ms(0)
+    a.close()
+    o.close()
