@@ -84,11 +84,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def ceiling_leg(torch, reps=10):
+def ceiling_leg(torch, n_small=None, reps=10):
     """Achievable streaming rates on this GPU with plain PyTorch kernels over 4 GiB:
     a write-only fill, a copy (4 GiB read, 4 GiB written) and an in-place add (the
-    same 4 GiB read and written, the access pattern of r/w).  Context for the
-    roofline fractions, which stay against the 8 TB/s specification."""
+    same 4 GiB read and written, the access pattern of r/w); with n_small also the
+    copy and the in-place add over n_small int32 words (the array's live size, so
+    the same bytes as one r/w or flatten).  Context for the roofline fractions,
+    which stay against the 8 TB/s specification."""
     n = 1 << 30  # int32 words: 4 GiB per buffer
     a = torch.empty(n, dtype=torch.int32, device="cuda")
     b = torch.empty_like(a)
@@ -109,6 +111,10 @@ def ceiling_leg(torch, reps=10):
     res = {"fill": rate(lambda: a.fill_(7), 4 * n), "copy": rate(lambda: b.copy_(a), 8 * n),
            "inplace_add": rate(lambda: a.add_(1), 8 * n), "bytes_per_buffer": 4 * n,
            "note": "torch fill_, copy_ and add_ over 4 GiB int32 buffers; bytes moved per call / time"}
+    if n_small:
+        sa, sb = a[:n_small], b[:n_small]
+        res["same_size"] = {"words": n_small, "copy": rate(lambda: sb.copy_(sa), 8 * n_small),
+                            "inplace_add": rate(lambda: sa.add_(1), 8 * n_small)}
     del a, b
     torch.cuda.empty_cache()
     return res
@@ -935,12 +941,17 @@ def main():
 
     ceilings = None
     if not args.no_ceiling:
-        ceilings = ceiling_leg(torch)
+        ceilings = ceiling_leg(torch, final_size)
         ceilings["flatten_over_copy"] = kernels["flatten"]["GBps"] / ceilings["copy"]["GBps"]
         ceilings["rw_over_inplace_add"] = kernels["rw"]["GBps"] / ceilings["inplace_add"]["GBps"]
+        same = ceilings["same_size"]
+        same["flatten_over_copy"] = kernels["flatten"]["GBps"] / same["copy"]["GBps"]
+        same["rw_over_inplace_add"] = kernels["rw"]["GBps"] / same["inplace_add"]["GBps"]
         log(f"plain kernels: fill {ceilings['fill']['GBps']:.0f} GB/s, copy {ceilings['copy']['GBps']:.0f} GB/s, "
             f"in-place add {ceilings['inplace_add']['GBps']:.0f} GB/s; flatten / copy "
-            f"{ceilings['flatten_over_copy']:.2f}, rw / in-place add {ceilings['rw_over_inplace_add']:.2f}")
+            f"{ceilings['flatten_over_copy']:.2f}, rw / in-place add {ceilings['rw_over_inplace_add']:.2f}; "
+            f"at the array's size: copy {same['copy']['GBps']:.0f}, in-place add {same['inplace_add']['GBps']:.0f} GB/s "
+            f"(flatten / copy {same['flatten_over_copy']:.2f}, rw / in-place add {same['rw_over_inplace_add']:.2f})")
 
     # Baselines beside it: the static array (pre-allocated for 2^28) and the
     # host-resized array, same insertion rounds (they have no shrink) and r/w.

@@ -21,10 +21,13 @@ def _first_diff(got, ref):
     return f"{bad.size} differ, first at {bad[:4]}"
 
 
-@pytest.mark.parametrize("V", [512, 256, 32])
-def test_config2_full_size_exact(V):
+@pytest.mark.parametrize("V,fused", [(512, True), (512, False), (256, True), (32, False)])
+def test_config2_full_size_exact(V, fused):
     """2^28 insertions over 12 rounds with shrink 1/10 after each, r/w x = 3x + 1,
-    flatten: every element against the list-form oracle."""
+    flatten: every element against the list-form oracle.  With `fused` each round
+    and its shrink are one ggarray_insert_gen_shrink call, as the benchmark runs
+    them (one launch per round at V = 512; at V = 256 the rounds of more than 8
+    tiles per LFVector take two)."""
     G = gg()
     rounds = wl.cfg2_round_threads()
     pool = G.Pool(4 * GiB)
@@ -32,8 +35,12 @@ def test_config2_full_size_exact(V):
     o = Oracle(4, V, 1024, forms=oracle.FORM_LIST)
     try:
         for r, n in enumerate(rounds):
-            a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=27), n)
-            a.shrink(1, 10)
+            gen = G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=27)
+            if fused:
+                a.insert_gen_shrink(gen, n, 1, 10)
+            else:
+                a.insert_gen(gen, n)
+                a.shrink(1, 10)
             o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=27)
             o.shrink(1, 10)
         a.rw(G.MUL3ADD1)
