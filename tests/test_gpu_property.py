@@ -1,6 +1,7 @@
 """Property-based GPU parity: random shapes (V, F, element size), random rounds of
 every producer kind (buffer with and without flags, Bernoulli, round-tag, keyed,
-per-thread counts, Poisson), random shrinks and r/w passes, drawn by Hypothesis;
+per-thread counts, Poisson), random shrinks, rounds fused with their shrink and
+r/w passes, drawn by Hypothesis;
 after every operation the GPU array must equal the CPU oracle bit for bit."""
 import numpy as np
 import pytest
@@ -24,6 +25,7 @@ OPS = st.one_of(
     st.tuples(st.just("poisson"), st.integers(0, 20000), st.integers(0, 7)),
     st.tuples(st.just("shrink"), st.integers(0, 7), st.integers(1, 7)),
     st.tuples(st.just("rw"), st.integers(0, 2)),
+    st.tuples(st.just("fused"), st.integers(0, 70000), st.booleans(), st.integers(0, 7), st.integers(1, 7)),
 )
 
 
@@ -79,6 +81,15 @@ def test_random_operation_sequences_match_oracle(pool, elem, V, F_log2, ops, see
             elif kind == "shrink":
                 num, den = min(op[1], op[2]), op[2]
                 a.shrink(num, den)
+                o.shrink(num, den)
+            elif kind == "fused":  # a round and its shrink in one call
+                n, keyed, num, den = op[1], op[2], min(op[3], op[4]), op[4]
+                if keyed:
+                    a.insert_gen_shrink(G.make_gen(G.GEN_KEYED, seed=9, round=step, tag=5), n, num, den)
+                    o.insert_gen(oracle.GEN_KEYED, n, seed=9, round=step, tag=5)
+                else:
+                    a.insert_gen_shrink(G.make_gen(G.GEN_ROUND_TAG, round=step, tag_shift=20), n, num, den)
+                    o.insert_gen(oracle.GEN_ROUND_TAG, n, round=step, tag_shift=20)
                 o.shrink(num, den)
             else:
                 a.rw(op[1])
