@@ -658,10 +658,13 @@ __device__ __forceinline__ void store_tile(const ArrRef& A, const TileArgs& I, c
 // Used when that still fills the GPU: rounds of up to 8 tiles per LFVector, or
 // arrays of 512 or more LFVectors (on configuration 2, 512 waves writing up to
 // 1 MiB each reach 4.8 TB/s, against 4.5 for a grow launch plus a store launch
-// of one wave per tile).  Fewer, longer LFVectors take the two-launch form.  The new bucket pointers stay in the
-// lanes that allocated them; a bucket that existed before the round is read
-// from the table, written by an earlier launch.
+// of one wave per tile).  Fewer, longer LFVectors take the two-launch form.  The
+// new bucket pointers stay in the lanes that allocated them; a bucket that
+// existed before the round is read from the table, written by an earlier launch.
 // LFVector v appends the elements the producer gives for g = c0 .. c0 + cnt - 1.
+// With a fused shrink (I.sh_den != 0) the wave then leaves the size the shrink
+// would leave and releases the buckets past it, exactly as a shrink launch after
+// the round would (an LFVector that fails to grow is frozen, then still shrunk).
 template <typename T, class Prod>
 __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs& I, const Prod& prod, uint32_t v,
                                                  uint64_t c0, uint64_t cnt) {
