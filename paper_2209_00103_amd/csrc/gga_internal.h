@@ -206,6 +206,23 @@ struct ServeItem {
 // ceil(live elements of the bucket / te) tiles.  In closed form: the nb - 1 full
 // buckets hold F 2^b elements, one tile each while F 2^b <= te and F 2^b / te
 // tiles after that (a geometric sum), and the last bucket holds the rest.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// A 16-byte store that streams past the caches (nt) with device-scope coherence
+// (sc1).  Used by the insertion of generated payloads: on configuration 2 the r/w
+// that follows the rounds reads such lines faster than after plain non-temporal
+// stores (step 0.919 -> 0.907 ms, r/w 5.52 -> 5.61 TB/s, three runs each; sc1
+// alone or no hint behave like plain write-back stores, whose dirty lines the
+// r/w pays for); and by flatten's output (5.62 -> 5.71 TB/s, four runs each).
+// r/w's own stores stay plain non-temporal (with sc1 it measured 5.0 TB/s).
+// There is no builtin for the sc1 bit, hence the inline assembly.  The compiler
+// does not count this store in its wait counters: a later wait that it places
+// for a load also covers the store (the vector-memory counter completes in
+// order), so the store only makes such waits longer, never too short.
+__device__ __forceinline__ void store_nt_sc1(gptr<u32x4> p, u32x4 x) {
+  asm volatile("global_store_dwordx4 %0, %1, off nt sc1" : : "v"(p), "v"(x) : "memory");
+}
+
 // Elements an LFVector of s elements keeps when a shrink pops floor(s num / den)
 // of them (num <= den; the product is split so that it cannot overflow).
 __host__ __device__ __forceinline__ uint64_t shrink_keep(uint64_t s, uint32_t num, uint32_t den) {

@@ -84,7 +84,6 @@ __device__ __forceinline__ bool status_current(uint64_t w, uint64_t epoch) {
   return (w >> 34) == (epoch & kEpochMask) && status_flag(w) != 0;
 }
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -441,19 +440,6 @@ __device__ __forceinline__ SlotMask wave_flags(const Prod& prod, uint64_t g0, ui
 // so that each store instruction of the wave covers whole 128-byte lines: with
 // 16-byte alignment only, every instruction left two partial lines for its
 // neighbour to complete (about 6% more HBM writes, measured).
-// A 16-byte store that streams past the caches (nt) with device-scope coherence
-// (sc1).  On configuration 2 the r/w that follows the insertion rounds reads such
-// lines faster than after plain non-temporal stores (step 0.919 -> 0.907 ms, r/w
-// 5.52 -> 5.61 TB/s, three runs each; sc1 alone or no hint behave like plain
-// write-back stores, whose dirty lines the r/w pays for).  There is no builtin
-// for the sc1 bit, hence the inline assembly.  The compiler does not count this
-// store in its wait counters; it is used only for producers that load nothing,
-// and a later wait that the compiler places for a load also covers it (the
-// vector-memory counter completes in order).
-__device__ __forceinline__ void store_nt_sc1(gptr<u32x4> p, u32x4 x) {
-  asm volatile("global_store_dwordx4 %0, %1, off nt sc1" : : "v"(p), "v"(x) : "memory");
-}
-
 template <typename T, class Prod>
 __device__ __forceinline__ void dense_store(T* dst, const Prod& prod, uint64_t g0, uint32_t n) {
   constexpr uint32_t VPL = 16 / sizeof(T);
