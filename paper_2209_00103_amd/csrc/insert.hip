@@ -931,7 +931,8 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
         const uint64_t idx = base + q;
         const uint32_t b = bucket_of(log2F, idx);
         const uint64_t p = sh.bp[b - sh.b_lo];
-        if (p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val;
+        // non-temporal: configuration 3 measured insertion +1-3% and the r/w after it +3-6%
+        if (p > kFailedPtr) __builtin_nontemporal_store(val, gmem(reinterpret_cast<T*>(p)) + offset_in(log2F, idx, b));
       }
     }
   }
