@@ -46,6 +46,8 @@ inline uint32_t stream_grid(const ggarray* a, uint32_t cap) {
   return (uint32_t)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
+typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
+
 // Exclusive prefix sums of the LFVector sizes (element offsets, Sec. IV) and of
 // their tile counts, by one workgroup of kScanThreads; entry V holds the totals.
 __device__ __forceinline__ void scan_array(const ArrRef& A, uint32_t te_log2, uint64_t* copy = nullptr) {
@@ -223,8 +225,10 @@ __device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
 // at element k * (256 * VPL) + i * VPL.  Every byte is touched once, so stores
 // are non-temporal; so are flatten's loads, while r/w loads through the cache,
 // which lets its non-temporal stores find the lines they overwrite (measured:
-// r/w 4.80 -> 5.31 TB/s, flatten slower with cached loads).  Flatten's stores
-// also carry device-scope coherence (store_nt_sc1); r/w's do not.
+// r/w 4.80 -> 5.31 TB/s, flatten slower with cached loads).  Neither carries the
+// device-scope bit that the insertion's stores do: with it r/w measured 5.0
+// TB/s, and flatten gained 1.5% on configuration 2 but slowed the batched step
+// that follows it by 3%.
 template <typename T, bool kFlatten, bool kNtLoad = kFlatten>
 __device__ __forceinline__ void stream_tile(T* src_, T* dst_, uint32_t cnt, uint32_t op) {
   const gptr<T> src = gmem(src_), dst = gmem(dst_);
@@ -266,7 +270,7 @@ __device__ __forceinline__ void stream_tile(T* src_, T* dst_, uint32_t cnt, uint
           for (uint32_t e = 0; e < VPL; ++e) tmp[e] = st[e0 + e];
           u32x4 x;
           __builtin_memcpy(&x, tmp, 16);
-          store_nt_sc1(reinterpret_cast<gptr<u32x4>>(dal + (uint64_t)j * VPL), x);
+          __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dal + (uint64_t)j * VPL));
         } else {
           for (uint32_t e = 0; e < VPL; ++e) {
             const int64_t i = e0 + e;
@@ -287,7 +291,7 @@ __device__ __forceinline__ void stream_tile(T* src_, T* dst_, uint32_t cnt, uint
 #pragma unroll
     for (uint32_t k = 0; k < kSlots; ++k) {
       if (kFlatten)
-        store_nt_sc1(reinterpret_cast<gptr<u32x4>>(dst + k * kSpan + tid * VPL), r[k]);
+        __builtin_nontemporal_store(r[k], reinterpret_cast<gptr<u32x4_a4>>(dst + k * kSpan + tid * VPL));
       else
         __builtin_nontemporal_store(op_vec<T>(op, r[k]), reinterpret_cast<gptr<u32x4>>(src + k * kSpan + tid * VPL));
     }
@@ -299,7 +303,7 @@ __device__ __forceinline__ void stream_tile(T* src_, T* dst_, uint32_t cnt, uint
       const u32x4 x = kNtLoad ? __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4>>(src + e))
                                : *reinterpret_cast<gptr<const u32x4>>(src + e);
       if (kFlatten)
-        store_nt_sc1(reinterpret_cast<gptr<u32x4>>(dst + e), x);
+        __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4_a4>>(dst + e));
       else
         __builtin_nontemporal_store(op_vec<T>(op, x), reinterpret_cast<gptr<u32x4>>(src + e));
     } else {

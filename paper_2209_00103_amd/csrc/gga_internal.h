@@ -213,8 +213,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // that follows the rounds reads such lines faster than after plain non-temporal
 // stores (step 0.919 -> 0.907 ms, r/w 5.52 -> 5.61 TB/s, three runs each; sc1
 // alone or no hint behave like plain write-back stores, whose dirty lines the
-// r/w pays for); and by flatten's output (5.62 -> 5.71 TB/s, four runs each).
-// r/w's own stores stay plain non-temporal (with sc1 it measured 5.0 TB/s).
+// r/w pays for).
 // There is no builtin for the sc1 bit, hence the inline assembly.  The compiler
 // does not count this store in its wait counters: a later wait that it places
 // for a load also covers the store (the vector-memory counter completes in
