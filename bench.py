@@ -412,9 +412,6 @@ def served_leg(G, wl, torch, np_, args):
         loads.append({"load": f, "offered_req_per_s": f * x, "batched": b,
                       "batched_prefix": {key: b_prefix[key] for key in ("req_per_s", "all", "append", "rw", "flatten")},
                       "per_request": p})
-        log(f"served load {f}: batched p50 {b['all']['p50_us']:.0f} us p99 {b['all']['p99_us']:.0f} us "
-            f"({b['req_per_s']:.3e} req/s, mean step {b['mean_step']:.0f}); per-request p99 "
-            f"{p['all']['p99_us']:.0f} us ({p['req_per_s']:.3e} req/s)")
     batched.close()
     per_req.close()
     fill.close()
@@ -653,7 +650,14 @@ def config3_leg(G, wl, torch, steps=3):
     """Configuration 3 at full size (irregular insertion): uint64, V = 65536,
     F = 1024, 2^26 threads with Poisson(3) counts capped at 16 (thresholds from the
     host), 4 insert phases each followed by r/w x + 1, then flatten.  Device time
-    per phase (HIP events), median over `steps` passes from an empty array."""
+    per phase (HIP events), median over `steps` passes from an empty array.
+
+    Two producers: gen mode (counts and payloads computed inside the insertion
+    kernel, which makes it bound by vector-ALU issue) and buffer mode, where the
+    same counts and payloads are prepared beforehand (untimed) and the round reads
+    them: counts from the host generator, payloads packed in thread order (the
+    flatten of one generated round into an empty array).  The two must give
+    identical arrays; buffer mode is the HBM-bound insertion roofline."""
     thr = wl.poisson_thresholds(3, 16)
     n, V = 1 << 26, 65536
     pool = G.Pool(16 << 30)
@@ -676,25 +680,68 @@ def config3_leg(G, wl, torch, steps=3):
                 a.rw(G.ADD1)
         with t.span("flatten"):
             a.flatten_into(out)
-        a.shrink(1, 1)
+        if rep < steps:
+            a.shrink(1, 1)
     torch.cuda.synchronize()
     assert a.last_error() == 0
-    a.close()
-    pool.close()
-    prev, phases = 0, []
+
+    # Buffer mode: the same rounds as prepared inputs.
+    pool2 = G.Pool(8 << 30)
+    scratch = G.GGArray(pool2, 8, V, 1024)
+    counts, packed = [], []
     for i in range(4):
-        ins = statistics.median(timer.ms(f"ins{i}"))
-        rw = statistics.median(timer.ms(f"rw{i}"))
-        added = sizes[i] - prev
-        prev = sizes[i]
-        phases.append({"inserted": added, "insert_us": 1e3 * ins, "insert_Gelem_s": added / (ins * 1e-3) / 1e9,
+        scratch.insert_gen(gens[i], n)
+        packed.append(scratch.flatten())
+        scratch.shrink(1, 1)
+        counts.append(torch.from_numpy(wl.poisson_counts(1, i, n, thr)).to("cuda"))
+        assert int(counts[-1].sum()) == packed[-1].numel()
+    scratch.close()
+    pool2.close()
+    b = G.GGArray(pool, 8, V, 1024)
+    out_b = torch.empty(sizes[-1], dtype=torch.int64, device="cuda")
+    tb = Timer(torch)
+    for rep in range(steps + 1):
+        t = tb if rep else Timer(torch)
+        for i in range(4):
+            with t.span(f"ins{i}"):
+                b.insert_packed(packed[i], counts[i])
+            with t.span(f"rw{i}"):
+                b.rw(G.ADD1)
+        with t.span("flatten"):
+            b.flatten_into(out_b)
+        if rep < steps:
+            b.shrink(1, 1)
+    torch.cuda.synchronize()
+    assert b.last_error() == 0
+    identical = bool(torch.equal(out, out_b))
+    b.close()
+    a.close()
+    del packed, counts, out, out_b
+    pool.close()
+
+    def phases_of(tm, with_rw=True):
+        prev, ph = 0, []
+        for i in range(4):
+            ins = statistics.median(tm.ms(f"ins{i}"))
+            rw = statistics.median(tm.ms(f"rw{i}"))
+            added = sizes[i] - prev
+            prev = sizes[i]
+            ph.append({"inserted": added, "insert_us": 1e3 * ins, "insert_Gelem_s": added / (ins * 1e-3) / 1e9,
                        "insert_GBps": 8 * added / (ins * 1e-3) / 1e9, "rw_us": 1e3 * rw,
                        "rw_GBps": 16 * sizes[i] / (rw * 1e-3) / 1e9})
+        return ph
+
+    phases = phases_of(timer)
+    bphases = phases_of(tb)
+    for p in bphases:  # algorithmic bytes of a buffer round: counts + payloads read, payloads written
+        p["insert_bytes"] = n + 16 * p["inserted"]
+        p["insert_traffic_GBps"] = p["insert_bytes"] / (p["insert_us"] * 1e-6) / 1e9
     fl = statistics.median(timer.ms("flatten"))
-    # The insertion is bound by vector-ALU issue (SplitMix64 per element): its roofline
-    # is the VALU instruction rate, from the committed counter summary (VALU wave
-    # instructions per launch, valid while the kernel sources are unchanged) over the
-    # live launch time, against 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+    # The generated insertion is bound by vector-ALU issue (SplitMix64 per element):
+    # its roofline is the VALU instruction rate, from the committed counter summary
+    # (VALU wave instructions per launch, valid while the kernel sources are
+    # unchanged) over the live launch time, against 256 CUs x 4 SIMDs x 16 lanes x
+    # 2.4 GHz.
     ins_us = statistics.median(p["insert_us"] for p in phases)
     valu = measured_counter(VALU_SUMMARY, "valu_per_launch", "insert")
     peak = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -703,9 +750,18 @@ def config3_leg(G, wl, torch, steps=3):
     if valu:
         roof["achieved"] = valu * 64 / (ins_us * 1e-6) / 1e12
         roof["frac"] = roof["achieved"] / peak
+    bus = statistics.median(p["insert_us"] for p in bphases)
+    bbytes = statistics.mean(p["insert_bytes"] for p in bphases)
+    broof = {"kernel": "insert_packed (tile sums + tile scan + insert_packed_kernel, one call)", "bound": "hbm",
+             "unit": "GB/s", "peak": HBM_PEAK_GBPS, "bytes_per_call": bbytes, "avg_call_us": bus,
+             "achieved": bbytes / (bus * 1e-6) / 1e9, "frac": bbytes / (bus * 1e-6) / 1e9 / HBM_PEAK_GBPS,
+             "timing": "events around the call (its three launches)"}
     return {"workload": "2^26 threads, Poisson(3) counts capped at 16, uint64 K(1,gid,16i+j), V = 65536, "
                         "4 x (insert, r/w x+1), flatten", "final_size": sizes[-1], "phases": phases,
-            "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9, "insert_roofline": roof}
+            "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9, "insert_roofline": roof,
+            "buffer_mode": {"phases": bphases, "insert_roofline": broof, "identical_to_gen_mode": identical,
+                            "inputs": "counts from the host generator, payloads packed in thread order "
+                                      "(prepared before the timed passes)"}}
 
 
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
@@ -1056,7 +1112,9 @@ def main():
             log("configuration 3: insert " + ", ".join(f"{p['insert_Gelem_s']:.1f}" for p in config3["phases"])
                 + f" Gelem/s (VALU issue {r3['frac'] if r3['frac'] is None else round(r3['frac'], 2)} of peak); "
                 + "r/w " + ", ".join(f"{p['rw_GBps']:.0f}" for p in config3["phases"])
-                + f" GB/s; flatten {config3['flatten_GBps']:.0f} GB/s")
+                + f" GB/s; flatten {config3['flatten_GBps']:.0f} GB/s; buffer mode insert "
+                + ", ".join(f"{p['insert_traffic_GBps']:.0f}" for p in config3["buffer_mode"]["phases"])
+                + f" GB/s (identical {config3['buffer_mode']['identical_to_gen_mode']})")
         except Exception as e:  # reported, never silently dropped
             config3 = {"error": str(e)}
             log(f"configuration-3 leg failed: {e}")
@@ -1120,7 +1178,84 @@ def main():
         "insertion_shootout": shootout,
         "memory_model": memory_model,
     }
-    print(json.dumps(line), flush=True)
+    # The full record goes to a file; stdout ends with one compact line (a few KB)
+    # that carries the headline, the roofline of the dominant kernel and the CPU
+    # baseline.
+    detail_path = write_detail(line)
+    print(json.dumps(headline(line, detail_path)), flush=True)
+
+
+def write_detail(line) -> str:
+    out_dir = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, "bench_detail.json")
+    with open(path, "w") as f:
+        json.dump(line, f, indent=1)
+    return os.path.relpath(path, ROOT)
+
+
+def _r(x, nd=4):
+    return None if x is None else round(float(x), nd)
+
+
+def headline(line, detail_path):
+    """The compact result line: contract keys, roofline, CPU baseline and the
+    headline comparisons (insert and r/w against the static array, batched and
+    served latency), each a number or null."""
+    k = line["kernels"]
+    roof = {key: (_r(v) if isinstance(v, float) else v) for key, v in line["roofline"].items()}
+    cpu = line["cpu_baseline"]
+    if cpu is not None:
+        cpu = {"value": _r(cpu["value"], 5), "unit": cpu["unit"], "cores": cpu["cores"], "kind": cpu["kind"],
+               "sample": cpu["sample"], "host_cpu": cpu["host_cpu"], "host_nproc": cpu["host_nproc"]}
+    head = {"insert_Gelem_s": _r(k["insert"]["Gelem_s"], 1), "rw_GBps": _r(k["rw"]["GBps"], 1),
+            "flatten_GBps": _r(k["flatten"]["GBps"], 1), "rw_frac": _r(k["rw"]["frac"]),
+            "flatten_frac": _r(k["flatten"]["frac"]), "insert_frac": _r(k["insert"]["frac"])}
+    bl = line.get("baselines") or {}
+    for key, src in (("static", bl.get("static")), ("static_closed_form", bl.get("static_closed_form"))):
+        if src:
+            head[key + "_insert_Gelem_s"] = _r(src.get("insert_Gelem_s"), 1)
+            head[key + "_rw_GBps"] = _r(src.get("rw_GBps"), 1)
+    c3 = line.get("config3") or {}
+    if "insert_roofline" in c3:
+        head["cfg3_insert_Gelem_s"] = _r(statistics.mean(p["insert_Gelem_s"] for p in c3["phases"]), 1)
+        head["cfg3_rw_GBps"] = _r(statistics.mean(p["rw_GBps"] for p in c3["phases"]), 1)
+        bm = c3.get("buffer_mode")
+        if bm:
+            head["cfg3_buffer_insert_GBps"] = _r(bm["insert_roofline"]["achieved"], 1)
+            head["cfg3_buffer_insert_frac"] = _r(bm["insert_roofline"]["frac"])
+            head["cfg3_buffer_identical"] = bm["identical_to_gen_mode"]
+    bt = (line.get("batched") or {}).get("timings")
+    if bt:
+        head["batched_ms"] = _r(bt["batched"]["mean_ms"], 3)
+        head["batched_graph_ms"] = _r(bt["batched_graph"]["mean_ms"], 3)
+        head["per_array_ms"] = _r(bt["per_array"]["mean_ms"], 3)
+    sv = line.get("served")
+    if sv:
+        head["served_saturation_req_s"] = _r(sv["saturation"]["req_per_s"], 0)
+        head["served_loads"] = [{"load": p["load"], "p50_us": _r(p["batched"]["all"]["p50_us"], 1),
+                                 "p99_us": _r(p["batched"]["all"]["p99_us"], 1)} for p in sv["loads"]]
+        m = sv.get("matched") or []
+        head["served_matched"] = [{"offered_req_s": _r(p["offered_req_per_s"], 0),
+                                   "batched_p50_us": _r(p["batched"]["all"]["p50_us"], 1),
+                                   "batched_p99_us": _r(p["batched"]["all"]["p99_us"], 1),
+                                   "per_request_p50_us": _r(p["per_request"]["all"]["p50_us"], 1),
+                                   "per_request_p99_us": _r(p["per_request"]["all"]["p99_us"], 1)} for p in m]
+    c1 = line.get("config1") or {}
+    if "step_us_eager" in c1:
+        head["cfg1_step_us"] = _r(c1["step_us_eager"], 1)
+    out = {key: line[key] for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                                      "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
+    out["value"] = _r(out["value"], 3)
+    out["ms_per_step"] = _r(out["ms_per_step"], 4)
+    out["config"] = line["config"]
+    out["roofline"] = roof
+    out["cpu_baseline"] = cpu
+    out["headline"] = head
+    out["parity_with_oracle"] = line["parity_with_oracle"]
+    out["ms_per_step_graph"] = _r(line["ms_per_step_graph"], 4)
+    out["detail"] = detail_path
+    return out
 
 
 if __name__ == "__main__":

@@ -161,6 +161,20 @@ int ggarray_insert(ggarray *a, const void *values, const uint8_t *flags, uint64_
 int ggarray_insert_counts(ggarray *a, const void *values, const uint8_t *counts,
                           uint32_t max_count, uint64_t n_threads, gga_stream s);
 
+/* ggarray_insert_packed: one insertion round in which logical thread gid inserts
+ *   counts[gid] elements (0..255; each thread's count enters the block prefix
+ *   sum of Sec. III-B), taken in order from a packed buffer: thread gid's
+ *   elements are values[P(gid) .. P(gid) + counts[gid]), P the exclusive prefix
+ *   sum of the counts (values: n_values elements, counts: n_threads bytes, both
+ *   device memory; for one round into an empty array the flatten equals the
+ *   first sum-of-counts values).  Because a tile's values and its outputs are
+ *   both contiguous, the round streams from the buffer into the buckets.  If the
+ *   counts sum to more than n_values nothing is inserted and the sticky
+ *   GGA_ERANGE is set.  The library keeps one offset word per 1024 logical
+ *   threads (grown like the look-back words: not during graph capture). */
+int ggarray_insert_packed(ggarray *a, const void *values, uint64_t n_values, const uint8_t *counts,
+                          uint64_t n_threads, gga_stream s);
+
 /* ggarray_insert_gen: one insertion round whose payloads are generated on the
  *   device by g (see GGA_GEN_*); `g` is a host pointer read before returning. */
 int ggarray_insert_gen(ggarray *a, const gga_gen *g, uint64_t n_threads, gga_stream s);
@@ -222,7 +236,11 @@ int ggarray_flatten(ggarray *a, void *out, uint64_t out_cap_elems, gga_stream s)
  *   written in that case too (the size of the committed contents). */
 int ggarray_size(ggarray *a, uint64_t *out_host, gga_stream s);
 
-/* ggarray_capacity: elements held by the allocated buckets, into *out_host.
+/* ggarray_capacity: elements held by the allocated buckets, into *out_host: the
+ *   memory side of the structure, which the paper bounds at about twice the live
+ *   data (abstract, Sec. V); exactly, each LFVector of s >= 1 elements holds
+ *   first_bucket * (2^nb - 1) <= 2 s + first_bucket - 1 elements, where nb is the
+ *   fewest buckets of Alg. 2 that reach s, and an empty LFVector holds none.
  *   Synchronises s. */
 int ggarray_capacity(ggarray *a, uint64_t *out_host, gga_stream s);
 
@@ -253,8 +271,22 @@ int ggarray_kernel_timing(ggarray *a, uint32_t on);
 int ggarray_kernel_ms(ggarray *a, uint32_t kind, float *ms);
 
 /* ggarray_last_error: the sticky device error of the array (GGA_OK if none).
- *   Synchronises s.  Does not clear it. */
+ *   Synchronises s.  Does not clear it.  The paper's growth (Alg. 2) does not say
+ *   what happens when an allocation fails; here a failed bucket allocation drops
+ *   the round of the affected LFVector, freezes it and sets GGA_ENOMEM, a bounded
+ *   wait that expires sets GGA_EHIP, and a flatten into a too-small buffer sets
+ *   GGA_ERANGE; the first error is kept until the array is destroyed. */
 int ggarray_last_error(ggarray *a, gga_stream s);
+
+/* ggarray_set_spin_limit: a failure-handling aid.  Every wait of an insertion
+ *   kernel on another workgroup (look-back, a bucket pointer, allocation counts)
+ *   gives up after `polls` polls (0 restores the default, 2^22), freezes the
+ *   LFVector it serves and sets the sticky GGA_EHIP; a tiny limit forces that
+ *   path from the host while every kernel still ends normally.  Applies to later
+ *   single-array calls on `a` (batches and servers copy the array's descriptor
+ *   when they are created).  After such an expiry the frozen LFVectors' contents
+ *   are unspecified; every other LFVector holds exactly its round. */
+int ggarray_set_spin_limit(ggarray *a, uint32_t polls);
 
 /* ------------------------------------------------------ device-side API --- */
 /* For user kernels that push elements themselves with gga::block_push_back

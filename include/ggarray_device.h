@@ -83,6 +83,8 @@ struct ArrRef {
   uint32_t V;
   uint32_t log2F;
   uint32_t salt;         // spreads the pool shards of different arrays
+  uint32_t spin;         // polls before a bounded wait gives up (kSpinLimit; a
+                         // failure-handling test may lower it from the host)
 };
 
 // ------------------------------------------------------------------ atomics --
@@ -393,7 +395,7 @@ __device__ uint64_t block_push_back(const ArrRef& A, uint32_t v, bool keep, T va
             st_rlx(slot, p);
           } else {
             uint32_t spins = 0;
-            while ((p = ld_rlx(slot)) == 0 && spins < kSpinLimit) {
+            while ((p = ld_rlx(slot)) == 0 && spins < A.spin) {
               ++spins;
               spin_pause();
             }

@@ -58,6 +58,7 @@ def lib():
             "orc_insert": (i32, [vp, vp, vp, u64]),
             "orc_insert_counts": (i32, [vp, vp, vp, u32, u64]),
             "orc_insert_segments": (i32, [vp, vp, vp, u64]),
+            "orc_insert_packed": (i32, [vp, vp, u64, vp, u64]),
             "orc_insert_gen": (i32, [vp, u32, u64, u32, u32, u32, vp, u64, u64]),
             "orc_shrink": (i32, [vp, u32, u32]),
             "orc_rw": (i32, [vp, u32]),
@@ -163,6 +164,13 @@ class Oracle:
         assert values.size == counts.size * max_count
         self._chk(lib().orc_insert_counts(self._h, _ptr(values), _ptr(counts), max_count,
                                           counts.size), "insert_counts")
+
+    def insert_packed(self, values: np.ndarray, counts: np.ndarray) -> int:
+        """Thread g inserts counts[g] elements, the next ones of `values` in thread
+        order; returns the status (ERANGE when the counts need more values)."""
+        values = np.ascontiguousarray(values, dtype=self.dtype)
+        counts = np.ascontiguousarray(counts, dtype=np.uint8)
+        return int(lib().orc_insert_packed(self._h, _ptr(values), values.size, _ptr(counts), counts.size))
 
     def insert_segments(self, values: np.ndarray, prefix: np.ndarray) -> int:
         """LFVector v appends values[prefix[v]:prefix[v + 1]]; returns the status

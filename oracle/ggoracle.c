@@ -323,6 +323,39 @@ int orc_insert_counts(orc_array *a, const void *values, const uint8_t *counts, u
     return ORC_OK;
 }
 
+/* Packed buffer mode: thread gid inserts counts[gid] elements, the next ones of
+ * `values` in thread order (the values of all threads lie back to back, so thread
+ * gid's are values[P .. P + counts[gid]) with P the sum of the counts before it).
+ * The multi-element insertion of Sec. III-B with another input layout.  Counts
+ * asking for more than n_values values: ORC_ERANGE, nothing inserted. */
+int orc_insert_packed(orc_array *a, const void *values, uint64_t n_values, const uint8_t *counts,
+                      uint64_t n_threads)
+{
+    if (!a || (n_threads && !counts) || (n_values && !values))
+        return ORC_EINVAL;
+    uint64_t total = 0;
+    for (uint64_t gid = 0; gid < n_threads; gid++)
+        total += counts[gid];
+    if (total > n_values)
+        return ORC_ERANGE;
+    if (n_threads == 0)
+        return ORC_OK;
+    uint64_t chunk = chunk_len(n_threads, a->n_vectors);
+    uint64_t next = 0; /* index of the next value to take */
+    for (uint32_t v = 0; v < a->n_vectors; v++) {
+        uint64_t g0 = (uint64_t)v * chunk;
+        uint64_t g1 = g0 + chunk < n_threads ? g0 + chunk : n_threads;
+        for (uint64_t gid = g0; gid < g1; gid++) {
+            for (uint32_t j = 0; j < counts[gid]; j++) {
+                int st = push(a, v, load_elem(values, a->elem_bytes, next++));
+                if (st)
+                    return st;
+            }
+        }
+    }
+    return ORC_OK;
+}
+
 /* Segment append (restoring a flat snapshot): LFVector v appends
  * values[prefix[v] .. prefix[v + 1]).  An LFVector whose pair decreases, runs past
  * n_values or spans 2^32 elements or more keeps its contents and the call returns

@@ -191,6 +191,12 @@ int gga_pool_set_fault(gga_pool* p, uint64_t fault_at, gga_stream s) {
   return GGA_OK;
 }
 
+int ggarray_set_spin_limit(ggarray* a, uint32_t polls) {
+  if (!a) return GGA_EINVAL;
+  a->ref.spin = polls ? polls : gga::kSpinLimit;
+  return GGA_OK;
+}
+
 // ------------------------------------------------------------------- GGArray --
 int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_vectors,
                    uint64_t first_bucket, gga_stream s) {
@@ -247,6 +253,7 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.V = n_vectors;
   R.log2F = a->log2F;
   R.salt = (uint32_t)((reinterpret_cast<uintptr_t>(a->meta) >> 8) * 2654435761u) & (kFreeShards - 1);
+  R.spin = kSpinLimit;
   a->status_cap = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed
   a->size_ub = 0;
@@ -263,6 +270,8 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   a->tev_set = 0;
   a->meta_bytes = off;
   a->retired_tab_bytes = 0;
+  a->pk_off = nullptr;
+  a->pk_cap = 0;
   p->n_arrays += 1;
   *out = a;
   return GGA_OK;
@@ -274,6 +283,7 @@ int ggarray_destroy(ggarray* a, gga_stream s) {
   int rc = launch_free_all(a, S(s));
   if (a->ref.status && hipFreeAsync(a->ref.status, S(s)) != hipSuccess) rc = GGA_EHIP;
   if (a->tile_tab && hipFreeAsync(a->tile_tab, S(s)) != hipSuccess) rc = GGA_EHIP;
+  if (a->pk_off && hipFreeAsync(a->pk_off, S(s)) != hipSuccess) rc = GGA_EHIP;
   for (uint32_t i = 0; i < a->n_retired; ++i)
     if (hipFreeAsync(a->retired[i], S(s)) != hipSuccess) rc = GGA_EHIP;
   if (hipStreamSynchronize(S(s)) != hipSuccess) rc = GGA_EHIP;
@@ -310,6 +320,12 @@ int ggarray_insert_counts(ggarray* a, const void* values, const uint8_t* counts,
   d.max_count = max_count;
   d.n_threads = n_threads;
   return launch_insert(a, d, S(s));
+}
+
+int ggarray_insert_packed(ggarray* a, const void* values, uint64_t n_values, const uint8_t* counts,
+                          uint64_t n_threads, gga_stream s) {
+  if (!a || (n_threads && !counts) || (n_values && !values)) return GGA_EINVAL;
+  return launch_insert_packed(a, values, counts, n_threads, n_values, S(s));
 }
 
 int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_stream s) {
@@ -423,7 +439,7 @@ int ggarray_capacity(ggarray* a, uint64_t* out_host, gga_stream s) {
 int ggarray_footprint(ggarray* a, uint64_t out[3]) {
   if (!a || !out) return GGA_EINVAL;
   out[0] = a->meta_bytes;
-  out[1] = a->status_cap * sizeof(uint64_t);
+  out[1] = (a->status_cap + a->pk_cap) * sizeof(uint64_t);
   out[2] = 16 * a->tab_cap + a->retired_tab_bytes;
   return GGA_OK;
 }

@@ -43,6 +43,8 @@ struct ggarray {
   uint32_t tev_set;       // bit k: events of kind k were recorded by a dispatch
   uint64_t meta_bytes;    // size of the metadata allocation
   uint64_t retired_tab_bytes;  // outgrown tile tables kept until destroy
+  uint64_t* pk_off;       // device: per-tile value offsets of packed rounds (+ total)
+  uint64_t pk_cap;        // words pk_off holds
 };
 
 // Hands an outgrown device buffer to the array, to be freed with it.
@@ -349,6 +351,8 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_nu
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);
+int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
+                         uint64_t n_values, hipStream_t s);
 int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
                            hipStream_t s);  // copy: also write the prefix there
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s);

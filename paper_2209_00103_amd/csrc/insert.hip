@@ -37,7 +37,7 @@ constexpr int kW = kB / 64;              // waves per workgroup
 constexpr int kFlagTile = (int)kInsertTile;  // logical threads per tile, 0/1 producers (one wave)
 constexpr int kCountK = 4;               // candidates per thread, multi-element producers
 constexpr int kCountTile = kB * kCountK; // 1024 logical threads per tile
-constexpr uint32_t kOwnWindow = 4096;     // outputs per owner-map pass
+constexpr uint32_t kOwnWindow = 8192;     // outputs per owner-map pass (16-bit entries, 16 KiB)
 
 // Look-back status word: epoch (30 bits) | flag (2 bits) | value (32 bits).  The
 // value is a count or an inclusive prefix relative to the LFVector's size at the
@@ -73,6 +73,7 @@ struct TileShared {
   uint32_t nb;
   uint32_t n_tile;
   uint32_t writable;   // static baseline: elements that fit
+  uint32_t frozen;     // the LFVector's frozen flag as the block read it
   uint32_t cnt[64];
 };
 
@@ -183,7 +184,7 @@ struct ProdPoisson {  // c = #{k : K(seed,gid,0x80|round) >= thr[k]}; insert K(s
 // published; the nearest predecessor with an inclusive prefix ends the search.
 // Returns false if a bounded wait expired.
 __device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint64_t epoch,
-                         uint64_t& out) {
+                         uint32_t limit, uint64_t& out) {
   const uint32_t lane = lane_id();
   const int64_t lo = (int64_t)(tile - t);
   int64_t hi = (int64_t)tile - 1;
@@ -197,7 +198,7 @@ __device__ bool lookback(const uint64_t* status, uint64_t tile, uint64_t t, uint
       for (uint32_t spins = 0;; ++spins) {
         w = ld_rlx(&status[mine]);
         if (status_current(w, epoch)) break;
-        if (spins >= kSpinLimit) {
+        if (spins >= limit) {
           ok = false;
           break;
         }
@@ -247,7 +248,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
   } else {
     uint64_t rel = 0;
     if (lane == 0 && !is_last) st_rlx(&A.status[tile], pack_status(epoch, kStA, n_t));
-    stalled = !lookback(A.status, tile, t, epoch, rel);
+    stalled = !lookback(A.status, tile, t, epoch, A.spin, rel);
     if (lane == 0 && !is_last && !stalled)
       st_rlx(&A.status[tile], pack_status(epoch, kStP, rel + n_t));
     base = old_size + rel;
@@ -283,7 +284,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
           failed = !q;
         } else {
           uint32_t spins = 0;
-          while ((p = ld_rlx(slot)) == 0 && spins < kSpinLimit) {
+          while ((p = ld_rlx(slot)) == 0 && spins < A.spin) {
             ++spins;
             spin_pause();
           }
@@ -301,7 +302,10 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
     n_alloc = (uint32_t)__popcll(__ballot(allocated));
     n_fail = (uint32_t)__popcll(__ballot(failed));
     if (lane == 0 && n_fail) set_error(A.err, kErrNoMem);
-    if (lane == 0 && __ballot(late)) set_error(A.err, kErrStall);
+    if (lane == 0 && __ballot(late)) {  // elements of this tile stay unwritten: freeze
+      set_error(A.err, kErrStall);
+      st_rlx32(&A.dead[v], 1u);
+    }
     if (lane == 0 && n_alloc && !is_last) fetch_add32(&A.alloc_done[v], n_alloc | (n_fail << 16));
   }
 
@@ -312,7 +316,7 @@ __device__ WaveRes resolve_wave(const ArrRef& A, const TileArgs& I, uint32_t v, 
     uint32_t failed = n_fail;
     if (others) {
       uint32_t done, spins = 0;
-      while (((done = ld_rlx32(&A.alloc_done[v])) & 0xFFFFu) < others && spins < kSpinLimit) {
+      while (((done = ld_rlx32(&A.alloc_done[v])) & 0xFFFFu) < others && spins < A.spin) {
         ++spins;
         spin_pause();
       }
@@ -838,11 +842,14 @@ __global__ __launch_bounds__(256) void static_atomic_kernel(StaticRef S, uint64_
 // Thread tid owns logical threads g0 + 4 tid .. g0 + 4 tid + 3 (blocked), so a
 // plain scan of per-thread counts orders the elements.  Once the tile's first
 // index is known, each thread writes, for each of its outputs, who produces it
-// (thread, logical thread, element number) into an LDS owner map; output q
-// (consecutive across lanes, so stores coalesce) then reads its entry, produces
-// the element and stores it.  One LDS write and one read per element replace a
-// binary search over the 256 prefixes per element; the map covers 4096 outputs
-// at a time (16 KiB), more rarely needing further passes.
+// into an LDS owner map of 16-bit entries (tid << 6 | j << 4 | r: element r of
+// logical thread 4 tid + j).  The outputs are then produced in output order by
+// consecutive lanes (no divergence from uneven counts), a segment per bucket run:
+// element stores up to the first 128-byte line of the run, then 16-byte
+// non-temporal stores of VPL consecutive outputs per lane that cover whole lines
+// across the wave (partial lines left by element-wise stores cost about 5% extra
+// HBM writes, measured), then the ragged tail.  Bucket and offset are computed
+// once per run, not per element.  The map covers 8192 outputs at a time.
 template <typename Prod>
 __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt, uint64_t gend,
                                                    uint32_t* cnt) {
@@ -855,10 +862,44 @@ __device__ __forceinline__ uint32_t produce_counts(const Prod& prod, uint64_t gt
   return c;
 }
 
+// Outputs own[0 .. n) of a run, stored at dst (element-aligned).
+template <typename T, class Prod>
+__device__ __forceinline__ void store_owned_run(T* dst_, const uint16_t* own, uint32_t n, const Prod& prod,
+                                                uint64_t g0) {
+  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T);
+  const uint32_t tid = threadIdx.x;
+  const gptr<T> dst = gmem(dst_);
+  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst_) & 127u) / sizeof(T));
+  uint32_t head = mis ? kLine - mis : 0u;
+  if (head > n) head = n;
+  if (tid < head) {
+    const uint32_t o = own[tid];
+    __builtin_nontemporal_store(prod.value(g0 + (o >> 4), o & 15u), dst + tid);
+  }
+  const uint32_t nv = (n - head) / VPL;
+  for (uint32_t q = tid; q < nv; q += kB) {
+    const uint32_t e = head + q * VPL;
+    T tmp[VPL];
+#pragma unroll
+    for (uint32_t k = 0; k < VPL; ++k) {
+      const uint32_t o = own[e + k];
+      tmp[k] = prod.value(g0 + (o >> 4), o & 15u);
+    }
+    u32x4 x;
+    __builtin_memcpy(&x, tmp, 16);
+    __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dst + e));
+  }
+  const uint32_t tail = head + nv * VPL + tid;
+  if (tail < n) {
+    const uint32_t o = own[tail];
+    __builtin_nontemporal_store(prod.value(g0 + (o >> 4), o & 15u), dst + tail);
+  }
+}
+
 template <typename T, class Prod, bool kStatic>
 __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S, TileArgs I,
                                                           Prod prod) {
-  __shared__ uint32_t s_own[kOwnWindow];  // output -> (thread, logical thread, element)
+  __shared__ uint16_t s_own[kOwnWindow];  // output -> (thread, logical thread, element)
   __shared__ TileShared sh;
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const bool ticketed = !kStatic && I.tpv > 1;
@@ -889,12 +930,16 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
     c = produce_counts<Prod>(prod, gt, gend, cnt);
   }
   if (g0 >= gend) return;
-  if (!kStatic && ld_rlx32(&A.dead[v])) return;
   const bool is_last = g0 + kCountTile >= gend;
 
   const uint32_t incl = wave_incl_scan(c);
   if (lane == 63) sh.cnt[w] = incl;
+  // One read of the frozen flag for the whole block: another tile of this
+  // LFVector may set it during this launch (a stalled look-back), and waves that
+  // read it at different moments would disagree on whether the tile runs.
+  if (!kStatic && tid == 0) sh.frozen = ld_rlx32(&A.dead[v]);
   __syncthreads();
+  if (!kStatic && sh.frozen) return;  // block-uniform
   uint32_t before = 0, n_t = 0;
 #pragma unroll
   for (int q = 0; q < kW; ++q) {
@@ -915,26 +960,196 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
   for (uint32_t w0 = 0; w0 < n_out; w0 += kOwnWindow) {
     const uint32_t w1 = n_out - w0 < kOwnWindow ? n_out : w0 + kOwnWindow;
     if (w0) __syncthreads();  // the previous window has been read
-    // Each thread names itself as the owner of its outputs in this window.
+    // Each thread names itself as the producer of its outputs in this window.
     uint32_t e = excl - w0;  // wraps for outputs before the window, which fail the test
 #pragma unroll
-    for (uint32_t j = 0; j < (uint32_t)kCountK; ++j)
+    for (uint32_t j = 0; j < (uint32_t)kCountK; ++j) {
+      const uint32_t ent = (tid << 6) | (j << 4);
       for (uint32_t r = 0; r < cnt[j]; ++r, ++e)
-        if (e < kOwnWindow) s_own[e] = (tid << 10) | (j << 8) | r;
-    __syncthreads();
-    for (uint32_t q = w0 + tid; q < w1; q += kB) {
-      const uint32_t o = s_own[q - w0];
-      const T val = prod.value(g0 + (uint64_t)(o >> 10) * kCountK + ((o >> 8) & 3u), o & 0xFFu);
-      if (kStatic) {
-        gmem(reinterpret_cast<T*>(S.data))[base + q] = val;
-      } else {
-        const uint64_t idx = base + q;
-        const uint32_t b = bucket_of(log2F, idx);
-        const uint64_t p = sh.bp[b - sh.b_lo];
-        // non-temporal: configuration 3 measured insertion +1-3% and the r/w after it +3-6%
-        if (p > kFailedPtr) __builtin_nontemporal_store(val, gmem(reinterpret_cast<T*>(p)) + offset_in(log2F, idx, b));
-      }
+        if (e < kOwnWindow) s_own[e] = (uint16_t)(ent | r);
     }
+    __syncthreads();
+    if (kStatic) {
+      store_owned_run<T, Prod>(reinterpret_cast<T*>(S.data) + base + w0, s_own, w1 - w0, prod, g0);
+      continue;
+    }
+    for (uint32_t i = w0; i < w1;) {  // one run per bucket the window's outputs reach
+      const uint64_t idx = base + i;
+      const uint32_t b = bucket_of(log2F, idx);
+      const uint64_t bs = bucket_start(log2F, b);
+      const uint64_t room = bs + bucket_len(log2F, b) - idx;
+      const uint32_t run = (uint64_t)(w1 - i) < room ? w1 - i : (uint32_t)room;
+      const uint64_t p = sh.bp[b - sh.b_lo];
+      if (p > kFailedPtr) store_owned_run<T, Prod>(reinterpret_cast<T*>(p) + (idx - bs), s_own + (i - w0), run, prod, g0);
+      i += run;
+    }
+  }
+}
+
+// ------------------------------------------- packed multi-element producer --
+// Thread gid inserts counts[gid] elements taken in order from a packed buffer:
+// its elements are values[P(gid) .. P(gid) + counts[gid]), P the exclusive prefix
+// of the counts over all threads.  Tiles are those of the multi-element kernel
+// (1024 logical threads, numbered LFVector by LFVector), so a tile's values are
+// contiguous in the buffer, and its outputs are contiguous in its LFVector: once
+// the tile knows where its values start (tile_off, from the two pre-passes below)
+// and its first index (the look-back), the round is a copy from one contiguous
+// range into at most a few bucket runs.  No per-element arithmetic is left.
+
+// Pre-pass 1: the count total of every tile.
+__global__ __launch_bounds__(kB) void packed_tile_sums_kernel(TileArgs I, const uint8_t* counts, uint64_t* tile_sum) {
+  __shared__ uint64_t wsum[kW];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint32_t v = (uint32_t)(blockIdx.x / I.tpv);
+  const uint64_t t = blockIdx.x - (uint64_t)v * I.tpv;
+  uint64_t g0, gend;
+  tile_range(I, v, t, kCountTile, g0, gend);
+  uint64_t c = 0;
+  for (uint32_t j = 0; j < (uint32_t)kCountK; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * kB + tid;  // coalesced byte loads
+    if (g < gend) c += counts[g];
+  }
+  c = wave_sum64(c);
+  if (lane == 0) wsum[w] = c;
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t sum = 0;
+    for (int q = 0; q < kW; ++q) sum += wsum[q];
+    tile_sum[blockIdx.x] = sum;
+  }
+}
+
+// Pre-pass 2: exclusive prefix of the tile totals in place (one workgroup of 1024
+// threads, 8 consecutive tiles per thread and pass); entry ntiles gets the total.
+__global__ __launch_bounds__(1024) void packed_tile_scan_kernel(uint64_t* tile_off, uint64_t ntiles) {
+  __shared__ uint64_t wtot[16];
+  __shared__ uint64_t carry_s;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < ntiles; base += 8192) {
+    uint64_t x[8], sum = 0;
+    const uint64_t i0 = base + (uint64_t)tid * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      x[k] = i0 + k < ntiles ? tile_off[i0 + k] : 0;
+      sum += x[k];
+    }
+    const uint64_t incl = wave_incl_scan64(sum);
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    uint64_t before = carry, all = carry;
+    for (uint32_t q = 0; q < 16; ++q) {
+      before += q < w ? wtot[q] : 0;
+      all += wtot[q];
+    }
+    uint64_t run = before + incl - sum;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (i0 + k < ntiles) tile_off[i0 + k] = run;
+      run += x[k];
+    }
+    carry = all;
+    __syncthreads();  // wtot is reused by the next pass
+  }
+  if (tid == 0) carry_s = carry;
+  __syncthreads();
+  if (tid == 0) tile_off[ntiles] = carry_s;
+}
+
+// n elements from src to dst by one workgroup: element stores up to the first
+// 128-byte line boundary of dst, then 16-byte non-temporal stores that each
+// cover whole lines across the wave (the loads take src's alignment), then the
+// ragged tail.
+template <typename T>
+__device__ __forceinline__ void block_copy(T* dst_, const T* src_, uint32_t n) {
+  typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
+  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T), kU = 4;
+  const uint32_t tid = threadIdx.x;
+  const gptr<T> dst = gmem(dst_);
+  const gptr<const T> src = gmem(src_);
+  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst_) & 127u) / sizeof(T));
+  uint32_t head = mis ? kLine - mis : 0u;
+  if (head > n) head = n;
+  if (tid < head) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tid), dst + tid);
+  const uint32_t nv = (n - head) / VPL;
+  uint32_t q = tid;
+  for (; q + (kU - 1) * kB < nv; q += kU * kB) {  // kU vectors in flight per thread
+    u32x4 x[kU];
+#pragma unroll
+    for (uint32_t k = 0; k < kU; ++k)
+      x[k] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + (q + k * kB) * VPL));
+#pragma unroll
+    for (uint32_t k = 0; k < kU; ++k)
+      __builtin_nontemporal_store(x[k], reinterpret_cast<gptr<u32x4>>(dst + head + (q + k * kB) * VPL));
+  }
+  for (; q < nv; q += kB) {
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + q * VPL));
+    __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+  }
+  const uint32_t tail = head + nv * VPL + tid;
+  if (tail < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tail), dst + tail);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kB) void insert_packed_kernel(ArrRef A, TileArgs I, const T* values, const uint8_t* counts,
+                                                           const uint64_t* tile_off, uint64_t ntiles,
+                                                           uint64_t n_values) {
+  __shared__ TileShared sh;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const bool ticketed = I.tpv > 1;
+  const uint32_t v = (uint32_t)(blockIdx.x / I.tpv);
+  uint64_t t = blockIdx.x - (uint64_t)v * I.tpv;
+  uint64_t k = 0;
+  if (ticketed && tid == 0) k = take_ticket(A, v);
+  uint64_t g0, gend;
+  tile_range(I, v, t, kCountTile, g0, gend);
+  if (ticketed && tid == 0) {
+    sh.tile = k;
+    settle_ticket(A, v, k, I.tpv);
+  }
+  __syncthreads();
+  const uint64_t epoch = ticketed ? sh.tile >> 32 : 0;
+  if (ticketed && (sh.tile & 0xFFFFFFFFull) != t) {  // dispatched out of order: take the ticket's tile
+    t = sh.tile & 0xFFFFFFFFull;
+    tile_range(I, v, t, kCountTile, g0, gend);
+  }
+  // Every block takes and settles its ticket before this uniform exit, so the
+  // LFVectors' epochs advance as in any other launch.
+  if (tile_off[ntiles] > n_values) {  // the counts ask for more values than given
+    if (blockIdx.x == 0 && tid == 0) set_error(A.err, kErrRange);
+    return;
+  }
+  if (g0 >= gend) return;
+  const bool is_last = g0 + kCountTile >= gend;
+  uint32_t c = 0;
+  for (uint32_t j = 0; j < (uint32_t)kCountK; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * kB + tid;
+    if (g < gend) c += counts[g];
+  }
+  c = (uint32_t)wave_sum64(c);
+  if (lane == 0) sh.cnt[w] = c;
+  if (tid == 0) sh.frozen = ld_rlx32(&A.dead[v]);
+  __syncthreads();
+  if (sh.frozen) return;  // block-uniform
+  uint32_t n_t = 0;
+#pragma unroll
+  for (int q = 0; q < kW; ++q) n_t += sh.cnt[q];
+  const uint64_t tile = (uint64_t)v * I.tpv + t;
+  if (w == 0) resolve_tile(A, I, v, t, tile, is_last, n_t, epoch, sh);
+  __syncthreads();
+  const uint32_t n_out = sh.n_tile;  // 0 if stalled
+  const uint64_t base = sh.base;
+  const T* src = values + tile_off[tile];
+  const uint32_t log2F = A.log2F;
+  for (uint32_t i = 0; i < n_out;) {  // one run per bucket the tile's outputs reach
+    const uint64_t idx = base + i;
+    const uint32_t b = bucket_of(log2F, idx);
+    const uint64_t bs = bucket_start(log2F, b);
+    const uint64_t room = bs + bucket_len(log2F, b) - idx;
+    const uint32_t run = (uint64_t)(n_out - i) < room ? n_out - i : (uint32_t)room;
+    const uint64_t p = sh.bp[b - sh.b_lo];
+    if (p > kFailedPtr) block_copy<T>(reinterpret_cast<T*>(p) + (idx - bs), src + i, run);
+    i += run;
   }
 }
 
@@ -1125,6 +1340,56 @@ int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefi
   else
     hipLaunchKernelGGL(segments_kernel<uint64_t>, grid, block, 0, s, a->ref, I, static_cast<const uint64_t*>(values),
                        prefix, n_values);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) sizes_changed(a, s);
+  return hip_status(e);
+}
+
+// Per-tile value offsets of a packed round: ntiles + 1 words, grown like the
+// look-back words (nothing is allocated while the stream is capturing).
+static int ensure_packed_offsets(ggarray* a, uint64_t words, hipStream_t s) {
+  if (words <= a->pk_cap) return GGA_OK;
+  if (stream_capturing(s)) return GGA_EINVAL;
+  uint64_t cap = a->pk_cap ? a->pk_cap : 4096;
+  while (cap < words) cap *= 2;
+  if (retire_buffer(a, a->pk_off, s) != GGA_OK) return GGA_EHIP;
+  a->pk_off = nullptr;
+  a->pk_cap = 0;
+  void* p = nullptr;
+  if (hipMallocAsync(&p, cap * sizeof(uint64_t), s) != hipSuccess) return GGA_EHIP;
+  a->pk_off = static_cast<uint64_t*>(p);
+  a->pk_cap = cap;
+  return GGA_OK;
+}
+
+int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
+                         uint64_t n_values, hipStream_t s) {
+  a->tev_set &= ~4u;  // not a timed round
+  if (n_threads == 0) return GGA_OK;
+  const uint64_t chunk = (n_threads + a->V - 1) / a->V;
+  const uint64_t tpv = (chunk + kCountTile - 1) / kCountTile;
+  const uint64_t ntiles = tpv * a->V;
+  if (ntiles > 0x7FFFFFFFull || chunk * 255u >= (1ull << 32)) return GGA_EINVAL;
+  if (tpv > 1) {
+    const int rc = ensure_status(a, ntiles, s);
+    if (rc) return rc;
+  }
+  int rc = ensure_packed_offsets(a, ntiles + 1, s);
+  if (rc) return rc;
+  TileArgs I{};
+  I.n_threads = n_threads;
+  I.chunk = chunk;
+  I.tpv = tpv;
+  I.elem_log2 = a->elem_log2;
+  grow_bound(a, n_values);
+  hipLaunchKernelGGL(packed_tile_sums_kernel, dim3((uint32_t)ntiles), dim3(kB), 0, s, I, counts, a->pk_off);
+  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, a->pk_off, ntiles);
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL(insert_packed_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
+                       static_cast<const uint32_t*>(values), counts, (const uint64_t*)a->pk_off, ntiles, n_values);
+  else
+    hipLaunchKernelGGL(insert_packed_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
+                       static_cast<const uint64_t*>(values), counts, (const uint64_t*)a->pk_off, ntiles, n_values);
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);

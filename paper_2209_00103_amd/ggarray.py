@@ -56,10 +56,12 @@ _SIGS = {
     "ggarray_destroy": [_vp, _vp],
     "ggarray_insert": [_vp, _vp, _vp, _u64, _vp],
     "ggarray_insert_counts": [_vp, _vp, _vp, _u32, _u64, _vp],
+    "ggarray_insert_packed": [_vp, _vp, _u64, _vp, _u64, _vp],
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
     "ggarray_kernel_timing": [_vp, _u32],
+    "ggarray_set_spin_limit": [_vp, _u32],
     "ggarray_kernel_ms": [_vp, _u32, _P(ctypes.c_float)],
     "ggarray_rw": [_vp, _u32, _vp],
     "ggarray_flatten": [_vp, _vp, _u64, _vp],
@@ -255,6 +257,14 @@ class GGArray:
         _check(lib().ggarray_insert_gen(self._h, ctypes.byref(gen), int(n_threads), _stream(stream)),
                "ggarray_insert_gen")
 
+    def insert_packed(self, values: torch.Tensor, counts: torch.Tensor, n_values=None, stream=None):
+        """Thread g inserts counts[g] elements, the next ones of `values` (packed in thread order)."""
+        n = counts.numel()
+        nv = values.numel() if n_values is None else int(n_values)
+        vp = _dev_ptr(values, "values", nv, self.elem_bytes) if nv else None
+        cp = _dev_ptr(counts, "counts", n, 1)
+        _check(lib().ggarray_insert_packed(self._h, vp, nv, cp, n, _stream(stream)), "ggarray_insert_packed")
+
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().ggarray_shrink(self._h, num, den, _stream(stream)), "ggarray_shrink")
 
@@ -355,6 +365,9 @@ class GGArray:
 
     def last_error(self, stream=None) -> int:
         return int(lib().ggarray_last_error(self._h, _stream(stream)))
+
+    def set_spin_limit(self, polls: int):
+        _check(lib().ggarray_set_spin_limit(self._h, int(polls)), "ggarray_set_spin_limit")
 
     def close(self, stream=None):
         if self._h:

@@ -60,6 +60,18 @@ int main(void)
                         for (uint64_t i = 0; i < n; i++)
                             counts[i] = (uint8_t)(rnd() % 20);
                         CHECK(orc_insert_counts(a, vals, counts, mx, n) == ORC_OK);
+                        /* the same counts (up to 19) against the packed layout: enough
+                         * values, then one value short of them */
+                        uint64_t need = 0;
+                        for (uint64_t i = 0; i < n; i++)
+                            need += counts[i];
+                        uint64_t *pk = (uint64_t *)malloc(8 * (need + 1));
+                        for (uint64_t i = 0; i < need; i++)
+                            pk[i] = rnd();
+                        CHECK(orc_insert_packed(a, pk, need, counts, n) == ORC_OK);
+                        if (need)
+                            CHECK(orc_insert_packed(a, pk, need - 1, counts, n) == ORC_ERANGE);
+                        free(pk);
                         free(vals);
                         free(counts);
                     } else if (kind == 2) {

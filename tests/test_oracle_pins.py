@@ -74,7 +74,7 @@ def _closed_form(F, idx):
 @pytest.mark.parametrize("logF", range(0, 15))
 def test_walk_equals_closed_form_exhaustive(logF):
     F = 1 << logF
-    n = 1 << 16
+    n = 1 << 22
     idx = np.arange(n, dtype=np.uint64)
     b, off = oracle.walk_many(F, idx)
     p = idx + np.uint64(F)
@@ -206,6 +206,60 @@ def test_insert_counts_clamps_to_max_count():
     vals = np.arange(6, dtype=np.uint32)  # 2 threads x 3 slots
     o.insert_counts(vals, np.array([7, 255], dtype=np.uint8), 3)
     assert o.flatten().tolist() == [0, 1, 2, 3, 4, 5]
+
+
+def test_insert_packed_hand():
+    """4 threads, V = 2 (threads 0,1 -> LFVector 0; 2,3 -> LFVector 1), packed values
+    taken in thread order: LFVector 0 gets thread 0's two and thread 1's none, then
+    LFVector 1 thread 2's three and thread 3's one."""
+    o = Oracle(4, 2, 4)
+    vals = np.array([10, 11, 20, 21, 22, 30, 99], dtype=np.uint32)
+    assert o.insert_packed(vals, np.array([2, 0, 3, 1], dtype=np.uint8)) == oracle.OK
+    assert o.vector_sizes().tolist() == [2, 4]
+    assert o.flatten().tolist() == [10, 11, 20, 21, 22, 30]
+    assert o.check() == 0
+
+
+@pytest.mark.parametrize("elem,V,n", [(4, 1, 5000), (8, 7, 20011), (4, 300, 257), (8, 64, 100000)])
+def test_insert_packed_one_round_is_identity(elem, V, n):
+    """Chunks are contiguous and LFVectors flatten in order, so one round into an
+    empty array flattens to exactly the first sum(counts) values, and LFVector v
+    holds the sum of its chunk's counts."""
+    rng = np.random.default_rng(V + n)
+    counts = rng.integers(0, 256, size=n, dtype=np.uint8)
+    counts[rng.random(n) < 0.3] = 0
+    total = int(counts.sum(dtype=np.uint64))
+    vals, _ = wl.random_round(rng, total + 5, 1.0, elem)
+    o = Oracle(elem, V, 8)
+    assert o.insert_packed(vals, counts) == oracle.OK
+    assert np.array_equal(o.flatten(), vals[:total])
+    chunk = -(-n // V)
+    sizes = np.zeros(V, dtype=np.uint64)
+    np.add.at(sizes, np.arange(n) // chunk, counts.astype(np.uint64))
+    assert np.array_equal(o.vector_sizes(), sizes)
+    assert o.check() == 0
+
+
+def test_insert_packed_too_few_values_inserts_nothing():
+    o = Oracle(8, 3, 2)
+    vals = np.arange(5, dtype=np.uint64)
+    assert o.insert_packed(vals, np.array([2, 2, 2], dtype=np.uint8)) == oracle.ERANGE
+    assert o.size() == 0 and o.capacity() == 0
+
+
+def test_insert_packed_equals_counts_layout():
+    """The same insertions given as counts with a padded layout (thread g's j-th
+    element at g * max + j) and as a packed buffer give the same array."""
+    rng = np.random.default_rng(3)
+    n, mc = 9000, 16
+    counts = rng.integers(0, mc + 1, size=n, dtype=np.uint8)
+    padded, _ = wl.random_round(rng, n * mc, 1.0, 8)
+    packed = np.concatenate([padded[g * mc:g * mc + int(counts[g])] for g in range(n)])
+    a, b = Oracle(8, 11, 16), Oracle(8, 11, 16)
+    a.insert_counts(padded, counts, mc)
+    assert b.insert_packed(packed, counts) == oracle.OK
+    assert np.array_equal(a.flatten(), b.flatten())
+    assert np.array_equal(a.vector_sizes(), b.vector_sizes())
 
 
 # ---------------------------------------------------------------------------
