@@ -84,6 +84,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def stage(name):
+    """A short progress mark on stderr as each leg starts (names the leg that was
+    running if the process ends early)."""
+    print(f"[{time.strftime('%H:%M:%S')}] {name}", file=sys.stderr, flush=True)
+
+
 def ceiling_leg(torch, n_small=None, reps=10):
     """Achievable streaming rates on this GPU with plain PyTorch kernels over 4 GiB:
     a write-only fill, a copy (4 GiB read, 4 GiB written) and an in-place add (the
@@ -395,14 +401,18 @@ def served_leg(G, wl, torch, np_, args):
     k_b = min(n, int(args.serve_baseline_requests))
     sat_pr = run(per_req, zeros, k_b)
     x = sat["req_per_s"]
-    # a load the per-request baseline can sustain: half its own saturation rate
-    low_rate = 0.5 * sat_pr["req_per_s"]
-    low_arrival = wl.cfg5_arrivals_ns(tr["gap"], low_rate)
-    low = {"offered_req_per_s": low_rate, "batched": run(batched, low_arrival, k_b),
-           "per_request": run(per_req, low_arrival, k_b)}
-    log(f"served at {low_rate:.3e} req/s: batched p50 {low['batched']['all']['p50_us']:.0f} us p99 "
-        f"{low['batched']['all']['p99_us']:.0f} us; per-request p50 {low['per_request']['all']['p50_us']:.0f} us "
-        f"p99 {low['per_request']['all']['p99_us']:.0f} us")
+    # loads the per-request baseline can sustain: 0.5 and 0.9 of its own saturation
+    # rate, both modes on the same requests
+    matched = []
+    for f in (0.5, 0.9):
+        rate = f * sat_pr["req_per_s"]
+        arrival = wl.cfg5_arrivals_ns(tr["gap"], rate)
+        m = {"load_of_per_request_saturation": f, "offered_req_per_s": rate,
+             "batched": run(batched, arrival, k_b), "per_request": run(per_req, arrival, k_b)}
+        matched.append(m)
+        log(f"served at {rate:.3e} req/s: batched p50 {m['batched']['all']['p50_us']:.0f} us p99 "
+            f"{m['batched']['all']['p99_us']:.0f} us; per-request p50 {m['per_request']['all']['p50_us']:.0f} us "
+            f"p99 {m['per_request']['all']['p99_us']:.0f} us")
     loads = []
     for f in cfg["loads"]:
         arrival = wl.cfg5_arrivals_ns(tr["gap"], f * x)
@@ -424,7 +434,7 @@ def served_leg(G, wl, torch, np_, args):
             "resident_initial_GB": ELEM * sum(sizes) / 1e9, "appended_GB": ELEM * int(length.sum()) / 1e9,
             "lanes": args.serve_lanes, "max_step": args.serve_step,
             "baseline": f"one launch per request, in order, on the first {k_b} requests, at most 1024 in flight",
-            "saturation": sat, "saturation_per_request": sat_pr, "low_load": low, "loads": loads}
+            "saturation": sat, "saturation_per_request": sat_pr, "matched": matched, "loads": loads}
 
 
 def mapped_baseline(G, torch, gens, rounds, steps):
@@ -452,68 +462,147 @@ def mapped_baseline(G, torch, gens, rounds, steps):
             "maps": maps, "timing": "host wall clock (growth synchronises)"}
 
 
-def two_phase_leg(G, torch, rounds, gens, V, ks=(1, 10, 100, 1000)):
-    """The two-phase pattern of Sec. VI-D: a growth phase (the configuration-2
-    rounds, 2^28 uint32 insertions with shrink 1/10) then a work phase of k passes
-    of x = x + 1 over the result.  Three ways: (a) GGArray, flatten, work on the
-    flat copy; (b) GGArray, work on the GGArray itself; (c) the mapped array, work
-    on it.  Device time of the whole pattern (HIP events), one run per k."""
-    out = {}
+def sparse_leg(G, torch, rounds, V, steps, warmup):
+    """The configuration-2 round sizes with Bernoulli(1/2) insertion instead of
+    every thread inserting: the GGArray takes its scan path (wave ballot, per-
+    LFVector tickets and decoupled look-back, Sec. III-B), the static array one
+    atomic per tile of 4096 threads.  Per round: inserted elements (4 B written
+    each) over the device time of the insertion call."""
+    gens = [G.make_gen(G.GEN_BERNOULLI, seed=1, round=r) for r in range(len(rounds))]
     pool = G.Pool(8 << 30)
     arr = G.GGArray(pool, ELEM, V, F)
-    flat = None
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def grow():
-        for r, n in enumerate(rounds):
-            arr.insert_gen_shrink(gens[r], n, 1, 10)
-
-    grow()  # warm-up (sizes the flat buffer, loads every kernel once)
-    size = arr.size()
-    flat = torch.empty(size, dtype=torch.int32, device="cuda")
-    arr.flatten_into(flat)
-    flat.add_(1)
-    arr.rw(G.ADD1)
+    added, prev = [], 0
+    for r, n in enumerate(rounds):  # sizing pass: elements each round inserts
+        arr.insert_gen(gens[r], n)
+        s1 = arr.size()
+        added.append(s1 - prev)
+        arr.shrink(1, 10)
+        prev = arr.size()
     arr.shrink(1, 1)
-    mp = G.MappedArray(ELEM, 1 << 28)
-    mp.insert_gen(gens[0], rounds[0])
-    mp.rw(G.ADD1)
-    mp.close()
-    for k in ks:
-        row = {}
-        for mode in ("flatten_then_static", "ggarray"):
-            torch.cuda.synchronize()
-            e0.record()
-            grow()
-            if mode == "flatten_then_static":
-                arr.flatten_into(flat)
-                for _ in range(k):
-                    flat.add_(1)
+    st = G.StaticArray(1 << 28, ELEM)
+    res = {}
+    for name in ("ggarray", "static"):
+        tm = Timer(torch)
+        for rep in range(warmup + steps):
+            t = tm if rep >= warmup else Timer(torch)
+            for r, n in enumerate(rounds):
+                with t.span(f"r{r}"):
+                    if name == "ggarray":
+                        arr.insert_gen(gens[r], n)
+                    else:
+                        st.insert_gen(gens[r], n)
+                if name == "ggarray":
+                    arr.shrink(1, 10)
+            if name == "ggarray":
+                arr.shrink(1, 1)
             else:
-                for _ in range(k):
-                    arr.rw(G.ADD1)
-            e1.record()
-            torch.cuda.synchronize()
-            row[mode + "_ms"] = e0.elapsed_time(e1)
-            arr.shrink(1, 1)
-        mp = G.MappedArray(ELEM, 1 << 28)
+                st.clear()
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for r, n in enumerate(rounds):
-            mp.insert_gen(gens[r], n)
-        for _ in range(k):
-            mp.rw(G.ADD1)
-        torch.cuda.synchronize()
-        row["mapped_ms_wall"] = (time.perf_counter() - t0) * 1e3
-        mp.close()
-        row["speedup_flatten_vs_mapped"] = row["mapped_ms_wall"] / row["flatten_then_static_ms"]
-        out[str(k)] = row
+        ms = [statistics.median(tm.ms(f"r{r}")) for r in range(len(rounds))]
+        res[name] = {"per_round_us": [round(1e3 * x, 2) for x in ms],
+                     "per_round_GBps": [round(ELEM * a / (x * 1e-3) / 1e9, 1) for a, x in zip(added, ms)],
+                     "Gelem_s": sum(added) / (sum(ms) * 1e-3) / 1e9,
+                     "last_round_GBps": ELEM * added[-1] / (ms[-1] * 1e-3) / 1e9}
+    assert arr.last_error() == 0 and st.last_error() == 0
+    st.close()
     arr.close()
     pool.close()
-    return {"workload": "growth: configuration-2 rounds (2^28 uint32, shrink 1/10 per round; the mapped array "
-                        "has no shrink); work: k passes of x + 1", "k": out,
-            "note": "(a) and (b) device time between events; (c) host wall clock, since mapping synchronises; "
-                    "the flat copy's work pass is torch's in-place add"}
+    res["inserted_per_round"] = added
+    res["insert_vs_static"] = res["ggarray"]["Gelem_s"] / res["static"]["Gelem_s"]
+    res["workload"] = ("configuration-2 round sizes (2^17, 2^17 .. 2^27 threads), each thread inserting "
+                       "K(1,gid,r) with probability 1/2; GGArray V = 512 (shrink 1/10 after each round, untimed) "
+                       "against the static array (one atomic per 4096-thread tile)")
+    return res
+
+
+def two_phase_leg(G, torch, V, ms=(1, 3, 10), ks=(1, 10, 100, 1000), iters=5, final=10**9):
+    """The two-phase application of Sec. VI-D: `iters` repetitions of a growth
+    phase, in which each of the s live elements' threads inserts m more (m rounds of
+    s threads, round-tag payloads), followed by a work phase of k passes of x + 1
+    over every element.  The starting size is final / (1 + m)^iters, so every m
+    ends at `final` uint32.  Three ways, each timed by device events around the
+    whole pattern: (a) the GGArray grows, is flattened into a flat buffer, and the
+    work runs there; (b) the work runs on the GGArray itself (its own r/w); (c) the
+    mapped array grows (host-driven mapping, which synchronises) and the work runs
+    on it.  (a) and (c) use the same work kernel (the flat-array r/w); the host
+    time (c) spends mapping is reported beside it."""
+    out = {}
+    pool = G.Pool(10 << 30)
+    arr = G.GGArray(pool, ELEM, V, F)
+    flat_buf = torch.empty(final, dtype=torch.int32, device="cuda")
+    flat = G.StaticArray(final, ELEM, buf=flat_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    tag = 24  # round-tag payloads (round << 24) | gid; gid < 2^24 is not needed for timing
+
+    def sizes_for(m):
+        s0 = max(1, round(final / (1 + m) ** iters))
+        return s0, [s0 * (1 + m) ** i for i in range(iters)]
+
+    def grow_gg(m, s_before, r0):
+        for j in range(m):
+            arr.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=(r0 + j) & 0xFF, tag_shift=tag), s_before)
+
+    rows = {}
+    for m in ms:
+        s0, starts = sizes_for(m)
+        for k in ks:
+            row = {}
+            for mode in ("flatten_then_work", "ggarray_work"):
+                arr.shrink(1, 1)
+                arr.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=0, tag_shift=tag), s0)
+                torch.cuda.synchronize()
+                e0.record()
+                for it, s_before in enumerate(starts):
+                    grow_gg(m, s_before, 1 + it * m)
+                    if mode == "flatten_then_work":
+                        n_live = s_before * (1 + m)
+                        arr.flatten_into(flat_buf[:n_live])
+                        flat.set_size(n_live)
+                        for _ in range(k):
+                            flat.rw(G.ADD1)
+                    else:
+                        for _ in range(k):
+                            arr.rw(G.ADD1)
+                e1.record()
+                torch.cuda.synchronize()
+                row[mode + "_ms"] = e0.elapsed_time(e1)
+            assert arr.last_error() == 0 and arr.size() == starts[-1] * (1 + m)
+            mp = G.MappedArray(ELEM, final + (final >> 4))
+            mp.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=0, tag_shift=tag), s0)
+            torch.cuda.synchronize()
+            map_host = 0.0
+            e0.record()
+            t_all = time.perf_counter()
+            for it, s_before in enumerate(starts):
+                for j in range(m):
+                    t = time.perf_counter()
+                    mp.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=(1 + it * m + j) & 0xFF, tag_shift=tag),
+                                  s_before)
+                    map_host += time.perf_counter() - t
+                for _ in range(k):
+                    mp.rw(G.ADD1)
+            e1.record()
+            torch.cuda.synchronize()
+            row["mapped_ms"] = e0.elapsed_time(e1)
+            row["mapped_wall_ms"] = (time.perf_counter() - t_all) * 1e3
+            row["mapped_insert_host_ms"] = map_host * 1e3
+            row["mapped_maps"] = mp.maps()
+            assert mp.size() == starts[-1] * (1 + m)
+            mp.close()
+            row["speedup_flatten_vs_mapped"] = row["mapped_ms"] / row["flatten_then_work_ms"]
+            row["speedup_ggarray_vs_mapped"] = row["mapped_ms"] / row["ggarray_work_ms"]
+            rows[f"m{m}_k{k}"] = row
+        out[str(m)] = {"start_size": s0, "final_size": starts[-1] * (1 + m)}
+    flat.close()
+    arr.close()
+    pool.close()
+    return {"workload": f"{iters} repetitions of (growth: each live element's thread inserts m more, "
+                        f"m in {list(ms)}; work: k passes of x + 1), final size {final} uint32, "
+                        f"GGArray V = {V}, F = {F}",
+            "sizes": out, "rows": rows,
+            "timing": "device events around the whole pattern on every side; (c)'s growth synchronises the host "
+                      "(mapping), its host time inside the insert calls is mapped_insert_host_ms",
+            "work_kernel": "(a) and (c): the flat-array r/w (one workgroup per 16 KiB tile); (b): the GGArray r/w"}
 
 
 def shootout_leg(G, torch, reps=3):
@@ -801,6 +890,7 @@ def main():
     from paper_2209_00103_amd import workloads as wl
 
     torch.cuda.set_device(0)
+    stage("configuration 2")
     V = args.vectors
     rounds = wl.cfg2_round_threads()
     gens = [G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=TAG_SHIFT) for r in range(len(rounds))]
@@ -997,6 +1087,7 @@ def main():
 
     ceilings = None
     if not args.no_ceiling:
+        stage("plain-kernel ceilings")
         ceilings = ceiling_leg(torch, final_size)
         ceilings["flatten_over_copy"] = kernels["flatten"]["GBps"] / ceilings["copy"]["GBps"]
         ceilings["rw_over_inplace_add"] = kernels["rw"]["GBps"] / ceilings["inplace_add"]["GBps"]
@@ -1013,6 +1104,7 @@ def main():
     # host-resized array, same insertion rounds (they have no shrink) and r/w.
     baselines = None
     if not args.no_baselines:
+        stage("baselines")
         baselines = {}
         st = G.StaticArray(1 << 28, ELEM)
         for rep in range(args.warmup + args.steps):
@@ -1066,11 +1158,24 @@ def main():
             f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s; mapped "
             f"{baselines['mapped'].get('insert_Gelem_s', baselines['mapped'].get('error'))}")
 
+    sparse = None
+    if not args.no_baselines:
+        stage("sparse rounds")
+        try:
+            sparse = sparse_leg(G, torch, rounds, V, args.steps, args.warmup)
+            log(f"sparse rounds: ggarray {sparse['ggarray']['Gelem_s']:.1f} Gelem/s (last round "
+                f"{sparse['ggarray']['last_round_GBps']:.0f} GB/s), static {sparse['static']['Gelem_s']:.1f} "
+                f"Gelem/s (last round {sparse['static']['last_round_GBps']:.0f} GB/s)")
+        except Exception as e:  # reported, never silently dropped
+            sparse = {"error": str(e)}
+            log(f"sparse leg failed: {e}")
+
     footprint_end = arr.footprint()  # after the timed steps: the tile table has been built
     arr.close()
     pool.close()
     batched = None
     if not args.no_batched:
+        stage("batched")
         batched = batched_leg(G, wl, torch, np, args.steps, args.warmup)
         t = batched["timings"]
         log(f"batched: one launch per phase {t['batched']['mean_ms']:.3f} ms (graph {t['batched_graph']['mean_ms']:.3f}),"
@@ -1078,6 +1183,7 @@ def main():
             f" identical {batched['batched_equals_per_array']}")
     shootout = memory_model = None
     if not args.no_shootout:
+        stage("shootout, memory model")
         try:
             shootout = shootout_leg(G, torch)
             log("shootout scan/atomic speedup: " + ", ".join(f"2^{20 + i}: {r['scan_speedup']:.2f}"
@@ -1095,6 +1201,7 @@ def main():
             log(f"memory model failed: {e}")
     config1 = None
     if not args.no_config1:
+        stage("configuration 1")
         try:
             config1 = config1_leg(G, wl, torch)
             o1 = config1["ops"]
@@ -1106,6 +1213,7 @@ def main():
             log(f"configuration-1 leg failed: {e}")
     config3 = None
     if not args.no_config3:
+        stage("configuration 3")
         try:
             config3 = config3_leg(G, wl, torch)
             r3 = config3["insert_roofline"]
@@ -1120,16 +1228,17 @@ def main():
             log(f"configuration-3 leg failed: {e}")
     two_phase = None
     if not args.no_two_phase:
+        stage("two-phase")
         try:
-            two_phase = two_phase_leg(G, torch, rounds, gens, V)
-            log("two-phase: " + "; ".join(f"k={k}: flatten+static {r['flatten_then_static_ms']:.2f} ms, ggarray "
-                                          f"{r['ggarray_ms']:.2f} ms, mapped {r['mapped_ms_wall']:.2f} ms"
-                                          for k, r in two_phase["k"].items()))
+            two_phase = two_phase_leg(G, torch, V)
+            log("two-phase speedup flatten+work vs mapped: " + ", ".join(
+                f"{key} {r['speedup_flatten_vs_mapped']:.2f}" for key, r in two_phase["rows"].items()))
         except Exception as e:  # reported, never silently dropped
             two_phase = {"error": str(e)}
             log(f"two-phase leg failed: {e}")
     served = None
     if not args.no_served:
+        stage("served")
         served = served_leg(G, wl, torch, np, args)
         log(f"served: saturation {served['saturation']['req_per_s']:.3e} req/s; " + "; ".join(
             f"{p['load']}x p50 {p['batched']['all']['p50_us']:.0f} us p99 {p['batched']['all']['p99_us']:.0f} us"
@@ -1138,6 +1247,7 @@ def main():
     cpu = None
     parity = None
     if not args.no_cpu:
+        stage("cpu oracle")
         rate, secs, reps, ref = cpu_baseline(rounds, V)
         got = G.as_unsigned(out)
         parity = bool(got.shape == ref.shape and np.array_equal(got, ref))
@@ -1160,6 +1270,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "baselines": baselines,
+        "sparse_rounds": sparse,
         "memory": {"capacity_elems": capacity, "live_elems": final_size, "capacity_over_live": capacity / final_size,
                    "per_round": mem_rounds,
                    "pool_bytes_in_use": pool_stats["in_use"], "pool_high_water": pool_stats["high_water"],
@@ -1212,10 +1323,21 @@ def headline(line, detail_path):
             "flatten_GBps": _r(k["flatten"]["GBps"], 1), "rw_frac": _r(k["rw"]["frac"]),
             "flatten_frac": _r(k["flatten"]["frac"]), "insert_frac": _r(k["insert"]["frac"])}
     bl = line.get("baselines") or {}
-    for key, src in (("static", bl.get("static")), ("static_closed_form", bl.get("static_closed_form"))):
+    for key, src in (("static", bl.get("static")),):
         if src:
             head[key + "_insert_Gelem_s"] = _r(src.get("insert_Gelem_s"), 1)
             head[key + "_rw_GBps"] = _r(src.get("rw_GBps"), 1)
+    sp = line.get("sparse_rounds") or {}
+    if "ggarray" in sp:
+        head["sparse_insert_Gelem_s"] = _r(sp["ggarray"]["Gelem_s"], 1)
+        head["sparse_static_insert_Gelem_s"] = _r(sp["static"]["Gelem_s"], 1)
+        head["sparse_last_round_GBps"] = _r(sp["ggarray"]["last_round_GBps"], 1)
+    if bl.get("static"):
+        # like for like: both sides timed by events around the calls (dispatch included)
+        ins_span = (1 << 28) / (k["insert"]["launches_per_step"] * k["insert"]["span_us"] * 1e-6) / 1e9
+        rw_span = k["rw"]["bytes_per_launch"] / (k["rw"]["span_us"] * 1e-6) / 1e9
+        head["insert_vs_static"] = _r(ins_span / bl["static"]["insert_Gelem_s"], 3)
+        head["rw_vs_static"] = _r(rw_span / bl["static"]["rw_GBps"], 3)
     c3 = line.get("config3") or {}
     if "insert_roofline" in c3:
         head["cfg3_insert_Gelem_s"] = _r(statistics.mean(p["insert_Gelem_s"] for p in c3["phases"]), 1)

@@ -441,6 +441,10 @@ int gga_static_size(gga_static *st, uint64_t *out_host, gga_stream s); /* synchr
 int gga_static_last_error(gga_static *st, gga_stream s);                /* synchronises */
 /* Empties the array and clears its sticky error (the buffer is kept).  Queued. */
 int gga_static_clear(gga_static *st, gga_stream s);
+/* Sets the size to n <= capacity (the first n elements of the buffer become the
+ *   live ones), e.g. after the buffer was filled by a GGArray flatten for a work
+ *   phase (the two-phase use of Sec. VI-C, VI-D).  Queued.  EINVAL past the capacity. */
+int gga_static_set_size(gga_static *st, uint64_t n, gga_stream s);
 
 /* ----------------------------------------- semi-static array baseline ------ */
 /* The host-resized array of Sec. III-A2: before each insertion round the host

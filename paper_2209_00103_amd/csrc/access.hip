@@ -22,9 +22,6 @@ constexpr uint32_t kScanThreads = 1024;
 // (4.47 TB/s at 2048, 4.70 at 16384, 5.13 at 32768, 5.27 at 65536).
 constexpr uint32_t kRwBlocks = 8192;
 constexpr uint32_t kFlattenBlocks = 65536;
-// The static-array baseline streams a flat buffer; it measured best with
-// non-temporal loads and 2048 workgroups (5.04 TB/s), and runs that way.
-constexpr uint32_t kStaticBlocks = 2048;
 // Table-driven r/w and flatten of one array: one workgroup per tile, up to this
 // many workgroups, looping beyond (configuration 2: flatten 5.33 -> 5.7 TB/s
 // against the search-located persistent grid).
@@ -458,22 +455,20 @@ __global__ __launch_bounds__(kRwThreads) void stream_table_kernel(ArrRef A, cons
   }
 }
 
-// Static / semi-static array r/w: the flat array cut into 16 KiB tiles, each
-// workgroup streaming a contiguous share of them (the same access pattern as the
-// GGArray r/w, without the bucket indirection).
-template <typename T>
+// Static / semi-static array r/w: the flat array cut into 16 KiB tiles, workgroup
+// w streaming tiles w, w + G, ... (the same access pattern as the GGArray r/w
+// through its tile table, without the bucket indirection).
+template <typename T, bool kNtLoad>
 __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const uint64_t* size,
                                                               uint64_t cap, uint32_t op, uint32_t te_log2) {
   uint64_t n = *size;
   if (n > cap) n = cap;
   const uint64_t te = 1ull << te_log2;
   const uint64_t total = (n + te - 1) >> te_log2;
-  const uint64_t G = gridDim.x;
-  const uint64_t t0 = total * blockIdx.x / G, t1 = total * (blockIdx.x + 1) / G;
-  for (uint64_t t = t0; t < t1; ++t) {
+  for (uint64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const uint64_t e0 = t << te_log2;
     const uint64_t rem = n - e0;
-    stream_tile<T, false, true>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
+    stream_tile<T, false, kNtLoad>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
   }
 }
 
@@ -822,13 +817,31 @@ int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
   return hip_status(hipGetLastError());
 }
 
+// The static array's r/w in the GGArray's launch shape: one workgroup per 16 KiB
+// tile of the capacity (up to kTableBlocks, looping beyond; workgroups past the
+// live tiles exit at once) and the same load policy (through the cache after an
+// insertion, streaming after an r/w), so that only the layout differs.
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
-  if (st->elem_bytes == 4)
-    hipLaunchKernelGGL((static_rw_kernel<uint32_t>), dim3(kStaticBlocks), dim3(kRwThreads), 0, s,
-                       static_cast<uint32_t*>(st->data), st->d_size, st->cap, op, 12u);
-  else
-    hipLaunchKernelGGL((static_rw_kernel<uint64_t>), dim3(kStaticBlocks), dim3(kRwThreads), 0, s,
-                       static_cast<uint64_t*>(st->data), st->d_size, st->cap, op, 11u);
+  const uint32_t te_log2 = st->elem_bytes == 4 ? 12u : 11u;
+  uint64_t tiles = (st->cap + (1ull << te_log2) - 1) >> te_log2;
+  const dim3 grid((uint32_t)(tiles < 1 ? 1 : (tiles > kTableBlocks ? kTableBlocks : tiles))), block(kRwThreads);
+  const bool nt = st->rw_last;
+  if (st->elem_bytes == 4) {
+    if (nt)
+      hipLaunchKernelGGL((static_rw_kernel<uint32_t, true>), grid, block, 0, s, static_cast<uint32_t*>(st->data),
+                         st->d_size, st->cap, op, te_log2);
+    else
+      hipLaunchKernelGGL((static_rw_kernel<uint32_t, false>), grid, block, 0, s, static_cast<uint32_t*>(st->data),
+                         st->d_size, st->cap, op, te_log2);
+  } else {
+    if (nt)
+      hipLaunchKernelGGL((static_rw_kernel<uint64_t, true>), grid, block, 0, s, static_cast<uint64_t*>(st->data),
+                         st->d_size, st->cap, op, te_log2);
+    else
+      hipLaunchKernelGGL((static_rw_kernel<uint64_t, false>), grid, block, 0, s, static_cast<uint64_t*>(st->data),
+                         st->d_size, st->cap, op, te_log2);
+  }
+  st->rw_last = true;
   return hip_status(hipGetLastError());
 }
 

@@ -619,6 +619,8 @@ static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_by
   uint8_t* m = static_cast<uint8_t*>(st->meta);
   st->d_size = reinterpret_cast<uint64_t*>(m);
   st->d_err = reinterpret_cast<uint32_t*>(m + 16);
+  st->d_done = reinterpret_cast<uint32_t*>(m + 32);
+  st->rw_last = false;
   return GGA_OK;
 }
 
@@ -706,6 +708,17 @@ int gga_static_clear(gga_static* st, gga_stream s) {
   if (hipMemsetAsync(st->d_size, 0, 8, S(s)) != hipSuccess ||
       hipMemsetAsync(st->d_err, 0, 4, S(s)) != hipSuccess)
     return GGA_EHIP;
+  st->rw_last = false;
+  return GGA_OK;
+}
+
+int gga_static_set_size(gga_static* st, uint64_t n, gga_stream s) {
+  if (!st || n > st->cap) return GGA_EINVAL;
+  if (hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(st->d_size), (int)(uint32_t)n, 1, S(s)) != hipSuccess ||
+      hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(reinterpret_cast<uint32_t*>(st->d_size) + 1),
+                        (int)(uint32_t)(n >> 32), 1, S(s)) != hipSuccess)
+    return GGA_EHIP;
+  st->rw_last = false;
   return GGA_OK;
 }
 

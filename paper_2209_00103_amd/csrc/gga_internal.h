@@ -97,9 +97,11 @@ struct gga_static {
   void* data;
   uint64_t cap;
   uint32_t elem_bytes;
-  void* meta;          // device block: size counter, sticky error
+  void* meta;          // device block: size counter, sticky error, round completion count
   uint64_t* d_size;
   uint32_t* d_err;
+  uint32_t* d_done;
+  bool rw_last;        // the last operation was an r/w (its loads then stream past the caches)
 };
 
 namespace gga {

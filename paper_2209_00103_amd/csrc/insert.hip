@@ -63,6 +63,7 @@ struct StaticRef {
   uint64_t cap;
   uint64_t* size;
   uint32_t* err;
+  uint32_t* done;  // waves of the current closed-form round that have finished
 };
 
 struct TileShared {
@@ -713,7 +714,14 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
   }
   const uint64_t fin = I.sh_den ? shrink_keep(s0 + cnt, I.sh_num, I.sh_den) : s0 + cnt;
   if (lane == 0) A.size[v] = fin;
-  const uint32_t n = (uint32_t)cnt;
+  // With a fused shrink, elements that would land in a bucket the shrink releases
+  // are popped anyway: they are not stored, so no store of this wave can still be
+  // in flight to a bucket when it goes back to the pool (whose link word the
+  // release writes), and the release needs no fence.
+  const uint32_t keep = nbuckets_for(log2F, fin);
+  uint64_t upto = s0 + cnt;
+  if (I.sh_den && bucket_start(log2F, keep) < upto) upto = bucket_start(log2F, keep) > s0 ? bucket_start(log2F, keep) : s0;
+  const uint32_t n = (uint32_t)(upto - s0);
   for (uint32_t i = 0; i < n;) {
     const uint64_t idx = s0 + i;
     const uint32_t bk = bucket_of(log2F, idx);
@@ -724,13 +732,8 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
     dense_store<T, Prod>(reinterpret_cast<T*>(p) + (idx - bs), prod, c0 + i, run);
     i += run;
   }
-  if (I.sh_den) {  // the fused shrink: release the buckets past the kept elements
-    const uint32_t keep = nbuckets_for(log2F, fin);
-    if (keep < hi) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the element stores land before a bucket is handed back
-      release_bucket(A, v, lane, keep, hi, held, mine, I.elem_log2);
-    }
-  }
+  if (I.sh_den && keep < hi)  // the fused shrink: release the buckets past the kept elements
+    release_bucket(A, v, lane, keep, hi, held, mine, I.elem_log2);
 }
 
 // The round's share of LFVector v: logical threads [v chunk, v chunk + chunk).
@@ -817,6 +820,35 @@ __global__ __launch_bounds__(64) void batch_dense_kernel(const BatchArr* items, 
   Prod p = prod;
   p.bind(it);
   store_tile<T, Prod>(it.A, item_args(it), p, blk - begins[i]);
+}
+
+// --------------------------------------- static array, closed-form rounds --
+// A round in which every thread inserts has its positions in closed form on the
+// static array too: thread g of the round lands at size + g.  One wave per tile of
+// 4096 threads stores its run exactly as the GGArray's dense rounds do (16-byte
+// non-temporal stores on whole 128-byte lines), so the two layouts are compared
+// on the same algorithm.  Every wave reads the size before the round (nothing
+// changes it during the launch); the last wave to finish moves it.  Elements past
+// the capacity are dropped with the sticky GGA_ERANGE, and the size counts them,
+// as in the atomic rounds.
+template <typename T, class Prod>
+__global__ __launch_bounds__(64) void static_dense_kernel(StaticRef S, uint64_t n, uint64_t ntiles, Prod prod) {
+  const uint32_t lane = lane_id();
+  const uint64_t base = ld_rlx(S.size);
+  const uint64_t g0 = (uint64_t)blockIdx.x * kWaveTile;
+  const uint32_t cnt = n - g0 < (uint64_t)kWaveTile ? (uint32_t)(n - g0) : (uint32_t)kWaveTile;
+  const uint64_t pos = base + g0;
+  const uint32_t lim = pos < S.cap ? (S.cap - pos < cnt ? (uint32_t)(S.cap - pos) : cnt) : 0u;
+  if (lim) dense_store<T, Prod>(reinterpret_cast<T*>(S.data) + pos, prod, g0, lim);
+  if (lane == 0) {
+    if (lim < cnt) set_error(S.err, kErrRange);
+    // The size read above completed before the stores were issued, so every wave
+    // counted here has read it.
+    if (fetch_add32(S.done, 1u) == ntiles - 1) {
+      st_rlx(S.size, base + n);
+      st_rlx32(S.done, 0u);
+    }
+  }
 }
 
 // ------------------------------------ static array, one atomic per element --
@@ -1396,8 +1428,9 @@ int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, 
 }
 
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {
+  st->rw_last = false;
   if (d.n_threads == 0) return GGA_OK;
-  StaticRef S{st->data, st->cap, st->d_size, st->d_err};
+  StaticRef S{st->data, st->cap, st->d_size, st->d_err, st->d_done};
   uint64_t blocks = (d.n_threads + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   const dim3 grid((uint32_t)blocks), block(256);
@@ -1421,15 +1454,44 @@ int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t
   return hip_status(hipGetLastError());
 }
 
+template <typename T>
+int launch_static_dense(const StaticRef& S, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
+  const dim3 grid((uint32_t)ntiles), block(64);
+  switch (d.mode) {
+    case kModeBuffer:
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdBuffer<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+                         ProdBuffer<T>{static_cast<const T*>(d.values), nullptr});
+      break;
+    case kModeRoundTag:
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+                         ProdRoundTag<T>{d.round, d.tag_shift});
+      break;
+    case kModeKeyed:
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdKeyed<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+                         ProdKeyed<T>{d.seed, d.round, d.tag_shift, d.tag});
+      break;
+    default:
+      return GGA_EINVAL;
+  }
+  return hip_status(hipGetLastError());
+}
+
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
+  st->rw_last = false;
   if (d.n_threads == 0) return GGA_OK;
   const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
   const uint64_t ntiles = (d.n_threads + tile - 1) / tile;
   if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;
+  const bool dense = d.mode == kModeRoundTag || d.mode == kModeKeyed || (d.mode == kModeBuffer && !d.flags);
+  if (dense) {
+    StaticRef S{st->data, st->cap, st->d_size, st->d_err, st->d_done};
+    return st->elem_bytes == 4 ? launch_static_dense<uint32_t>(S, d, ntiles, s)
+                               : launch_static_dense<uint64_t>(S, d, ntiles, s);
+  }
   TileArgs I{};
   I.n_threads = d.n_threads;
   I.elem_log2 = st->elem_bytes == 4 ? 2u : 3u;
-  StaticRef S{st->data, st->cap, st->d_size, st->d_err};
+  StaticRef S{st->data, st->cap, st->d_size, st->d_err, st->d_done};
   ArrRef A{};
   const int rc = st->elem_bytes == 4 ? dispatch<uint32_t, true>(A, S, I, d, ntiles, s)
                                      : dispatch<uint64_t, true>(A, S, I, d, ntiles, s);

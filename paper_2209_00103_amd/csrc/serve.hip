@@ -224,6 +224,11 @@ int run_batched(RunState& R) {
   std::vector<uint64_t> begins;
   std::vector<ServeItem> sitems;
   std::vector<uint32_t> reqs, a_reqs;
+  struct Picked {
+    uint32_t r;
+    uint64_t off, s_before;  // flatten: its arena offset; the array's size before the request
+  };
+  std::vector<Picked> picked;
   uint64_t next = 0;
   const uint64_t n = tr->n;
 
@@ -276,7 +281,8 @@ int run_batched(RunState& R) {
       reqs.clear();
       a_reqs.clear();
       uint64_t blocks = 0, grid = 0;
-      while (reqs.size() + a_reqs.size() < sv->cfg.max_step && !ready.empty()) {
+      picked.clear();
+      while (picked.size() < sv->cfg.max_step && !ready.empty()) {
         const Head h = ready.top();
         const uint32_t a = h.second;
         if (busy[a] || q[a].empty() || tr->arrival_ns[q[a].front()] != h.first) {
@@ -290,7 +296,8 @@ int run_batched(RunState& R) {
           const uint64_t len = tr->length[r];
           const uint64_t chunk = (len + arr->V - 1) / arr->V;
           ntiles = (chunk + kInsertTile - 1) / kInsertTile * arr->V;
-          if (!items.empty() && blocks + ntiles > 0x7FFFFFFFull - sv->cfg.max_step) break;  // the step is full
+          if (blocks && blocks + ntiles > 0x7FFFFFFFull - sv->cfg.max_step) break;  // the step is full
+          blocks += ntiles;
         }
         uint64_t off = kNone;
         const uint64_t s_before = R.size[a];
@@ -302,15 +309,68 @@ int run_batched(RunState& R) {
         ready.pop();
         q[a].pop_front();
         if (ad == 2) {
+          if (tr->kind[r] == GGA_REQ_APPEND) blocks -= ntiles;
           R.reject(r);
           requeue(a);
           continue;
         }
         busy[a] = 1;
+        picked.push_back(Picked{r, off, s_before});
+      }
+      if (picked.empty()) continue;
+      if (picked.size() == 1) {
+        // A step of one request (light load) skips the step table: the request runs
+        // with the single-array launches on the lane's stream, as it would alone.
+        const Picked& p1 = picked[0];
+        const uint32_t r = p1.r;
+        ggarray* arr = sv->arrays[tr->target[r]];
+        int rc = GGA_OK;
+        if (tr->kind[r] == GGA_REQ_APPEND) {
+          InsertDesc d{};
+          d.mode = kModeKeyed;
+          d.n_threads = tr->length[r];
+          d.seed = sv->cfg.seed;
+          d.round = sv->cfg.append_round;
+          d.tag_shift = sv->cfg.append_shift;
+          d.tag = r;
+          d.max_count = 1;
+          rc = launch_insert(arr, d, l.s);
+          if (!rc && hipEventRecord(l.ev_a, l.s) != hipSuccess) rc = GGA_EHIP;
+          l.a_reqs.assign(1, r);
+        } else {
+          rc = launch_scan(arr, l.s);
+          if (!rc && hipEventRecord(l.ev_a, l.s) != hipSuccess) rc = GGA_EHIP;
+          if (!rc && tr->kind[r] == GGA_REQ_RW) rc = launch_rw(arr, sv->cfg.rw_op, l.s);
+          if (!rc && tr->kind[r] == GGA_REQ_FLATTEN) {
+            R.out_offset[r] = p1.off;
+            R.flat_bytes[r] = p1.s_before * sv->elem_bytes;
+            rc = launch_flatten(arr, sv->arena + p1.off, p1.s_before, l.s);
+            if (!rc && R.dev_out_len &&
+                hipMemcpyAsync(R.dev_out_len + r, arr->ref.prefix + arr->V, sizeof(uint64_t),
+                               hipMemcpyDeviceToDevice, l.s) != hipSuccess)
+              rc = GGA_EHIP;
+          }
+          l.reqs.assign(1, r);
+        }
+        if (rc) return rc;
+        if (hipEventRecord(l.ev, l.s) != hipSuccess) return GGA_EHIP;
+        R.t_issue[r] = now_ns(R.t0);
+        l.busy = true;
+        l.a_done = false;
+        ++R.steps;
+        ++R.issued;
+        if (R.largest < 1) R.largest = 1;
+        continue;
+      }
+      blocks = 0;
+      for (const Picked& pk : picked) {
+        const uint32_t r = pk.r;
+        ggarray* arr = sv->arrays[tr->target[r]];
         const uint8_t kind = tr->kind[r];
         (kind == GGA_REQ_APPEND ? a_reqs : reqs).push_back(r);
         if (kind == GGA_REQ_APPEND) {
           BatchArr it;
+          uint64_t ntiles = 0;
           const int rc = prepare_round_item(arr, tr->length[r], r, (uint32_t)items.size(), &it, &ntiles, l.s, true);
           if (rc) return rc;
           items.push_back(it);
@@ -321,13 +381,13 @@ int run_batched(RunState& R) {
         } else {
           const bool flat = kind == GGA_REQ_FLATTEN;
           if (flat) {
-            R.out_offset[r] = off;
-            R.flat_bytes[r] = s_before * sv->elem_bytes;
+            R.out_offset[r] = pk.off;
+            R.flat_bytes[r] = pk.s_before * sv->elem_bytes;
           }
-          sitems.push_back(ServeItem{arr->ref, flat ? (void*)(sv->arena + off) : nullptr, s_before,
+          sitems.push_back(ServeItem{arr->ref, flat ? (void*)(sv->arena + pk.off) : nullptr, pk.s_before,
                                      flat && R.dev_out_len ? R.dev_out_len + r : nullptr,
                                      flat ? kOpFlatten : sv->cfg.rw_op, arr->elem_log2});
-          grid += (s_before >> te_log2) + 2ull * arr->V;
+          grid += (pk.s_before >> te_log2) + 2ull * arr->V;
           arr->prefix_valid = true;
           arr->scan_tag = 0;  // the server runs eagerly
         }

@@ -85,6 +85,7 @@ _SIGS = {
     "gga_static_size": [_vp, _P(_u64), _vp],
     "gga_static_last_error": [_vp, _vp],
     "gga_static_clear": [_vp, _vp],
+    "gga_static_set_size": [_vp, _u64, _vp],
     "gga_batch_create": [_P(_vp), _vp, _u32, _vp],
     "gga_batch_destroy": [_vp, _vp],
     "gga_batch_insert_gen": [_vp, _P(GenSpec), _vp, _vp],
@@ -476,9 +477,13 @@ class Server:
 class StaticArray:
     """Pre-allocated flat array baseline (caller-owned buffer of cap elements)."""
 
-    def __init__(self, cap: int, elem_bytes: int, device="cuda", stream=None):
+    def __init__(self, cap: int, elem_bytes: int, device="cuda", stream=None, buf: torch.Tensor | None = None):
         self.elem_bytes = elem_bytes
-        self.buf = torch.empty(max(int(cap), 1), dtype=_dtype(elem_bytes), device=device)
+        if buf is None:
+            buf = torch.empty(max(int(cap), 1), dtype=_dtype(elem_bytes), device=device)
+        elif buf.numel() < cap or buf.element_size() != elem_bytes or not buf.is_contiguous():
+            raise ValueError("buf must be a contiguous tensor of at least cap elements of elem_bytes each")
+        self.buf = buf
         self.cap = int(cap)
         self._h = _vp()
         _check(lib().gga_static_create(ctypes.byref(self._h), self.buf.data_ptr(), self.cap,
@@ -515,6 +520,9 @@ class StaticArray:
 
     def clear(self, stream=None):
         _check(lib().gga_static_clear(self._h, _stream(stream)), "gga_static_clear")
+
+    def set_size(self, n: int, stream=None):
+        _check(lib().gga_static_set_size(self._h, int(n), _stream(stream)), "gga_static_set_size")
 
     def close(self, stream=None):
         if self._h:

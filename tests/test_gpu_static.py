@@ -1,0 +1,113 @@
+"""The flat-array baselines (Table II's static and host-resized arrays, the paper's
+memMap) on rounds in which every thread inserts: positions are then in closed form
+(thread g of a round lands at size + g), so the contents are compared element by
+element with the oracle of one LFVector (whose flatten is the concatenation of the
+rounds in thread order), across tiles, ragged tails and capacity overflow; and
+their r/w, launched one workgroup per 16 KiB tile, after insertions and after
+another r/w."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Oracle
+from paper_2209_00103_amd import workloads as wl
+from tests.gpu_util import dev, gg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_static_closed_form_rounds(elem):
+    G = gg()
+    st = G.StaticArray(1 << 22, elem)
+    o = Oracle(elem, 1, 1, forms=oracle.FORM_LIST)
+    rng = np.random.default_rng(elem)
+    for r, n in enumerate([1, 4095, 4096, 4097, 100003, 1 << 20]):
+        if r % 3 == 0:
+            st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=24), n)
+            o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=24)
+        elif r % 3 == 1:
+            st.insert_gen(G.make_gen(G.GEN_KEYED, seed=3, round=r, tag=5, tag_shift=21), n)
+            o.insert_gen(oracle.GEN_KEYED, n, seed=3, round=r, tag=5, tag_shift=21)
+        else:
+            vals, _ = wl.random_round(rng, n, 1.0, elem)
+            st.insert(dev(vals))
+            o.insert(vals)
+        assert st.size() == o.size()
+        assert np.array_equal(G.as_unsigned(st.data()), o.flatten()), f"round {r}"
+    for op in (G.ADD1, G.MUL3ADD1, G.ADD1_X30, G.ADD1):  # r/w after insertion, then after r/w
+        st.rw(op)
+        o.rw(op)
+        assert np.array_equal(G.as_unsigned(st.data()), o.flatten()), f"rw {op}"
+    assert st.last_error() == 0
+    st.close()
+
+
+def test_static_closed_form_overflow():
+    """A closed-form round that runs past the capacity over several tiles keeps the
+    elements below it, drops the rest and reports GGA_ERANGE."""
+    G = gg()
+    cap = 3 * 4096 + 1000
+    st = G.StaticArray(cap, 4)
+    st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=1, tag_shift=20), 5000)
+    st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=2, tag_shift=20), 20000)
+    assert st.last_error() == G.ERANGE
+    want = np.concatenate([(1 << 20) | np.arange(5000, dtype=np.uint32),
+                           (2 << 20) | np.arange(cap - 5000, dtype=np.uint32)])
+    got = G.as_unsigned(st.buf[:cap])
+    assert np.array_equal(got, want)
+    st.clear()
+    st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=3, tag_shift=20), 7)
+    assert st.last_error() == 0 and st.size() == 7
+    st.close()
+
+
+def test_semistatic_and_mapped_closed_form_rounds():
+    G = gg()
+    ss = G.SemiStaticArray(4, 1000)
+    mp = G.MappedArray(4, 1 << 24)
+    o = Oracle(4, 1, 1, forms=oracle.FORM_LIST)
+    for r, n in enumerate([3000, 1 << 17, 77777, 1 << 20]):
+        g = G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=24)
+        ss.insert_gen(g, n)
+        mp.insert_gen(g, n)
+        o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=24)
+    ss.rw(G.MUL3ADD1)
+    mp.rw(G.MUL3ADD1)
+    o.rw(oracle.OP_MUL3ADD1)
+    ref = o.flatten()
+    assert np.array_equal(G.as_unsigned(ss.data()), ref)
+    assert np.array_equal(G.as_unsigned(mp.data()), ref)
+    ss.close()
+    mp.close()
+
+
+def test_static_over_flattened_buffer():
+    """The work phase of the two-phase use: a GGArray flattened into a buffer that
+    a static array wraps (its size set to the flattened length) is worked on by
+    the static r/w, giving the oracle's r/w of the same contents."""
+    import torch
+
+    G = gg()
+    pool = G.Pool(256 << 20)
+    a = G.GGArray(pool, 4, 7, 8)
+    o = Oracle(4, 7, 8, forms=oracle.FORM_LIST)
+    for r in range(3):
+        a.insert_gen(G.make_gen(G.GEN_BERNOULLI, seed=2, round=r), 300001)
+        o.insert_gen(oracle.GEN_BERNOULLI, 300001, seed=2, round=r)
+    n = a.size()
+    buf = torch.full((n + 100,), 7, dtype=torch.int32, device="cuda")
+    st = G.StaticArray(n + 100, 4, buf=buf)
+    a.flatten_into(buf[:n])
+    st.set_size(n)
+    for op in (G.ADD1, G.MUL3ADD1, G.ADD1):
+        st.rw(op)
+        o.rw(op)
+    assert st.size() == n and st.last_error() == 0
+    assert np.array_equal(G.as_unsigned(buf[:n]), o.flatten())
+    assert (G.as_unsigned(buf[n:]) == 7).all()  # past the size: untouched
+    with pytest.raises(G.GGAError):
+        st.set_size(n + 101)
+    st.close()
+    a.close()
+    pool.close()
