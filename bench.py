@@ -28,6 +28,7 @@ import platform
 import statistics
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -638,31 +639,45 @@ def shootout_leg(G, torch, reps=3):
             "rows": rows}
 
 
-def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=6):
+def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=1000):
     """The memory comparison of Sec. V (Fig. 3), measured: a workload inserts
     N * LogNormal(0, sigma) elements.  A static array must be sized in advance;
     sized to fail at most 1% of the time it holds N * e^(2.326 sigma).  The
-    GGArray (V = 512, F = 1024) is grown to the drawn size and its capacity read
-    back.  Reported per sigma: mean allocated / live for both."""
+    GGArray is grown to each drawn size and its capacity read back; its first
+    bucket is picked by the capacity bound (C <= 2S + V(F - 1) per array): the
+    largest power of two with V * F <= N / 64, so the per-LFVector rounding stays
+    small against the live data, as it does for Fig. 3's large arrays.  Reported
+    per sigma over `samples` draws: mean and largest allocated / live for both."""
     rng = np_.random.default_rng(1)
-    pool = G.Pool(4 << 30)
+    Fm = 1
+    while V * Fm * 2 <= N // 64:
+        Fm *= 2
+    pool = G.Pool(16 << 30)
+    a = G.GGArray(pool, ELEM, V, Fm)
     rows = []
     z99 = 2.3263478740408408
+    cap_max = 1 << 30  # draws are clamped here, so that twice the live data fits the 16 GiB pool
     for sigma in [0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0]:
         x = np_.maximum(1, np_.rint(N * np_.exp(sigma * rng.standard_normal(samples)))).astype(np_.int64)
+        x = np_.minimum(x, cap_max)
         static_cap = N * float(np_.exp(z99 * sigma))
-        gg_ratio, st_ratio = [], []
+        gg_ratio = []
         for n in x:
-            a = G.GGArray(pool, ELEM, V, F)
             a.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=0, tag_shift=40), int(n))
             gg_ratio.append(a.capacity() / int(n))
-            st_ratio.append(static_cap / int(n))
-            a.close()
-        rows.append({"sigma": sigma, "ggarray_capacity_over_live": float(np_.mean(gg_ratio)),
-                     "static_1pct_capacity_over_live": float(np_.mean(st_ratio)),
+            a.shrink(1, 1)  # back to empty: every bucket returns to the pool
+        st_ratio = static_cap / x
+        rows.append({"sigma": sigma,
+                     "ggarray_capacity_over_live": float(np_.mean(gg_ratio)),
+                     "ggarray_capacity_over_live_max": float(np_.max(gg_ratio)),
+                     "static_1pct_capacity_over_live": float(np_.mean(st_ratio[x <= static_cap])),
                      "static_fits_fraction": float(np_.mean(x <= static_cap))})
+    assert a.last_error() == 0
+    a.close()
     pool.close()
-    return {"workload": f"N = {N}, {samples} draws per sigma, GGArray V = {V}, F = {F}", "rows": rows}
+    return {"workload": f"N = {N}, {samples} draws per sigma (clamped at 2^30), GGArray V = {V}, "
+                        f"F = {Fm} (V*F <= N/64)",
+            "rows": rows}
 
 
 def config1_leg(G, wl, torch, reps=50):
@@ -735,7 +750,7 @@ def config1_leg(G, wl, torch, reps=50):
             "ops": ops, "step_us_eager": eager_us, "step_us_graph": graph_us, "reps": reps}
 
 
-def config3_leg(G, wl, torch, steps=3):
+def config3_leg(G, wl, torch, steps=3, pool_gib=24, close_gen_first=True):
     """Configuration 3 at full size (irregular insertion): uint64, V = 65536,
     F = 1024, 2^26 threads with Poisson(3) counts capped at 16 (thresholds from the
     host), 4 insert phases each followed by r/w x + 1, then flatten.  Device time
@@ -749,7 +764,9 @@ def config3_leg(G, wl, torch, steps=3):
     identical arrays; buffer mode is the HBM-bound insertion roofline."""
     thr = wl.poisson_thresholds(3, 16)
     n, V = 1 << 26, 65536
-    pool = G.Pool(16 << 30)
+    # Both arrays of the leg (about 7.9 GB of buckets each) fit the pool together;
+    # the generated-payload array is closed before the buffer-mode one is built.
+    pool = G.Pool(pool_gib << 30)
     a = G.GGArray(pool, 8, V, 1024)
     gens = [G.make_gen(G.GEN_POISSON, seed=1, round=i, max_count=16, thresholds=thr) for i in range(4)]
     sizes = []
@@ -772,7 +789,9 @@ def config3_leg(G, wl, torch, steps=3):
         if rep < steps:
             a.shrink(1, 1)
     torch.cuda.synchronize()
-    assert a.last_error() == 0
+    assert a.last_error() == 0, f"generated rounds: device error {a.last_error()}"
+    if close_gen_first:
+        a.close()
 
     # Buffer mode: the same rounds as prepared inputs.
     pool2 = G.Pool(8 << 30)
@@ -783,7 +802,7 @@ def config3_leg(G, wl, torch, steps=3):
         packed.append(scratch.flatten())
         scratch.shrink(1, 1)
         counts.append(torch.from_numpy(wl.poisson_counts(1, i, n, thr)).to("cuda"))
-        assert int(counts[-1].sum()) == packed[-1].numel()
+        assert int(counts[-1].sum()) == packed[-1].numel(), "host counts differ from the generated round"
     scratch.close()
     pool2.close()
     b = G.GGArray(pool, 8, V, 1024)
@@ -801,7 +820,7 @@ def config3_leg(G, wl, torch, steps=3):
         if rep < steps:
             b.shrink(1, 1)
     torch.cuda.synchronize()
-    assert b.last_error() == 0
+    assert b.last_error() == 0, f"buffer-mode rounds: device error {b.last_error()}"
     identical = bool(torch.equal(out, out_b))
     b.close()
     a.close()
@@ -839,6 +858,7 @@ def config3_leg(G, wl, torch, steps=3):
     if valu:
         roof["achieved"] = valu * 64 / (ins_us * 1e-6) / 1e12
         roof["frac"] = roof["achieved"] / peak
+    sweep = config3_v_sweep(G, torch, gens, n, sizes[-1], steps)
     bus = statistics.median(p["insert_us"] for p in bphases)
     bbytes = statistics.mean(p["insert_bytes"] for p in bphases)
     broof = {"kernel": "insert_packed (tile sums + tile scan + insert_packed_kernel, one call)", "bound": "hbm",
@@ -848,9 +868,52 @@ def config3_leg(G, wl, torch, steps=3):
     return {"workload": "2^26 threads, Poisson(3) counts capped at 16, uint64 K(1,gid,16i+j), V = 65536, "
                         "4 x (insert, r/w x+1), flatten", "final_size": sizes[-1], "phases": phases,
             "flatten_us": 1e3 * fl, "flatten_GBps": 16 * sizes[-1] / (fl * 1e-3) / 1e9, "insert_roofline": roof,
+            "v_sweep": sweep,
             "buffer_mode": {"phases": bphases, "insert_roofline": broof, "identical_to_gen_mode": identical,
                             "inputs": "counts from the host generator, payloads packed in thread order "
                                       "(prepared before the timed passes)"}}
+
+
+def config3_v_sweep(G, torch, gens, n, final_size, steps, vs=(512, 4096)):
+    """Configuration 3's generated rounds with fewer LFVectors: V = 512 gives each
+    LFVector 128 tiles of 1024 threads per round (tickets and the decoupled
+    look-back at scale), V = 4096 gives 16.  Same 4 x (insert, r/w x + 1) passes;
+    V changes the order of the elements but not the total, which is checked."""
+    rows = []
+    for V in vs:
+        pool = G.Pool(16 << 30)
+        a = G.GGArray(pool, 8, V, 1024)
+        tm = Timer(torch)
+        sizes = []
+        for rep in range(steps + 1):
+            t = tm if rep else Timer(torch)
+            sizes = []
+            for i in range(4):
+                with t.span(f"ins{i}"):
+                    a.insert_gen(gens[i], n)
+                with t.span(f"rw{i}"):
+                    a.rw(G.ADD1)
+                if rep == 0:
+                    sizes.append(a.size())
+            if rep == 0:
+                first_sizes = sizes
+            if rep < steps:
+                a.shrink(1, 1)
+        torch.cuda.synchronize()
+        assert a.last_error() == 0, f"V = {V}: device error {a.last_error()}"
+        assert first_sizes[-1] == final_size, "the total does not depend on V"
+        prev, ph = 0, []
+        for i in range(4):
+            ins = statistics.median(tm.ms(f"ins{i}"))
+            rw = statistics.median(tm.ms(f"rw{i}"))
+            added = first_sizes[i] - prev
+            prev = first_sizes[i]
+            ph.append({"insert_us": 1e3 * ins, "insert_Gelem_s": added / (ins * 1e-3) / 1e9,
+                       "rw_us": 1e3 * rw, "rw_GBps": 16 * first_sizes[i] / (rw * 1e-3) / 1e9})
+        rows.append({"V": V, "tiles_per_lfvector": (n // V + 1023) // 1024, "phases": ph})
+        a.close()
+        pool.close()
+    return rows
 
 
 def cpu_baseline(rounds, V, min_seconds=10.0, max_reps=4):
@@ -959,7 +1022,7 @@ def main():
         graph_ms = g0.elapsed_time(g1) / args.steps
         del graph
     except Exception as e:  # reported, never silently dropped
-        log(f"graph replay failed: {e}")
+        log(f"graph replay failed: {e!r}\n{traceback.format_exc()}")
     log(f"graph replay: {graph_ms} ms/step")
 
     # Per-kernel durations: the same K steps again with events around every call, and
@@ -1152,7 +1215,7 @@ def main():
             baselines["mapped"] = mapped_baseline(G, torch, gens, rounds, args.steps)
         except Exception as e:  # reported, never silently dropped
             baselines["mapped"] = {"error": str(e)}
-            log(f"mapped baseline failed: {e}")
+            log(f"mapped baseline failed: {e!r}\n{traceback.format_exc()}")
         log(f"static insert {baselines['static']['insert_Gelem_s']:.1f} Gelem/s rw "
             f"{baselines['static']['rw_GBps']:.0f} GB/s; semi-static insert "
             f"{baselines['semi_static']['insert_Gelem_s']:.1f} Gelem/s; mapped "
@@ -1168,7 +1231,7 @@ def main():
                 f"Gelem/s (last round {sparse['static']['last_round_GBps']:.0f} GB/s)")
         except Exception as e:  # reported, never silently dropped
             sparse = {"error": str(e)}
-            log(f"sparse leg failed: {e}")
+            log(f"sparse leg failed: {e!r}\n{traceback.format_exc()}")
 
     footprint_end = arr.footprint()  # after the timed steps: the tile table has been built
     arr.close()
@@ -1190,7 +1253,7 @@ def main():
                                                           for i, r in enumerate(shootout["rows"])))
         except Exception as e:  # reported, never silently dropped
             shootout = {"error": str(e)}
-            log(f"shootout failed: {e}")
+            log(f"shootout failed: {e!r}\n{traceback.format_exc()}")
         try:
             memory_model = memory_model_leg(G, torch, np)
             log("memory model: " + ", ".join(f"s={r['sigma']}: gg {r['ggarray_capacity_over_live']:.2f} "
@@ -1198,7 +1261,7 @@ def main():
                                              for r in memory_model["rows"]))
         except Exception as e:
             memory_model = {"error": str(e)}
-            log(f"memory model failed: {e}")
+            log(f"memory model failed: {e!r}\n{traceback.format_exc()}")
     config1 = None
     if not args.no_config1:
         stage("configuration 1")
@@ -1210,7 +1273,7 @@ def main():
                 + f" us, r/w {o1['rw']['p50_us']:.1f} us, flatten {o1['flatten']['p50_us']:.1f} us")
         except Exception as e:  # reported, never silently dropped
             config1 = {"error": str(e)}
-            log(f"configuration-1 leg failed: {e}")
+            log(f"configuration-1 leg failed: {e!r}\n{traceback.format_exc()}")
     config3 = None
     if not args.no_config3:
         stage("configuration 3")
@@ -1225,7 +1288,7 @@ def main():
                 + f" GB/s (identical {config3['buffer_mode']['identical_to_gen_mode']})")
         except Exception as e:  # reported, never silently dropped
             config3 = {"error": str(e)}
-            log(f"configuration-3 leg failed: {e}")
+            log(f"configuration-3 leg failed: {e!r}\n{traceback.format_exc()}")
     two_phase = None
     if not args.no_two_phase:
         stage("two-phase")
@@ -1235,7 +1298,7 @@ def main():
                 f"{key} {r['speedup_flatten_vs_mapped']:.2f}" for key, r in two_phase["rows"].items()))
         except Exception as e:  # reported, never silently dropped
             two_phase = {"error": str(e)}
-            log(f"two-phase leg failed: {e}")
+            log(f"two-phase leg failed: {e!r}\n{traceback.format_exc()}")
     served = None
     if not args.no_served:
         stage("served")

@@ -216,14 +216,19 @@ __device__ __forceinline__ uint8_t* pool_pop(PoolRef P, uint32_t cls, uint32_t s
   return nullptr;
 }
 
+// The bump pointer only moves by a successful compare-and-swap, so it never
+// passes the limit and never moves back.  (Adding first and subtracting again on
+// failure is not safe: a failed add that is undone after a smaller add has
+// succeeded past it moves the pointer back over that block, which the next
+// allocation then receives a second time.)
 __device__ __forceinline__ uint8_t* global_bump(PoolRef P, uint64_t bytes) {
   PoolHdr* H = P.hdr;
-  const uint64_t old = fetch_add(&H->bump, bytes);
-  if (old + bytes > ld_rlx(&H->limit)) {
-    sub_nr(&H->bump, bytes);
-    return nullptr;
+  const uint64_t limit = H->limit;  // written by the host before any launch
+  uint64_t old = ld_rlx(&H->bump);
+  for (;;) {
+    if (old + bytes > limit) return nullptr;
+    if (cas_rlx(&H->bump, old, old + bytes)) return P.base + old;
   }
-  return P.base + old;
 }
 
 __device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t bytes, uint32_t clog) {

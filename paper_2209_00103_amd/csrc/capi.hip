@@ -619,7 +619,7 @@ static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_by
   uint8_t* m = static_cast<uint8_t*>(st->meta);
   st->d_size = reinterpret_cast<uint64_t*>(m);
   st->d_err = reinterpret_cast<uint32_t*>(m + 16);
-  st->d_done = reinterpret_cast<uint32_t*>(m + 32);
+  st->d_done = reinterpret_cast<uint32_t*>(m + 128);  // its own cache line: the size's is read by every wave
   st->rw_last = false;
   return GGA_OK;
 }

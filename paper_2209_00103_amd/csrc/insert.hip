@@ -828,26 +828,33 @@ __global__ __launch_bounds__(64) void batch_dense_kernel(const BatchArr* items, 
 // 4096 threads stores its run exactly as the GGArray's dense rounds do (16-byte
 // non-temporal stores on whole 128-byte lines), so the two layouts are compared
 // on the same algorithm.  Every wave reads the size before the round (nothing
-// changes it during the launch); the last wave to finish moves it.  Elements past
+// changes it during the launch); the last workgroup to finish moves it.  Elements past
 // the capacity are dropped with the sticky GGA_ERANGE, and the size counts them,
 // as in the atomic rounds.
+constexpr uint32_t kDenseWaves = 16;  // tiles (waves) per workgroup of the static closed-form round
 template <typename T, class Prod>
-__global__ __launch_bounds__(64) void static_dense_kernel(StaticRef S, uint64_t n, uint64_t ntiles, Prod prod) {
+__global__ __launch_bounds__(64 * kDenseWaves) void static_dense_kernel(StaticRef S, uint64_t n, uint64_t nblocks,
+                                                                        Prod prod) {
   const uint32_t lane = lane_id();
-  const uint64_t base = ld_rlx(S.size);
-  const uint64_t g0 = (uint64_t)blockIdx.x * kWaveTile;
-  const uint32_t cnt = n - g0 < (uint64_t)kWaveTile ? (uint32_t)(n - g0) : (uint32_t)kWaveTile;
-  const uint64_t pos = base + g0;
-  const uint32_t lim = pos < S.cap ? (S.cap - pos < cnt ? (uint32_t)(S.cap - pos) : cnt) : 0u;
-  if (lim) dense_store<T, Prod>(reinterpret_cast<T*>(S.data) + pos, prod, g0, lim);
-  if (lane == 0) {
-    if (lim < cnt) set_error(S.err, kErrRange);
-    // The size read above completed before the stores were issued, so every wave
-    // counted here has read it.
-    if (fetch_add32(S.done, 1u) == ntiles - 1) {
-      st_rlx(S.size, base + n);
-      st_rlx32(S.done, 0u);
-    }
+  // The size before the round.  Nothing writes it until every workgroup has
+  // counted itself done below, so a plain load is current (and served by the
+  // cache after the first: every wave reading it with device scope, and one
+  // counter atomic per wave, measured slower than the stores themselves).
+  const uint64_t base = *S.size;
+  const uint64_t g0 = ((uint64_t)blockIdx.x * kDenseWaves + (threadIdx.x >> 6)) * kWaveTile;
+  if (g0 < n) {
+    const uint32_t cnt = n - g0 < (uint64_t)kWaveTile ? (uint32_t)(n - g0) : (uint32_t)kWaveTile;
+    const uint64_t pos = base + g0;
+    const uint32_t lim = pos < S.cap ? (S.cap - pos < cnt ? (uint32_t)(S.cap - pos) : cnt) : 0u;
+    if (lim) dense_store<T, Prod>(reinterpret_cast<T*>(S.data) + pos, prod, g0, lim);
+    if (lane == 0 && lim < cnt) set_error(S.err, kErrRange);
+  }
+  // Every wave of the workgroup has its size (the stores needed it) before the
+  // workgroup counts itself; the last workgroup moves the size.
+  __syncthreads();
+  if (threadIdx.x == 0 && fetch_add32(S.done, 1u) == nblocks - 1) {
+    st_rlx(S.size, base + n);
+    st_rlx32(S.done, 0u);
   }
 }
 
@@ -1394,37 +1401,53 @@ static int ensure_packed_offsets(ggarray* a, uint64_t words, hipStream_t s) {
   return GGA_OK;
 }
 
-int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
-                         uint64_t n_values, hipStream_t s) {
-  a->tev_set &= ~4u;  // not a timed round
-  if (n_threads == 0) return GGA_OK;
+// The kernels of one packed round: tile totals, their prefix (off: ntiles + 1
+// words), then the copy.  A.status holds the look-back words when tpv > 1.
+static int queue_packed(ggarray* a, const ArrRef& A, uint64_t* off, const void* values, const uint8_t* counts,
+                        const TileArgs& I, uint64_t ntiles, uint64_t n_values, hipStream_t s) {
+  grow_bound(a, n_values);
+  hipLaunchKernelGGL(packed_tile_sums_kernel, dim3((uint32_t)ntiles), dim3(kB), 0, s, I, counts, off);
+  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off, ntiles);
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL(insert_packed_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, A, I,
+                       static_cast<const uint32_t*>(values), counts, (const uint64_t*)off, ntiles, n_values);
+  else
+    hipLaunchKernelGGL(insert_packed_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, A, I,
+                       static_cast<const uint64_t*>(values), counts, (const uint64_t*)off, ntiles, n_values);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) sizes_changed(a, s);
+  return hip_status(e);
+}
+
+// Tile geometry of a packed round; GGA_EINVAL if the round is too large.
+static int packed_geometry(const ggarray* a, uint64_t n_threads, TileArgs& I, uint64_t& ntiles) {
   const uint64_t chunk = (n_threads + a->V - 1) / a->V;
   const uint64_t tpv = (chunk + kCountTile - 1) / kCountTile;
-  const uint64_t ntiles = tpv * a->V;
+  ntiles = tpv * a->V;
   if (ntiles > 0x7FFFFFFFull || chunk * 255u >= (1ull << 32)) return GGA_EINVAL;
-  if (tpv > 1) {
-    const int rc = ensure_status(a, ntiles, s);
-    if (rc) return rc;
-  }
-  int rc = ensure_packed_offsets(a, ntiles + 1, s);
-  if (rc) return rc;
-  TileArgs I{};
+  I = TileArgs{};
   I.n_threads = n_threads;
   I.chunk = chunk;
   I.tpv = tpv;
   I.elem_log2 = a->elem_log2;
-  grow_bound(a, n_values);
-  hipLaunchKernelGGL(packed_tile_sums_kernel, dim3((uint32_t)ntiles), dim3(kB), 0, s, I, counts, a->pk_off);
-  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, a->pk_off, ntiles);
-  if (a->elem_bytes == 4)
-    hipLaunchKernelGGL(insert_packed_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
-                       static_cast<const uint32_t*>(values), counts, (const uint64_t*)a->pk_off, ntiles, n_values);
-  else
-    hipLaunchKernelGGL(insert_packed_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
-                       static_cast<const uint64_t*>(values), counts, (const uint64_t*)a->pk_off, ntiles, n_values);
-  const hipError_t e = hipGetLastError();
-  if (e == hipSuccess) sizes_changed(a, s);
-  return hip_status(e);
+  return GGA_OK;
+}
+
+int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
+                         uint64_t n_values, hipStream_t s) {
+  a->tev_set &= ~4u;  // not a timed round
+  if (n_threads == 0) return GGA_OK;
+  TileArgs I;
+  uint64_t ntiles = 0;
+  int rc = packed_geometry(a, n_threads, I, ntiles);
+  if (rc) return rc;
+  if (I.tpv > 1) {
+    rc = ensure_status(a, ntiles, s);
+    if (rc) return rc;
+  }
+  rc = ensure_packed_offsets(a, ntiles + 1, s);
+  if (rc) return rc;
+  return queue_packed(a, a->ref, a->pk_off, values, counts, I, ntiles, n_values, s);
 }
 
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {
@@ -1456,18 +1479,19 @@ int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t
 
 template <typename T>
 int launch_static_dense(const StaticRef& S, const InsertDesc& d, uint64_t ntiles, hipStream_t s) {
-  const dim3 grid((uint32_t)ntiles), block(64);
+  const uint64_t nblocks = (ntiles + kDenseWaves - 1) / kDenseWaves;
+  const dim3 grid((uint32_t)nblocks), block(64 * kDenseWaves);
   switch (d.mode) {
     case kModeBuffer:
-      hipLaunchKernelGGL((static_dense_kernel<T, ProdBuffer<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdBuffer<T>>), grid, block, 0, s, S, d.n_threads, nblocks,
                          ProdBuffer<T>{static_cast<const T*>(d.values), nullptr});
       break;
     case kModeRoundTag:
-      hipLaunchKernelGGL((static_dense_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdRoundTag<T>>), grid, block, 0, s, S, d.n_threads, nblocks,
                          ProdRoundTag<T>{d.round, d.tag_shift});
       break;
     case kModeKeyed:
-      hipLaunchKernelGGL((static_dense_kernel<T, ProdKeyed<T>>), grid, block, 0, s, S, d.n_threads, ntiles,
+      hipLaunchKernelGGL((static_dense_kernel<T, ProdKeyed<T>>), grid, block, 0, s, S, d.n_threads, nblocks,
                          ProdKeyed<T>{d.seed, d.round, d.tag_shift, d.tag});
       break;
     default:

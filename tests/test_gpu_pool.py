@@ -67,3 +67,66 @@ def test_pool_concurrent_alloc_free_no_overlap():
     assert st["frees"] - before["frees"] == threads * k + threads * k // 2
     a.close()
     pool.close()
+
+
+def test_pool_exhaustion_concurrent_no_overlap():
+    """The same stress on a 64 MiB pool that cannot hold the demand (blocks of 256 B
+    .. 512 KiB, about 11 GiB asked for): many allocations fail while others
+    succeed at the same time, both from the arenas and from the global bump
+    pointer.  The blocks handed out must still be distinct, inside the region and
+    intact, and all of them must go back.  (A bump pointer that undid failed adds
+    could hand one block out twice here.)"""
+    K = ctypes.CDLL(KLIB)
+    K.ggt_pool_stress.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    K.ggt_pool_stress.restype = ctypes.c_int
+    K.ggt_ref_bytes.restype = ctypes.c_uint64
+    G = gg()
+    pool = G.Pool(64 << 20)
+    a = G.GGArray(pool, 4, 1, 1)
+    nb = int(K.ggt_ref_bytes())
+    ref = a.device_ref(nb)
+    threads, k, nclass = 16384, 8, 12
+    ptr = torch.zeros(threads * k, dtype=torch.int64, device="cuda")
+    cls = torch.zeros(threads * k, dtype=torch.int32, device="cuda")
+    err = torch.zeros(1, dtype=torch.int32, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    before = pool.stats()
+    base, end = pool.mem.data_ptr(), pool.mem.data_ptr() + pool.mem.numel()
+
+    def phase(p):
+        assert K.ggt_pool_stress(ref, nb, threads, k, p, 11, nclass, ptr.data_ptr(), cls.data_ptr(),
+                                 err.data_ptr(), s) == 0
+        torch.cuda.synchronize()
+
+    def check_live():
+        P = ptr.cpu().numpy().view(np.uint64)
+        C = cls.cpu().numpy().astype(np.uint64)
+        live = P != 0
+        P, C = P[live], C[live]
+        assert P.size > 0
+        assert np.all(P >= base) and np.all(P + (np.uint64(1) << C) <= end)
+        order = np.argsort(P)
+        lo, hi = P[order], P[order] + (np.uint64(1) << C[order])
+        assert np.all(hi[:-1] <= lo[1:]), "two live blocks overlap"
+        return int(sum(1 << int(c) for c in C)), int(P.size)
+
+    phase(0)
+    assert int((ptr == 0).sum()) > 0, "the pool was meant to run out"
+    live0, _ = check_live()
+    err.zero_()  # the failures counted in phase 0 could spill into the signature count
+    phase(3)
+    assert int(err.item()) >> 16 == 0, "a live block lost its signature"
+    assert pool.stats()["in_use"] - before["in_use"] == live0
+    phase(1)
+    phase(2)  # freed blocks are taken again, by other shards' allocations too
+    live2, _ = check_live()
+    err.zero_()
+    phase(3)
+    assert int(err.item()) >> 16 == 0, "a live block lost its signature"
+    assert pool.stats()["in_use"] - before["in_use"] == live2
+    phase(4)
+    assert pool.stats()["in_use"] == before["in_use"]
+    a.close()
+    pool.close()
