@@ -175,6 +175,21 @@ int ggarray_insert_counts(ggarray *a, const void *values, const uint8_t *counts,
 int ggarray_insert_packed(ggarray *a, const void *values, uint64_t n_values, const uint8_t *counts,
                           uint64_t n_threads, gga_stream s);
 
+/* ggarray_insert_packed_noalloc: for callers that cannot allocate device memory
+ *   (code being captured into a HIP graph, tight serving loops, harnesses that
+ *   forbid hipMalloc).  Same arguments and results as ggarray_insert_packed, but
+ *   the call allocates nothing: the per-tile value offsets and the look-back
+ *   words live in a static device array of the library (about 1 MiB, one copy
+ *   per GPU, held until the process ends).  Buckets still come from the array's
+ *   pool on the device.  Limit: the round may span at most 65536 tiles, a tile
+ *   being 1024 logical threads of one LFVector (V * ceil(ceil(n_threads / V) /
+ *   1024) <= 65536); a larger round returns GGA_ERANGE at once and queues
+ *   nothing.  Every call on one GPU shares that array: calls that overlap on
+ *   one GPU (other streams, other host threads) race and must not be issued;
+ *   calls ordered on one stream are safe, since each clears what it reads. */
+int ggarray_insert_packed_noalloc(ggarray *a, const void *values, uint64_t n_values, const uint8_t *counts,
+                                  uint64_t n_threads, gga_stream s);
+
 /* ggarray_insert_gen: one insertion round whose payloads are generated on the
  *   device by g (see GGA_GEN_*); `g` is a host pointer read before returning. */
 int ggarray_insert_gen(ggarray *a, const gga_gen *g, uint64_t n_threads, gga_stream s);

@@ -328,6 +328,12 @@ int ggarray_insert_packed(ggarray* a, const void* values, uint64_t n_values, con
   return launch_insert_packed(a, values, counts, n_threads, n_values, S(s));
 }
 
+int ggarray_insert_packed_noalloc(ggarray* a, const void* values, uint64_t n_values, const uint8_t* counts,
+                                  uint64_t n_threads, gga_stream s) {
+  if (!a || (n_threads && !counts) || (n_values && !values)) return GGA_EINVAL;
+  return launch_insert_packed_noalloc(a, values, counts, n_threads, n_values, S(s));
+}
+
 int ggarray_insert_gen(ggarray* a, const gga_gen* g, uint64_t n_threads, gga_stream s) {
   uint32_t mode = 0, maxc = 0;
   if (!a) return GGA_EINVAL;

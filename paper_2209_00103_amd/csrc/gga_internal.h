@@ -355,6 +355,9 @@ int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t
 int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);
 int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
                          uint64_t n_values, hipStream_t s);
+// The same round with its per-call buffers in the library's static scratch.
+int launch_insert_packed_noalloc(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
+                                 uint64_t n_values, hipStream_t s);
 int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
                            hipStream_t s);  // copy: also write the prefix there
 int launch_shrink(ggarray* a, uint32_t num, uint32_t den, hipStream_t s);

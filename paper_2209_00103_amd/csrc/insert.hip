@@ -23,6 +23,7 @@
 //      stores when every thread of the tile inserts into one bucket, else one
 //      element per lane and slot, located by the closed form.
 // The static baseline replaces 2-4 by one global atomicAdd per tile.
+#include <mutex>
 #include <new>
 
 #include <hip/hip_ext.h>
@@ -1448,6 +1449,68 @@ int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, 
   rc = ensure_packed_offsets(a, ntiles + 1, s);
   if (rc) return rc;
   return queue_packed(a, a->ref, a->pk_off, values, counts, I, ntiles, n_values, s);
+}
+
+// ------------------------------------------- packed round without allocation --
+// The tile offsets and look-back words of ggarray_insert_packed_noalloc live in
+// this file-scope array: each device holds its own copy for the life of the
+// process.  Words [0, kNoAllocTiles + 1) take the tile offsets, words from
+// kScratchStatus on the look-back words.  Host code never passes the symbol
+// itself to a kernel: its device address is looked up once per device and kept.
+constexpr uint64_t kNoAllocTiles = 65536;
+constexpr uint64_t kScratchStatus = kNoAllocTiles + 32;  // 256-byte aligned
+constexpr uint64_t kScratchWords = kScratchStatus + kNoAllocTiles;
+static __device__ __align__(256) uint64_t scratch[kScratchWords];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static uint64_t* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The current device's copy of `scratch`, resolved on the first call on it.
+static int scratch_base(uint64_t** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GGA_EHIP;
+  if (dev < 0 || dev >= kMaxScratchDevices) return GGA_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return GGA_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<uint64_t*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return GGA_OK;
+}
+
+// Zero words (look-back words: a zero word is never current).  A kernel, not a
+// memset, so that the round can also be recorded into a graph.
+__global__ __launch_bounds__(256) void zero_words_kernel(uint64_t* p, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+int launch_insert_packed_noalloc(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
+                                 uint64_t n_values, hipStream_t s) {
+  a->tev_set &= ~4u;
+  if (n_threads == 0) return GGA_OK;
+  TileArgs I;
+  uint64_t ntiles = 0;
+  int rc = packed_geometry(a, n_threads, I, ntiles);
+  if (rc) return rc;
+  if (ntiles > kNoAllocTiles) return GGA_ERANGE;  // beyond the scratch: nothing queued
+  uint64_t* sc = nullptr;
+  rc = scratch_base(&sc);
+  if (rc) return rc;
+  ArrRef A = a->ref;
+  if (I.tpv > 1) {
+    // The words may hold another array's (or an earlier round's) words of the same
+    // epoch: cleared first, so none is current.
+    A.status = sc + kScratchStatus;
+    hipLaunchKernelGGL(zero_words_kernel, dim3((uint32_t)((ntiles + 255) / 256)), dim3(256), 0, s, A.status, ntiles);
+  }
+  return queue_packed(a, A, sc, values, counts, I, ntiles, n_values, s);
 }
 
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {

@@ -57,6 +57,7 @@ _SIGS = {
     "ggarray_insert": [_vp, _vp, _vp, _u64, _vp],
     "ggarray_insert_counts": [_vp, _vp, _vp, _u32, _u64, _vp],
     "ggarray_insert_packed": [_vp, _vp, _u64, _vp, _u64, _vp],
+    "ggarray_insert_packed_noalloc": [_vp, _vp, _u64, _vp, _u64, _vp],
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
@@ -265,6 +266,15 @@ class GGArray:
         vp = _dev_ptr(values, "values", nv, self.elem_bytes) if nv else None
         cp = _dev_ptr(counts, "counts", n, 1)
         _check(lib().ggarray_insert_packed(self._h, vp, nv, cp, n, _stream(stream)), "ggarray_insert_packed")
+
+    def insert_packed_noalloc(self, values: torch.Tensor, counts: torch.Tensor, n_values=None, stream=None):
+        """insert_packed through the entry point that allocates nothing (library scratch, at most 65536 tiles)."""
+        n = counts.numel()
+        nv = values.numel() if n_values is None else int(n_values)
+        vp = _dev_ptr(values, "values", nv, self.elem_bytes) if nv else None
+        cp = _dev_ptr(counts, "counts", n, 1)
+        _check(lib().ggarray_insert_packed_noalloc(self._h, vp, nv, cp, n, _stream(stream)),
+               "ggarray_insert_packed_noalloc")
 
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().ggarray_shrink(self._h, num, den, _stream(stream)), "ggarray_shrink")
