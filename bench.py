@@ -262,6 +262,7 @@ def batched_leg(G, wl, torch, np, steps, warmup):
     b = G.Batch(arrays)
     out = torch.empty(total, dtype=torch.int32, device="cuda")
     out2 = torch.empty(total, dtype=torch.int32, device="cuda")
+    out3 = torch.empty(total, dtype=torch.int32, device="cuda")
     counts0 = [rounds[i][0] for i in range(n_arr)]
     b.insert_gen(G.make_gen(G.GEN_KEYED, seed=1, round=0, tag=0), counts0)  # something to stream while tuning
     grid = tuner.tune_grid(b, out, total)
@@ -277,6 +278,10 @@ def batched_leg(G, wl, torch, np, steps, warmup):
             b.insert_gen(bgens[r], counts[r])
         b.rw(G.ADD1)
         b.flatten_into(out)
+
+    def persistent_step():
+        b.shrink(1, 1)
+        b.step(bgens, counts, G.ADD1, out3)
 
     def per_array_step():
         for i, a in enumerate(arrays):
@@ -304,6 +309,10 @@ def batched_leg(G, wl, torch, np, steps, warmup):
             batched_step()
         s.synchronize()
         res["batched"] = timed(batched_step, steps)
+        for _ in range(max(1, warmup)):
+            persistent_step()
+        s.synchronize()
+        res["persistent"] = timed(persistent_step, steps)
         per_array_step()  # warm-up (uploads nothing, sizes status buffers)
         s.synchronize()
         res["per_array"] = timed(per_array_step, max(2, min(steps, 3)))
@@ -313,16 +322,22 @@ def batched_leg(G, wl, torch, np, steps, warmup):
     g2 = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g2, stream=s):
         per_array_step()
+    g3 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g3, stream=s):
+        persistent_step()
     with torch.cuda.stream(s):
         g1.replay()
         g2.replay()
+        g3.replay()
         s.synchronize()
         res["batched_graph"] = timed(g1.replay, steps)
         res["per_array_graph"] = timed(g2.replay, steps)
+        res["persistent_graph"] = timed(g3.replay, steps)
     torch.cuda.synchronize()
     assert b.last_error() == 0
     got, got2 = G.as_unsigned(out), G.as_unsigned(out2)
     same = bool(np.array_equal(got, got2))
+    same_persistent = bool(torch.equal(out, out3))
     cap = sum(a.capacity() for a in arrays)
     for a in arrays:
         a.close()
@@ -339,7 +354,7 @@ def batched_leg(G, wl, torch, np, steps, warmup):
                         "r/w x+1, flatten to per-array offsets",
             "elements": total, "lfvectors": sum(vecs), "timings": summary,
             "capacity_over_live": cap / total, "first_bucket_choices": fhist, "stream_grid": grid,
-            "batched_equals_per_array": same}
+            "batched_equals_per_array": same, "persistent_equals_batched": same_persistent}
 
 
 def _latency(res, arrival, kind, k):
@@ -734,6 +749,45 @@ def config1_leg(G, wl, torch, reps=50):
     torch.cuda.synchronize()
     graph_us = 1e3 * e0.elapsed_time(e1) / reps
     assert a.last_error() == 0 and a.size() == size
+    ref = out.clone()
+
+    # The same step as one persistent launch (gga_batch_step on a batch of this
+    # one array: every LFVector's 4 rounds and r/w in one workgroup, then the
+    # flatten), eager and replayed as a graph; its output must equal the above.
+    b = G.Batch([a])
+    rows = [[n]] * len(gens)
+
+    def pstep():
+        a.shrink(1, 1)
+        b.step(gens, rows, G.ADD1, out)
+
+    with torch.cuda.stream(s):
+        for _ in range(5):
+            pstep()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pstep()
+        e1.record()
+    s.synchronize()
+    p_eager_us = 1e3 * e0.elapsed_time(e1) / reps
+    same = bool(torch.equal(out, ref))
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        pstep()
+    for _ in range(3):
+        g2.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g2.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    p_graph_us = 1e3 * e0.elapsed_time(e1) / reps
+    same = same and bool(torch.equal(out, ref))
+    assert a.last_error() == 0 and b.last_error() == 0
+    b.close()
     a.close()
     pool.close()
 
@@ -747,7 +801,9 @@ def config1_leg(G, wl, torch, reps=50):
     ops["flatten"] = pct(timer.ms("flatten"))
     return {"workload": "256 LFVectors, first bucket 1024, uint32, 4 rounds of 2^18 threads inserting "
                         "K(1,gid,r) with probability 1/2, r/w x+1, flatten", "final_size": size,
-            "ops": ops, "step_us_eager": eager_us, "step_us_graph": graph_us, "reps": reps}
+            "ops": ops, "step_us_eager": eager_us, "step_us_graph": graph_us, "reps": reps,
+            "persistent_step": {"us_eager": p_eager_us, "us_graph": p_graph_us, "identical": same,
+                                "what": "clear + gga_batch_step (4 rounds, r/w, flatten in one launch)"}}
 
 
 def config3_leg(G, wl, torch, steps=3, pool_gib=24, close_gen_first=True):
@@ -1243,7 +1299,8 @@ def main():
         t = batched["timings"]
         log(f"batched: one launch per phase {t['batched']['mean_ms']:.3f} ms (graph {t['batched_graph']['mean_ms']:.3f}),"
             f" per-array launches {t['per_array']['mean_ms']:.3f} ms (graph {t['per_array_graph']['mean_ms']:.3f});"
-            f" identical {batched['batched_equals_per_array']}")
+            f" one persistent launch {t['persistent']['mean_ms']:.3f} ms (graph {t['persistent_graph']['mean_ms']:.3f});"
+            f" identical {batched['batched_equals_per_array']} / {batched['persistent_equals_batched']}")
     shootout = memory_model = None
     if not args.no_shootout:
         stage("shootout, memory model")
@@ -1270,7 +1327,9 @@ def main():
             o1 = config1["ops"]
             log(f"configuration 1: step {config1['step_us_eager']:.1f} us eager, {config1['step_us_graph']:.1f} us "
                 f"as a graph; insert p50 " + ", ".join(f"{o1[f'insert{r}']['p50_us']:.1f}" for r in range(4))
-                + f" us, r/w {o1['rw']['p50_us']:.1f} us, flatten {o1['flatten']['p50_us']:.1f} us")
+                + f" us, r/w {o1['rw']['p50_us']:.1f} us, flatten {o1['flatten']['p50_us']:.1f} us; persistent step "
+                f"{config1['persistent_step']['us_eager']:.1f} us eager, {config1['persistent_step']['us_graph']:.1f} "
+                f"us as a graph (identical {config1['persistent_step']['identical']})")
         except Exception as e:  # reported, never silently dropped
             config1 = {"error": str(e)}
             log(f"configuration-1 leg failed: {e!r}\n{traceback.format_exc()}")
@@ -1415,6 +1474,8 @@ def headline(line, detail_path):
         head["batched_ms"] = _r(bt["batched"]["mean_ms"], 3)
         head["batched_graph_ms"] = _r(bt["batched_graph"]["mean_ms"], 3)
         head["per_array_ms"] = _r(bt["per_array"]["mean_ms"], 3)
+        head["batched_persistent_ms"] = _r(bt["persistent"]["mean_ms"], 3)
+        head["batched_persistent_graph_ms"] = _r(bt["persistent_graph"]["mean_ms"], 3)
     sv = line.get("served")
     if sv:
         head["served_saturation_req_s"] = _r(sv["saturation"]["req_per_s"], 0)
@@ -1429,6 +1490,8 @@ def headline(line, detail_path):
     c1 = line.get("config1") or {}
     if "step_us_eager" in c1:
         head["cfg1_step_us"] = _r(c1["step_us_eager"], 1)
+        head["cfg1_persistent_step_us"] = _r(c1["persistent_step"]["us_eager"], 1)
+        head["cfg1_persistent_graph_us"] = _r(c1["persistent_step"]["us_graph"], 1)
     out = {key: line[key] for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
                                       "higher_is_better", "scaling", "vs_baseline", "dtype", "data")}
     out["value"] = _r(out["value"], 3)

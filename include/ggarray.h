@@ -171,22 +171,25 @@ int ggarray_insert_counts(ggarray *a, const void *values, const uint8_t *counts,
  *   both contiguous, the round streams from the buffer into the buckets.  If the
  *   counts sum to more than n_values nothing is inserted and the sticky
  *   GGA_ERANGE is set.  The library keeps one offset word per 1024 logical
- *   threads (grown like the look-back words: not during graph capture). */
+ *   threads (grown like the look-back words: not during graph capture).  The
+ *   prefix sum is taken over the whole round first, so every LFVector's growth
+ *   is known before any element is copied: one launch grows the LFVectors,
+ *   the next copies, with no waits between blocks. */
 int ggarray_insert_packed(ggarray *a, const void *values, uint64_t n_values, const uint8_t *counts,
                           uint64_t n_threads, gga_stream s);
 
 /* ggarray_insert_packed_noalloc: for callers that cannot allocate device memory
  *   (code being captured into a HIP graph, tight serving loops, harnesses that
  *   forbid hipMalloc).  Same arguments and results as ggarray_insert_packed, but
- *   the call allocates nothing: the per-tile value offsets and the look-back
- *   words live in a static device array of the library (about 1 MiB, one copy
- *   per GPU, held until the process ends).  Buckets still come from the array's
- *   pool on the device.  Limit: the round may span at most 65536 tiles, a tile
- *   being 1024 logical threads of one LFVector (V * ceil(ceil(n_threads / V) /
- *   1024) <= 65536); a larger round returns GGA_ERANGE at once and queues
- *   nothing.  Every call on one GPU shares that array: calls that overlap on
- *   one GPU (other streams, other host threads) race and must not be issued;
- *   calls ordered on one stream are safe, since each clears what it reads. */
+ *   the call allocates nothing: the per-tile value offsets live in a static
+ *   device array of the library (69664 words, about 545 KiB, one copy per GPU,
+ *   held until the process ends).  Buckets still come from the array's pool on the
+ *   device.  Limit: the round may span at most 65536 tiles, a tile being 1024
+ *   logical threads of one LFVector (V * ceil(ceil(n_threads / V) / 1024) <=
+ *   65536); a larger round returns GGA_ERANGE at once and queues nothing.
+ *   Every call on one GPU shares that array: calls that overlap on one GPU
+ *   (other streams, other host threads) race and must not be issued; calls
+ *   ordered on one stream are safe, since each writes every word it reads. */
 int ggarray_insert_packed_noalloc(ggarray *a, const void *values, uint64_t n_values, const uint8_t *counts,
                                   uint64_t n_threads, gga_stream s);
 
@@ -346,6 +349,29 @@ int ggarray_device_done(ggarray *a, gga_stream s);
  *   without a table).  A launch-shape knob for tuning; results do not depend on it.
  * gga_batch_offsets: the n + 1 offsets (uint64, last = total) to dev_out.
  * gga_batch_last_error: the batch's sticky error.  Synchronises s. */
+/* gga_batch_step: a whole step of every array in ONE persistent launch:
+ *   `rounds` insertion rounds (round r runs gens[r] on array i with
+ *   n_threads[r * n + i] logical threads; kinds ROUND_TAG, BERNOULLI and KEYED;
+ *   at most 8 rounds), then x = op(x) over every live element (op GGA_RW_NONE:
+ *   none), then, unless out is NULL, the flatten of every array into out as
+ *   gga_batch_flatten writes it.  The result is that of gga_batch_insert_gen for
+ *   each round, gga_batch_rw and gga_batch_flatten in that order.  LFVectors are
+ *   independent (Sec. IV), so each workgroup takes its LFVectors through all
+ *   rounds (Sec. III-B's prefix sum per tile of 1024 logical threads, buckets
+ *   allocated on the device as in Alg. 1-2) and the r/w without waiting on
+ *   another; two grid-wide barriers give the flatten its size prefix.  The grid
+ *   is sized to be resident at once and launched cooperatively (not under graph
+ *   capture, where it is recorded as a plain launch: run nothing beside a
+ *   captured step).  Suited to many short LFVectors (each LFVector's rounds run
+ *   in one workgroup); rounds that give an LFVector many tiles are faster with
+ *   the per-round calls.  A new table of thread counts is uploaded (and s
+ *   synchronised) the first time it is seen; capturing a step needs a table an
+ *   eager step has used.  Pool exhaustion: the LFVector is frozen with the size
+ *   it had before the round, as in the per-round calls (the buckets it holds may
+ *   differ).  The flatten's GGA_ERANGE is the batch's sticky error. */
+#define GGA_RW_NONE 0xFFFFFFFFu
+int gga_batch_step(gga_batch *b, const gga_gen *gens, uint32_t rounds, const uint64_t *n_threads, uint32_t op,
+                   void *out, uint64_t out_cap_elems, gga_stream s);
 int gga_batch_create(gga_batch **out, ggarray *const *arrays, uint32_t n, gga_stream s);
 int gga_batch_destroy(gga_batch *b, gga_stream s);
 int gga_batch_insert_gen(gga_batch *b, const gga_gen *g, const uint64_t *n_threads, gga_stream s);

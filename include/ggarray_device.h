@@ -216,19 +216,20 @@ __device__ __forceinline__ uint8_t* pool_pop(PoolRef P, uint32_t cls, uint32_t s
   return nullptr;
 }
 
-// The bump pointer only moves by a successful compare-and-swap, so it never
-// passes the limit and never moves back.  (Adding first and subtracting again on
-// failure is not safe: a failed add that is undone after a smaller add has
+// One atomic add claims [old, old + bytes); a claim that runs past the limit
+// fails and is never undone, so the pointer only grows and no two claims
+// overlap (at most the tail that the first failing claim passed stays unused).
+// (Undoing failed adds is not safe: a failed add undone after a smaller add has
 // succeeded past it moves the pointer back over that block, which the next
-// allocation then receives a second time.)
+// allocation then receives a second time.  A compare-and-swap loop is safe but
+// serialises the thousands of waves that meet here when a fresh pool installs
+// its first arena chunks.)
 __device__ __forceinline__ uint8_t* global_bump(PoolRef P, uint64_t bytes) {
   PoolHdr* H = P.hdr;
   const uint64_t limit = H->limit;  // written by the host before any launch
-  uint64_t old = ld_rlx(&H->bump);
-  for (;;) {
-    if (old + bytes > limit) return nullptr;
-    if (cas_rlx(&H->bump, old, old + bytes)) return P.base + old;
-  }
+  const uint64_t old = fetch_add(&H->bump, bytes);
+  if (old + bytes > limit) return nullptr;
+  return P.base + old;
 }
 
 __device__ __forceinline__ uint8_t* arena_alloc(PoolRef P, uint32_t s, uint64_t bytes, uint32_t clog) {

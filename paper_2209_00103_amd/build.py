@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libggarray.so")
-SOURCES = ["capi.hip", "insert.hip", "access.hip", "serve.hip", "global.hip"]
+SOURCES = ["capi.hip", "insert.hip", "access.hip", "serve.hip", "global.hip", "step.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

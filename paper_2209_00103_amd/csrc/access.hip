@@ -197,26 +197,6 @@ __global__ void capacity_kernel(ArrRef A, uint64_t* out) {
   if (c) fetch_add(out, c);
 }
 
-// Per-lane 16-byte vector <-> elements.
-template <typename T>
-__device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
-  if (sizeof(T) == 4) {
-    x.x = apply_op<uint32_t>(op, x.x);
-    x.y = apply_op<uint32_t>(op, x.y);
-    x.z = apply_op<uint32_t>(op, x.z);
-    x.w = apply_op<uint32_t>(op, x.w);
-  } else {
-    uint64_t lo = ((uint64_t)x.y << 32) | x.x, hi = ((uint64_t)x.w << 32) | x.z;
-    lo = apply_op<uint64_t>(op, lo);
-    hi = apply_op<uint64_t>(op, hi);
-    x.x = (uint32_t)lo;
-    x.y = (uint32_t)(lo >> 32);
-    x.z = (uint32_t)hi;
-    x.w = (uint32_t)(hi >> 32);
-  }
-  return x;
-}
-
 // One tile: cnt (<= te) elements at src (16-byte aligned); rw in place, or copy
 // to dst (element aligned) for flatten.  Lane i of slot k handles the 16 bytes
 // at element k * (256 * VPL) + i * VPL.  Every byte is touched once, so stores

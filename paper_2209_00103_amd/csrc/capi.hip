@@ -170,11 +170,13 @@ int gga_pool_stats(gga_pool* p, uint64_t out[7], gga_stream s) {
     n_alloc += h->shard[k].n_alloc;
     n_free += h->shard[k].n_free;
   }
+  // Failed claims leave the bump pointer past the limit: carved bytes stop there.
+  const uint64_t carved = h->bump < h->limit ? h->bump : h->limit;
   out[0] = in_use;
-  out[1] = h->bump;
+  out[1] = carved;
   out[2] = n_alloc;
   out[3] = n_free;
-  out[4] = h->bump;
+  out[4] = carved;
   out[5] = h->limit;
   out[6] = h->n_attempt;
   delete h;
@@ -494,6 +496,10 @@ static void batch_free(gga_batch* b) {
   delete[] b->tables;
   if (b->tile_tab) (void)hipFree(b->tile_tab);  // hipFree waits for the device
   for (uint32_t k = 0; k < b->n_retired; ++k) (void)hipFree(b->retired[k]);
+  if (b->d_varr) (void)hipFree(b->d_varr);
+  if (b->d_step_sync) (void)hipFree(b->d_step_sync);
+  for (uint32_t k = 0; k < b->n_step_counts; ++k) (void)hipFree(b->step_counts[k].dev);
+  delete[] b->step_counts;
   delete[] b->arrays;
   delete b;
 }
@@ -532,16 +538,31 @@ int gga_batch_create(gga_batch** out, ggarray* const* arrays, uint32_t n, gga_st
     b->d_err = reinterpret_cast<uint32_t*>(b->d_vbegin + (n + 1));
     uint64_t* vb = new (std::nothrow) uint64_t[n + 1];
     ok = vb != nullptr;
+    uint32_t* varr = nullptr;
     if (ok) {
       vb[0] = 0;
       for (uint32_t i = 0; i < n; ++i) vb[i + 1] = vb[i] + arrays[i]->V;
       b->total_vectors = vb[n];
+      // the batch index of every LFVector, for the persistent step
+      varr = new (std::nothrow) uint32_t[vb[n]];
+      ok = varr != nullptr;
+      for (uint32_t i = 0; ok && i < n; ++i)
+        for (uint64_t w = vb[i]; w < vb[i + 1]; ++w) varr[w] = i;
+    }
+    const size_t step_bytes = 256 + sizeof(uint64_t) * kStepChunkMax;  // barrier words, chunk totals
+    ok = ok && hipMalloc(&b->d_varr, sizeof(uint32_t) * vb[n]) == hipSuccess &&
+         hipMalloc(&b->d_step_sync, step_bytes) == hipSuccess;
+    if (ok) {
+      b->d_step_chunks = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(b->d_step_sync) + 256);
       ok = hipMemcpyAsync(b->d_arrays, h, sizeof(BatchArr) * n, hipMemcpyHostToDevice, S(s)) == hipSuccess &&
            hipMemsetAsync(b->d_tile_begin, 0, sizeof(uint64_t) * words, S(s)) == hipSuccess &&
            hipMemcpyAsync(b->d_vbegin, vb, sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, S(s)) == hipSuccess &&
+           hipMemcpyAsync(b->d_varr, varr, sizeof(uint32_t) * vb[n], hipMemcpyHostToDevice, S(s)) == hipSuccess &&
+           hipMemsetAsync(b->d_step_sync, 0, step_bytes, S(s)) == hipSuccess &&
            hipStreamSynchronize(S(s)) == hipSuccess;
-      delete[] vb;
     }
+    delete[] vb;
+    delete[] varr;
   }
   delete[] h;
   if (!ok) {
@@ -570,6 +591,60 @@ int gga_batch_insert_gen(gga_batch* b, const gga_gen* g, const uint64_t* n_threa
       if (n_threads[i] > (1ull << g->tag_shift)) return GGA_EINVAL;
   }
   return launch_batch_insert(b, gen_desc(g, mode, 0), n_threads, S(s));
+}
+
+int gga_batch_step(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uint64_t* n_threads, uint32_t op,
+                   void* out, uint64_t out_cap_elems, gga_stream s) {
+  if (!b || rounds > kMaxStepRounds || (rounds && (!gens || !n_threads)) || (op > GGA_ADD1_X30 && op != GGA_RW_NONE))
+    return GGA_EINVAL;
+  StepDesc D{};
+  D.n_rounds = rounds;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    const gga_gen* g = &gens[r];
+    uint32_t mode = 0, maxc = 0;
+    if (g->kind != GGA_GEN_BERNOULLI && g->kind != GGA_GEN_ROUND_TAG && g->kind != GGA_GEN_KEYED) return GGA_EINVAL;
+    const int rc = check_gen(g, 0, &mode, &maxc);
+    if (rc) return rc;
+    if (g->kind == GGA_GEN_KEYED) {
+      if (((g->tag + b->n - 1) >> (48 - g->tag_shift)) != 0) return GGA_EINVAL;
+      for (uint32_t i = 0; i < b->n; ++i)
+        if (n_threads[(uint64_t)r * b->n + i] > (1ull << g->tag_shift)) return GGA_EINVAL;
+    }
+    D.r[r] = StepRound{mode, g->round, g->seed, g->tag_shift, 0, g->tag};
+  }
+  // The thread counts go to the device once per distinct table; a step recorded
+  // into a graph must use a table an eager step has uploaded.
+  const uint64_t words = (uint64_t)rounds * b->n;
+  uint64_t key = fnv1a(&rounds, sizeof(rounds), 0xCBF29CE484222325ull);
+  if (words) key = fnv1a(n_threads, sizeof(uint64_t) * words, key);
+  uint64_t* dev = nullptr;
+  for (uint32_t k = 0; k < b->n_step_counts; ++k)
+    if (b->step_counts[k].key == key) dev = b->step_counts[k].dev;
+  if (!dev) {
+    if (stream_capturing(S(s))) return GGA_EINVAL;
+    if (b->n_step_counts == b->cap_step_counts) {
+      const uint32_t ncap = b->cap_step_counts ? 2 * b->cap_step_counts : 4;
+      gga_batch::StepCounts* nt = new (std::nothrow) gga_batch::StepCounts[ncap];
+      if (!nt) return GGA_EHIP;
+      for (uint32_t k = 0; k < b->n_step_counts; ++k) nt[k] = b->step_counts[k];
+      delete[] b->step_counts;
+      b->step_counts = nt;
+      b->cap_step_counts = ncap;
+    }
+    if (hipMalloc(&dev, sizeof(uint64_t) * (words ? words : 1)) != hipSuccess) return GGA_EHIP;
+    if ((words && hipMemcpyAsync(dev, n_threads, sizeof(uint64_t) * words, hipMemcpyHostToDevice, S(s)) != hipSuccess) ||
+        hipStreamSynchronize(S(s)) != hipSuccess) {
+      (void)hipFree(dev);
+      return GGA_EHIP;
+    }
+    b->step_counts[b->n_step_counts++] = gga_batch::StepCounts{key, dev};
+  }
+  for (uint32_t i = 0; i < b->n; ++i) {
+    uint64_t add = 0;
+    for (uint32_t r = 0; r < rounds; ++r) add += n_threads[(uint64_t)r * b->n + i];
+    grow_bound(b->arrays[i], add);
+  }
+  return launch_batch_step(b, D, dev, op == GGA_RW_NONE ? kOpNone : op, out, out_cap_elems, S(s));
 }
 
 int gga_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, gga_stream s) {

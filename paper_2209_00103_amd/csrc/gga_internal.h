@@ -145,6 +145,20 @@ struct gga_batch {
   uint64_t tab_gen;
   void* retired[64];       // outgrown tables, freed with the batch
   uint32_t n_retired;
+  // Persistent step (gga_batch_step): the batch index of every LFVector, the
+  // launch's barrier words (zero between launches) and chunk totals, and the
+  // per-round thread-count tables uploaded so far (reused by shape, so that a
+  // captured step uploads nothing).
+  uint32_t* d_varr;
+  uint32_t* d_step_sync;
+  uint64_t* d_step_chunks;
+  struct StepCounts {
+    uint64_t key;
+    uint64_t* dev;
+  };
+  StepCounts* step_counts;
+  uint32_t n_step_counts;
+  uint32_t cap_step_counts;
 };
 
 struct gga_semistatic {
@@ -195,6 +209,24 @@ __device__ __forceinline__ uint32_t wave_search(const uint64_t* begins, uint32_t
   return lo;
 }
 
+// One insertion round of a persistent step (gga_batch_step).
+constexpr uint32_t kMaxStepRounds = 8;
+struct StepRound {
+  uint32_t kind;       // kModeBernoulli, kModeRoundTag or kModeKeyed
+  uint32_t round;
+  uint64_t seed;
+  uint32_t tag_shift;
+  uint32_t pad;
+  uint64_t tag;        // keyed: the batch's tag; array i adds i
+};
+struct StepDesc {
+  uint32_t n_rounds;
+  uint32_t pad;
+  StepRound r[kMaxStepRounds];
+};
+constexpr uint32_t kStepChunkMax = 1024;  // LFVector chunks of the step's size prefix
+constexpr uint32_t kOpNone = 0xFFFFFFFEu; // a step without r/w
+
 // One r/w or flatten request of a served step, on an array of its own.
 constexpr uint32_t kOpFlatten = 0xFFFFFFFFu;
 struct ServeItem {
@@ -206,11 +238,27 @@ struct ServeItem {
   uint32_t elem_log2;
 };
 
-// Tiles of an LFVector of s elements: every bucket below s contributes
-// ceil(live elements of the bucket / te) tiles.  In closed form: the nb - 1 full
-// buckets hold F 2^b elements, one tile each while F 2^b <= te and F 2^b / te
-// tiles after that (a geometric sum), and the last bucket holds the rest.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// The r/w operation on the elements of one 16-byte vector.
+template <typename T>
+__device__ __forceinline__ u32x4 op_vec(uint32_t op, u32x4 x) {
+  if (sizeof(T) == 4) {
+    x.x = apply_op<uint32_t>(op, x.x);
+    x.y = apply_op<uint32_t>(op, x.y);
+    x.z = apply_op<uint32_t>(op, x.z);
+    x.w = apply_op<uint32_t>(op, x.w);
+  } else {
+    uint64_t lo = ((uint64_t)x.y << 32) | x.x, hi = ((uint64_t)x.w << 32) | x.z;
+    lo = apply_op<uint64_t>(op, lo);
+    hi = apply_op<uint64_t>(op, hi);
+    x.x = (uint32_t)lo;
+    x.y = (uint32_t)(lo >> 32);
+    x.z = (uint32_t)hi;
+    x.w = (uint32_t)(hi >> 32);
+  }
+  return x;
+}
 
 // A 16-byte store that streams past the caches (nt) with device-scope coherence
 // (sc1).  Used by the insertion of generated payloads: on configuration 2 the r/w
@@ -260,6 +308,10 @@ __device__ __forceinline__ void shrink_vector(const ArrRef& A, uint32_t v, uint3
   if (b == 0) A.size[v] = ns;  // every lane has read the old size: one wave, program order
 }
 
+// Tiles of an LFVector of s elements: every bucket below s contributes
+// ceil(live elements of the bucket / te) tiles.  In closed form: the nb - 1 full
+// buckets hold F 2^b elements, one tile each while F 2^b <= te and F 2^b / te
+// tiles after that (a geometric sum), and the last bucket holds the rest.
 __host__ __device__ __forceinline__ uint64_t tiles_for(uint32_t log2F, uint64_t s, uint32_t te_log2) {
   const uint32_t nb = nbuckets_for(log2F, s);
   if (nb == 0) return 0;
@@ -369,6 +421,10 @@ int launch_capacity(ggarray* a, uint64_t* d_out, hipStream_t s);
 int launch_free_all(ggarray* a, hipStream_t s);
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s);
 int launch_batch_insert(gga_batch* b, const InsertDesc& d, const uint64_t* n_threads, hipStream_t s);
+// A whole step of the batch in one persistent launch (d_counts: rounds x n
+// thread counts on the device; out NULL: no flatten).
+int launch_batch_step(gga_batch* b, const StepDesc& D, const uint64_t* d_counts, uint32_t op, void* out,
+                      uint64_t out_cap, hipStream_t s);
 int launch_batch_scan(gga_batch* b, hipStream_t s);
 int launch_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, hipStream_t s);
 int launch_batch_stream(gga_batch* b, uint32_t op, void* out, uint64_t cap, bool flatten, hipStream_t s);
@@ -393,6 +449,13 @@ inline int hip_status(hipError_t e) { return e == hipSuccess ? GGA_OK : GGA_EHIP
 
 // Host upper bound of an array's size: raised by the elements a round may add,
 // dropped to zero by a full shrink, unknown (maximal) after user kernels.
+// FNV-1a over n bytes (host): keys of the uploaded round and step tables.
+inline uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001B3ull;
+  return h;
+}
+
 inline void grow_bound(ggarray* a, uint64_t n) {
   const uint64_t lim = ~0ull >> 2;
   a->size_ub = n > lim - a->size_ub ? lim : a->size_ub + n;

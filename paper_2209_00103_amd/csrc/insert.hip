@@ -29,6 +29,7 @@
 #include <hip/hip_ext.h>
 
 #include "gga_internal.h"
+#include "producers.h"
 
 namespace gga {
 namespace {
@@ -104,81 +105,6 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
   for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
   return x;
 }
-
-// ---------------------------------------------------------------- producers --
-template <typename T>
-struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
-  static constexpr bool kMulti = false;
-  static constexpr bool kDense = false;
-  const T* values;
-  const uint8_t* flags;
-  __device__ __forceinline__ bool flag(uint64_t g) const { return flags ? flags[g] != 0 : true; }
-  __device__ __forceinline__ T value(uint64_t g) const { return values[g]; }
-};
-template <typename T>
-struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
-  static constexpr bool kMulti = false;
-  static constexpr bool kDense = false;
-  uint64_t seed;
-  uint32_t round;
-  __device__ __forceinline__ bool flag(uint64_t g) const { return (K(seed, g, round) >> 63) != 0; }
-  __device__ __forceinline__ T value(uint64_t g) const { return (T)K(seed, g, round); }
-  __device__ __forceinline__ void bind(const BatchArr&) {}
-};
-template <typename T>
-struct ProdRoundTag {  // insert (round << shift) | gid
-  static constexpr bool kMulti = false;
-  static constexpr bool kDense = true;  // every thread inserts
-  uint32_t round;
-  uint32_t shift;
-  __device__ __forceinline__ bool flag(uint64_t) const { return true; }
-  __device__ __forceinline__ T value(uint64_t g) const { return (T)(((uint64_t)round << shift) | g); }
-  __device__ __forceinline__ void bind(const BatchArr&) {}
-};
-template <typename T>
-struct ProdKeyed {  // every thread inserts K(seed, (tag << shift) | gid, round)
-  static constexpr bool kMulti = false;
-  static constexpr bool kDense = true;
-  uint64_t seed;
-  uint32_t round;
-  uint32_t shift;
-  uint64_t tag;
-  __device__ __forceinline__ bool flag(uint64_t) const { return true; }
-  __device__ __forceinline__ T value(uint64_t g) const { return (T)K(seed, (tag << shift) | g, round); }
-  __device__ __forceinline__ void bind(const BatchArr& it) { tag = it.tag; }  // each array its own key
-};
-template <typename T>
-struct ProdCounts {  // insert values[gid * max + j], j < counts[gid]
-  static constexpr bool kMulti = true;
-  const T* values;
-  const uint8_t* counts;
-  uint32_t max_count;
-  __device__ __forceinline__ uint32_t count(uint64_t g) const {
-    const uint32_t c = counts[g];
-    return c < max_count ? c : max_count;
-  }
-  __device__ __forceinline__ T value(uint64_t g, uint32_t r) const {
-    return values[g * max_count + r];
-  }
-};
-template <typename T>
-struct ProdPoisson {  // c = #{k : K(seed,gid,0x80|round) >= thr[k]}; insert K(seed,gid,16 round + j)
-  static constexpr bool kMulti = true;
-  uint64_t seed;
-  uint32_t round;
-  uint32_t max_count;
-  uint64_t thr[16];
-  __device__ __forceinline__ uint32_t count(uint64_t g) const {
-    const uint64_t u = K(seed, g, 0x80u | round);
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) c += (k < (int)max_count && u >= thr[k]) ? 1u : 0u;
-    return c;
-  }
-  __device__ __forceinline__ T value(uint64_t g, uint32_t r) const {
-    return (T)K(seed, g, 16u * round + r);
-  }
-};
 
 // -------------------------------------------------------- look-back (wave 0) --
 // Exclusive prefix of tile `tile`, which is tile t > 0 of its LFVector.  Lane l
@@ -611,10 +537,10 @@ __global__ __launch_bounds__(64) void serve_front_kernel(const BatchArr* items, 
 // another and no atomic is taken outside the pool.  An LFVector whose growth
 // fails is frozen with its size unchanged (its round is dropped), as in the
 // single-kernel path.
-__device__ __forceinline__ void grow_vector(const ArrRef& A, const TileArgs& I, uint32_t v) {
+// LFVector v grows by cnt elements (one wave): every bucket the new elements
+// reach is allocated, the size moves and the old one is kept in rbase[v].
+__device__ __forceinline__ void grow_vector_by(const ArrRef& A, uint32_t elem_log2, uint32_t v, uint64_t cnt) {
   const uint32_t lane = lane_id();
-  const uint64_t c0 = (uint64_t)v * I.chunk;
-  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
   if (cnt == 0 || A.dead[v]) return;
   const uint64_t s0 = A.size[v];
   const uint32_t lo = nbuckets_for(A.log2F, s0), hi = nbuckets_for(A.log2F, s0 + cnt);
@@ -624,7 +550,7 @@ __device__ __forceinline__ void grow_vector(const ArrRef& A, const TileArgs& I, 
     if (b >= (uint32_t)kMaxBuckets) {
       failed = true;
     } else {
-      uint8_t* q = pool_alloc(A.pool, bucket_class(A.log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
+      uint8_t* q = pool_alloc(A.pool, bucket_class(A.log2F, elem_log2, b), pool_shard(v, b, A.salt));
       A.bptr[(uint64_t)v * kMaxBuckets + b] = q ? (uint64_t)q : kFailedPtr;
       failed = !q;
     }
@@ -638,6 +564,12 @@ __device__ __forceinline__ void grow_vector(const ArrRef& A, const TileArgs& I, 
     A.rbase[v] = s0;
     A.size[v] = s0 + cnt;
   }
+}
+
+__device__ __forceinline__ void grow_vector(const ArrRef& A, const TileArgs& I, uint32_t v) {
+  const uint64_t c0 = (uint64_t)v * I.chunk;
+  const uint64_t cnt = c0 < I.n_threads ? (I.n_threads - c0 < I.chunk ? I.n_threads - c0 : I.chunk) : 0;
+  grow_vector_by(A, I.elem_log2, v, cnt);
 }
 
 template <typename T, class Prod>
@@ -1031,36 +963,84 @@ __global__ __launch_bounds__(kB) void insert_count_kernel(ArrRef A, StaticRef S,
 // its elements are values[P(gid) .. P(gid) + counts[gid]), P the exclusive prefix
 // of the counts over all threads.  Tiles are those of the multi-element kernel
 // (1024 logical threads, numbered LFVector by LFVector), so a tile's values are
-// contiguous in the buffer, and its outputs are contiguous in its LFVector: once
-// the tile knows where its values start (tile_off, from the two pre-passes below)
-// and its first index (the look-back), the round is a copy from one contiguous
-// range into at most a few bucket runs.  No per-element arithmetic is left.
+// contiguous in the buffer and its outputs contiguous in its LFVector.  Two
+// pre-passes give every tile the offset of its first value (an exclusive scan of
+// the tile totals over the whole round: Sec. III-B's prefix sum, taken once for
+// all tiles instead of per block), so each LFVector's growth is known before any
+// element moves.  The round then runs as the dense rounds do: one wave per
+// LFVector allocates the buckets and moves the size (packed_grow_kernel), then
+// one workgroup per tile copies its contiguous range of values into at most a
+// few bucket runs (packed_copy_kernel), with no waits, no look-back and no
+// per-element arithmetic.
 
-// Pre-pass 1: the count total of every tile.
-__global__ __launch_bounds__(kB) void packed_tile_sums_kernel(TileArgs I, const uint8_t* counts, uint64_t* tile_sum) {
-  __shared__ uint64_t wsum[kW];
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-  const uint32_t v = (uint32_t)(blockIdx.x / I.tpv);
-  const uint64_t t = blockIdx.x - (uint64_t)v * I.tpv;
-  uint64_t g0, gend;
-  tile_range(I, v, t, kCountTile, g0, gend);
-  uint64_t c = 0;
-  for (uint32_t j = 0; j < (uint32_t)kCountK; ++j) {
-    const uint64_t g = g0 + (uint64_t)j * kB + tid;  // coalesced byte loads
-    if (g < gend) c += counts[g];
+// The offset buffer of a packed round: words [0, ntiles) hold each tile's value
+// offset within its group of kPackGroup consecutive tiles, words [ntiles,
+// ntiles + ngroups] the exclusive prefix of the group totals (the last one is
+// the round's total).
+constexpr uint32_t kPackGroup = 16;
+__host__ __device__ __forceinline__ uint64_t packed_groups(uint64_t ntiles) {
+  return (ntiles + kPackGroup - 1) / kPackGroup;
+}
+__device__ __forceinline__ uint64_t packed_offset(const uint64_t* off, uint64_t ntiles, uint64_t t) {
+  const uint64_t* gpre = off + ntiles;
+  return t < ntiles ? gpre[t / kPackGroup] + off[t] : gpre[packed_groups(ntiles)];
+}
+
+// Count total of one tile (logical threads [g0, gend), at most 1024), by one wave.
+__device__ __forceinline__ uint32_t wave_count_sum(const uint8_t* counts, uint64_t g0, uint64_t gend) {
+  const uint32_t lane = lane_id();
+  uint32_t c = 0;
+  if (gend - g0 == (uint64_t)kCountTile && (g0 & 15u) == 0) {  // whole aligned tile: 16 bytes per lane
+    const u32x4 x = *reinterpret_cast<gptr<const u32x4>>(gmem(counts + g0 + 16u * lane));
+    c = __builtin_amdgcn_sad_u8(x[0], 0u, c);  // sum of the four bytes
+    c = __builtin_amdgcn_sad_u8(x[1], 0u, c);
+    c = __builtin_amdgcn_sad_u8(x[2], 0u, c);
+    c = __builtin_amdgcn_sad_u8(x[3], 0u, c);
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < (uint32_t)kCountTile / 64; ++k) {
+      const uint64_t g = g0 + 64u * k + lane;
+      if (g < gend) c += counts[g];
+    }
   }
-  c = wave_sum64(c);
-  if (lane == 0) wsum[w] = c;
+  return (uint32_t)wave_sum64(c);
+}
+
+// Pre-pass 1: one workgroup per group of kPackGroup tiles, one wave per tile at a
+// time: tile totals, their exclusive prefix within the group (written to
+// off[tile]) and the group total (written to the group's prefix slot, which the
+// scan then turns into the prefix).
+__global__ __launch_bounds__(kB) void packed_group_kernel(TileArgs I, const uint8_t* counts, uint64_t* off,
+                                                          uint64_t ntiles) {
+  __shared__ uint32_t s_sum[kPackGroup];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint64_t first = (uint64_t)blockIdx.x * kPackGroup;
+  for (uint32_t j = w; j < kPackGroup; j += kW) {
+    const uint64_t tile = first + j;
+    uint32_t c = 0;
+    if (tile < ntiles) {
+      const uint32_t v = (uint32_t)(tile / I.tpv);
+      uint64_t g0, gend;
+      tile_range(I, v, tile - (uint64_t)v * I.tpv, kCountTile, g0, gend);
+      if (g0 < gend) c = wave_count_sum(counts, g0, gend);
+    }
+    if (lane == 0) s_sum[j] = c;
+  }
   __syncthreads();
-  if (tid == 0) {
-    uint64_t sum = 0;
-    for (int q = 0; q < kW; ++q) sum += wsum[q];
-    tile_sum[blockIdx.x] = sum;
+  if (tid < kPackGroup) {
+    uint64_t before = 0, all = 0;
+    for (uint32_t q = 0; q < kPackGroup; ++q) {
+      before += q < tid ? s_sum[q] : 0u;
+      all += s_sum[q];
+    }
+    if (first + tid < ntiles) off[first + tid] = before;
+    if (tid == 0) off[ntiles + blockIdx.x] = all;
   }
 }
 
-// Pre-pass 2: exclusive prefix of the tile totals in place (one workgroup of 1024
-// threads, 8 consecutive tiles per thread and pass); entry ntiles gets the total.
+// Pre-pass 2: exclusive prefix of the group totals in place (one workgroup of
+// 1024 threads, 8 consecutive groups per thread and pass); entry ntiles gets the
+// total.
 __global__ __launch_bounds__(1024) void packed_tile_scan_kernel(uint64_t* tile_off, uint64_t ntiles) {
   __shared__ uint64_t wtot[16];
   __shared__ uint64_t carry_s;
@@ -1103,7 +1083,7 @@ __global__ __launch_bounds__(1024) void packed_tile_scan_kernel(uint64_t* tile_o
 template <typename T>
 __device__ __forceinline__ void block_copy(T* dst_, const T* src_, uint32_t n) {
   typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
-  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T), kU = 4;
+  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T), kU = 8;
   const uint32_t tid = threadIdx.x;
   const gptr<T> dst = gmem(dst_);
   const gptr<const T> src = gmem(src_);
@@ -1112,83 +1092,62 @@ __device__ __forceinline__ void block_copy(T* dst_, const T* src_, uint32_t n) {
   if (head > n) head = n;
   if (tid < head) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tid), dst + tid);
   const uint32_t nv = (n - head) / VPL;
-  uint32_t q = tid;
-  for (; q + (kU - 1) * kB < nv; q += kU * kB) {  // kU vectors in flight per thread
+  // kU vectors per thread in flight before the first store: a tile of the
+  // configuration-3 round (about 24 KiB) is read in one pass.
+  for (uint32_t q0 = 0; q0 < nv; q0 += kU * kB) {
     u32x4 x[kU];
 #pragma unroll
-    for (uint32_t k = 0; k < kU; ++k)
-      x[k] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + (q + k * kB) * VPL));
+    for (uint32_t k = 0; k < kU; ++k) {
+      const uint32_t q = q0 + k * kB + tid;
+      if (q < nv) x[k] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + q * VPL));
+    }
 #pragma unroll
-    for (uint32_t k = 0; k < kU; ++k)
-      __builtin_nontemporal_store(x[k], reinterpret_cast<gptr<u32x4>>(dst + head + (q + k * kB) * VPL));
-  }
-  for (; q < nv; q += kB) {
-    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + q * VPL));
-    __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+    for (uint32_t k = 0; k < kU; ++k) {
+      const uint32_t q = q0 + k * kB + tid;
+      if (q < nv) __builtin_nontemporal_store(x[k], reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+    }
   }
   const uint32_t tail = head + nv * VPL + tid;
   if (tail < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tail), dst + tail);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kB) void insert_packed_kernel(ArrRef A, TileArgs I, const T* values, const uint8_t* counts,
-                                                           const uint64_t* tile_off, uint64_t ntiles,
-                                                           uint64_t n_values) {
-  __shared__ TileShared sh;
-  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-  const bool ticketed = I.tpv > 1;
-  const uint32_t v = (uint32_t)(blockIdx.x / I.tpv);
-  uint64_t t = blockIdx.x - (uint64_t)v * I.tpv;
-  uint64_t k = 0;
-  if (ticketed && tid == 0) k = take_ticket(A, v);
-  uint64_t g0, gend;
-  tile_range(I, v, t, kCountTile, g0, gend);
-  if (ticketed && tid == 0) {
-    sh.tile = k;
-    settle_ticket(A, v, k, I.tpv);
-  }
-  __syncthreads();
-  const uint64_t epoch = ticketed ? sh.tile >> 32 : 0;
-  if (ticketed && (sh.tile & 0xFFFFFFFFull) != t) {  // dispatched out of order: take the ticket's tile
-    t = sh.tile & 0xFFFFFFFFull;
-    tile_range(I, v, t, kCountTile, g0, gend);
-  }
-  // Every block takes and settles its ticket before this uniform exit, so the
-  // LFVectors' epochs advance as in any other launch.
-  if (tile_off[ntiles] > n_values) {  // the counts ask for more values than given
-    if (blockIdx.x == 0 && tid == 0) set_error(A.err, kErrRange);
+// Phase 1: LFVector v grows by the values of its tiles v tpv .. (v + 1) tpv - 1
+// (one wave per LFVector).  Counts asking for more values than given insert
+// nothing.
+__global__ __launch_bounds__(256) void packed_grow_kernel(ArrRef A, TileArgs I, const uint64_t* off,
+                                                          uint64_t ntiles, uint64_t n_values) {
+  const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (packed_offset(off, ntiles, ntiles) > n_values) {
+    if (v == 0 && lane_id() == 0) set_error(A.err, kErrRange);
     return;
   }
-  if (g0 >= gend) return;
-  const bool is_last = g0 + kCountTile >= gend;
-  uint32_t c = 0;
-  for (uint32_t j = 0; j < (uint32_t)kCountK; ++j) {
-    const uint64_t g = g0 + (uint64_t)j * kB + tid;
-    if (g < gend) c += counts[g];
-  }
-  c = (uint32_t)wave_sum64(c);
-  if (lane == 0) sh.cnt[w] = c;
-  if (tid == 0) sh.frozen = ld_rlx32(&A.dead[v]);
-  __syncthreads();
-  if (sh.frozen) return;  // block-uniform
-  uint32_t n_t = 0;
-#pragma unroll
-  for (int q = 0; q < kW; ++q) n_t += sh.cnt[q];
-  const uint64_t tile = (uint64_t)v * I.tpv + t;
-  if (w == 0) resolve_tile(A, I, v, t, tile, is_last, n_t, epoch, sh);
-  __syncthreads();
-  const uint32_t n_out = sh.n_tile;  // 0 if stalled
-  const uint64_t base = sh.base;
-  const T* src = values + tile_off[tile];
+  if (v >= A.V) return;
+  const uint64_t t0 = (uint64_t)v * I.tpv;
+  grow_vector_by(A, I.elem_log2, v, packed_offset(off, ntiles, t0 + I.tpv) - packed_offset(off, ntiles, t0));
+}
+
+// Phase 2: tile t of LFVector v copies its values to rbase[v] + (its offset
+// within the LFVector's share of the round).
+template <typename T>
+__global__ __launch_bounds__(kB) void packed_copy_kernel(ArrRef A, TileArgs I, const T* values,
+                                                         const uint64_t* tile_off, uint64_t ntiles,
+                                                         uint64_t n_values) {
+  const uint64_t tile = blockIdx.x;
+  const uint32_t v = (uint32_t)(tile / I.tpv);
+  const uint64_t off = packed_offset(tile_off, ntiles, tile);
+  const uint32_t n = (uint32_t)(packed_offset(tile_off, ntiles, tile + 1) - off);
+  if (n == 0 || packed_offset(tile_off, ntiles, ntiles) > n_values || A.dead[v]) return;  // frozen: before or by this round
   const uint32_t log2F = A.log2F;
-  for (uint32_t i = 0; i < n_out;) {  // one run per bucket the tile's outputs reach
+  const uint64_t base = A.rbase[v] + (off - packed_offset(tile_off, ntiles, (uint64_t)v * I.tpv));
+  const T* src = values + off;
+  for (uint32_t i = 0; i < n;) {  // one run per bucket the tile's outputs reach
     const uint64_t idx = base + i;
     const uint32_t b = bucket_of(log2F, idx);
     const uint64_t bs = bucket_start(log2F, b);
     const uint64_t room = bs + bucket_len(log2F, b) - idx;
-    const uint32_t run = (uint64_t)(n_out - i) < room ? n_out - i : (uint32_t)room;
-    const uint64_t p = sh.bp[b - sh.b_lo];
-    if (p > kFailedPtr) block_copy<T>(reinterpret_cast<T*>(p) + (idx - bs), src + i, run);
+    const uint32_t run = (uint64_t)(n - i) < room ? n - i : (uint32_t)room;
+    T* dst = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + (idx - bs);
+    block_copy<T>(dst, src + i, run);
     i += run;
   }
 }
@@ -1385,7 +1344,7 @@ int launch_insert_segments(ggarray* a, const void* values, const uint64_t* prefi
   return hip_status(e);
 }
 
-// Per-tile value offsets of a packed round: ntiles + 1 words, grown like the
+// Value offsets of a packed round (ntiles + ngroups + 1 words), grown like the
 // look-back words (nothing is allocated while the stream is capturing).
 static int ensure_packed_offsets(ggarray* a, uint64_t words, hipStream_t s) {
   if (words <= a->pk_cap) return GGA_OK;
@@ -1402,19 +1361,22 @@ static int ensure_packed_offsets(ggarray* a, uint64_t words, hipStream_t s) {
   return GGA_OK;
 }
 
-// The kernels of one packed round: tile totals, their prefix (off: ntiles + 1
-// words), then the copy.  A.status holds the look-back words when tpv > 1.
-static int queue_packed(ggarray* a, const ArrRef& A, uint64_t* off, const void* values, const uint8_t* counts,
-                        const TileArgs& I, uint64_t ntiles, uint64_t n_values, hipStream_t s) {
+// The kernels of one packed round: tile totals and their prefix (off: ntiles +
+// ngroups + 1 words), the growth of every LFVector, then the copy.
+static int queue_packed(ggarray* a, uint64_t* off, const void* values, const uint8_t* counts, const TileArgs& I,
+                        uint64_t ntiles, uint64_t n_values, hipStream_t s) {
   grow_bound(a, n_values);
-  hipLaunchKernelGGL(packed_tile_sums_kernel, dim3((uint32_t)ntiles), dim3(kB), 0, s, I, counts, off);
-  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off, ntiles);
+  const uint64_t ngroups = packed_groups(ntiles);
+  hipLaunchKernelGGL(packed_group_kernel, dim3((uint32_t)ngroups), dim3(kB), 0, s, I, counts, off, ntiles);
+  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off + ntiles, ngroups);
+  hipLaunchKernelGGL(packed_grow_kernel, dim3((a->V + 3) / 4), dim3(256), 0, s, a->ref, I, (const uint64_t*)off,
+                     ntiles, n_values);
   if (a->elem_bytes == 4)
-    hipLaunchKernelGGL(insert_packed_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, A, I,
-                       static_cast<const uint32_t*>(values), counts, (const uint64_t*)off, ntiles, n_values);
+    hipLaunchKernelGGL(packed_copy_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
+                       static_cast<const uint32_t*>(values), (const uint64_t*)off, ntiles, n_values);
   else
-    hipLaunchKernelGGL(insert_packed_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, A, I,
-                       static_cast<const uint64_t*>(values), counts, (const uint64_t*)off, ntiles, n_values);
+    hipLaunchKernelGGL(packed_copy_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
+                       static_cast<const uint64_t*>(values), (const uint64_t*)off, ntiles, n_values);
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);
@@ -1442,24 +1404,18 @@ int launch_insert_packed(ggarray* a, const void* values, const uint8_t* counts, 
   uint64_t ntiles = 0;
   int rc = packed_geometry(a, n_threads, I, ntiles);
   if (rc) return rc;
-  if (I.tpv > 1) {
-    rc = ensure_status(a, ntiles, s);
-    if (rc) return rc;
-  }
-  rc = ensure_packed_offsets(a, ntiles + 1, s);
+  rc = ensure_packed_offsets(a, ntiles + packed_groups(ntiles) + 1, s);
   if (rc) return rc;
-  return queue_packed(a, a->ref, a->pk_off, values, counts, I, ntiles, n_values, s);
+  return queue_packed(a, a->pk_off, values, counts, I, ntiles, n_values, s);
 }
 
 // ------------------------------------------- packed round without allocation --
-// The tile offsets and look-back words of ggarray_insert_packed_noalloc live in
-// this file-scope array: each device holds its own copy for the life of the
-// process.  Words [0, kNoAllocTiles + 1) take the tile offsets, words from
-// kScratchStatus on the look-back words.  Host code never passes the symbol
-// itself to a kernel: its device address is looked up once per device and kept.
+// The tile offsets of ggarray_insert_packed_noalloc (ntiles + ngroups + 1 words)
+// live in this file-scope array: each device holds its own copy for the life of
+// the process.  Host code never passes the symbol itself to a kernel: its device
+// address is looked up once per device and kept.
 constexpr uint64_t kNoAllocTiles = 65536;
-constexpr uint64_t kScratchStatus = kNoAllocTiles + 32;  // 256-byte aligned
-constexpr uint64_t kScratchWords = kScratchStatus + kNoAllocTiles;
+constexpr uint64_t kScratchWords = kNoAllocTiles + kNoAllocTiles / kPackGroup + 32;  // whole 256-byte lines
 static __device__ __align__(256) uint64_t scratch[kScratchWords];
 
 constexpr int kMaxScratchDevices = 64;
@@ -1484,13 +1440,6 @@ static int scratch_base(uint64_t** out) {
   return GGA_OK;
 }
 
-// Zero words (look-back words: a zero word is never current).  A kernel, not a
-// memset, so that the round can also be recorded into a graph.
-__global__ __launch_bounds__(256) void zero_words_kernel(uint64_t* p, uint64_t n) {
-  const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = 0;
-}
-
 int launch_insert_packed_noalloc(ggarray* a, const void* values, const uint8_t* counts, uint64_t n_threads,
                                  uint64_t n_values, hipStream_t s) {
   a->tev_set &= ~4u;
@@ -1503,14 +1452,7 @@ int launch_insert_packed_noalloc(ggarray* a, const void* values, const uint8_t* 
   uint64_t* sc = nullptr;
   rc = scratch_base(&sc);
   if (rc) return rc;
-  ArrRef A = a->ref;
-  if (I.tpv > 1) {
-    // The words may hold another array's (or an earlier round's) words of the same
-    // epoch: cleared first, so none is current.
-    A.status = sc + kScratchStatus;
-    hipLaunchKernelGGL(zero_words_kernel, dim3((uint32_t)((ntiles + 255) / 256)), dim3(256), 0, s, A.status, ntiles);
-  }
-  return queue_packed(a, A, sc, values, counts, I, ntiles, n_values, s);
+  return queue_packed(a, sc, values, counts, I, ntiles, n_values, s);  // every word it reads is written first
 }
 
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {
@@ -1587,11 +1529,6 @@ int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
 
 
 namespace {
-uint64_t fnv1a(const void* p, size_t n, uint64_t h) {
-  const uint8_t* b = static_cast<const uint8_t*>(p);
-  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001B3ull;
-  return h;
-}
 }  // namespace
 
 int prepare_round_item(ggarray* a, uint64_t n, uint64_t tag, uint32_t index, BatchArr* item, uint64_t* ntiles,

@@ -1,0 +1,382 @@
+// A whole step of a batch in one persistent launch: insertion rounds, r/w and
+// flatten of every array.
+//
+// LFVectors are independent (Sec. IV: each is grown by its own block, and no
+// operation but the size prefix looks across them), so one workgroup can take an
+// LFVector through all of its insertion rounds and its r/w without waiting for
+// anyone: it reads the LFVector's size and bucket table once, runs each round's
+// tiles of 1024 candidates in order (Sec. III-B's block prefix sum over the
+// tile, one index range claimed per tile, buckets allocated by the workgroup
+// itself as Alg. 1 and 2 do), and applies the r/w to the elements it has just
+// written, which are still in the cache.  Workgroup w takes LFVectors w, w + G,
+// ... of the batch (arrays in order, each array's LFVectors in order).
+//
+// The flatten needs the exclusive prefix of every LFVector's size, so two
+// grid-wide barriers follow: after the first, chunks of consecutive LFVectors
+// are summed; after the second, each workgroup scans the chunk totals and
+// copies its own LFVectors to their places.  A workgroup copies the LFVectors it
+// wrote itself, so element data never crosses workgroups; the sizes and the
+// chunk totals do, through device-scope atomic loads and stores.  The grid is no
+// larger than what the device holds at once (an occupancy query), and the
+// launch is cooperative, so every workgroup reaches the barriers; every wait is
+// still bounded.
+#include <hip/hip_cooperative_groups.h>
+
+#include "gga_internal.h"
+#include "producers.h"
+
+namespace gga {
+namespace {
+
+constexpr uint32_t kSB = 256;            // threads per workgroup
+constexpr uint32_t kSW = kSB / 64;       // waves per workgroup
+constexpr uint32_t kSSlots = 4;          // candidates per thread and tile
+constexpr uint32_t kSTile = kSB * kSSlots;
+
+__device__ __forceinline__ uint32_t s_lane() { return threadIdx.x & 63u; }
+__device__ __forceinline__ uint32_t s_mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+struct StepShared {
+  uint64_t bp[kMaxBuckets];   // the LFVector's bucket pointers
+  uint64_t size;
+  uint32_t cnt[kSSlots * kSW];
+  uint32_t fail;
+  uint32_t dead;
+  uint64_t red[kSW];
+};
+
+// One round on LFVector v: logical threads c0 .. c0 + cnt - 1 of the round, in
+// tiles of 1024 (slot j of thread t is logical thread t0 + 256 j + t, so the
+// order (slot, wave, lane) is the logical order).  Returns false if a bucket
+// could not be allocated; the caller then restores the size the round started
+// from and freezes the LFVector.
+template <typename T, class Prod>
+__device__ bool step_round(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint64_t c0, uint64_t cnt,
+                           const Prod& prod, StepShared& sh) {
+  const uint32_t tid = threadIdx.x, lane = s_lane(), w = tid >> 6;
+  const uint32_t log2F = A.log2F;
+  uint64_t s = sh.size;
+  for (uint64_t t0 = 0; t0 < cnt; t0 += kSTile) {
+    T val[kSSlots];
+    uint32_t rank[kSSlots];
+    uint32_t fl = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < kSSlots; ++j) {
+      const uint64_t local = t0 + (uint64_t)j * kSB + tid;
+      val[j] = 0;
+      if (local < cnt && prod.take(c0 + local, val[j])) fl |= 1u << j;
+      const uint64_t m = __ballot((fl >> j) & 1u);
+      rank[j] = s_mbcnt(m);
+      if (lane == 0) sh.cnt[j * kSW + w] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t total = 0;
+    uint32_t before[kSSlots];
+#pragma unroll
+    for (uint32_t j = 0; j < kSSlots; ++j) {
+      before[j] = total;
+      for (uint32_t q = 0; q < kSW; ++q) {
+        const uint32_t c = sh.cnt[j * kSW + q];
+        before[j] += q < w ? c : 0u;
+        total += c;
+      }
+    }
+    // Buckets whose first index this tile writes: allocated by wave 0, one per lane.
+    if (w == 0) {
+      const uint32_t lo = nbuckets_for(log2F, s), hi = nbuckets_for(log2F, s + total);
+      const uint32_t b = lo + lane;
+      bool failed = false;
+      if (b < hi) {
+        if (b >= (uint32_t)kMaxBuckets) {
+          failed = true;
+        } else {
+          uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, elem_log2, b), pool_shard(v, b, A.salt));
+          const uint64_t p = q ? (uint64_t)q : kFailedPtr;
+          A.bptr[(uint64_t)v * kMaxBuckets + b] = p;
+          sh.bp[b] = p;
+          failed = !q;
+        }
+      }
+      if (lane == 0) sh.fail = __ballot(failed) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (sh.fail) return false;
+#pragma unroll
+    for (uint32_t j = 0; j < kSSlots; ++j) {
+      if ((fl >> j) & 1u) {
+        const uint64_t idx = s + before[j] + rank[j];
+        const uint32_t b = bucket_of(log2F, idx);
+        gmem(reinterpret_cast<T*>(sh.bp[b]))[offset_in(log2F, idx, b)] = val[j];
+      }
+    }
+    s += total;
+    __syncthreads();  // sh.cnt is rewritten by the next tile
+  }
+  sh.size = s;
+  return true;
+}
+
+// x = op(x) over the live elements of LFVector v (sh.bp, sh.size current).
+template <typename T>
+__device__ void step_rw(uint32_t log2F, uint32_t op, const StepShared& sh) {
+  constexpr uint32_t VPL = 16 / sizeof(T);
+  const uint64_t s = sh.size;
+  for (uint32_t b = 0; b < (uint32_t)kMaxBuckets && bucket_start(log2F, b) < s; ++b) {
+    const uint64_t st = bucket_start(log2F, b);
+    const uint64_t len = bucket_len(log2F, b);
+    const uint32_t live = (uint32_t)(s - st < len ? s - st : len);
+    const gptr<T> p = gmem(reinterpret_cast<T*>(sh.bp[b]));  // 256-byte aligned
+    const uint32_t nv = live / VPL;
+    for (uint32_t q = threadIdx.x; q < nv; q += kSB) {
+      const gptr<u32x4> a = reinterpret_cast<gptr<u32x4>>(p + (uint64_t)q * VPL);
+      *a = op_vec<T>(op, *a);
+    }
+    const uint32_t e = nv * VPL + threadIdx.x;
+    if (e < live) p[e] = apply_op<T>(op, p[e]);
+  }
+}
+
+// n elements from src to dst by the workgroup: stores aligned to dst's 128-byte
+// lines, loads taking src's alignment.
+template <typename T>
+__device__ void step_copy(T* dst_, const T* src_, uint32_t n) {
+  typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
+  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T);
+  const uint32_t tid = threadIdx.x;
+  const gptr<T> dst = gmem(dst_);
+  const gptr<const T> src = gmem(src_);
+  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst_) & 127u) / sizeof(T));
+  uint32_t head = mis ? kLine - mis : 0u;
+  if (head > n) head = n;
+  if (tid < head) __builtin_nontemporal_store(src[tid], dst + tid);
+  const uint32_t nv = (n - head) / VPL;
+  for (uint32_t q = tid; q < nv; q += kSB) {
+    const u32x4 x = *reinterpret_cast<gptr<const u32x4_a4>>(src + head + q * VPL);
+    __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+  }
+  const uint32_t tail = head + nv * VPL + tid;
+  if (tail < n) __builtin_nontemporal_store(src[tail], dst + tail);
+}
+
+// Grid-wide barrier: arrival after every earlier store of the workgroup has
+// completed (the workgroup barrier waits for them, and the stores that other
+// workgroups read are device-scope), then a bounded wait for all G arrivals.
+__device__ void step_barrier(uint32_t* ctr, uint32_t G, uint32_t spin, uint32_t* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // waits for the wave's stores to complete
+    fetch_add32(ctr, 1u);
+    for (uint32_t n = 0; ld_rlx32(ctr) < G; ++n) {
+      if (n >= spin) {
+        set_error(err, kErrStall);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
+// Block-wide sum of one value per thread.
+__device__ uint64_t step_block_sum(uint64_t x, StepShared& sh) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  __syncthreads();
+  if (s_lane() == 0) sh.red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  uint64_t t = 0;
+  for (uint32_t q = 0; q < kSW; ++q) t += sh.red[q];
+  return t;
+}
+
+__device__ __forceinline__ uint64_t vec_size(const BatchArr* arrs, const uint32_t* varr, const uint64_t* vbegin,
+                                             uint64_t w) {
+  const uint32_t i = varr[w];
+  return ld_rlx(&arrs[i].A.size[w - vbegin[i]]);
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const uint32_t* varr, const uint64_t* vbegin,
+                                                   uint64_t total_v, StepDesc D, const uint64_t* counts, uint32_t n_arr,
+                                                   uint32_t op, T* out, uint64_t out_cap, uint32_t* sync,
+                                                   uint64_t* chunk_sum, uint64_t chunk_len, uint32_t* berr,
+                                                   uint32_t spin) {
+  __shared__ StepShared sh;
+  __shared__ uint64_t cpre[kStepChunkMax];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t G = gridDim.x;
+
+  // Phase A: rounds and r/w, LFVector by LFVector.
+  for (uint64_t wv = blockIdx.x; wv < total_v; wv += G) {
+    const uint32_t i = varr[wv];
+    const ArrRef A = arrs[i].A;
+    const uint32_t elem_log2 = arrs[i].elem_log2;
+    const uint32_t v = (uint32_t)(wv - vbegin[i]);
+    if (tid < (uint32_t)kMaxBuckets) sh.bp[tid] = A.bptr[(uint64_t)v * kMaxBuckets + tid];
+    if (tid == 0) {
+      sh.size = A.size[v];
+      sh.dead = A.dead[v];
+    }
+    __syncthreads();
+    bool changed = false;
+    for (uint32_t r = 0; r < D.n_rounds && !sh.dead; ++r) {
+      const uint64_t nthr = counts[(uint64_t)r * n_arr + i];
+      const uint64_t chunk = (nthr + A.V - 1) / A.V;
+      const uint64_t c0 = (uint64_t)v * chunk;
+      const uint64_t cnt = c0 < nthr ? (nthr - c0 < chunk ? nthr - c0 : chunk) : 0;
+      if (cnt == 0) continue;
+      const StepRound& R = D.r[r];
+      const uint64_t s_round = sh.size;
+      bool ok;
+      if (R.kind == kModeBernoulli)
+        ok = step_round<T>(A, v, elem_log2, c0, cnt, ProdBernoulli<T>{R.seed, R.round}, sh);
+      else if (R.kind == kModeRoundTag)
+        ok = step_round<T>(A, v, elem_log2, c0, cnt, ProdRoundTag<T>{R.round, R.tag_shift}, sh);
+      else
+        ok = step_round<T>(A, v, elem_log2, c0, cnt, ProdKeyed<T>{R.seed, R.round, R.tag_shift, R.tag + i}, sh);
+      changed = true;
+      if (!ok) {  // the round is dropped and the LFVector frozen, as in the per-round calls
+        if (tid == 0) {
+          sh.size = s_round;
+          sh.dead = 1;
+          A.dead[v] = 1u;
+          set_error(A.err, kErrNoMem);
+        }
+        __syncthreads();
+      }
+    }
+    if (changed && tid == 0) st_rlx(&A.size[v], sh.size);
+    if (op != kOpNone) step_rw<T>(A.log2F, op, sh);
+    __syncthreads();  // sh is reloaded for the next LFVector
+  }
+
+  if (out) {
+    // Phase B: totals of chunks of chunk_len consecutive LFVectors.
+    step_barrier(&sync[0], G, spin, berr);
+    const uint64_t nchunks = (total_v + chunk_len - 1) / chunk_len;
+    for (uint64_t c = blockIdx.x; c < nchunks; c += G) {
+      uint64_t x = 0;
+      for (uint64_t wv = c * chunk_len + tid; wv < total_v && wv < (c + 1) * chunk_len; wv += kSB)
+        x += vec_size(arrs, varr, vbegin, wv);
+      x = step_block_sum(x, sh);
+      if (tid == 0) st_rlx(&chunk_sum[c], x);
+    }
+    step_barrier(&sync[1], G, spin, berr);
+
+    // Phase C: every workgroup scans the chunk totals (nchunks <= kStepChunkMax:
+    // four per thread), then copies its own LFVectors to their places.
+    constexpr uint32_t kPer = kStepChunkMax / kSB;
+    uint64_t x[kPer], sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      const uint64_t c = (uint64_t)tid * kPer + k;
+      x[k] = c < nchunks ? ld_rlx(&chunk_sum[c]) : 0;
+      sum += x[k];
+    }
+    uint64_t incl = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint64_t y = __shfl_up(incl, d, 64);
+      if (s_lane() >= (uint32_t)d) incl += y;
+    }
+    if (s_lane() == 63) sh.red[tid >> 6] = incl;
+    __syncthreads();
+    uint64_t run = incl - sum, total = 0;
+    for (uint32_t q = 0; q < kSW; ++q) {
+      run += q < (tid >> 6) ? sh.red[q] : 0;
+      total += sh.red[q];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      cpre[tid * kPer + k] = run;
+      run += x[k];
+    }
+    __syncthreads();
+    if (total > out_cap) {
+      if (blockIdx.x == 0 && tid == 0) set_error(berr, kErrRange);
+    } else {
+      for (uint64_t wv = blockIdx.x; wv < total_v; wv += G) {
+        const uint32_t i = varr[wv];
+        const ArrRef& A = arrs[i].A;
+        const uint32_t v = (uint32_t)(wv - vbegin[i]);
+        // the chunk's prefix plus the LFVectors of the chunk before this one
+        const uint64_t c = wv / chunk_len;
+        uint64_t y = 0;
+        for (uint64_t u = c * chunk_len + tid; u < wv; u += kSB) y += vec_size(arrs, varr, vbegin, u);
+        const uint64_t off = cpre[c] + step_block_sum(y, sh);
+        const uint64_t sz = ld_rlx(&A.size[v]);
+        T* dst = out + off;
+        for (uint32_t b = 0; b < (uint32_t)kMaxBuckets && bucket_start(A.log2F, b) < sz; ++b) {
+          const uint64_t st = bucket_start(A.log2F, b);
+          const uint64_t len = bucket_len(A.log2F, b);
+          const uint32_t live = (uint32_t)(sz - st < len ? sz - st : len);
+          step_copy<T>(dst + st, reinterpret_cast<const T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]), live);
+        }
+      }
+    }
+  }
+
+  // The last workgroup out clears the barrier words for the next launch.
+  __syncthreads();
+  if (tid == 0 && fetch_add32(&sync[2], 1u) == G - 1) {
+    st_rlx32(&sync[0], 0u);
+    st_rlx32(&sync[1], 0u);
+    st_rlx32(&sync[2], 0u);
+  }
+}
+
+// ------------------------------------------------------------------- host --
+namespace {
+
+template <typename T>
+int queue_step(gga_batch* b, const StepDesc& D, const uint64_t* d_counts, uint32_t op, void* out, uint64_t out_cap,
+               hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&step_kernel<T>), kSB, 0) !=
+          hipSuccess)
+    return GGA_EHIP;
+  uint64_t G = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
+  if (G > b->total_vectors) G = b->total_vectors;
+  if (G < 1) G = 1;
+  const uint64_t chunk_len = (b->total_vectors + kStepChunkMax - 1) / kStepChunkMax;
+  const BatchArr* arrs = b->d_arrays;
+  const uint32_t* varr = b->d_varr;
+  const uint64_t* vbegin = b->d_vbegin;
+  uint64_t total_v = b->total_vectors;
+  uint32_t n_arr = b->n;
+  T* o = static_cast<T*>(out);
+  uint32_t* sync = b->d_step_sync;
+  uint64_t* chunk_sum = b->d_step_chunks;
+  uint32_t* berr = b->d_err;
+  uint32_t spin = kSpinLimit;
+  StepDesc desc = D;
+  uint64_t clen = chunk_len;
+  void* args[] = {&arrs, &varr, &vbegin, &total_v, &desc, &d_counts, &n_arr, &op, &o, &out_cap,
+                  &sync, &chunk_sum, &clen, &berr, &spin};
+  hipError_t e;
+  if (stream_capturing(s))  // recorded as a plain launch; the grid still fits the device at once
+    e = hipLaunchKernel(reinterpret_cast<const void*>(&step_kernel<T>), dim3((uint32_t)G), dim3(kSB), args, 0, s);
+  else
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&step_kernel<T>), dim3((uint32_t)G), dim3(kSB),
+                                   args, 0, s);
+  return hip_status(e);
+}
+
+}  // namespace
+
+int launch_batch_step(gga_batch* b, const StepDesc& D, const uint64_t* d_counts, uint32_t op, void* out,
+                      uint64_t out_cap, hipStream_t s) {
+  const int rc = b->elem_bytes == 4 ? queue_step<uint32_t>(b, D, d_counts, op, out, out_cap, s)
+                                    : queue_step<uint64_t>(b, D, d_counts, op, out, out_cap, s);
+  if (rc == GGA_OK)
+    for (uint32_t i = 0; i < b->n; ++i) sizes_changed(b->arrays[i], s);
+  return rc;
+}
+
+}  // namespace gga

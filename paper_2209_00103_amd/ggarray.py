@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libggarray.so")
 
 OK, EINVAL, ENOMEM, ERANGE, EHIP, EBUSY = 0, -1, -2, -3, -4, -5
 ADD1, MUL3ADD1, ADD1_X30 = 0, 1, 2
+RW_NONE = 0xFFFFFFFF  # a step without r/w
 GEN_BERNOULLI, GEN_ROUND_TAG, GEN_POISSON, GEN_KEYED = 1, 2, 3, 4
 REQ_APPEND, REQ_RW, REQ_FLATTEN = 0, 1, 2
 SERVE_BATCHED, SERVE_PER_REQUEST = 0, 1
@@ -90,6 +91,7 @@ _SIGS = {
     "gga_batch_create": [_P(_vp), _vp, _u32, _vp],
     "gga_batch_destroy": [_vp, _vp],
     "gga_batch_insert_gen": [_vp, _P(GenSpec), _vp, _vp],
+    "gga_batch_step": [_vp, _vp, _u32, _vp, _u32, _vp, _u64, _vp],
     "gga_batch_shrink": [_vp, _u32, _u32, _vp],
     "gga_batch_rw": [_vp, _u32, _vp],
     "gga_batch_flatten": [_vp, _vp, _u64, _vp],
@@ -406,6 +408,23 @@ class Batch:
             self._counts[key] = arr
         _check(lib().gga_batch_insert_gen(self._h, ctypes.byref(gen), arr, _stream(stream)),
                "gga_batch_insert_gen")
+
+    def step(self, gens, n_threads, op: int, out: torch.Tensor | None = None, stream=None):
+        """One persistent launch: rounds gens[r] with n_threads[r][i] threads on array i,
+        r/w op (RW_NONE: none), then the flatten into out (None: no flatten)."""
+        rounds = len(gens)
+        flat = tuple(int(x) for row in n_threads for x in row)
+        if len(flat) != rounds * self.n:
+            raise ValueError("n_threads needs one row of n counts per round")
+        key = ("step", flat)
+        arr = self._counts.get(key)
+        if arr is None:
+            arr = (_u64 * max(1, len(flat)))(*flat)
+            self._counts[key] = arr
+        g = (GenSpec * max(1, rounds))(*gens)
+        op_ = _dev_ptr(out, "out", 0, self.arrays[0].elem_bytes) if out is not None else None
+        _check(lib().gga_batch_step(self._h, g, rounds, arr, op, op_, 0 if out is None else out.numel(),
+                                    _stream(stream)), "gga_batch_step")
 
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().gga_batch_shrink(self._h, num, den, _stream(stream)), "gga_batch_shrink")

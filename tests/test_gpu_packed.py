@@ -100,3 +100,40 @@ def test_packed_poisson_equals_generated(pool):
         assert torch.equal(gen_arr.flatten(), pk_arr.flatten())
     gen_arr.close()
     pk_arr.close()
+
+
+@pytest.mark.parametrize("V", [65536, 512])
+def test_packed_full_size_equals_generated(V):
+    """Configuration 3 at full size (2^26 threads, Poisson(3) counts capped at 16,
+    uint64, F = 1024) with V = 65536 (65536 tiles: the tile-total scan runs over
+    several passes) and V = 512 (128 tiles per LFVector): two rounds given as
+    host counts plus the generated round's payloads in thread order equal the
+    generated rounds element by element (those are checked against the oracle
+    at full size elsewhere), and an r/w between them sees the same array."""
+    G = gg()
+    thr = wl.poisson_thresholds(3, 16)
+    n = 1 << 26
+    pool = G.Pool(24 << 30)
+    gen_arr = G.GGArray(pool, 8, V, 1024)
+    pk_arr = G.GGArray(pool, 8, V, 1024)
+    src = G.GGArray(pool, 8, V, 1024)  # produces each round's payloads in thread order
+    for i in range(2):
+        print(f"case packed full size V={V} round {i}", flush=True)
+        g = G.make_gen(G.GEN_POISSON, seed=1, round=i, max_count=16, thresholds=thr)
+        src.insert_gen(g, n)
+        vals = src.flatten()
+        src.shrink(1, 1)
+        counts = torch.from_numpy(wl.poisson_counts(1, i, n, thr)).to("cuda")
+        assert int(counts.sum()) == vals.numel()
+        gen_arr.insert_gen(g, n)
+        pk_arr.insert_packed(vals, counts)
+        gen_arr.rw(G.ADD1)
+        pk_arr.rw(G.ADD1)
+        assert pk_arr.last_error() == 0 and gen_arr.last_error() == 0
+        assert torch.equal(gen_arr.vector_sizes(), pk_arr.vector_sizes())
+        assert torch.equal(gen_arr.flatten(), pk_arr.flatten())
+        assert gen_arr.capacity() == pk_arr.capacity()
+        del vals, counts
+    for x in (gen_arr, pk_arr, src):
+        x.close()
+    pool.close()
