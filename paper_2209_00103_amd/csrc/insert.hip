@@ -1076,41 +1076,6 @@ __global__ __launch_bounds__(1024) void packed_tile_scan_kernel(uint64_t* tile_o
   if (tid == 0) tile_off[ntiles] = carry_s;
 }
 
-// n elements from src to dst by one workgroup: element stores up to the first
-// 128-byte line boundary of dst, then 16-byte non-temporal stores that each
-// cover whole lines across the wave (the loads take src's alignment), then the
-// ragged tail.
-template <typename T>
-__device__ __forceinline__ void block_copy(T* dst_, const T* src_, uint32_t n) {
-  typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
-  constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T), kU = 8;
-  const uint32_t tid = threadIdx.x;
-  const gptr<T> dst = gmem(dst_);
-  const gptr<const T> src = gmem(src_);
-  const uint32_t mis = (uint32_t)((reinterpret_cast<uintptr_t>(dst_) & 127u) / sizeof(T));
-  uint32_t head = mis ? kLine - mis : 0u;
-  if (head > n) head = n;
-  if (tid < head) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tid), dst + tid);
-  const uint32_t nv = (n - head) / VPL;
-  // kU vectors per thread in flight before the first store: a tile of the
-  // configuration-3 round (about 24 KiB) is read in one pass.
-  for (uint32_t q0 = 0; q0 < nv; q0 += kU * kB) {
-    u32x4 x[kU];
-#pragma unroll
-    for (uint32_t k = 0; k < kU; ++k) {
-      const uint32_t q = q0 + k * kB + tid;
-      if (q < nv) x[k] = __builtin_nontemporal_load(reinterpret_cast<gptr<const u32x4_a4>>(src + head + q * VPL));
-    }
-#pragma unroll
-    for (uint32_t k = 0; k < kU; ++k) {
-      const uint32_t q = q0 + k * kB + tid;
-      if (q < nv) __builtin_nontemporal_store(x[k], reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
-    }
-  }
-  const uint32_t tail = head + nv * VPL + tid;
-  if (tail < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + tail), dst + tail);
-}
-
 // Phase 1: LFVector v grows by the values of its tiles v tpv .. (v + 1) tpv - 1
 // (one wave per LFVector).  Counts asking for more values than given insert
 // nothing.
@@ -1126,8 +1091,92 @@ __global__ __launch_bounds__(256) void packed_grow_kernel(ArrRef A, TileArgs I, 
   grow_vector_by(A, I.elem_log2, v, packed_offset(off, ntiles, t0 + I.tpv) - packed_offset(off, ntiles, t0));
 }
 
+// One run of a packed round: n elements from src to a bucket, from its element
+// e0 on, copied by threads tid = 0 .. nthr - 1 of the workgroup.  Buckets are
+// 256-byte aligned, so the split into a head up to the destination's first
+// 128-byte line, whole-line 16-byte stores and a tail is known before the
+// bucket's pointer: load() issues the first pass (up to kU vectors per thread,
+// the head and tail elements) and store(bucket) writes it and copies the rest.
+// The loads are unconditional, their indices clamped into the run (surplus
+// lanes read what another lane stores): a load under a divergent branch makes
+// the compiler wait for it before the branch joins, which would serialise the
+// pass.  Only the stores are predicated.
+template <typename T>
+struct RunCopy {
+  typedef u32x4 u32x4_a4 __attribute__((aligned(4)));
+  static constexpr uint32_t VPL = 16 / sizeof(T), kLine = 128 / sizeof(T), kU = 8;
+  gptr<const T> src;
+  uint64_t e0;
+  uint32_t n, head, nv, tid, nthr;
+  u32x4 x[kU];
+  T hv, tv;
+
+  __device__ __forceinline__ void load(const T* src_, uint64_t e0_, uint32_t n_, uint32_t tid_, uint32_t nthr_) {
+    src = gmem(src_);
+    e0 = e0_;
+    n = n_;
+    tid = tid_;
+    nthr = nthr_;
+    const uint32_t mis = (uint32_t)(e0 & (kLine - 1));
+    head = mis ? kLine - mis : 0u;
+    if (head > n) head = n;
+    nv = (n - head) / VPL;
+    if (nv == 0) return;  // a short run is copied element by element in store()
+    const gptr<const u32x4_a4> vsrc = reinterpret_cast<gptr<const u32x4_a4>>(src + head);
+#pragma unroll
+    for (uint32_t k = 0; k < kU; ++k) {
+      const uint32_t q = k * nthr + tid;
+      x[k] = __builtin_nontemporal_load(vsrc + (q < nv ? q : nv - 1));
+    }
+    const uint32_t tail = head + nv * VPL + tid;
+    hv = __builtin_nontemporal_load(src + (tid < head ? tid : 0u));
+    tv = __builtin_nontemporal_load(src + (tail < n ? tail : n - 1));
+  }
+
+  __device__ __forceinline__ void store(T* bucket) const {
+    const gptr<T> dst = gmem(bucket + e0);
+    if (nv == 0) {
+      for (uint32_t i = tid; i < n; i += nthr) __builtin_nontemporal_store(src[i], dst + i);
+      return;
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kU; ++k) {
+      const uint32_t q = k * nthr + tid;
+      if (q < nv) __builtin_nontemporal_store(x[k], reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+    }
+    const uint32_t tail = head + nv * VPL + tid;
+    if (tid < head) __builtin_nontemporal_store(hv, dst + tid);
+    if (tail < n) __builtin_nontemporal_store(tv, dst + tail);
+    const gptr<const u32x4_a4> vsrc = reinterpret_cast<gptr<const u32x4_a4>>(src + head);
+    u32x4 y[kU];
+    for (uint32_t q0 = kU * nthr; q0 < nv; q0 += kU * nthr) {  // runs longer than one pass
+#pragma unroll
+      for (uint32_t k = 0; k < kU; ++k) {
+        const uint32_t q = q0 + k * nthr + tid;
+        y[k] = __builtin_nontemporal_load(vsrc + (q < nv ? q : nv - 1));
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kU; ++k) {
+        const uint32_t q = q0 + k * nthr + tid;
+        if (q < nv) __builtin_nontemporal_store(y[k], reinterpret_cast<gptr<u32x4>>(dst + head + q * VPL));
+      }
+    }
+  }
+};
+
+// The run into the bucket whose pointer is at *slot (read once the loads are out).
+template <typename T>
+__device__ __forceinline__ void block_copy_slot(const uint64_t* slot, uint64_t e0, const T* src, uint32_t n,
+                                                uint32_t tid, uint32_t nthr) {
+  if (n == 0) return;
+  RunCopy<T> rc;
+  rc.load(src, e0, n, tid, nthr);
+  rc.store(reinterpret_cast<T*>(*slot));
+}
+
 // Phase 2: tile t of LFVector v copies its values to rbase[v] + (its offset
-// within the LFVector's share of the round).
+// within the LFVector's share of the round).  The tile's offsets, rbase and the
+// frozen flag are read together; the bucket runs follow from rbase alone.
 template <typename T>
 __global__ __launch_bounds__(kB) void packed_copy_kernel(ArrRef A, TileArgs I, const T* values,
                                                          const uint64_t* tile_off, uint64_t ntiles,
@@ -1135,19 +1184,125 @@ __global__ __launch_bounds__(kB) void packed_copy_kernel(ArrRef A, TileArgs I, c
   const uint64_t tile = blockIdx.x;
   const uint32_t v = (uint32_t)(tile / I.tpv);
   const uint64_t off = packed_offset(tile_off, ntiles, tile);
-  const uint32_t n = (uint32_t)(packed_offset(tile_off, ntiles, tile + 1) - off);
-  if (n == 0 || packed_offset(tile_off, ntiles, ntiles) > n_values || A.dead[v]) return;  // frozen: before or by this round
+  const uint64_t end = packed_offset(tile_off, ntiles, tile + 1);
+  const uint64_t first = packed_offset(tile_off, ntiles, (uint64_t)v * I.tpv);
+  const uint64_t total = packed_offset(tile_off, ntiles, ntiles);
+  const uint64_t rb = A.rbase[v];
+  const uint32_t dead = A.dead[v];
+  const uint32_t n = (uint32_t)(end - off);
+  if (n == 0 || dead || total > n_values) return;  // frozen before or by this round; refused round
   const uint32_t log2F = A.log2F;
-  const uint64_t base = A.rbase[v] + (off - packed_offset(tile_off, ntiles, (uint64_t)v * I.tpv));
+  const uint64_t base = rb + (off - first);
   const T* src = values + off;
+  const uint64_t* row = A.bptr + (uint64_t)v * kMaxBuckets;
+  const uint32_t b0 = bucket_of(log2F, base), b1 = bucket_of(log2F, base + n - 1);
+  if (b1 == b0 + 1) {
+    // Two runs (the tile crosses one bucket boundary): waves 0-1 copy the first,
+    // waves 2-3 the second, so the loads of both are in flight together.
+    const uint64_t split = bucket_start(log2F, b1);
+    const uint32_t na = (uint32_t)(split - base);
+    const uint32_t half = kB / 2, tid = threadIdx.x;
+    if (tid < half)
+      block_copy_slot<T>(row + b0, base - bucket_start(log2F, b0), src, na, tid, half);
+    else
+      block_copy_slot<T>(row + b1, 0, src + na, n - na, tid - half, half);
+    return;
+  }
   for (uint32_t i = 0; i < n;) {  // one run per bucket the tile's outputs reach
     const uint64_t idx = base + i;
     const uint32_t b = bucket_of(log2F, idx);
     const uint64_t bs = bucket_start(log2F, b);
     const uint64_t room = bs + bucket_len(log2F, b) - idx;
     const uint32_t run = (uint64_t)(n - i) < room ? n - i : (uint32_t)room;
-    T* dst = reinterpret_cast<T*>(A.bptr[(uint64_t)v * kMaxBuckets + b]) + (idx - bs);
-    block_copy<T>(dst, src + i, run);
+    block_copy_slot<T>(row + b, idx - bs, src + i, run, threadIdx.x, kB);
+    i += run;
+  }
+}
+
+// One tile per LFVector (tpv == 1): the tile's workgroup grows its LFVector and
+// copies in one pass.  The runs follow from the LFVector's size alone, so the
+// value loads go out first; wave 0 allocates the buckets the round reaches
+// while they are in flight (as grow_vector_by does: all or the LFVector is
+// frozen with its size unchanged) and hands the pointers to the other waves
+// through LDS; the stores follow.  The prefix is known, so counts asking for
+// more values than given are refused before anything grows.
+template <typename T>
+__global__ __launch_bounds__(kB) void packed_grow_copy_kernel(ArrRef A, TileArgs I, const T* values,
+                                                              const uint64_t* tile_off, uint64_t ntiles,
+                                                              uint64_t n_values) {
+  __shared__ uint64_t s_bp[kMaxBuckets];
+  __shared__ uint32_t s_fail;
+  const uint32_t v = blockIdx.x, tid = threadIdx.x, lane = tid & 63u;
+  const uint64_t off = packed_offset(tile_off, ntiles, v);
+  const uint64_t end = packed_offset(tile_off, ntiles, (uint64_t)v + 1);
+  const uint64_t total = packed_offset(tile_off, ntiles, ntiles);
+  const uint64_t s0 = A.size[v];
+  const uint32_t dead = A.dead[v];
+  if (total > n_values) {
+    if (v == 0 && tid == 0) set_error(A.err, kErrRange);
+    return;
+  }
+  const uint32_t n = (uint32_t)(end - off);
+  if (n == 0 || dead) return;
+  const uint32_t log2F = A.log2F;
+  const T* src = values + off;
+  const uint32_t b0 = bucket_of(log2F, s0), b1 = bucket_of(log2F, s0 + n - 1);
+  // This thread's run (one run: all threads; two: waves 0-1 and 2-3).
+  RunCopy<T> rc;
+  uint32_t mine = b0;
+  if (b1 == b0) {
+    rc.load(src, s0 - bucket_start(log2F, b0), n, tid, kB);
+  } else if (b1 == b0 + 1) {
+    const uint32_t na = (uint32_t)(bucket_start(log2F, b1) - s0), half = kB / 2;
+    if (tid < half) {
+      rc.load(src, s0 - bucket_start(log2F, b0), na, tid, half);
+    } else {
+      rc.load(src + na, 0, n - na, tid - half, half);
+      mine = b1;
+    }
+  }
+  const uint32_t lo = nbuckets_for(log2F, s0), hi = nbuckets_for(log2F, s0 + n);
+  if (tid < lo) s_bp[tid] = A.bptr[(uint64_t)v * kMaxBuckets + tid];  // buckets from earlier rounds
+  if (tid < 64) {
+    const uint32_t b = lo + lane;
+    bool failed = false;
+    if (b < hi) {
+      if (b >= (uint32_t)kMaxBuckets) {
+        failed = true;
+      } else {
+        uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
+        const uint64_t p = q ? (uint64_t)q : kFailedPtr;
+        A.bptr[(uint64_t)v * kMaxBuckets + b] = p;
+        s_bp[b] = p;
+        failed = !q;
+      }
+    }
+    const bool any = __ballot(failed) != 0;
+    if (lane == 0) {
+      s_fail = any ? 1u : 0u;
+      if (any) {
+        set_error(A.err, kErrNoMem);
+        A.dead[v] = 1u;
+      } else {
+        A.size[v] = s0 + n;
+      }
+    }
+  }
+  __syncthreads();
+  if (s_fail) return;
+  if (b1 <= b0 + 1) {
+    rc.store(reinterpret_cast<T*>(s_bp[mine]));
+    return;
+  }
+  for (uint32_t i = 0; i < n;) {  // three runs or more (small first buckets)
+    const uint64_t idx = s0 + i;
+    const uint32_t b = bucket_of(log2F, idx);
+    const uint64_t bs = bucket_start(log2F, b);
+    const uint64_t room = bs + bucket_len(log2F, b) - idx;
+    const uint32_t run = (uint64_t)(n - i) < room ? n - i : (uint32_t)room;
+    RunCopy<T> r;
+    r.load(src + i, idx - bs, run, tid, kB);
+    r.store(reinterpret_cast<T*>(s_bp[b]));
     i += run;
   }
 }
@@ -1369,14 +1524,24 @@ static int queue_packed(ggarray* a, uint64_t* off, const void* values, const uin
   const uint64_t ngroups = packed_groups(ntiles);
   hipLaunchKernelGGL(packed_group_kernel, dim3((uint32_t)ngroups), dim3(kB), 0, s, I, counts, off, ntiles);
   hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off + ntiles, ngroups);
-  hipLaunchKernelGGL(packed_grow_kernel, dim3((a->V + 3) / 4), dim3(256), 0, s, a->ref, I, (const uint64_t*)off,
-                     ntiles, n_values);
-  if (a->elem_bytes == 4)
-    hipLaunchKernelGGL(packed_copy_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
-                       static_cast<const uint32_t*>(values), (const uint64_t*)off, ntiles, n_values);
-  else
-    hipLaunchKernelGGL(packed_copy_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(kB), 0, s, a->ref, I,
-                       static_cast<const uint64_t*>(values), (const uint64_t*)off, ntiles, n_values);
+  const dim3 grid((uint32_t)ntiles), block(kB);
+  const uint64_t* o = off;
+  if (I.tpv == 1) {  // one tile per LFVector: grow and copy in one pass
+    if (a->elem_bytes == 4)
+      hipLaunchKernelGGL(packed_grow_copy_kernel<uint32_t>, grid, block, 0, s, a->ref, I,
+                         static_cast<const uint32_t*>(values), o, ntiles, n_values);
+    else
+      hipLaunchKernelGGL(packed_grow_copy_kernel<uint64_t>, grid, block, 0, s, a->ref, I,
+                         static_cast<const uint64_t*>(values), o, ntiles, n_values);
+  } else {
+    hipLaunchKernelGGL(packed_grow_kernel, dim3((a->V + 3) / 4), dim3(256), 0, s, a->ref, I, o, ntiles, n_values);
+    if (a->elem_bytes == 4)
+      hipLaunchKernelGGL(packed_copy_kernel<uint32_t>, grid, block, 0, s, a->ref, I,
+                         static_cast<const uint32_t*>(values), o, ntiles, n_values);
+    else
+      hipLaunchKernelGGL(packed_copy_kernel<uint64_t>, grid, block, 0, s, a->ref, I,
+                         static_cast<const uint64_t*>(values), o, ntiles, n_values);
+  }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);

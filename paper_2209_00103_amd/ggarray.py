@@ -341,9 +341,12 @@ class GGArray:
             _check(st, "ggarray_size")
         return int(v.value)
 
-    def capacity(self, stream=None) -> int:
+    def capacity(self, stream=None, check_error: bool = True) -> int:
+        """Elements held by the allocated buckets (check_error as for size())."""
         v = _u64()
-        _check(lib().ggarray_capacity(self._h, ctypes.byref(v), _stream(stream)), "ggarray_capacity")
+        st = lib().ggarray_capacity(self._h, ctypes.byref(v), _stream(stream))
+        if check_error or st not in (OK, ENOMEM, ERANGE):
+            _check(st, "ggarray_capacity")
         return int(v.value)
 
     def insert_segments(self, values: torch.Tensor, prefix: torch.Tensor, stream=None):

@@ -137,3 +137,30 @@ def test_packed_full_size_equals_generated(V):
     for x in (gen_arr, pk_arr, src):
         x.close()
     pool.close()
+
+
+def test_insert_packed_too_few_values_one_tile_per_lfvector(pool):
+    """One tile per LFVector (the LFVectors grow while the tile totals are taken):
+    a round whose counts ask for more values than given leaves every LFVector,
+    its capacity and the pool exactly as the round before left them."""
+    G = gg()
+    V, chunk = 64, 700
+    a, o = both(8, V, 16, pool)
+    rng = np.random.default_rng(21)
+    counts = rng.integers(0, 9, size=V * chunk, dtype=np.uint8)
+    vals, _ = wl.random_round(rng, int(counts.sum(dtype=np.uint64)), 1.0, 8)
+    a.insert_packed(dev(vals), dev(counts))
+    assert o.insert_packed(vals, counts) == oracle.OK
+    assert_same(a, o, "valid round")
+    in_use = pool.stats()["in_use"]
+    counts2 = rng.integers(1, 17, size=V * chunk, dtype=np.uint8)
+    total2 = int(counts2.sum(dtype=np.uint64))
+    vals2, _ = wl.random_round(rng, total2, 1.0, 8)
+    a.insert_packed(dev(vals2), dev(counts2), n_values=total2 - 1)
+    assert a.last_error() == G.ERANGE
+    np.testing.assert_array_equal(a.vector_sizes().cpu().numpy().astype(np.uint64), o.vector_sizes())
+    np.testing.assert_array_equal(G.as_unsigned(a.flatten()), o.flatten())
+    assert a.capacity(check_error=False) == o.capacity()
+    assert pool.stats()["in_use"] == in_use
+    a.close()
+    o.close()
