@@ -549,11 +549,13 @@ int gga_batch_create(gga_batch** out, ggarray* const* arrays, uint32_t n, gga_st
       for (uint32_t i = 0; ok && i < n; ++i)
         for (uint64_t w = vb[i]; w < vb[i + 1]; ++w) varr[w] = i;
     }
-    const size_t step_bytes = 256 + sizeof(uint64_t) * kStepChunkMax;  // barrier words, chunk totals
+    // barrier words, chunk totals, per-LFVector sizes
+    const size_t step_bytes = 256 + sizeof(uint64_t) * kStepChunkMax + sizeof(uint64_t) * (ok ? vb[n] : 0);
     ok = ok && hipMalloc(&b->d_varr, sizeof(uint32_t) * vb[n]) == hipSuccess &&
          hipMalloc(&b->d_step_sync, step_bytes) == hipSuccess;
     if (ok) {
       b->d_step_chunks = reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(b->d_step_sync) + 256);
+      b->d_step_vsize = b->d_step_chunks + kStepChunkMax;
       ok = hipMemcpyAsync(b->d_arrays, h, sizeof(BatchArr) * n, hipMemcpyHostToDevice, S(s)) == hipSuccess &&
            hipMemsetAsync(b->d_tile_begin, 0, sizeof(uint64_t) * words, S(s)) == hipSuccess &&
            hipMemcpyAsync(b->d_vbegin, vb, sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, S(s)) == hipSuccess &&

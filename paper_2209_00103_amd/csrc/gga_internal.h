@@ -152,6 +152,7 @@ struct gga_batch {
   uint32_t* d_varr;
   uint32_t* d_step_sync;
   uint64_t* d_step_chunks;
+  uint64_t* d_step_vsize;    // final size of every LFVector (the per-wave step's flatten prefix)
   struct StepCounts {
     uint64_t key;
     uint64_t* dev;

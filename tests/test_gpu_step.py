@@ -197,3 +197,48 @@ def test_step_graph_replays(pool):
     b.close()
     for a in arrays:
         a.close()
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+def test_step_per_wave_many_lfvectors(pool, elem):
+    """More than 4096 LFVectors (each wave takes its own LFVectors): keyed,
+    Bernoulli and round-tag rounds, some giving an LFVector several 1024-candidate
+    tiles or several buckets, then r/w and flatten; bit-exact against the
+    per-round calls and the oracle."""
+    G = gg()
+    shapes = [(3000, 4), (1, 64), (1200, 1), (900, 256)]
+    arrays = [G.GGArray(pool, elem, V, F) for V, F in shapes]
+    twins = [G.GGArray(pool, elem, V, F) for V, F in shapes]
+    oracles = [Oracle(elem, V, F) for V, F in shapes]
+    b, bt = G.Batch(arrays), G.Batch(twins)
+    counts = [[3000 * 7 + 11, 5000, 1200 * 3, 900 * 2500 + 7],
+              [3000 * 2, 0, 1200 * 40 + 3, 900 * 1100],
+              [12345, 70000, 1199, 900 * 3]]
+    gens = [G.make_gen(G.GEN_KEYED, seed=3, round=0, tag=40),
+            G.make_gen(G.GEN_BERNOULLI, seed=3, round=1),
+            G.make_gen(G.GEN_ROUND_TAG, round=2, tag_shift=24)]
+    kinds = ["keyed", "bern", "tag"]
+    dt = torch.int32 if elem == 4 else torch.int64
+    cap = sum(sum(c) for c in counts) + sum(counts[0])  # both steps' elements
+    out = torch.empty(cap, dtype=dt, device="cuda")
+    print(f"case step per wave elem={elem}", flush=True)
+    b.step(gens, counts, G.MUL3ADD1, out)
+    for r in range(3):
+        bt.insert_gen(gens[r], counts[r])
+    bt.rw(G.MUL3ADD1)
+    _oracle_rounds(oracles, kinds, gens, counts, elem_op=oracle.OP_MUL3ADD1)
+    assert b.last_error() == 0
+    _check_flat(out, oracles, "per-wave step")
+    for i, (a, t, o) in enumerate(zip(arrays, twins, oracles)):
+        np.testing.assert_array_equal(gpu_sizes(a), o.vector_sizes(), err_msg=f"array {i}")
+        np.testing.assert_array_equal(gpu_flat(t), o.flatten(), err_msg=f"twin {i}")
+        assert a.capacity() == o.capacity(), f"array {i}"
+    # a second step on top, without r/w
+    b.step(gens[:1], counts[:1], G.RW_NONE, out)
+    _oracle_rounds(oracles, kinds[:1], gens[:1], counts[:1], rw=False)
+    assert b.last_error() == 0
+    _check_flat(out, oracles, "second step")
+    b.close()
+    bt.close()
+    for a in arrays + twins:
+        a.close()
