@@ -11,10 +11,12 @@
 // written, which are still in the cache.  Workgroup w takes LFVectors w, w + G,
 // ... of the batch (arrays in order, each array's LFVectors in order).
 //
-// The flatten needs the exclusive prefix of every LFVector's size, so two
-// grid-wide barriers follow: after the first, chunks of consecutive LFVectors
-// are summed; after the second, each workgroup scans the chunk totals and
-// copies its own LFVectors to their places.  A workgroup copies the LFVectors it
+// The flatten needs the exclusive prefix of every LFVector's size (each final
+// size is also written to a flat per-LFVector array), so grid-wide barriers
+// follow: after the first, chunks of consecutive LFVectors are summed; after the
+// second, each workgroup scans the chunk totals and copies its own LFVectors to
+// their places.  With at most 1024 LFVectors a chunk is one LFVector and the
+// second barrier is not needed.  A workgroup copies the LFVectors it
 // wrote itself, so element data never crosses workgroups; the sizes and the
 // chunk totals do, through device-scope atomic loads and stores.  The grid is no
 // larger than what the device holds at once (an occupancy query), and the
@@ -244,12 +246,6 @@ __device__ uint64_t step_block_sum(uint64_t x, StepShared& sh) {
   return t;
 }
 
-__device__ __forceinline__ uint64_t vec_size(const BatchArr* arrs, const uint32_t* varr, const uint64_t* vbegin,
-                                             uint64_t w) {
-  const uint32_t i = varr[w];
-  return ld_rlx(&arrs[i].A.size[w - vbegin[i]]);
-}
-
 }  // namespace
 
 template <typename T>
@@ -257,7 +253,7 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
                                                    uint64_t total_v, StepDesc D, const uint64_t* counts, uint32_t n_arr,
                                                    uint32_t op, T* out, uint64_t out_cap, uint32_t* sync,
                                                    uint64_t* chunk_sum, uint64_t chunk_len, uint32_t* berr,
-                                                   uint32_t spin, uint64_t* /*vsize: the per-wave kernel's*/) {
+                                                   uint32_t spin, uint64_t* vsize) {
   __shared__ StepShared sh;
   __shared__ uint64_t cpre[kStepChunkMax];
   const uint32_t tid = threadIdx.x;
@@ -303,22 +299,27 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
       }
     }
     if (changed && tid == 0) st_rlx(&A.size[v], sh.size);
+    if (tid == 0) st_rlx(&vsize[wv], sh.size);
     if (op != kOpNone) step_rw<T>(A.log2F, op, sh);
     __syncthreads();  // sh is reloaded for the next LFVector
   }
 
   if (out) {
-    // Phase B: totals of chunks of chunk_len consecutive LFVectors.
+    // Phase B: totals of chunks of chunk_len consecutive LFVectors (with at most
+    // kStepChunkMax LFVectors a chunk is one LFVector: its size is the total).
     step_barrier(&sync[0], G, spin, berr);
     const uint64_t nchunks = (total_v + chunk_len - 1) / chunk_len;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += G) {
-      uint64_t x = 0;
-      for (uint64_t wv = c * chunk_len + tid; wv < total_v && wv < (c + 1) * chunk_len; wv += kSB)
-        x += vec_size(arrs, varr, vbegin, wv);
-      x = step_block_sum(x, sh);
-      if (tid == 0) st_rlx(&chunk_sum[c], x);
+    const uint64_t* ctot = chunk_len == 1 ? vsize : chunk_sum;
+    if (chunk_len > 1) {
+      for (uint64_t c = blockIdx.x; c < nchunks; c += G) {
+        uint64_t x = 0;
+        for (uint64_t wv = c * chunk_len + tid; wv < total_v && wv < (c + 1) * chunk_len; wv += kSB)
+          x += ld_rlx(&vsize[wv]);
+        x = step_block_sum(x, sh);
+        if (tid == 0) st_rlx(&chunk_sum[c], x);
+      }
+      step_barrier(&sync[1], G, spin, berr);
     }
-    step_barrier(&sync[1], G, spin, berr);
 
     // Phase C: every workgroup scans the chunk totals (nchunks <= kStepChunkMax:
     // four per thread), then copies its own LFVectors to their places.
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
       const uint64_t c = (uint64_t)tid * kPer + k;
-      x[k] = c < nchunks ? ld_rlx(&chunk_sum[c]) : 0;
+      x[k] = c < nchunks ? ld_rlx(&ctot[c]) : 0;
       sum += x[k];
     }
     uint64_t incl = sum;
@@ -359,9 +360,9 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
         // the chunk's prefix plus the LFVectors of the chunk before this one
         const uint64_t c = wv / chunk_len;
         uint64_t y = 0;
-        for (uint64_t u = c * chunk_len + tid; u < wv; u += kSB) y += vec_size(arrs, varr, vbegin, u);
-        const uint64_t off = cpre[c] + step_block_sum(y, sh);
-        const uint64_t sz = ld_rlx(&A.size[v]);
+        for (uint64_t u = c * chunk_len + tid; u < wv; u += kSB) y += ld_rlx(&vsize[u]);
+        const uint64_t off = cpre[c] + (chunk_len > 1 ? step_block_sum(y, sh) : 0);
+        const uint64_t sz = ld_rlx(&vsize[wv]);
         T* dst = out + off;
         for (uint32_t b = 0; b < (uint32_t)kMaxBuckets && bucket_start(A.log2F, b) < sz; ++b) {
           const uint64_t st = bucket_start(A.log2F, b);
@@ -605,14 +606,17 @@ __global__ __launch_bounds__(kSB) void step_wave_kernel(const BatchArr* arrs, co
     // Phase B: totals of chunks of chunk_len consecutive LFVectors.
     step_barrier(&sync[0], G, spin, berr);
     const uint64_t nchunks = (total_v + chunk_len - 1) / chunk_len;
-    for (uint64_t c = blockIdx.x; c < nchunks; c += G) {
-      uint64_t x = 0;
-      for (uint64_t wv = c * chunk_len + tid; wv < total_v && wv < (c + 1) * chunk_len; wv += kSB)
-        x += ld_rlx(&vsize[wv]);
-      x = step_block_sum(x, sh);
-      if (tid == 0) st_rlx(&chunk_sum[c], x);
+    const uint64_t* ctot = chunk_len == 1 ? vsize : chunk_sum;
+    if (chunk_len > 1) {
+      for (uint64_t c = blockIdx.x; c < nchunks; c += G) {
+        uint64_t x = 0;
+        for (uint64_t wv = c * chunk_len + tid; wv < total_v && wv < (c + 1) * chunk_len; wv += kSB)
+          x += ld_rlx(&vsize[wv]);
+        x = step_block_sum(x, sh);
+        if (tid == 0) st_rlx(&chunk_sum[c], x);
+      }
+      step_barrier(&sync[1], G, spin, berr);
     }
-    step_barrier(&sync[1], G, spin, berr);
 
     // Phase C: every workgroup scans the chunk totals; each wave copies its
     // LFVectors to their places.
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(kSB) void step_wave_kernel(const BatchArr* arrs, co
 #pragma unroll
     for (uint32_t k = 0; k < kPer; ++k) {
       const uint64_t c = (uint64_t)tid * kPer + k;
-      x[k] = c < nchunks ? ld_rlx(&chunk_sum[c]) : 0;
+      x[k] = c < nchunks ? ld_rlx(&ctot[c]) : 0;
       sum += x[k];
     }
     uint64_t incl = sum;
