@@ -519,10 +519,44 @@ def sparse_leg(G, torch, rounds, V, steps, warmup):
                      "per_round_GBps": [round(ELEM * a / (x * 1e-3) / 1e9, 1) for a, x in zip(added, ms)],
                      "Gelem_s": sum(added) / (sum(ms) * 1e-3) / 1e9,
                      "last_round_GBps": ELEM * added[-1] / (ms[-1] * 1e-3) / 1e9}
+    # The same round sizes as prepared buffers (uint32 values, one flag byte per
+    # thread set with probability 1/2, drawn untimed): the scan and look-back path
+    # then reads 5 B per thread and writes 4 B per inserted element, an HBM-scale
+    # figure for it.
+    gen_t = torch.Generator(device="cuda")
+    gen_t.manual_seed(7)
+    bufs = []
+    for n in rounds:
+        vals = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda", generator=gen_t)
+        flags = (torch.rand(n, device="cuda", generator=gen_t) < 0.5).to(torch.uint8)
+        bufs.append((vals, flags, int(flags.sum())))
+    for name in ("ggarray", "static"):
+        tm = Timer(torch)
+        for rep in range(warmup + steps):
+            t = tm if rep >= warmup else Timer(torch)
+            for r, (vals, flags, _) in enumerate(bufs):
+                with t.span(f"r{r}"):
+                    (arr if name == "ggarray" else st).insert(vals, flags)
+                if name == "ggarray":
+                    arr.shrink(1, 10)
+            if name == "ggarray":
+                arr.shrink(1, 1)
+            else:
+                st.clear()
+        torch.cuda.synchronize()
+        ms = [statistics.median(tm.ms(f"r{r}")) for r in range(len(rounds))]
+        byt = [5 * n + ELEM * b[2] for n, b in zip(rounds, bufs)]
+        res[name + "_buffer"] = {"per_round_us": [round(1e3 * x, 2) for x in ms],
+                                 "per_round_GBps": [round(y / (x * 1e-3) / 1e9, 1) for y, x in zip(byt, ms)],
+                                 "Gelem_s": sum(b[2] for b in bufs) / (sum(ms) * 1e-3) / 1e9,
+                                 "last_round_GBps": byt[-1] / (ms[-1] * 1e-3) / 1e9,
+                                 "last_round_frac": byt[-1] / (ms[-1] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
     assert arr.last_error() == 0 and st.last_error() == 0
+    del bufs
     st.close()
     arr.close()
     pool.close()
+    res["buffer_bytes"] = "read 4 B value + 1 B flag per thread, write 4 B per inserted element"
     res["inserted_per_round"] = added
     res["insert_vs_static"] = res["ggarray"]["Gelem_s"] / res["static"]["Gelem_s"]
     res["workload"] = ("configuration-2 round sizes (2^17, 2^17 .. 2^27 threads), each thread inserting "
@@ -1284,7 +1318,9 @@ def main():
             sparse = sparse_leg(G, torch, rounds, V, args.steps, args.warmup)
             log(f"sparse rounds: ggarray {sparse['ggarray']['Gelem_s']:.1f} Gelem/s (last round "
                 f"{sparse['ggarray']['last_round_GBps']:.0f} GB/s), static {sparse['static']['Gelem_s']:.1f} "
-                f"Gelem/s (last round {sparse['static']['last_round_GBps']:.0f} GB/s)")
+                f"Gelem/s (last round {sparse['static']['last_round_GBps']:.0f} GB/s); buffer mode last round "
+                f"{sparse['ggarray_buffer']['last_round_GBps']:.0f} GB/s against static "
+                f"{sparse['static_buffer']['last_round_GBps']:.0f} GB/s")
         except Exception as e:  # reported, never silently dropped
             sparse = {"error": str(e)}
             log(f"sparse leg failed: {e!r}\n{traceback.format_exc()}")
@@ -1454,6 +1490,9 @@ def headline(line, detail_path):
         head["sparse_insert_Gelem_s"] = _r(sp["ggarray"]["Gelem_s"], 1)
         head["sparse_static_insert_Gelem_s"] = _r(sp["static"]["Gelem_s"], 1)
         head["sparse_last_round_GBps"] = _r(sp["ggarray"]["last_round_GBps"], 1)
+        if "ggarray_buffer" in sp:
+            head["sparse_buffer_last_round_GBps"] = _r(sp["ggarray_buffer"]["last_round_GBps"], 1)
+            head["sparse_buffer_static_last_round_GBps"] = _r(sp["static_buffer"]["last_round_GBps"], 1)
     if bl.get("static"):
         # like for like: both sides timed by events around the calls (dispatch included)
         ins_span = (1 << 28) / (k["insert"]["launches_per_step"] * k["insert"]["span_us"] * 1e-6) / 1e9

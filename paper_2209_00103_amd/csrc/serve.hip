@@ -273,8 +273,17 @@ int run_batched(RunState& R) {
       l.reqs.clear();
       l.busy = false;
     }
+    // Ready requests are spread over the idle lanes: each takes its share, so at
+    // low load requests go out at once as single-request steps on lanes of their
+    // own (running side by side), and steps grow only when requests outnumber the
+    // idle lanes.
+    uint32_t idle = 0;
+    for (const Lane& l : sv->lanes) idle += l.busy ? 0u : 1u;
     for (Lane& l : sv->lanes) {
       if (l.busy || ready.empty()) continue;
+      const size_t share = (ready.size() + idle - 1) / idle;
+      const size_t cap = share < sv->cfg.max_step ? (share ? share : 1) : sv->cfg.max_step;
+      --idle;
       items.clear();
       begins.clear();
       sitems.clear();
@@ -282,7 +291,7 @@ int run_batched(RunState& R) {
       a_reqs.clear();
       uint64_t blocks = 0, grid = 0;
       picked.clear();
-      while (picked.size() < sv->cfg.max_step && !ready.empty()) {
+      while (picked.size() < cap && !ready.empty()) {
         const Head h = ready.top();
         const uint32_t a = h.second;
         if (busy[a] || q[a].empty() || tr->arrival_ns[q[a].front()] != h.first) {
