@@ -164,9 +164,14 @@ __device__ __forceinline__ uint32_t bucket_class(uint32_t log2F, uint32_t elem_l
 // LFVectors can grow in the same kernel without meeting on one address:
 //
 //  * Bucket b of LFVector v of an array with salt z belongs to free-list shard
-//    f = (v + b + z) mod 4096 and to arena shard f mod 256, so the LFVectors of
-//    an array (up to 4096 of them) never share a free list for a given bucket,
-//    and a bucket released by shrink is found again by the same LFVector.
+//    f = (v + b + z) mod 4096 and to arena shard (f / 16) mod 256, so the
+//    LFVectors of an array (up to 4096 of them) never share a free list for a
+//    given bucket, and a bucket released by shrink is found again by the same
+//    LFVector.  Sixteen consecutive LFVectors share an arena shard, so buckets
+//    that grow in the same launch lie side by side in the order in which r/w
+//    and flatten visit them (scattered 8-64 KiB buckets stream about 5% slower
+//    than the same bytes in address order; configuration 3's r/w measured
+//    4.79-4.93 -> 4.84-5.07 TB/s with this mapping, insertion unchanged).
 //  * Freed blocks go to one tagged Treiber stack per (size class, free shard).
 //    A head packs a 24-bit version tag above the 40-bit block index (offset /
 //    256 + 1, 0 = empty); the tag changes on every update, so a stale head never
@@ -190,7 +195,7 @@ __device__ __forceinline__ uint32_t bucket_class(uint32_t log2F, uint32_t elem_l
 __device__ __forceinline__ uint32_t pool_shard(uint32_t v, uint32_t b, uint32_t salt) {
   return (v + b + salt) & (uint32_t)(kFreeShards - 1);
 }
-__device__ __forceinline__ uint32_t arena_shard(uint32_t f) { return f & (uint32_t)(kArenaShards - 1); }
+__device__ __forceinline__ uint32_t arena_shard(uint32_t f) { return (f >> 4) & (uint32_t)(kArenaShards - 1); }
 
 __device__ __forceinline__ bool cas_rlx(uint64_t* p, uint64_t& expected, uint64_t desired) {
   return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,

@@ -430,14 +430,31 @@ __global__ __launch_bounds__(256) void batch_table_kernel(const BatchArr* items,
                elem_begin[i]);
 }
 
+// Load policy of r/w.  Non-temporal loads (kNtLoad) serve an r/w that directly
+// follows another r/w of the array (configuration 2: 5.3 against 4.9 TB/s) and
+// every r/w of at least kNtLoadBytes of elements; a smaller array read after an
+// insertion or a flatten loads through the cache.  Measured on single arrays
+// (u32, V = 512, r/w after an insertion), cached against non-temporal loads:
+// 6.07 against 5.27 TB/s at 0.54 GB, 5.74 against 5.59 at 1.07 GB, 5.68 against
+// 5.78 at 2.15 GB and 5.41 against 5.56 at 4.29 GB; configuration 4's batch
+// (3.84 GB of buckets of at most 64 KiB) 4.40 against 4.70 TB/s.
+constexpr uint64_t kNtLoadBytes = 5ull << 28;  // 1.25 GiB
+
+// Tiles [sp.t, sp.end) of a tile table, stride sp.step.
+template <typename T, bool kFlatten, bool kNtLoad>
+__device__ __forceinline__ void table_tiles(const uint64_t* __restrict__ tab, const TileSpan& sp, uint32_t op,
+                                            T* out) {
+  for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
+    const uint64_t src = tab[2 * t], w = tab[2 * t + 1];
+    stream_tile<T, kFlatten, kNtLoad>(reinterpret_cast<T*>(src), kFlatten ? out + (w & 0xFFFFFFFFFFFFull) : nullptr,
+                                      (uint32_t)(w >> 48), op);
+  }
+}
+
 // r/w or flatten of one array through its tile table: each XCD's workgroups
 // stride over their eighth of the tiles (one tile each when the grid covers the
-// array).  Without a table
-// for the current state (more tiles than it holds) the grid walks the buckets.
-// r/w loads through the cache by default; kNtLoad (non-temporal loads) serves an
-// r/w that directly follows another r/w of the array, where it measured faster
-// (configuration 2: 5.3 against 4.9 TB/s), while after an insertion or a flatten
-// loads through the cache are faster (5.5 against 5.1).
+// array).  Without a table for the current state (more tiles than it holds) the
+// grid walks the buckets.
 template <typename T, bool kFlatten, bool kNtLoad = kFlatten>
 __global__ __launch_bounds__(kRwThreads) void stream_table_kernel(ArrRef A, const uint64_t* __restrict__ tab,
                                                                  uint64_t cap, uint32_t op, T* out,
@@ -453,11 +470,10 @@ __global__ __launch_bounds__(kRwThreads) void stream_table_kernel(ArrRef A, cons
     return;
   }
   const TileSpan sp = xcd_span(total);
-  for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
-    const uint64_t src = tab[2 * t], w = tab[2 * t + 1];
-    stream_tile<T, kFlatten, kNtLoad>(reinterpret_cast<T*>(src), kFlatten ? out + (w & 0xFFFFFFFFFFFFull) : nullptr,
-                                      (uint32_t)(w >> 48), op);
-  }
+  if (!kFlatten && !kNtLoad && A.prefix[A.V] * sizeof(T) >= kNtLoadBytes)
+    table_tiles<T, false, true>(tab, sp, op, out);
+  else
+    table_tiles<T, kFlatten, kNtLoad>(tab, sp, op, out);
 }
 
 // Static / semi-static array r/w: the flat array cut into 16 KiB tiles, streamed
@@ -471,6 +487,14 @@ __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const ui
   const uint64_t te = 1ull << te_log2;
   const uint64_t total = (n + te - 1) >> te_log2;
   const TileSpan sp = xcd_span(total);
+  if (!kNtLoad && n * sizeof(T) >= kNtLoadBytes) {
+    for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
+      const uint64_t e0 = t << te_log2;
+      const uint64_t rem = n - e0;
+      stream_tile<T, false, true>(data + e0, nullptr, (uint32_t)(rem < te ? rem : te), op);
+    }
+    return;
+  }
   for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
     const uint64_t e0 = t << te_log2;
     const uint64_t rem = n - e0;
@@ -539,9 +563,10 @@ __global__ __launch_bounds__(256) void batch_shrink_kernel(const BatchArr* items
 }
 
 // r/w or flatten of every array of the batch.  With a tile table covering the
-// batch, each XCD's workgroups stride over their eighth of it; otherwise a persistent grid:
-// workgroup w takes the w-th contiguous share of the tiles and walks it array by
-// array.  Flatten writes array i at out + elem_begin[i].
+// batch, each XCD's workgroups stride over their eighth of it (r/w with
+// non-temporal loads from kNtLoadBytes of elements on); otherwise a persistent
+// grid: workgroup w takes the w-th contiguous share of the tiles and walks it
+// array by array.  Flatten writes array i at out + elem_begin[i].
 template <typename T, bool kFlatten>
 __global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr* items, const uint64_t* tile_begin,
                                                                  const uint64_t* elem_begin, uint32_t n,
@@ -556,11 +581,10 @@ __global__ __launch_bounds__(kRwThreads) void batch_stream_kernel(const BatchArr
   const uint64_t G = gridDim.x;
   if (total <= tcap) {
     const TileSpan sp = xcd_span(total);
-    for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
-      const uint64_t src = tab[2 * t], w = tab[2 * t + 1];
-      stream_tile<T, kFlatten>(reinterpret_cast<T*>(src), kFlatten ? out + (w & 0xFFFFFFFFFFFFull) : nullptr,
-                               (uint32_t)(w >> 48), op);
-    }
+    if (!kFlatten && elem_begin[n] * sizeof(T) >= kNtLoadBytes)
+      table_tiles<T, false, true>(tab, sp, op, out);
+    else
+      table_tiles<T, kFlatten, kFlatten>(tab, sp, op, out);
     return;
   }
   uint64_t g0 = total * blockIdx.x / G;

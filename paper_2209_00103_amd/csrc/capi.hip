@@ -254,7 +254,8 @@ int ggarray_create(ggarray** out, gga_pool* p, uint32_t elem_bytes, uint32_t n_v
   R.pool = p->ref;
   R.V = n_vectors;
   R.log2F = a->log2F;
-  R.salt = (uint32_t)((reinterpret_cast<uintptr_t>(a->meta) >> 8) * 2654435761u) & (kFreeShards - 1);
+  R.salt = p->next_salt & (kFreeShards - 1);  // arrays created in a row: consecutive shards
+  p->next_salt += n_vectors;
   R.spin = kSpinLimit;
   a->status_cap = 0;
   a->prefix_valid = true;  // all sizes zero and prefix arrays zeroed

@@ -11,6 +11,7 @@ struct gga_pool {
   void* dev_base;
   uint64_t bytes;
   int n_arrays;
+  uint32_t next_salt;  // salt of the next array: arrays take consecutive free-list shards
 };
 
 struct ggarray {
