@@ -476,9 +476,11 @@ __global__ __launch_bounds__(kRwThreads) void stream_table_kernel(ArrRef A, cons
     table_tiles<T, kFlatten, kNtLoad>(tab, sp, op, out);
 }
 
-// Static / semi-static array r/w: the flat array cut into 16 KiB tiles, streamed
-// with the tile order and XCD split of the GGArray r/w through its tile table,
-// without the bucket indirection.
+// Static / semi-static array r/w: the flat array cut into 16 KiB tiles, workgroup
+// w streaming tiles w, w + G, ... (the GGArray's tile size and load policy
+// without the bucket indirection).  A contiguous array streams faster in this
+// plain order than with the GGArray's split of the tiles over the XCDs
+// (configuration 2's static r/w 6.35 against 6.07 TB/s), so it keeps it.
 template <typename T, bool kNtLoad>
 __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const uint64_t* size,
                                                               uint64_t cap, uint32_t op, uint32_t te_log2) {
@@ -486,7 +488,7 @@ __global__ __launch_bounds__(kRwThreads) void static_rw_kernel(T* data, const ui
   if (n > cap) n = cap;
   const uint64_t te = 1ull << te_log2;
   const uint64_t total = (n + te - 1) >> te_log2;
-  const TileSpan sp = xcd_span(total);
+  const TileSpan sp{blockIdx.x, total, gridDim.x};
   if (!kNtLoad && n * sizeof(T) >= kNtLoadBytes) {
     for (uint64_t t = sp.t; t < sp.end; t += sp.step) {
       const uint64_t e0 = t << te_log2;

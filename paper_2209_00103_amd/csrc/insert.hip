@@ -351,18 +351,60 @@ struct SlotMask {  // bit j: slot j of this lane inserts
   }
 };
 
+// Flags read from memory: every lane reads the flag of every slot, at the last
+// thread of the tile for slots past its end, and masks afterwards.  A flag read
+// under a divergent branch costs a full memory round trip per slot (the
+// compiler waits for each such load before the branch joins), while
+// unconditional loads, 16 of them gathered before any result is used, are
+// issued back to back (buffer-mode Bernoulli rounds: 1.76 -> 3.30 TB/s).
+// Computed flags keep the plain loop (batching them only adds registers).
 template <class Prod>
 __device__ __forceinline__ SlotMask wave_flags(const Prod& prod, uint64_t g0, uint64_t gend) {
   const uint32_t lane = lane_id();
   SlotMask m;
 #pragma unroll
   for (int k = 0; k < kMaskWords; ++k) m.w[k] = 0;
+  if constexpr (!Prod::kLoads) {  // computed flags: no loads to batch
 #pragma unroll 16
-  for (int j = 0; j < kWaveSlots; ++j) {
-    const uint64_t g = g0 + (uint64_t)j * 64 + lane;
-    if (g < gend && prod.flag(g)) m.w[j >> 6] |= 1ull << (j & 63);
+    for (int j = 0; j < kWaveSlots; ++j) {
+      const uint64_t g = g0 + (uint64_t)j * 64 + lane;
+      if (g < gend && prod.flag(g)) m.w[j >> 6] |= 1ull << (j & 63);
+    }
+    return m;
+  }
+  if (g0 >= gend) return m;
+  const uint64_t last = gend - 1;
+  for (int j0 = 0; j0 < kWaveSlots; j0 += 16) {  // 16 flags in flight before the first is used
+    bool f[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint64_t g = g0 + (uint64_t)(j0 + k) * 64 + lane;
+      f[k] = prod.flag(g < gend ? g : last);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int j = j0 + k;
+      if (f[k] && g0 + (uint64_t)j * 64 + lane < gend) m.w[j >> 6] |= 1ull << (j & 63);
+    }
   }
   return m;
+}
+
+// The payloads of slots [j0, j0 + kValBatch) of this lane, loaded before any of
+// them is stored (a store may alias the payload buffer, so the compiler cannot
+// move later loads above it); slots past the tile read its last thread.
+constexpr int kValBatch = 16;
+static_assert(kWaveSlots % kValBatch == 0, "whole payload batches");
+template <typename T, class Prod>
+__device__ __forceinline__ void wave_values(const Prod& prod, uint64_t g0, uint64_t gend, int j0,
+                                            T (&v)[kValBatch]) {
+  const uint32_t lane = lane_id();
+  const uint64_t last = gend - 1;
+#pragma unroll
+  for (int k = 0; k < kValBatch; ++k) {
+    const uint64_t g = g0 + (uint64_t)(j0 + k) * 64 + lane;
+    v[k] = prod.value(g < gend ? g : last);
+  }
 }
 
 // Every thread of the tile inserts and the tile lies in one bucket: element i is
@@ -383,17 +425,37 @@ __device__ __forceinline__ void dense_store(T* dst, const Prod& prod, uint64_t g
   const gptr<T> d = gmem(dst);
   if (lane < head) d[lane] = prod.value(g0 + lane);
   const uint32_t nv = (n - head) / VPL;
-  for (uint32_t q = lane; q < nv; q += 64) {
-    const uint32_t e = head + q * VPL;
-    T tmp[VPL];
+  if constexpr (Prod::kDense) {  // generated payloads: no loads in the loop
+    for (uint32_t q = lane; q < nv; q += 64) {
+      const uint32_t e = head + q * VPL;
+      T tmp[VPL];
 #pragma unroll
-    for (uint32_t k = 0; k < VPL; ++k) tmp[k] = prod.value(g0 + e + k);
-    u32x4 x;
-    __builtin_memcpy(&x, tmp, 16);
-    if constexpr (Prod::kDense)  // generated payloads: no loads in the loop
+      for (uint32_t k = 0; k < VPL; ++k) tmp[k] = prod.value(g0 + e + k);
+      u32x4 x;
+      __builtin_memcpy(&x, tmp, 16);
       store_nt_sc1(reinterpret_cast<gptr<u32x4>>(d + e), x);
-    else
-      __builtin_nontemporal_store(x, reinterpret_cast<gptr<u32x4>>(d + e));
+    }
+  } else {
+    // Payloads from memory: kU vectors per lane are loaded (clamped to the last
+    // one) before any is stored, since a store may alias the payload buffer.
+    constexpr uint32_t kU = 4;
+    for (uint32_t q0 = 0; q0 < nv; q0 += 64 * kU) {
+      u32x4 x[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) {
+        const uint32_t q = q0 + u * 64 + lane;
+        const uint32_t e = head + (q < nv ? q : nv - 1) * VPL;
+        T tmp[VPL];
+#pragma unroll
+        for (uint32_t k = 0; k < VPL; ++k) tmp[k] = prod.value(g0 + e + k);
+        __builtin_memcpy(&x[u], tmp, 16);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) {
+        const uint32_t q = q0 + u * 64 + lane;
+        if (q < nv) __builtin_nontemporal_store(x[u], reinterpret_cast<gptr<u32x4>>(d + head + q * VPL));
+      }
+    }
   }
   const uint32_t tail = head + nv * VPL + lane;
   if (tail < n) d[tail] = prod.value(g0 + tail);
@@ -459,7 +521,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     dense_store<T, Prod>(dst, prod, g0, n_t);
     return;
   }
-  if (kStatic || r.nb == 1) {
+  if ((kStatic || r.nb == 1) && !Prod::kLoads) {
 #pragma unroll 16
     for (int j = 0; j < kWaveSlots; ++j) {
       const bool f = bits.get(j);
@@ -470,15 +532,48 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     }
     return;
   }
+  if (kStatic || r.nb == 1) {
+    for (int j0 = 0; j0 < kWaveSlots; j0 += kValBatch) {
+      T v[kValBatch];
+      wave_values<T, Prod>(prod, g0, gend, j0, v);
+#pragma unroll
+      for (int k = 0; k < kValBatch; ++k) {
+        const bool f = bits.get(j0 + k);
+        const uint64_t m = __ballot(f);
+        const uint32_t q = run + mbcnt(m);
+        if (f && q < lim) gmem(dst)[q] = v[k];
+        run += (uint32_t)__popcll(m);
+      }
+    }
+    return;
+  }
   // The tile spans several buckets: locate each element by the closed form.
-  for (int j = 0; j < kWaveSlots; ++j) {
-    const bool f = bits.get(j);
-    const uint64_t m = __ballot(f);
-    const uint64_t idx = r.base + run + mbcnt(m);
-    const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
-    const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
-    if (f && p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
-    run += (uint32_t)__popcll(m);
+  if constexpr (!Prod::kLoads) {
+    for (int j = 0; j < kWaveSlots; ++j) {
+      const bool f = bits.get(j);
+      const uint64_t m = __ballot(f);
+      const uint64_t idx = r.base + run + mbcnt(m);
+      const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
+      const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
+      if (f && p > kFailedPtr)
+        gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = prod.value(g0 + (uint64_t)j * 64 + lane);
+      run += (uint32_t)__popcll(m);
+    }
+    return;
+  }
+  for (int j0 = 0; j0 < kWaveSlots; j0 += kValBatch) {
+    T v[kValBatch];
+    wave_values<T, Prod>(prod, g0, gend, j0, v);
+#pragma unroll
+    for (int k = 0; k < kValBatch; ++k) {
+      const bool f = bits.get(j0 + k);
+      const uint64_t m = __ballot(f);
+      const uint64_t idx = r.base + run + mbcnt(m);
+      const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
+      const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
+      if (f && p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = v[k];
+      run += (uint32_t)__popcll(m);
+    }
   }
 }
 

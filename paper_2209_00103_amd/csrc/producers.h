@@ -8,19 +8,25 @@
 
 namespace gga {
 
+// Thread gid inserts values[gid] iff flags[gid] != 0.  Without flags (every
+// thread inserts) only the dense kernels run, and they read values alone, so
+// flag() reads flags unconditionally (a test per slot would keep each flag load
+// under a branch, which costs a memory round trip per slot).
 template <typename T>
-struct ProdBuffer {  // thread gid inserts values[gid] iff flags[gid] != 0
+struct ProdBuffer {
   static constexpr bool kMulti = false;
   static constexpr bool kDense = false;
+  static constexpr bool kLoads = true;  // flags and payloads come from memory
   const T* values;
   const uint8_t* flags;
-  __device__ __forceinline__ bool flag(uint64_t g) const { return flags ? flags[g] != 0 : true; }
+  __device__ __forceinline__ bool flag(uint64_t g) const { return flags[g] != 0; }
   __device__ __forceinline__ T value(uint64_t g) const { return values[g]; }
 };
 template <typename T>
 struct ProdBernoulli {  // h = K(seed, gid, round); insert (T)h iff top bit
   static constexpr bool kMulti = false;
   static constexpr bool kDense = false;
+  static constexpr bool kLoads = false;
   uint64_t seed;
   uint32_t round;
   __device__ __forceinline__ bool flag(uint64_t g) const { return (K(seed, g, round) >> 63) != 0; }
@@ -36,6 +42,7 @@ template <typename T>
 struct ProdRoundTag {  // insert (round << shift) | gid
   static constexpr bool kMulti = false;
   static constexpr bool kDense = true;  // every thread inserts
+  static constexpr bool kLoads = false;
   uint32_t round;
   uint32_t shift;
   __device__ __forceinline__ bool flag(uint64_t) const { return true; }
@@ -50,6 +57,7 @@ template <typename T>
 struct ProdKeyed {  // every thread inserts K(seed, (tag << shift) | gid, round)
   static constexpr bool kMulti = false;
   static constexpr bool kDense = true;
+  static constexpr bool kLoads = false;
   uint64_t seed;
   uint32_t round;
   uint32_t shift;
