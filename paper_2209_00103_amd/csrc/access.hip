@@ -851,12 +851,15 @@ int launch_flatten(ggarray* a, void* out, uint64_t cap, hipStream_t s) {
 }
 
 // The static array's r/w in the GGArray's launch shape: one workgroup per 16 KiB
-// tile of the capacity (up to kTableBlocks, looping beyond; workgroups past the
-// live tiles exit at once) and the same load policy (through the cache after an
-// insertion, streaming after an r/w), so that only the layout differs.
+// tile of the host's bound of its size (up to kTableBlocks, looping beyond) and
+// the same load policy, so that only the layout differs.  (A grid sized for the
+// capacity dispatches a workgroup per empty tile: 2^30-element capacity holding
+// 6.25e7 elements streamed at 5.0 TB/s against 6.35 for the same bytes sized to
+// fit.)
 int launch_static_rw(gga_static* st, uint32_t op, hipStream_t s) {
   const uint32_t te_log2 = st->elem_bytes == 4 ? 12u : 11u;
-  uint64_t tiles = (st->cap + (1ull << te_log2) - 1) >> te_log2;
+  const uint64_t ub = st->size_ub < st->cap ? st->size_ub : st->cap;
+  const uint64_t tiles = (ub + (1ull << te_log2) - 1) >> te_log2;
   const dim3 grid(xcd_grid(tiles > kTableBlocks ? kTableBlocks : tiles)), block(kRwThreads);
   const bool nt = st->rw_last;
   if (st->elem_bytes == 4) {

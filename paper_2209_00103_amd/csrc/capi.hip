@@ -705,6 +705,7 @@ static int static_init(gga_static* st, void* buf, uint64_t cap, uint32_t elem_by
   st->d_err = reinterpret_cast<uint32_t*>(m + 16);
   st->d_done = reinterpret_cast<uint32_t*>(m + 128);  // its own cache line: the size's is read by every wave
   st->rw_last = false;
+  st->size_ub = 0;
   return GGA_OK;
 }
 
@@ -714,7 +715,10 @@ static int static_read(gga_static* st, uint64_t* size_out, hipStream_t s) {
       hipMemcpyAsync(&h[1], st->d_err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return GGA_EHIP;
-  if (size_out) *size_out = h[0] < st->cap ? h[0] : st->cap;
+  if (size_out) {
+    *size_out = h[0] < st->cap ? h[0] : st->cap;
+    st->size_ub = *size_out;
+  }
   return map_device_error((uint32_t)h[1]);
 }
 
@@ -793,6 +797,7 @@ int gga_static_clear(gga_static* st, gga_stream s) {
       hipMemsetAsync(st->d_err, 0, 4, S(s)) != hipSuccess)
     return GGA_EHIP;
   st->rw_last = false;
+  st->size_ub = 0;
   return GGA_OK;
 }
 
@@ -803,6 +808,7 @@ int gga_static_set_size(gga_static* st, uint64_t n, gga_stream s) {
                         (int)(uint32_t)(n >> 32), 1, S(s)) != hipSuccess)
     return GGA_EHIP;
   st->rw_last = false;
+  st->size_ub = n;
   return GGA_OK;
 }
 

@@ -103,6 +103,7 @@ struct gga_static {
   uint32_t* d_err;
   uint32_t* d_done;
   bool rw_last;        // the last operation was an r/w (its loads then stream past the caches)
+  uint64_t size_ub;    // host upper bound of the size (sizes the r/w grid)
 };
 
 namespace gga {

@@ -1715,9 +1715,17 @@ int launch_insert_packed_noalloc(ggarray* a, const void* values, const uint8_t* 
   return queue_packed(a, sc, values, counts, I, ntiles, n_values, s);  // every word it reads is written first
 }
 
+// A round of n threads (each inserting at most `per`) raises the host's bound
+// of the static array's size by at most n * per, never past the capacity.
+static void static_grow_bound(gga_static* st, uint64_t n, uint64_t per) {
+  const uint64_t room = st->cap - (st->size_ub < st->cap ? st->size_ub : st->cap);
+  st->size_ub += (per && n > room / per) ? room : n * per;
+}
+
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s) {
   st->rw_last = false;
   if (d.n_threads == 0) return GGA_OK;
+  static_grow_bound(st, d.n_threads, 1);
   StaticRef S{st->data, st->cap, st->d_size, st->d_err, st->d_done};
   uint64_t blocks = (d.n_threads + 255) / 256;
   if (blocks > 65536) blocks = 65536;
@@ -1768,6 +1776,7 @@ int launch_static_dense(const StaticRef& S, const InsertDesc& d, uint64_t ntiles
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s) {
   st->rw_last = false;
   if (d.n_threads == 0) return GGA_OK;
+  static_grow_bound(st, d.n_threads, multi_mode(d.mode) ? d.max_count : 1u);
   const uint64_t tile = multi_mode(d.mode) ? kCountTile : kFlagTile;
   const uint64_t ntiles = (d.n_threads + tile - 1) / tile;
   if (ntiles > 0x7FFFFFFFull) return GGA_EINVAL;

@@ -111,3 +111,50 @@ def test_static_over_flattened_buffer():
     st.close()
     a.close()
     pool.close()
+
+
+def test_static_rw_reaches_every_live_element_as_the_size_changes():
+    """The static r/w launches one workgroup per tile of the host's bound of the
+    size, which set_size, rounds (at most n per round of n threads), clear and a
+    read of the size move: after each of them the r/w reaches every live element
+    of a capacity far above the size, and nothing past it."""
+    import torch
+
+    G = gg()
+    cap = 1 << 24
+    buf = torch.arange(cap, dtype=torch.int32, device="cuda")
+    st = G.StaticArray(cap, 4, buf=buf)
+    want = np.arange(cap, dtype=np.uint32)
+
+    def check(n, tag):
+        st.rw(G.ADD1)
+        want[:n] += 1
+        assert np.array_equal(G.as_unsigned(buf), want), tag
+
+    st.set_size(5000)
+    check(5000, "set_size")
+    st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=1, tag_shift=24), 70001)
+    want[5000:75001] = (1 << 24) | np.arange(70001, dtype=np.uint32)
+    check(75001, "dense round")
+    rng = np.random.default_rng(5)
+    vals, flags = wl.random_round(rng, 300000, 0.3, 4)
+    st.insert(dev(vals), dev(flags))
+    kept = vals[flags != 0]
+    n = 75001 + kept.size
+    got = G.as_unsigned(buf[75001:n])  # tiles take their places in any order: compare as multisets
+    assert np.array_equal(np.sort(got), np.sort(kept))
+    want[75001:n] = got
+    check(n, "sparse round (bound above the size)")
+    assert st.size() == n  # a read makes the bound exact
+    st.insert_gen(G.make_gen(G.GEN_KEYED, seed=4, round=2, tag=1, tag_shift=22), 4097)
+    o = Oracle(4, 1, 1, forms=oracle.FORM_LIST)
+    o.insert_gen(oracle.GEN_KEYED, 4097, seed=4, round=2, tag=1, tag_shift=22)
+    want[n:n + 4097] = o.flatten()
+    n += 4097
+    check(n, "round after a size read")
+    st.clear()
+    st.insert_gen(G.make_gen(G.GEN_ROUND_TAG, round=3, tag_shift=24), 3)
+    want[:3] = (3 << 24) | np.arange(3, dtype=np.uint32)
+    check(3, "after clear")
+    assert st.last_error() == 0
+    st.close()
