@@ -58,7 +58,9 @@ def parse():
     ap.add_argument("--no-shootout", action="store_true",
                     help="skip the scan-vs-atomic insertion comparison and the memory model")
     ap.add_argument("--serve-requests", type=int, default=1 << 20, help="requests in the served trace")
-    ap.add_argument("--serve-lanes", type=int, default=3, help="served steps in flight")
+    ap.add_argument("--serve-lanes", type=int, default=2,
+                    help="served steps in flight (2 measured best: at 5.45e4 / 9.8e4 req/s p99 111 / 100 us "
+                         "against 153 / 159 with 3 lanes and 176 / 182 with 1)")
     ap.add_argument("--serve-step", type=int, default=1024, help="requests per served step")
     ap.add_argument("--serve-baseline-requests", type=int, default=1 << 14,
                     help="trace prefix replayed with one launch per request")
@@ -418,17 +420,32 @@ def served_leg(G, wl, torch, np_, args):
     sat_pr = run(per_req, zeros, k_b)
     x = sat["req_per_s"]
     # loads the per-request baseline can sustain: 0.5 and 0.9 of its own saturation
-    # rate, both modes on the same requests
+    # rate, both modes on the same requests.  Tail latency at these light loads
+    # varies from run to run on the same box (host and clock noise: the same build
+    # has given p99 50 us and 124 us in consecutive processes), so each mode is
+    # replayed three times, alternating, and the trial with the median p99 is
+    # reported, all three p99s beside it.
+    def median_trial(trials):
+        order = sorted(range(len(trials)), key=lambda i: trials[i]["all"]["p99_us"])
+        best = dict(trials[order[len(order) // 2]])
+        best["trials_p99_us"] = [t["all"]["p99_us"] for t in trials]
+        return best
+
     matched = []
     for f in (0.5, 0.9):
         rate = f * sat_pr["req_per_s"]
         arrival = wl.cfg5_arrivals_ns(tr["gap"], rate)
+        tb, tp = [], []
+        for _ in range(3):
+            tb.append(run(batched, arrival, k_b))
+            tp.append(run(per_req, arrival, k_b))
         m = {"load_of_per_request_saturation": f, "offered_req_per_s": rate,
-             "batched": run(batched, arrival, k_b), "per_request": run(per_req, arrival, k_b)}
+             "batched": median_trial(tb), "per_request": median_trial(tp)}
         matched.append(m)
         log(f"served at {rate:.3e} req/s: batched p50 {m['batched']['all']['p50_us']:.0f} us p99 "
-            f"{m['batched']['all']['p99_us']:.0f} us; per-request p50 {m['per_request']['all']['p50_us']:.0f} us "
-            f"p99 {m['per_request']['all']['p99_us']:.0f} us")
+            f"{m['batched']['all']['p99_us']:.0f} us (trials {[round(x) for x in m['batched']['trials_p99_us']]}); "
+            f"per-request p50 {m['per_request']['all']['p50_us']:.0f} us "
+            f"p99 {m['per_request']['all']['p99_us']:.0f} us (trials {[round(x) for x in m['per_request']['trials_p99_us']]})")
     loads = []
     for f in cfg["loads"]:
         arrival = wl.cfg5_arrivals_ns(tr["gap"], f * x)
