@@ -318,6 +318,27 @@ __device__ __forceinline__ void pool_free(PoolRef P, uint8_t* ptr, uint32_t cls,
   add_nr(&H->shard[arena_shard(s)].n_free, 1ull);
 }
 
+// A block of class cls taken for free-list shard s and given back to it in the
+// same launch with nothing written into it (a bucket that a round reaches and
+// its fused shrink releases again).  When that list is not empty, its pop and
+// push would leave it as it was (the top block back on top, with the same link),
+// so the call only counts one allocation and one release; an empty list, or a
+// pool with fault injection armed, takes the full path (arena or bump pointer,
+// failure included, then the push).  Returns false where the allocation fails.
+__device__ __forceinline__ bool pool_alloc_release(PoolRef P, uint32_t cls, uint32_t s) {
+  PoolHdr* H = P.hdr;
+  if (cls <= (uint32_t)kMaxClassLog2 && !H->fault_at &&
+      (ld_rlx(&H->heads[(uint64_t)cls * kFreeShards + s]) & kIdxMask)) {
+    add_nr(&H->shard[arena_shard(s)].n_alloc, 1ull);
+    add_nr(&H->shard[arena_shard(s)].n_free, 1ull);
+    return true;
+  }
+  uint8_t* p = pool_alloc(P, cls, s);
+  if (!p) return false;
+  pool_free(P, p, cls, s);
+  return true;
+}
+
 // -------------------------------------------------------- element pointers --
 // Bucket pointers are kept as integers, so the compiler cannot tell that they
 // address device memory and would access elements with flat instructions, whose

@@ -711,12 +711,19 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
   const uint32_t log2F = A.log2F;
   const uint64_t s0 = A.size[v];
   const uint32_t lo = nbuckets_for(log2F, s0), hi = nbuckets_for(log2F, s0 + cnt);
+  // With a fused shrink, the buckets from `keep` on go back to the pool at the end
+  // of this launch; those the round itself reaches are allocated and released
+  // with nothing stored in them (pool_alloc_release: counted, not moved).
+  const uint64_t fin = I.sh_den ? shrink_keep(s0 + cnt, I.sh_num, I.sh_den) : s0 + cnt;
+  const uint32_t keep = nbuckets_for(log2F, fin);
   const uint32_t b = lo + lane;
   uint64_t q = 0;
   bool failed = false;
   if (b < hi) {
     if (b >= (uint32_t)kMaxBuckets) {
       failed = true;
+    } else if (I.sh_den && b >= keep) {
+      failed = !pool_alloc_release(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
     } else {
       uint8_t* p = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
       q = p ? (uint64_t)p : kFailedPtr;
@@ -740,13 +747,11 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
     }
     return;
   }
-  const uint64_t fin = I.sh_den ? shrink_keep(s0 + cnt, I.sh_num, I.sh_den) : s0 + cnt;
   if (lane == 0) A.size[v] = fin;
   // With a fused shrink, elements that would land in a bucket the shrink releases
   // are popped anyway: they are not stored, so no store of this wave can still be
   // in flight to a bucket when it goes back to the pool (whose link word the
   // release writes), and the release needs no fence.
-  const uint32_t keep = nbuckets_for(log2F, fin);
   uint64_t upto = s0 + cnt;
   if (I.sh_den && bucket_start(log2F, keep) < upto) upto = bucket_start(log2F, keep) > s0 ? bucket_start(log2F, keep) : s0;
   const uint32_t n = (uint32_t)(upto - s0);
