@@ -281,9 +281,8 @@ def batched_leg(G, wl, torch, np, steps, warmup):
         b.rw(G.ADD1)
         b.flatten_into(out)
 
-    def persistent_step():
-        b.shrink(1, 1)
-        b.step(bgens, counts, G.ADD1, out3)
+    def persistent_step():  # the clear runs inside the step's launch
+        b.step(bgens, counts, G.ADD1, out3, clear=True)
 
     def per_array_step():
         for i, a in enumerate(arrays):
@@ -802,15 +801,15 @@ def config1_leg(G, wl, torch, reps=50):
     assert a.last_error() == 0 and a.size() == size
     ref = out.clone()
 
-    # The same step as one persistent launch (gga_batch_step on a batch of this
-    # one array: every LFVector's 4 rounds and r/w in one workgroup, then the
-    # flatten), eager and replayed as a graph; its output must equal the above.
+    # The same step as one persistent launch (gga_batch_step_clear on a batch of
+    # this one array: every LFVector's clear, 4 rounds and r/w in one workgroup,
+    # then the flatten), eager and replayed as a graph; its output must equal the
+    # above.
     b = G.Batch([a])
     rows = [[n]] * len(gens)
 
-    def pstep():
-        a.shrink(1, 1)
-        b.step(gens, rows, G.ADD1, out)
+    def pstep():  # the clear runs inside the step's launch
+        b.step(gens, rows, G.ADD1, out, clear=True)
 
     with torch.cuda.stream(s):
         for _ in range(5):

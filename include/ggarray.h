@@ -372,6 +372,19 @@ int ggarray_device_done(ggarray *a, gga_stream s);
 #define GGA_RW_NONE 0xFFFFFFFFu
 int gga_batch_step(gga_batch *b, const gga_gen *gens, uint32_t rounds, const uint64_t *n_threads, uint32_t op,
                    void *out, uint64_t out_cap_elems, gga_stream s);
+
+/* gga_batch_step_clear: gga_batch_shrink(b, 1, 1) followed by gga_batch_step
+ *   with the same arguments, in that one launch.  The result (sizes, contents,
+ *   the pool's allocation and release counts, out) is that of the two calls;
+ *   a bucket an LFVector held before the clear and reaches again in the rounds
+ *   stays in place rather than going through its free list (a push and a pop of
+ *   the same block), and the held buckets the rounds do not reach go back to the
+ *   pool at the end.  A frozen LFVector gives back every bucket and stays
+ *   frozen, as after ggarray_shrink.  Same validation, graph capture and error
+ *   behaviour as gga_batch_step. */
+int gga_batch_step_clear(gga_batch *b, const gga_gen *gens, uint32_t rounds, const uint64_t *n_threads, uint32_t op,
+                         void *out, uint64_t out_cap_elems, gga_stream s);
+
 int gga_batch_create(gga_batch **out, ggarray *const *arrays, uint32_t n, gga_stream s);
 int gga_batch_destroy(gga_batch *b, gga_stream s);
 int gga_batch_insert_gen(gga_batch *b, const gga_gen *g, const uint64_t *n_threads, gga_stream s);

@@ -339,6 +339,22 @@ __device__ __forceinline__ bool pool_alloc_release(PoolRef P, uint32_t cls, uint
   return true;
 }
 
+// A block that a clear earlier in the same launch released to free-list shard s,
+// taken again by the same LFVector with nothing written to it in between: a
+// push followed by a pop of that list gives the block back and leaves the list
+// as it was, so the call counts one release and one allocation and the block
+// stays where it is.  With fault injection armed the allocation attempt counts
+// too and may fail (false: the caller then releases the block for real, as the
+// clear would have).
+__device__ __forceinline__ bool pool_reuse(PoolRef P, uint32_t s) {
+  PoolHdr* H = P.hdr;
+  const uint64_t fault_at = H->fault_at;
+  if (fault_at && fetch_add(&H->n_attempt, 1) + 1 == fault_at) return false;
+  add_nr(&H->shard[arena_shard(s)].n_alloc, 1ull);
+  add_nr(&H->shard[arena_shard(s)].n_free, 1ull);
+  return true;
+}
+
 // -------------------------------------------------------- element pointers --
 // Bucket pointers are kept as integers, so the compiler cannot tell that they
 // address device memory and would access elements with flat instructions, whose

@@ -596,12 +596,13 @@ int gga_batch_insert_gen(gga_batch* b, const gga_gen* g, const uint64_t* n_threa
   return launch_batch_insert(b, gen_desc(g, mode, 0), n_threads, S(s));
 }
 
-int gga_batch_step(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uint64_t* n_threads, uint32_t op,
-                   void* out, uint64_t out_cap_elems, gga_stream s) {
+static int batch_step(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uint64_t* n_threads, uint32_t op,
+                      void* out, uint64_t out_cap_elems, gga_stream s, bool clear) {
   if (!b || rounds > kMaxStepRounds || (rounds && (!gens || !n_threads)) || (op > GGA_ADD1_X30 && op != GGA_RW_NONE))
     return GGA_EINVAL;
   StepDesc D{};
   D.n_rounds = rounds;
+  D.clear = clear ? 1u : 0u;
   for (uint32_t r = 0; r < rounds; ++r) {
     const gga_gen* g = &gens[r];
     uint32_t mode = 0, maxc = 0;
@@ -645,9 +646,20 @@ int gga_batch_step(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uin
   for (uint32_t i = 0; i < b->n; ++i) {
     uint64_t add = 0;
     for (uint32_t r = 0; r < rounds; ++r) add += n_threads[(uint64_t)r * b->n + i];
+    if (clear) b->arrays[i]->size_ub = 0;
     grow_bound(b->arrays[i], add);
   }
   return launch_batch_step(b, D, dev, op == GGA_RW_NONE ? kOpNone : op, out, out_cap_elems, S(s));
+}
+
+int gga_batch_step(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uint64_t* n_threads, uint32_t op,
+                   void* out, uint64_t out_cap_elems, gga_stream s) {
+  return batch_step(b, gens, rounds, n_threads, op, out, out_cap_elems, s, false);
+}
+
+int gga_batch_step_clear(gga_batch* b, const gga_gen* gens, uint32_t rounds, const uint64_t* n_threads, uint32_t op,
+                         void* out, uint64_t out_cap_elems, gga_stream s) {
+  return batch_step(b, gens, rounds, n_threads, op, out, out_cap_elems, s, true);
 }
 
 int gga_batch_shrink(gga_batch* b, uint32_t num, uint32_t den, gga_stream s) {

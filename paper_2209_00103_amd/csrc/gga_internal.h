@@ -224,7 +224,7 @@ struct StepRound {
 };
 struct StepDesc {
   uint32_t n_rounds;
-  uint32_t pad;
+  uint32_t clear;  // shrink every LFVector 1/1 ahead of the rounds (buckets it uses again stay in place)
   StepRound r[kMaxStepRounds];
 };
 constexpr uint32_t kStepChunkMax = 1024;  // LFVector chunks of the step's size prefix

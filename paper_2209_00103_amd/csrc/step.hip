@@ -42,6 +42,8 @@ __device__ __forceinline__ uint32_t s_mbcnt(uint64_t m) {
 
 struct StepShared {
   uint64_t bp[kMaxBuckets];   // the LFVector's bucket pointers
+  uint64_t reused;            // buckets below keep_hi that the rounds have taken again
+  uint32_t keep_hi;           // with a clear: buckets [0, keep_hi) held from before it
   uint64_t size;
   uint32_t cnt[kSSlots * kSW];
   uint32_t fail;
@@ -56,6 +58,8 @@ struct StepShared {
 // from and freezes the LFVector.
 // Wave 0 allocates the buckets whose first index lies in [s, s + n) (one per
 // lane) into the LFVector's table and sh.bp; sh.fail says whether any failed.
+// After a clear in the same launch, a bucket the LFVector held before it is taken
+// again in place (pool_reuse) instead of from the pool.
 __device__ void step_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint64_t s, uint64_t n,
                            StepShared& sh) {
   const uint32_t lane = s_lane();
@@ -63,10 +67,13 @@ __device__ void step_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint
   const uint32_t log2F = A.log2F;
   const uint32_t lo = nbuckets_for(log2F, s), hi = nbuckets_for(log2F, s + n);
   const uint32_t b = lo + lane;
-  bool failed = false;
+  bool failed = false, reuse = false;
   if (b < hi) {
     if (b >= (uint32_t)kMaxBuckets) {
       failed = true;
+    } else if (b < sh.keep_hi) {
+      reuse = pool_reuse(A.pool, pool_shard(v, b, A.salt));
+      failed = !reuse;
     } else {
       uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, elem_log2, b), pool_shard(v, b, A.salt));
       const uint64_t p = q ? (uint64_t)q : kFailedPtr;
@@ -75,7 +82,41 @@ __device__ void step_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint
       failed = !q;
     }
   }
-  if (lane == 0) sh.fail = __ballot(failed) ? 1u : 0u;
+  // Both ballots are taken by the whole wave (a ballot under `lane == 0` would see
+  // lane 0 alone); bit l of the reuse ballot is bucket lo + l.
+  const uint64_t rm = __ballot(reuse);
+  const uint64_t fm = __ballot(failed);
+  if (lane == 0) {
+    sh.fail = fm ? 1u : 0u;
+    sh.reused |= rm << lo;
+  }
+}
+
+// The clear ahead of a step's rounds, for one LFVector: a frozen LFVector gives
+// back every bucket it holds (as shrink does), any other keeps its buckets
+// [0, keep_hi) for the rounds to take again.  `lane` is the caller's lane in the
+// wave that does it.
+__device__ __forceinline__ uint32_t step_clear(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint32_t lane,
+                                               uint64_t size, bool dead) {
+  if (dead) {
+    release_bucket(A, v, lane, 0, kMaxBuckets, false, 0, elem_log2);
+    return 0;
+  }
+  return nbuckets_for(A.log2F, size);
+}
+
+// After the rounds: the clear's release of the held buckets [0, keep_hi) the
+// rounds did not take again (nothing of this launch was written to them, so no
+// fence is needed before they go back).
+__device__ __forceinline__ void step_release_unused(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint32_t lane,
+                                                    uint32_t keep_hi, uint64_t reused, uint64_t& bp) {
+  if (lane < keep_hi && !((reused >> lane) & 1u)) {
+    if (bp > kFailedPtr)
+      pool_free(A.pool, reinterpret_cast<uint8_t*>(bp), bucket_class(A.log2F, elem_log2, lane),
+                pool_shard(v, lane, A.salt));
+    A.bptr[(uint64_t)v * kMaxBuckets + lane] = 0;
+    bp = 0;
+  }
 }
 
 // A round in which every logical thread inserts (round-tag, keyed): element i
@@ -269,9 +310,25 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
     if (tid == 0) {
       sh.size = A.size[v];
       sh.dead = A.dead[v];
+      sh.keep_hi = 0;
+      sh.reused = 0;
     }
     __syncthreads();
     bool changed = false;
+    if (D.clear) {
+      const uint64_t s_old = sh.size;
+      const bool was_dead = sh.dead != 0;
+      __syncthreads();  // every thread has read the old size
+      if (tid < 64) {
+        const uint32_t kh = step_clear(A, v, elem_log2, tid, s_old, was_dead);
+        if (tid == 0) {
+          sh.keep_hi = kh;
+          sh.size = 0;
+        }
+      }
+      __syncthreads();
+      changed = true;
+    }
     for (uint32_t r = 0; r < D.n_rounds && !sh.dead; ++r) {
       const uint64_t nthr = counts[(uint64_t)r * n_arr + i];
       const uint64_t chunk = (nthr + A.V - 1) / A.V;
@@ -297,6 +354,15 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
         }
         __syncthreads();
       }
+    }
+    if (D.clear) {
+      __syncthreads();  // the rounds' bucket bookkeeping is complete
+      if (tid < 64) {
+        uint64_t bp = tid < (uint32_t)kMaxBuckets ? sh.bp[tid] : 0;
+        step_release_unused(A, v, elem_log2, tid, sh.keep_hi, sh.reused, bp);
+        if (tid < (uint32_t)kMaxBuckets) sh.bp[tid] = bp;
+      }
+      __syncthreads();
     }
     if (changed && tid == 0) st_rlx(&A.size[v], sh.size);
     if (tid == 0) st_rlx(&vsize[wv], sh.size);
@@ -393,14 +459,19 @@ __global__ __launch_bounds__(kSB) void step_kernel(const BatchArr* arrs, const u
 namespace {
 
 // Wave 0 .. 63: allocate buckets [nbuckets(s), nbuckets(s + n)) (lane b: bucket
-// b), keeping the pointer in the lane.  False if any allocation failed.
-__device__ bool wave_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint64_t s, uint64_t n, uint64_t& bp) {
+// b), keeping the pointer in the lane; a bucket below keep_hi (held from before
+// the step's clear) is taken again in place.  False if any allocation failed.
+__device__ bool wave_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint64_t s, uint64_t n, uint64_t& bp,
+                           uint32_t keep_hi, uint64_t& reused) {
   const uint32_t lane = s_lane(), log2F = A.log2F;
   const uint32_t lo = nbuckets_for(log2F, s), hi = nbuckets_for(log2F, s + n);
-  bool failed = false;
+  bool failed = false, reuse = false;
   if (lane >= lo && lane < hi) {
     if (lane >= (uint32_t)kMaxBuckets) {
       failed = true;
+    } else if (lane < keep_hi) {
+      reuse = pool_reuse(A.pool, pool_shard(v, lane, A.salt));
+      failed = !reuse;
     } else {
       uint8_t* q = pool_alloc(A.pool, bucket_class(log2F, elem_log2, lane), pool_shard(v, lane, A.salt));
       bp = q ? (uint64_t)q : kFailedPtr;
@@ -408,6 +479,7 @@ __device__ bool wave_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint
       failed = !q;
     }
   }
+  reused |= __ballot(reuse);
   return __ballot(failed) == 0;
 }
 
@@ -417,11 +489,11 @@ __device__ bool wave_alloc(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint
 // candidate t0 + 64 j + l), positions from the slot ballots.
 template <typename T, class Prod>
 __device__ bool wave_round(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint64_t c0, uint64_t cnt,
-                           const Prod& prod, uint64_t& bp, uint64_t& s) {
+                           const Prod& prod, uint64_t& bp, uint64_t& s, uint32_t keep_hi, uint64_t& reused) {
   constexpr uint32_t VPL = 16 / sizeof(T);
   const uint32_t lane = s_lane(), log2F = A.log2F;
   if constexpr (Prod::kDense) {
-    if (!wave_alloc(A, v, elem_log2, s, cnt, bp)) return false;
+    if (!wave_alloc(A, v, elem_log2, s, cnt, bp, keep_hi, reused)) return false;
     for (uint64_t i = 0; i < cnt;) {
       const uint64_t idx = s + i;
       const uint32_t b = bucket_of(log2F, idx);
@@ -462,7 +534,7 @@ __device__ bool wave_round(const ArrRef& A, uint32_t v, uint32_t elem_log2, uint
         m[j] = __ballot(f);
         total += (uint32_t)__popcll(m[j]);
       }
-      if (!wave_alloc(A, v, elem_log2, s, total, bp)) return false;
+      if (!wave_alloc(A, v, elem_log2, s, total, bp, keep_hi, reused)) return false;
       uint64_t run = s;
 #pragma unroll
       for (uint32_t j = 0; j < kSlots; ++j) {
@@ -572,6 +644,14 @@ __global__ __launch_bounds__(kSB) void step_wave_kernel(const BatchArr* arrs, co
     uint64_t s = A.size[v];
     bool dead = A.dead[v] != 0;
     bool changed = false;
+    uint32_t keep_hi = 0;
+    uint64_t reused = 0;
+    if (D.clear) {
+      keep_hi = step_clear(A, v, elem_log2, lane, s, dead);
+      if (dead) bp = 0;
+      s = 0;
+      changed = true;
+    }
     for (uint32_t r = 0; r < D.n_rounds && !dead; ++r) {
       const uint64_t nthr = counts[(uint64_t)r * n_arr + i];
       const uint64_t chunk = (nthr + A.V - 1) / A.V;
@@ -582,11 +662,12 @@ __global__ __launch_bounds__(kSB) void step_wave_kernel(const BatchArr* arrs, co
       const uint64_t s_round = s;
       bool ok;
       if (R.kind == kModeBernoulli)
-        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdBernoulli<T>{R.seed, R.round}, bp, s);
+        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdBernoulli<T>{R.seed, R.round}, bp, s, keep_hi, reused);
       else if (R.kind == kModeRoundTag)
-        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdRoundTag<T>{R.round, R.tag_shift}, bp, s);
+        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdRoundTag<T>{R.round, R.tag_shift}, bp, s, keep_hi, reused);
       else
-        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdKeyed<T>{R.seed, R.round, R.tag_shift, R.tag + i}, bp, s);
+        ok = wave_round<T>(A, v, elem_log2, c0, cnt, ProdKeyed<T>{R.seed, R.round, R.tag_shift, R.tag + i}, bp, s,
+                           keep_hi, reused);
       changed = true;
       if (!ok) {  // the round is dropped and the LFVector frozen, as in the per-round calls
         s = s_round;
@@ -597,6 +678,7 @@ __global__ __launch_bounds__(kSB) void step_wave_kernel(const BatchArr* arrs, co
         }
       }
     }
+    if (D.clear) step_release_unused(A, v, elem_log2, lane, keep_hi, reused, bp);
     if (changed && lane == 0) st_rlx(&A.size[v], s);
     if (lane == 0) st_rlx(&vsize[wv], s);
     if (op != kOpNone) wave_rw<T>(A.log2F, op, bp, s);

@@ -92,6 +92,7 @@ _SIGS = {
     "gga_batch_destroy": [_vp, _vp],
     "gga_batch_insert_gen": [_vp, _P(GenSpec), _vp, _vp],
     "gga_batch_step": [_vp, _vp, _u32, _vp, _u32, _vp, _u64, _vp],
+    "gga_batch_step_clear": [_vp, _vp, _u32, _vp, _u32, _vp, _u64, _vp],
     "gga_batch_shrink": [_vp, _u32, _u32, _vp],
     "gga_batch_rw": [_vp, _u32, _vp],
     "gga_batch_flatten": [_vp, _vp, _u64, _vp],
@@ -412,9 +413,10 @@ class Batch:
         _check(lib().gga_batch_insert_gen(self._h, ctypes.byref(gen), arr, _stream(stream)),
                "gga_batch_insert_gen")
 
-    def step(self, gens, n_threads, op: int, out: torch.Tensor | None = None, stream=None):
+    def step(self, gens, n_threads, op: int, out: torch.Tensor | None = None, stream=None, clear: bool = False):
         """One persistent launch: rounds gens[r] with n_threads[r][i] threads on array i,
-        r/w op (RW_NONE: none), then the flatten into out (None: no flatten)."""
+        r/w op (RW_NONE: none), then the flatten into out (None: no flatten).  With
+        clear, every array is first emptied (shrink 1/1) in the same launch."""
         rounds = len(gens)
         flat = tuple(int(x) for row in n_threads for x in row)
         if len(flat) != rounds * self.n:
@@ -426,8 +428,9 @@ class Batch:
             self._counts[key] = arr
         g = (GenSpec * max(1, rounds))(*gens)
         op_ = _dev_ptr(out, "out", 0, self.arrays[0].elem_bytes) if out is not None else None
-        _check(lib().gga_batch_step(self._h, g, rounds, arr, op, op_, 0 if out is None else out.numel(),
-                                    _stream(stream)), "gga_batch_step")
+        fn, name = (lib().gga_batch_step_clear, "gga_batch_step_clear") if clear else \
+            (lib().gga_batch_step, "gga_batch_step")
+        _check(fn(self._h, g, rounds, arr, op, op_, 0 if out is None else out.numel(), _stream(stream)), name)
 
     def shrink(self, num: int, den: int, stream=None):
         _check(lib().gga_batch_shrink(self._h, num, den, _stream(stream)), "gga_batch_shrink")

@@ -4,7 +4,8 @@ oracle and against the per-round batch calls on twin arrays, for the
 configuration-1 shape, uneven batches of keyed rounds, uint64 round-tag rounds,
 more LFVectors than the step's prefix chunks (several LFVectors per chunk),
 several tiles per LFVector, a step on a non-empty state, a step without r/w or
-flatten, a too-small output and replays of a captured step."""
+flatten, a too-small output, replays of a captured step, and the step with a
+clear in the same launch against a clear followed by the step."""
 import numpy as np
 import pytest
 import torch
@@ -242,3 +243,92 @@ def test_step_per_wave_many_lfvectors(pool, elem):
     bt.close()
     for a in arrays + twins:
         a.close()
+
+
+def _pool_counts(p):
+    st = p.stats()
+    return st["in_use"], st["allocs"], st["frees"]
+
+
+@pytest.mark.parametrize("shapes", [[(256, 1024)], [(3000, 4), (1, 64), (1200, 1), (900, 256)]],
+                         ids=["workgroup-per-lfvector", "wave-per-lfvector"])
+def test_step_clear_equals_shrink_then_step(shapes):
+    """gga_batch_step_clear against gga_batch_shrink(1, 1) + gga_batch_step on twin
+    arrays in pools of their own, over passes that grow, shrink and grow again (so
+    held buckets are taken again, left unreached and released, or joined by new
+    ones): sizes, flatten, capacity and the pools' in-use bytes, allocation and
+    release counts are equal, and both equal the oracle's clear and rounds."""
+    G = gg()
+    pa, pb = G.Pool(1024 * MiB), G.Pool(1024 * MiB)
+    arrays = [G.GGArray(pa, 4, V, F) for V, F in shapes]
+    twins = [G.GGArray(pb, 4, V, F) for V, F in shapes]
+    oracles = [Oracle(4, V, F) for V, F in shapes]
+    b, bt = G.Batch(arrays), G.Batch(twins)
+    # per pass: thread counts per round, in units of V; the last pass takes the
+    # buckets of the one before again round by round (reuse beyond bucket 0)
+    scale = [[7, 3, 11], [1, 1, 1], [30, 2, 9], [12, 4, 20]]
+    out = torch.empty(sum(V * 45 for V, _ in shapes), dtype=torch.int32, device="cuda")
+    out_t = torch.empty_like(out)
+    for p, sc in enumerate(scale):
+        print(f"case step clear {len(shapes)} arrays pass {p}", flush=True)
+        counts = [[V * k + (i % 5) for i, (V, _) in enumerate(shapes)] for k in sc]
+        gens = [G.make_gen(G.GEN_KEYED, seed=7, round=3 * p, tag=0),
+                G.make_gen(G.GEN_BERNOULLI, seed=7, round=3 * p + 1),
+                G.make_gen(G.GEN_ROUND_TAG, round=3 * p + 2, tag_shift=24)]
+        b.step(gens, counts, G.ADD1, out, clear=True)
+        bt.shrink(1, 1)
+        bt.step(gens, counts, G.ADD1, out_t)
+        for o in oracles:
+            o.shrink(1, 1)
+        _oracle_rounds(oracles, ["keyed", "bern", "tag"], gens, counts)
+        assert b.last_error() == 0 and bt.last_error() == 0
+        _check_flat(out, oracles, f"clear pass {p}")
+        _check_flat(out_t, oracles, f"twin pass {p}")
+        for i, (a, t, o) in enumerate(zip(arrays, twins, oracles)):
+            np.testing.assert_array_equal(gpu_sizes(a), o.vector_sizes(), err_msg=f"array {i} pass {p}")
+            assert a.capacity() == t.capacity() == o.capacity(), f"array {i} pass {p}"
+        assert _pool_counts(pa) == _pool_counts(pb), f"pass {p}: {pa.stats()} vs {pb.stats()}"
+    b.close()
+    bt.close()
+    for a in arrays + twins:
+        a.close()
+    pa.close()
+    pb.close()
+
+
+def test_step_clear_under_fault_injection_matches_shrink_then_step():
+    """One LFVector, one bucket per round (F = 64, rounds of 64, 128, 256 and 512
+    round-tag threads), so allocation attempts come in bucket order.  A failure
+    injected at the third attempt of the second pass freezes the LFVector at the
+    size before that round, with the same buckets held and the same pool counts
+    as the shrink-then-step twin; the next clear gives every bucket back."""
+    G = gg()
+    pa, pb = G.Pool(64 * MiB), G.Pool(64 * MiB)
+    a, t = G.GGArray(pa, 4, 1, 64), G.GGArray(pb, 4, 1, 64)
+    b, bt = G.Batch([a]), G.Batch([t])
+    counts = [[64], [128], [256], [512]]
+    out = torch.empty(1024, dtype=torch.int32, device="cuda")
+    for p in range(3):
+        print(f"case step clear fault pass {p}", flush=True)
+        gens = [G.make_gen(G.GEN_ROUND_TAG, round=4 * p + r, tag_shift=20) for r in range(4)]
+        if p == 1:
+            pa.set_fault(pa.stats()["attempts"] + 3)
+            pb.set_fault(pb.stats()["attempts"] + 3)
+        b.step(gens, counts, G.RW_NONE, out, clear=True)
+        bt.shrink(1, 1)
+        bt.step(gens, counts, G.RW_NONE, out)
+        pa.set_fault(0)
+        pb.set_fault(0)
+        want_err = G.ENOMEM if p >= 1 else 0
+        assert a.last_error() == want_err and t.last_error() == want_err, f"pass {p}"
+        want = 960 if p == 0 else (192 if p == 1 else 0)
+        assert a.size(check_error=False) == t.size(check_error=False) == want, f"pass {p}"
+        assert a.capacity(check_error=False) == t.capacity(check_error=False), f"pass {p}"
+        assert _pool_counts(pa) == _pool_counts(pb), f"pass {p}: {pa.stats()} vs {pb.stats()}"
+    assert pa.stats()["in_use"] == 0
+    b.close()
+    bt.close()
+    a.close()
+    t.close()
+    pa.close()
+    pb.close()
