@@ -68,6 +68,8 @@ def parse():
                     help="rocprofv3 counter summary with measured HBM bytes per launch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy (torch), to calibrate HBM byte counters")
+    ap.add_argument("--batched-counters", action="store_true",
+                    help="only run the configuration-4 batch with one launch per phase (for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +83,42 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes": 2 * a.numel() * 4, "repeats": 3}), flush=True)
+
+
+def batched_counters():
+    """The configuration-4 batch alone, for hardware counters: first buckets from the
+    capacity rule (no tuning), two passes of clear, 4 keyed rounds, r/w x + 1 and
+    flatten with one launch per phase (no cooperative launch)."""
+    import torch
+    from paper_2209_00103_amd import autotune as at, ggarray as G, workloads as wl
+    torch.cuda.set_device(0)
+    sizes = [int(x) for x in wl.cfg4_sizes(1, 512)]
+    vecs = [wl.cfg4_vectors(n) for n in sizes]
+    firsts = []
+    for n, V in zip(sizes, vecs):
+        rounds = wl.cfg4_round_threads(n, 4)
+        ok = [F for F in at.CANDIDATES if at.predicted_ratio(n, V, F, rounds) <= 2.0] or [at.CANDIDATES[0]]
+        firsts.append(max(ok))
+    total = sum(sizes)
+    pool = G.Pool(int(4 * total * 2.2) + (256 << 20))
+    arrays = [G.GGArray(pool, 4, V, F) for V, F in zip(vecs, firsts)]
+    b = G.Batch(arrays)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    counts = [[wl.cfg4_round_threads(n, 4)[r] for n in sizes] for r in range(4)]
+    gens = [G.make_gen(G.GEN_KEYED, seed=1, round=r, tag=0) for r in range(4)]
+    for _ in range(2):
+        b.shrink(1, 1)
+        for r in range(4):
+            b.insert_gen(gens[r], counts[r])
+        b.rw(G.ADD1)
+        b.flatten_into(out)
+    torch.cuda.synchronize()
+    assert b.last_error() == 0
+    b.close()
+    for a in arrays:
+        a.close()
+    pool.close()
+    print(json.dumps({"batched_counters_elements": total, "passes": 2}), flush=True)
 
 
 def log(msg):
@@ -1045,6 +1083,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_counters:
+        batched_counters()
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
