@@ -151,7 +151,11 @@ int ggarray_destroy(ggarray *a, gga_stream s);
  *   elements; flags: n_threads bytes or NULL; both device memory.  Missing buckets
  *   are allocated on the device.  Pool exhaustion leaves every affected LFVector
  *   exactly as it was before the round, freezes it for later insertions and sets
- *   the sticky GGA_ENOMEM. */
+ *   the sticky GGA_ENOMEM.  With flags, a round that gives an LFVector more than
+ *   one tile of 4096 threads runs as a few launches (flag masks and tile counts,
+ *   their prefix, growth, copy) in a per-array buffer of about 0.13 bytes per
+ *   thread, grown when needed (under graph capture, where it cannot grow, the
+ *   round runs as one launch with a per-LFVector look-back instead). */
 int ggarray_insert(ggarray *a, const void *values, const uint8_t *flags, uint64_t n_threads,
                    gga_stream s);
 

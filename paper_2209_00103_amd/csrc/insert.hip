@@ -1407,6 +1407,107 @@ __global__ __launch_bounds__(kB) void packed_grow_copy_kernel(ArrRef A, TileArgs
   }
 }
 
+// ------------------------------------------- flagged rounds in two passes --
+// A round from buffers with flags, whose LFVectors span several 4096-thread
+// tiles, runs in the packed form instead of one launch with per-LFVector tickets
+// and the decoupled look-back: flag_mask_kernel reads the flags once (one wave
+// per tile, as the one-launch kernel does), keeps each lane's slot mask (512
+// bytes per tile) and writes the tile's count in the packed offset layout; the
+// group scan and the grow launch of the packed rounds follow; flag_copy_kernel
+// then takes each tile's masks and payloads and stores the kept payloads at
+// offsets known in advance, with no waits.  Element order, sizes and buckets are
+// those of the one-launch kernel; the flags cost 1/8 byte per thread more (the
+// masks written and read back).
+__global__ __launch_bounds__(kB) void flag_mask_kernel(TileArgs I, const uint8_t* flags, uint64_t* masks,
+                                                       uint64_t* off, uint64_t ntiles) {
+  __shared__ uint32_t s_sum[kPackGroup];
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const uint64_t first = (uint64_t)blockIdx.x * kPackGroup;
+  const ProdBuffer<uint32_t> prod{nullptr, flags};  // flags only
+  for (uint32_t j = w; j < kPackGroup; j += kW) {
+    const uint64_t tile = first + j;
+    uint32_t c = 0;
+    if (tile < ntiles) {
+      const uint32_t v = (uint32_t)(tile / I.tpv);
+      uint64_t g0, gend;
+      tile_range(I, v, tile - (uint64_t)v * I.tpv, kWaveTile, g0, gend);
+      const SlotMask m = wave_flags<ProdBuffer<uint32_t>>(prod, g0, gend);
+#pragma unroll
+      for (int k = 0; k < kMaskWords; ++k) masks[(tile * kMaskWords + k) * 64 + lane] = m.w[k];
+      c = (uint32_t)wave_sum64((uint64_t)m.count());
+    }
+    if (lane == 0) s_sum[j] = c;
+  }
+  __syncthreads();
+  if (tid < kPackGroup) {
+    uint64_t before = 0, all = 0;
+    for (uint32_t q = 0; q < kPackGroup; ++q) {
+      before += q < tid ? s_sum[q] : 0u;
+      all += s_sum[q];
+    }
+    if (first + tid < ntiles) off[first + tid] = before;
+    if (tid == 0) off[ntiles + blockIdx.x] = all;
+  }
+}
+
+// One wave per tile: the tile's kept payloads go to the LFVector's elements
+// rbase[v] + (tile offset within the LFVector) on, in slot order (the logical
+// thread order), payloads loaded kValBatch slots ahead of their stores.  The
+// buckets were allocated by the grow launch; lane k holds the pointer of the
+// k-th bucket the tile reaches.
+template <typename T>
+__global__ __launch_bounds__(64) void flag_copy_kernel(ArrRef A, TileArgs I, const T* values,
+                                                       const uint64_t* masks, const uint64_t* off,
+                                                       uint64_t ntiles) {
+  const uint64_t tile = blockIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t v = (uint32_t)(tile / I.tpv);
+  uint64_t g0, gend;
+  tile_range(I, v, tile - (uint64_t)v * I.tpv, kWaveTile, g0, gend);
+  if (g0 >= gend || A.dead[v]) return;
+  const uint64_t o0 = packed_offset(off, ntiles, tile);
+  const uint32_t n_t = (uint32_t)(packed_offset(off, ntiles, tile + 1) - o0);
+  if (n_t == 0) return;
+  const uint64_t base = A.rbase[v] + (o0 - packed_offset(off, ntiles, (uint64_t)v * I.tpv));
+  SlotMask bits;
+#pragma unroll
+  for (int k = 0; k < kMaskWords; ++k) bits.w[k] = masks[(tile * kMaskWords + k) * 64 + lane];
+  const uint32_t log2F = A.log2F;
+  const uint32_t b_lo = bucket_of(log2F, base), b_hi = bucket_of(log2F, base + n_t - 1);
+  const uint64_t bp = b_lo + lane <= b_hi ? A.bptr[(uint64_t)v * kMaxBuckets + b_lo + lane] : 0;
+  const ProdBuffer<T> prod{values, nullptr};
+  uint32_t run = 0;
+  if (b_lo == b_hi) {
+    const gptr<T> dst = gmem(reinterpret_cast<T*>(__shfl(bp, 0, 64)) + offset_in(log2F, base, b_lo));
+    for (int j0 = 0; j0 < kWaveSlots; j0 += kValBatch) {
+      T val[kValBatch];
+      wave_values<T, ProdBuffer<T>>(prod, g0, gend, j0, val);
+#pragma unroll
+      for (int k = 0; k < kValBatch; ++k) {
+        const bool f = bits.get(j0 + k);
+        const uint64_t m = __ballot(f);
+        if (f) dst[run + mbcnt(m)] = val[k];
+        run += (uint32_t)__popcll(m);
+      }
+    }
+    return;
+  }
+  for (int j0 = 0; j0 < kWaveSlots; j0 += kValBatch) {
+    T val[kValBatch];
+    wave_values<T, ProdBuffer<T>>(prod, g0, gend, j0, val);
+#pragma unroll
+    for (int k = 0; k < kValBatch; ++k) {
+      const bool f = bits.get(j0 + k);
+      const uint64_t m = __ballot(f);
+      const uint64_t idx = base + run + mbcnt(m);
+      const uint32_t b = f ? bucket_of(log2F, idx) : b_lo;
+      const uint64_t p = __shfl(bp, (int)(b - b_lo), 64);
+      if (f) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val[k];
+      run += (uint32_t)__popcll(m);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- dispatch --
 template <typename T, bool kStatic>
 int dispatch(const ArrRef& A, const StaticRef& S, const TileArgs& I, const InsertDesc& d,
@@ -1528,6 +1629,9 @@ int ensure_status(ggarray* a, uint64_t ntiles, hipStream_t s) {
 
 }  // namespace
 
+static int queue_flag_rounds(ggarray* a, const InsertDesc& d, const TileArgs& I, uint64_t ntiles, hipStream_t s);
+static bool flag_rounds_fit(const ggarray* a, uint64_t ntiles, hipStream_t s);
+
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_num, uint32_t sh_den) {
   if (sh_num == 0) sh_den = 0;  // a shrink that pops nothing
   a->tev_set &= ~4u;            // set again below if this round is timed
@@ -1569,6 +1673,11 @@ int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_nu
     return st;
   }
 
+  if (d.mode == kModeBuffer && d.flags && tpv > 1 && flag_rounds_fit(a, ntiles, s)) {
+    int st = queue_flag_rounds(a, d, I, ntiles, s);
+    if (sh_den && st == GGA_OK) st = launch_shrink(a, sh_num, sh_den, s);
+    return st;
+  }
   if (tpv > 1) {
     const int rc = ensure_status(a, ntiles, s);
     if (rc) return rc;
@@ -1642,6 +1751,40 @@ static int queue_packed(ggarray* a, uint64_t* off, const void* values, const uin
       hipLaunchKernelGGL(packed_copy_kernel<uint64_t>, grid, block, 0, s, a->ref, I,
                          static_cast<const uint64_t*>(values), o, ntiles, n_values);
   }
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) sizes_changed(a, s);
+  return hip_status(e);
+}
+
+// Words of a flagged round in two passes: the slot masks, then the packed offsets.
+static uint64_t flag_round_words(uint64_t ntiles) {
+  return ntiles * kMaskWords * 64 + ntiles + packed_groups(ntiles) + 1;
+}
+
+// Whether the two-pass form can run: its buffer is large enough or can be grown
+// (not while the stream is capturing; a captured round then takes the one-launch
+// form).
+static bool flag_rounds_fit(const ggarray* a, uint64_t ntiles, hipStream_t s) {
+  return flag_round_words(ntiles) <= a->pk_cap || !stream_capturing(s);
+}
+
+// A buffer round with flags over LFVectors of several tiles: masks and tile
+// counts, their prefix, the growth of every LFVector, then the copy.
+static int queue_flag_rounds(ggarray* a, const InsertDesc& d, const TileArgs& I, uint64_t ntiles, hipStream_t s) {
+  int rc = ensure_packed_offsets(a, flag_round_words(ntiles), s);
+  if (rc) return rc;
+  uint64_t* masks = a->pk_off;
+  uint64_t* off = masks + ntiles * kMaskWords * 64;
+  const uint64_t ngroups = packed_groups(ntiles);
+  hipLaunchKernelGGL(flag_mask_kernel, dim3((uint32_t)ngroups), dim3(kB), 0, s, I, d.flags, masks, off, ntiles);
+  hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off + ntiles, ngroups);
+  hipLaunchKernelGGL(packed_grow_kernel, dim3((a->V + 3) / 4), dim3(256), 0, s, a->ref, I, off, ntiles, ~0ull);
+  if (a->elem_bytes == 4)
+    hipLaunchKernelGGL(flag_copy_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(64), 0, s, a->ref, I,
+                       static_cast<const uint32_t*>(d.values), masks, off, ntiles);
+  else
+    hipLaunchKernelGGL(flag_copy_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(64), 0, s, a->ref, I,
+                       static_cast<const uint64_t*>(d.values), masks, off, ntiles);
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);
