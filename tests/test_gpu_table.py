@@ -413,3 +413,40 @@ def test_kernel_timing_events(pool):
         a.kernel_ms(0)
     a.close()
     o.close()
+
+
+def test_flagged_round_captured_before_its_buffer_exists(pool):
+    """A round from buffers with flags over several tiles per LFVector runs in two
+    passes through a per-array buffer; captured in a graph before that buffer
+    exists (it cannot grow under capture) it runs as one launch with tickets and
+    the decoupled look-back.  Replays of the captured round and eager rounds of
+    the same inputs between them (two passes) all equal the oracle."""
+    from tests.gpu_util import dev
+
+    G = gg()
+    V, F, n = 3, 64, 50000  # 16667 threads per LFVector: 5 tiles of 4096
+    a, o = G.GGArray(pool, 4, V, F), Oracle(4, V, F)
+    rng = np.random.default_rng(11)
+    vals, flags = wl.random_round(rng, n, 0.7, 4)
+    dv, df = dev(vals), dev(flags)
+    gen = G.make_gen(G.GEN_BERNOULLI, seed=4, round=2)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a.insert_gen(gen, n)  # a generated round of this shape grows the look-back words
+    s.synchronize()
+    o.insert_gen(oracle.GEN_BERNOULLI, n, seed=4, round=2)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        a.insert(dv, df)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        o.insert(vals, flags)
+        _check(G, a.flatten(), o, f"after replay {rep}")
+        a.insert(dv, df)  # eager: two passes
+        o.insert(vals, flags)
+        _check(G, a.flatten(), o, f"after eager round {rep}")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
