@@ -344,11 +344,8 @@ int run_batched(RunState& R) {
           d.tag = r;
           d.max_count = 1;
           rc = launch_insert(arr, d, l.s);
-          if (!rc && hipEventRecord(l.ev_a, l.s) != hipSuccess) rc = GGA_EHIP;
-          l.a_reqs.assign(1, r);
         } else {
           rc = launch_scan(arr, l.s);
-          if (!rc && hipEventRecord(l.ev_a, l.s) != hipSuccess) rc = GGA_EHIP;
           if (!rc && tr->kind[r] == GGA_REQ_RW) rc = launch_rw(arr, sv->cfg.rw_op, l.s);
           if (!rc && tr->kind[r] == GGA_REQ_FLATTEN) {
             R.out_offset[r] = p1.off;
@@ -359,13 +356,16 @@ int run_batched(RunState& R) {
                                hipMemcpyDeviceToDevice, l.s) != hipSuccess)
               rc = GGA_EHIP;
           }
-          l.reqs.assign(1, r);
         }
         if (rc) return rc;
+        // One event for the whole step: with a single request there is nothing to
+        // release before the step ends (one event record and query fewer than
+        // the table steps take).
+        l.reqs.assign(1, r);
         if (hipEventRecord(l.ev, l.s) != hipSuccess) return GGA_EHIP;
         R.t_issue[r] = now_ns(R.t0);
         l.busy = true;
-        l.a_done = false;
+        l.a_done = true;
         ++R.steps;
         ++R.issued;
         if (R.largest < 1) R.largest = 1;
