@@ -374,6 +374,7 @@ __device__ __forceinline__ SlotMask wave_flags(const Prod& prod, uint64_t g0, ui
   }
   if (g0 >= gend) return m;
   const uint64_t last = gend - 1;
+#pragma unroll 1
   for (int j0 = 0; j0 < kWaveSlots; j0 += 16) {  // 16 flags in flight before the first is used
     bool f[16];
 #pragma unroll
@@ -386,6 +387,28 @@ __device__ __forceinline__ SlotMask wave_flags(const Prod& prod, uint64_t g0, ui
       const int j = j0 + k;
       if (f[k] && g0 + (uint64_t)j * 64 + lane < gend) m.w[j >> 6] |= 1ull << (j & 63);
     }
+  }
+  return m;
+}
+
+// Computed 0/1 producers (take(): flag and payload from one hash): every slot's
+// payload is kept in registers from the flag pass, so the store pass does not
+// hash again (a hash under the flag branch costs the whole wave its issue slots
+// whatever the flags; configuration-2 sparse rounds: 159 -> 193 Gelem/s, at 110
+// VGPRs for 4-byte elements).
+template <typename T, class Prod>
+__device__ __forceinline__ SlotMask wave_take(const Prod& prod, uint64_t g0, uint64_t gend, T (&vals)[kWaveSlots]) {
+  const uint32_t lane = lane_id();
+  SlotMask m;
+#pragma unroll
+  for (int k = 0; k < kMaskWords; ++k) m.w[k] = 0;
+#pragma unroll
+  for (int j = 0; j < kWaveSlots; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * 64 + lane;
+    T v = 0;
+    const bool f = g < gend && prod.take(g, v);
+    vals[j] = v;
+    if (f) m.w[j >> 6] |= 1ull << (j & 63);
   }
   return m;
 }
@@ -480,7 +503,13 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
   } else {
     tile_range(I, v, t, kWaveTile, g0, gend);
   }
-  SlotMask bits = wave_flags<Prod>(prod, g0, gend);
+  // The static array's rounds are bound by the atomic on its size, not by
+  // hashing: they keep the smaller register footprint.
+  constexpr bool kKeep = !Prod::kLoads && !Prod::kDense && !kStatic;
+  T kept[kKeep ? kWaveSlots : 1];
+  SlotMask bits;
+  if constexpr (kKeep) bits = wave_take<T, Prod>(prod, g0, gend, kept);
+  else bits = wave_flags<Prod>(prod, g0, gend);
   uint64_t epoch = 0;
   if (ticketed) {
     if (lane == 0) settle_ticket(A, v, k, I.tpv);
@@ -490,7 +519,8 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     if (k != t) {  // dispatched out of order: redo the first pass for the ticket
       t = k;
       tile_range(I, v, t, kWaveTile, g0, gend);
-      bits = wave_flags<Prod>(prod, g0, gend);
+      if constexpr (kKeep) bits = wave_take<T, Prod>(prod, g0, gend, kept);
+      else bits = wave_flags<Prod>(prod, g0, gend);
     }
   }
   if (g0 >= gend) return;
@@ -521,6 +551,30 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     dense_store<T, Prod>(dst, prod, g0, n_t);
     return;
   }
+  if constexpr (kKeep) {
+    if (r.nb == 1) {
+#pragma unroll
+      for (int j = 0; j < kWaveSlots; ++j) {
+        const bool f = bits.get(j);
+        const uint64_t m = __ballot(f);
+        const uint32_t q = run + mbcnt(m);
+        if (f && q < lim) gmem(dst)[q] = kept[j];
+        run += (uint32_t)__popcll(m);
+      }
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < kWaveSlots; ++j) {
+      const bool f = bits.get(j);
+      const uint64_t m = __ballot(f);
+      const uint64_t idx = r.base + run + mbcnt(m);
+      const uint32_t b = f ? bucket_of(log2F, idx) : r.b_lo;
+      const uint64_t p = __shfl(r.bp, (int)(b - r.b_lo), 64);
+      if (f && p > kFailedPtr) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = kept[j];
+      run += (uint32_t)__popcll(m);
+    }
+    return;
+  }
   if ((kStatic || r.nb == 1) && !Prod::kLoads) {
 #pragma unroll 16
     for (int j = 0; j < kWaveSlots; ++j) {
@@ -533,6 +587,7 @@ __device__ __forceinline__ void wave_tile(const ArrRef& A, const StaticRef& S, c
     return;
   }
   if (kStatic || r.nb == 1) {
+#pragma unroll 1  // one batch of payloads in registers at a time
     for (int j0 = 0; j0 < kWaveSlots; j0 += kValBatch) {
       T v[kValBatch];
       wave_values<T, Prod>(prod, g0, gend, j0, v);
