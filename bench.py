@@ -783,12 +783,14 @@ def memory_model_leg(G, torch, np_, N=1 << 20, V=512, samples=1000):
             "rows": rows}
 
 
-def config1_leg(G, wl, torch, reps=50):
+def config1_leg(G, wl, torch, reps=200, warm=100):
     """Configuration 1 (small, launch-bound, cache-resident): 256 LFVectors, first
     bucket 1024, uint32, 2^18 threads per round inserting K(1, gid, r) with
     probability 1/2 over 4 rounds, r/w x + 1, flatten (about 2 MiB live).  Reported
     as latency: per-operation device time (HIP events; median and p10/p90 over
-    `reps` steps) and the whole step eager and replayed as a HIP graph."""
+    `reps` steps) and the whole step eager and replayed as a HIP graph.  Each
+    variant first runs `warm` untimed steps: the step is tens of microseconds, and
+    a short burst after another leg measured 30-46 us for the same graph."""
     cfg = wl.CFG1
     pool = G.Pool(256 << 20)
     a = G.GGArray(pool, 4, cfg["V"], cfg["F"])
@@ -811,7 +813,7 @@ def config1_leg(G, wl, torch, reps=50):
 
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
-        for _ in range(5):
+        for _ in range(warm):
             step()
         timer = Timer(torch)
         for _ in range(reps):
@@ -826,7 +828,7 @@ def config1_leg(G, wl, torch, reps=50):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         step()
-    for _ in range(3):
+    for _ in range(warm):
         g.replay()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -850,7 +852,7 @@ def config1_leg(G, wl, torch, reps=50):
         b.step(gens, rows, G.ADD1, out, clear=True)
 
     with torch.cuda.stream(s):
-        for _ in range(5):
+        for _ in range(warm):
             pstep()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -863,7 +865,7 @@ def config1_leg(G, wl, torch, reps=50):
     g2 = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g2, stream=s):
         pstep()
-    for _ in range(3):
+    for _ in range(warm):
         g2.replay()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
