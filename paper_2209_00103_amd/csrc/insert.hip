@@ -25,6 +25,7 @@
 // The static baseline replaces 2-4 by one global atomicAdd per tile.
 #include <mutex>
 #include <new>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -1486,6 +1487,44 @@ __device__ __forceinline__ SlotMask mask_pass_flags(const uint8_t* flags, uint64
   return m;
 }
 
+// Lane-blocked masks.  When every tile of a round starts and ends on a whole
+// 16-byte payload vector (the LFVector chunk and the thread count multiples of
+// E = 16 / sizeof(T), the payloads 16-byte aligned, the flags E-byte aligned),
+// lane l of a tile owns threads g0 + 64 E c + E l + i (chunk c < 64 / E, i < E)
+// as bit E c + i of its mask word: the mask pass reads E flag bytes per load and
+// the copy pass one 16-byte payload vector per chunk, where the slot layout
+// reads one byte and one element per lane and load.
+template <uint32_t E>
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t x) {
+  uint32_t b = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < E; ++i) b |= (uint32_t)(((x >> (8 * i)) & 0xFFu) != 0u) << i;
+  return b;
+}
+
+// One tile in lane-blocked masks, every flag word loaded before the first is
+// tested (batching a wave's four tiles of the mask pass into one set of loads
+// measured slower: 51 against 44 us).
+template <uint32_t E>
+__device__ __forceinline__ uint64_t mask_pass_blocked(const uint8_t* flags, uint64_t g0, uint64_t gend) {
+  static_assert(E == 2 || E == 4, "16-byte vectors of 4- or 8-byte elements");
+  typedef typename std::conditional<E == 4, uint32_t, uint16_t>::type W;
+  constexpr uint32_t C = 64 / E;
+  const uint32_t lane = lane_id();
+  if (g0 >= gend) return 0;
+  W f[C];
+#pragma unroll
+  for (uint32_t c = 0; c < C; ++c) {
+    const uint64_t g = g0 + (uint64_t)c * 64 * E + lane * E;
+    f[c] = *reinterpret_cast<const W*>(flags + (g < gend ? g : gend - E));  // clamped to the tile's last E flags
+  }
+  uint64_t m = 0;
+#pragma unroll
+  for (uint32_t c = 0; c < C; ++c)
+    if (g0 + (uint64_t)c * 64 * E + lane * E < gend) m |= (uint64_t)nonzero_bytes<E>(f[c]) << (c * E);
+  return m;
+}
+
 // A round from buffers with flags, whose LFVectors span several 4096-thread
 // tiles, runs in the packed form instead of one launch with per-LFVector tickets
 // and the decoupled look-back: flag_mask_kernel reads the flags once (one wave
@@ -1495,7 +1534,10 @@ __device__ __forceinline__ SlotMask mask_pass_flags(const uint8_t* flags, uint64
 // then takes each tile's masks and payloads and stores the kept payloads at
 // offsets known in advance, with no waits.  Element order, sizes and buckets are
 // those of the one-launch kernel; the flags cost 1/8 byte per thread more (the
-// masks written and read back).
+// masks written and read back).  E = 1: the slot layout; E = 2, 4: lane-blocked
+// masks (configuration-2 sparse rounds, 2^27 threads at V = 512: mask pass 56 ->
+// 44 us, copy pass 166 -> 161 us).
+template <uint32_t E>
 __global__ __launch_bounds__(kB) void flag_mask_kernel(TileArgs I, const uint8_t* flags, uint64_t* masks,
                                                        uint64_t* off, uint64_t ntiles) {
   __shared__ uint32_t s_sum[kPackGroup];
@@ -1508,10 +1550,16 @@ __global__ __launch_bounds__(kB) void flag_mask_kernel(TileArgs I, const uint8_t
       const uint32_t v = (uint32_t)(tile / I.tpv);
       uint64_t g0, gend;
       tile_range(I, v, tile - (uint64_t)v * I.tpv, kWaveTile, g0, gend);
-      const SlotMask m = mask_pass_flags(flags, g0, gend);
+      if constexpr (E == 1) {
+        const SlotMask m = mask_pass_flags(flags, g0, gend);
 #pragma unroll
-      for (int k = 0; k < kMaskWords; ++k) masks[(tile * kMaskWords + k) * 64 + lane] = m.w[k];
-      c = (uint32_t)wave_sum64((uint64_t)m.count());
+        for (int k = 0; k < kMaskWords; ++k) masks[(tile * kMaskWords + k) * 64 + lane] = m.w[k];
+        c = (uint32_t)wave_sum64((uint64_t)m.count());
+      } else {
+        const uint64_t m = mask_pass_blocked<E>(flags, g0, gend);
+        masks[tile * 64 + lane] = m;
+        c = (uint32_t)wave_sum64((uint64_t)__popcll(m));
+      }
     }
     if (lane == 0) s_sum[j] = c;
   }
@@ -1582,6 +1630,96 @@ __global__ __launch_bounds__(64) void flag_copy_kernel(ArrRef A, TileArgs I, con
       if (f) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val[k];
       run += (uint32_t)__popcll(m);
     }
+  }
+}
+
+// The copy pass over lane-blocked masks: chunk c of the tile is one 16-byte
+// payload vector per lane (kChunkBatch chunks loaded ahead of their stores); the
+// kept elements of a chunk take their places in thread order from E ballots
+// (bit i of every lane's E bits) and the lane's own rank, are gathered in LDS,
+// and leave it as contiguous runs (64 consecutive elements per store, as the
+// slot layout's ballots give: stores scattered over a lane-blocked chunk
+// measured 181 against 166 us).  kOne: the tile's elements all land in one
+// bucket, at dst1 on.
+constexpr uint32_t kChunkBatch = 8;
+template <typename T, bool kOne>
+__device__ __forceinline__ void copy_blocked(const T* values, uint64_t g0, uint64_t gend, uint64_t word,
+                                             gptr<T> dst1, uint64_t base, uint32_t log2F, uint32_t b_lo,
+                                             uint64_t bp, T* s_keep) {
+  constexpr uint32_t E = 16 / sizeof(T), C = 64 / E;
+  static_assert(kMaskWords == 1 && C % kChunkBatch == 0, "one 64-bit mask word per lane");
+  const uint32_t lane = lane_id();
+  const gptr<const T> src = gmem(values);
+  uint32_t run = 0;
+#pragma unroll 1
+  for (uint32_t c0 = 0; c0 < C; c0 += kChunkBatch) {
+    u32x4 x[kChunkBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkBatch; ++u) {
+      const uint64_t g = g0 + (uint64_t)(c0 + u) * 64 * E + lane * E;
+      x[u] = *reinterpret_cast<gptr<const u32x4>>(src + (g < gend ? g : gend - E));  // clamped to the tile's last vector
+    }
+    const uint32_t first = run;  // the batch's first position in the tile
+#pragma unroll
+    for (uint32_t u = 0; u < kChunkBatch; ++u) {
+      const uint32_t bits = (uint32_t)(word >> ((c0 + u) * E)) & ((1u << E) - 1u);
+      uint32_t pos = run - first;
+#pragma unroll
+      for (uint32_t i = 0; i < E; ++i) {
+        const uint64_t m = __ballot((bits >> i) & 1u);
+        pos += mbcnt(m);
+        run += (uint32_t)__popcll(m);
+      }
+      T el[E];
+      __builtin_memcpy(el, &x[u], 16);
+#pragma unroll
+      for (uint32_t i = 0; i < E; ++i) {
+        if ((bits >> i) & 1u) s_keep[pos++] = el[i];
+      }
+    }
+    __syncthreads();  // one wave: its LDS writes before its reads
+    const uint32_t cnt = run - first;
+    for (uint32_t e0 = 0; e0 < cnt; e0 += 64) {  // uniform trip count: the shuffle below needs every lane
+      const uint32_t e = e0 + lane;
+      const bool f = e < cnt;
+      const T val = s_keep[f ? e : 0];
+      if constexpr (kOne) {
+        if (f) dst1[first + e] = val;
+      } else {
+        const uint64_t idx = base + first + e;
+        const uint32_t b = f ? bucket_of(log2F, idx) : b_lo;
+        const uint64_t p = __shfl(bp, (int)(b - b_lo), 64);
+        if (f) gmem(reinterpret_cast<T*>(p))[offset_in(log2F, idx, b)] = val;
+      }
+    }
+    __syncthreads();  // the reads before the next batch's writes
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void flag_copy_blocked_kernel(ArrRef A, TileArgs I, const T* values,
+                                                               const uint64_t* masks, const uint64_t* off,
+                                                               uint64_t ntiles) {
+  __shared__ T s_keep[kChunkBatch * 64 * (16 / sizeof(T))];
+  const uint64_t tile = blockIdx.x;
+  const uint32_t lane = lane_id();
+  const uint32_t v = (uint32_t)(tile / I.tpv);
+  uint64_t g0, gend;
+  tile_range(I, v, tile - (uint64_t)v * I.tpv, kWaveTile, g0, gend);
+  if (g0 >= gend || A.dead[v]) return;
+  const uint64_t o0 = packed_offset(off, ntiles, tile);
+  const uint32_t n_t = (uint32_t)(packed_offset(off, ntiles, tile + 1) - o0);
+  if (n_t == 0) return;
+  const uint64_t base = A.rbase[v] + (o0 - packed_offset(off, ntiles, (uint64_t)v * I.tpv));
+  const uint64_t word = masks[tile * 64 + lane];
+  const uint32_t log2F = A.log2F;
+  const uint32_t b_lo = bucket_of(log2F, base), b_hi = bucket_of(log2F, base + n_t - 1);
+  const uint64_t bp = b_lo + lane <= b_hi ? A.bptr[(uint64_t)v * kMaxBuckets + b_lo + lane] : 0;
+  if (b_lo == b_hi) {
+    const gptr<T> dst1 = gmem(reinterpret_cast<T*>(__shfl(bp, 0, 64)) + offset_in(log2F, base, b_lo));
+    copy_blocked<T, true>(values, g0, gend, word, dst1, base, log2F, b_lo, bp, s_keep);
+  } else {
+    copy_blocked<T, false>(values, g0, gend, word, gptr<T>{}, base, log2F, b_lo, bp, s_keep);
   }
 }
 
@@ -1853,15 +1991,34 @@ static int queue_flag_rounds(ggarray* a, const InsertDesc& d, const TileArgs& I,
   uint64_t* masks = a->pk_off;
   uint64_t* off = masks + ntiles * kMaskWords * 64;
   const uint64_t ngroups = packed_groups(ntiles);
-  hipLaunchKernelGGL(flag_mask_kernel, dim3((uint32_t)ngroups), dim3(kB), 0, s, I, d.flags, masks, off, ntiles);
+  // Lane-blocked masks when every tile starts and ends on a whole 16-byte payload
+  // vector and the buffers are aligned for the vector loads; else the slot layout.
+  const uint32_t E = 16u / a->elem_bytes;
+  const bool blocked = I.chunk % E == 0 && I.n_threads % E == 0 &&
+                       (reinterpret_cast<uintptr_t>(d.values) & 15u) == 0 &&
+                       (reinterpret_cast<uintptr_t>(d.flags) & (E - 1)) == 0;
+  const dim3 mgrid((uint32_t)ngroups), mblock(kB), cgrid((uint32_t)ntiles), cblock(64);
+  if (!blocked)
+    hipLaunchKernelGGL(flag_mask_kernel<1>, mgrid, mblock, 0, s, I, d.flags, masks, off, ntiles);
+  else if (E == 4)
+    hipLaunchKernelGGL(flag_mask_kernel<4>, mgrid, mblock, 0, s, I, d.flags, masks, off, ntiles);
+  else
+    hipLaunchKernelGGL(flag_mask_kernel<2>, mgrid, mblock, 0, s, I, d.flags, masks, off, ntiles);
   hipLaunchKernelGGL(packed_tile_scan_kernel, dim3(1), dim3(1024), 0, s, off + ntiles, ngroups);
   hipLaunchKernelGGL(packed_grow_kernel, dim3((a->V + 3) / 4), dim3(256), 0, s, a->ref, I, off, ntiles, ~0ull);
-  if (a->elem_bytes == 4)
-    hipLaunchKernelGGL(flag_copy_kernel<uint32_t>, dim3((uint32_t)ntiles), dim3(64), 0, s, a->ref, I,
-                       static_cast<const uint32_t*>(d.values), masks, off, ntiles);
-  else
-    hipLaunchKernelGGL(flag_copy_kernel<uint64_t>, dim3((uint32_t)ntiles), dim3(64), 0, s, a->ref, I,
-                       static_cast<const uint64_t*>(d.values), masks, off, ntiles);
+  if (a->elem_bytes == 4) {
+    const uint32_t* vals = static_cast<const uint32_t*>(d.values);
+    if (blocked)
+      hipLaunchKernelGGL(flag_copy_blocked_kernel<uint32_t>, cgrid, cblock, 0, s, a->ref, I, vals, masks, off, ntiles);
+    else
+      hipLaunchKernelGGL(flag_copy_kernel<uint32_t>, cgrid, cblock, 0, s, a->ref, I, vals, masks, off, ntiles);
+  } else {
+    const uint64_t* vals = static_cast<const uint64_t*>(d.values);
+    if (blocked)
+      hipLaunchKernelGGL(flag_copy_blocked_kernel<uint64_t>, cgrid, cblock, 0, s, a->ref, I, vals, masks, off, ntiles);
+    else
+      hipLaunchKernelGGL(flag_copy_kernel<uint64_t>, cgrid, cblock, 0, s, a->ref, I, vals, masks, off, ntiles);
+  }
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) sizes_changed(a, s);
   return hip_status(e);

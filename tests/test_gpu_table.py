@@ -450,3 +450,38 @@ def test_flagged_round_captured_before_its_buffer_exists(pool):
     assert a.last_error() == 0
     a.close()
     o.close()
+
+
+@pytest.mark.parametrize("elem", [4, 8])
+@pytest.mark.parametrize("F", [64, 1 << 16])
+@pytest.mark.parametrize("case", ["blocked", "odd_count", "payloads_unaligned", "flags_unaligned"])
+def test_flagged_rounds_in_both_mask_layouts(pool, elem, F, case):
+    """Rounds from buffers with flags over several tiles per LFVector (two passes)
+    keep lane-blocked masks when every tile starts and ends on a whole 16-byte
+    payload vector and both buffers are aligned for the vector loads (a ragged
+    last LFVector included), and the slot layout otherwise: a thread count that
+    is not a multiple of the vector, payloads or flags off their alignment.  With
+    first buckets of 64 elements a tile's kept elements cross several buckets;
+    with 2^16 they land in one.  Every round's flatten equals the oracle."""
+    from tests.gpu_util import dev
+
+    G = gg()
+    V = 5
+    a, o = G.GGArray(pool, elem, V, F), Oracle(elem, V, F)
+    rng = np.random.default_rng(23)
+    dt = np.uint32 if elem == 4 else np.uint64
+    sv = 1 if case == "payloads_unaligned" else 0
+    sf = 1 if case == "flags_unaligned" else 0
+    # 99996 threads: chunks of 20000 (5 tiles of 4096), the last LFVector 19996
+    for r, (n, p) in enumerate([(99996, 0.6), (102400, 0.3), (99996, 0.95)]):
+        if case == "odd_count":
+            n += 1
+        vals, flags = wl.random_round(rng, n, p, elem)
+        dv = dev(np.concatenate([np.zeros(sv, dt), vals]))[sv:]
+        df = dev(np.concatenate([np.zeros(sf, np.uint8), flags]))[sf:]
+        a.insert(dv, df)
+        o.insert(vals, flags)
+        _check(G, a.flatten(), o, f"{case}, round {r}")
+    assert a.last_error() == 0
+    a.close()
+    o.close()
