@@ -62,6 +62,47 @@ def test_config2_full_size_exact(V, fused):
         pool.close()
 
 
+
+@pytest.mark.parametrize("source", ["buffers", "generated"])
+def test_config2_sparse_full_size_exact(source):
+    """The configuration-2 round sizes with Bernoulli(1/2) insertion at V = 512,
+    as the benchmark's sparse legs run them: from buffers of uint32 payloads and
+    flag bytes (a round of several tiles per LFVector takes the two passes with
+    lane-blocked masks, a smaller one the one-launch kernel), or drawn by the
+    producer (the scan with per-LFVector tickets and the decoupled look-back);
+    shrink 1/10 after each round, r/w x = 3x + 1, flatten: every element against
+    the list-form oracle."""
+    G = gg()
+    rounds = wl.cfg2_round_threads()
+    pool = G.Pool(4 * GiB)
+    a = G.GGArray(pool, 4, 512, 1024)
+    o = Oracle(4, 512, 1024, forms=oracle.FORM_LIST)
+    rng = np.random.default_rng(2209)
+    try:
+        for r, n in enumerate(rounds):
+            print(f"case sparse full size, {source}, round {r}, {n} threads", flush=True)
+            if source == "buffers":
+                vals, flags = wl.random_round(rng, n, 0.5, 4)
+                a.insert(G.to_device(vals), G.to_device(flags))
+                o.insert(vals, flags)
+                del vals, flags
+            else:
+                a.insert_gen(G.make_gen(G.GEN_BERNOULLI, seed=1, round=r), n)
+                o.insert_gen(oracle.GEN_BERNOULLI, n, seed=1, round=r)
+            a.shrink(1, 10)
+            o.shrink(1, 10)
+        a.rw(G.MUL3ADD1)
+        o.rw(oracle.OP_MUL3ADD1)
+        np.testing.assert_array_equal(a.vector_sizes().cpu().numpy().astype(np.uint64), o.vector_sizes())
+        got, ref = G.as_unsigned(a.flatten()), o.flatten()
+        assert got.size == ref.size == a.size()
+        assert np.array_equal(got, ref), _first_diff(got, ref)
+        assert a.capacity() == o.capacity() and a.last_error() == 0
+    finally:
+        o.close()
+        a.close()
+        pool.close()
+
 def test_config3_full_size_exact():
     """2^26 threads, Poisson(3) counts capped at 16, u64 payloads, V = 65536,
     4 insert phases each followed by r/w +1, flatten: every element of every
