@@ -155,7 +155,11 @@ int ggarray_destroy(ggarray *a, gga_stream s);
  *   one tile of 4096 threads runs as a few launches (flag masks and tile counts,
  *   their prefix, growth, copy) in a per-array buffer of about 0.13 bytes per
  *   thread, grown when needed (under graph capture, where it cannot grow, the
- *   round runs as one launch with a per-LFVector look-back instead). */
+ *   round runs as one launch with a per-LFVector look-back instead).  Those
+ *   launches read 16-byte payload vectors when values is 16-byte aligned, flags
+ *   is aligned to E = 16 / element bytes, and n_threads and every LFVector's
+ *   share ceil(n_threads / V) are multiples of E; any other input gives the same
+ *   result through one-element loads. */
 int ggarray_insert(ggarray *a, const void *values, const uint8_t *flags, uint64_t n_threads,
                    gga_stream s);
 
