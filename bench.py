@@ -5,8 +5,10 @@ Workload (one step): configuration 2 of the project, the paper's doubling-growth
 experiment at scale (Sec. VI-C) -- a GGArray of 512 LFVectors of uint32 with
 first bucket 1024 receives 2^28 insertions over 12 growth rounds (n_0 = 2^17,
 n_r = 2^(16+r)); after every round each LFVector pops a tenth of its elements
-(shrink 1/10, applied by the round's own launch through ggarray_insert_gen_shrink);
-then one r/w pass x = 3x + 1 over every live element; then the
+(shrink 1/10); the twelve rounds and their shrinks are one
+ggarray_insert_gen_rounds call, which runs them in one launch (each LFVector's
+wave takes it through every round); then one r/w pass x = 3x + 1 over every
+live element; then the
 prefix-sum flatten into a contiguous buffer; then the array is emptied (shrink
 1/1) for the next step.  Payloads are generated on the device: thread gid of
 round r inserts (r << 27) | gid.  All input is synthetic.
@@ -238,14 +240,20 @@ class Timer:
 
 
 def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None, round_ms=None):
+    """One step.  The rounds run as one ggarray_insert_gen_rounds call (one launch),
+    except in the per-kernel pass (timer / round_ms given), which times each round
+    as its own ggarray_insert_gen_shrink launch (the round, then its shrink 1/10)."""
     def span(name):
         return timer.span(name) if timer else _Null()
 
-    for r, n in enumerate(rounds):
-        with span(f"insert{r}"):
-            arr.insert_gen_shrink(gens[r], n, 1, 10)  # the round, then its shrink 1/10, in one launch
-        if round_ms is not None:  # kernel timing on: the launch's own start / end events
-            round_ms[r].append(arr.kernel_ms(2))
+    if timer is None and round_ms is None:
+        arr.insert_gen_rounds(gens, rounds, 1, 10)
+    else:
+        for r, n in enumerate(rounds):
+            with span(f"insert{r}"):
+                arr.insert_gen_shrink(gens[r], n, 1, 10)
+            if round_ms is not None:  # kernel timing on: the launch's own start / end events
+                round_ms[r].append(arr.kernel_ms(2))
     with span("prefix"):
         arr.prefix_into(prefix_buf)
     with span("rw"):
@@ -1145,7 +1153,7 @@ def main():
     ms_step_wall = wall * 1e3 / args.steps
 
     # The same step captured once as a HIP graph and replayed K times (one
-    # submission per step instead of ~40 launches).
+    # submission per step instead of about six launches).
     graph_ms = None
     try:
         gs = torch.cuda.Stream()
@@ -1188,6 +1196,20 @@ def main():
         k_fl.append(arr.kernel_ms(1))
     torch.cuda.synchronize()
     assert arr.last_error() == 0, "device error during the per-kernel pass"
+
+    # The twelve rounds as the timed steps run them, one ggarray_insert_gen_rounds
+    # launch, timed alone from an empty array (each rep ends with the clear).
+    k_one = []
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        arr.insert_gen_rounds(gens, rounds, 1, 10)
+        e1.record()
+        arr.shrink(1, 1)
+        torch.cuda.synchronize()
+        k_one.append(e0.elapsed_time(e1))
+    assert arr.last_error() == 0, "device error during the one-launch rounds"
 
     # The same r/w and flatten with the caches cold: before each, 1 GiB of unrelated
     # data is read (clean lines), evicting the array from L2 and the 256 MB Infinity
@@ -1254,6 +1276,11 @@ def main():
                    "cache_assisted_rounds": [r for r, b in enumerate(ins_bytes) if b < (256 << 20)],
                    "last_round_GBps": gbps(ins_bytes[-1], ins_ms[-1]),
                    "fused": "each launch also applies its round's shrink 1/10 (pops and bucket releases)",
+                   "one_launch": {"avg_us": round(1e3 * statistics.mean(k_one), 2),
+                                  "Gelem_s": (1 << 28) / (statistics.mean(k_one) * 1e-3) / 1e9,
+                                  "GBps": gbps(sum(ins_bytes), statistics.mean(k_one)),
+                                  "note": "all twelve rounds and shrinks in one ggarray_insert_gen_rounds "
+                                          "launch, as the timed steps run them; events around the call"},
                    "span_us": round(1e3 * sum(ins_span_ms) / len(rounds), 2),
                    "timing": "events recorded by each launch's own dispatch; span_us: events around the call"},
         "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,
@@ -1538,7 +1565,8 @@ def headline(line, detail_path):
                "sample": cpu["sample"], "host_cpu": cpu["host_cpu"], "host_nproc": cpu["host_nproc"]}
     head = {"insert_Gelem_s": _r(k["insert"]["Gelem_s"], 1), "rw_GBps": _r(k["rw"]["GBps"], 1),
             "flatten_GBps": _r(k["flatten"]["GBps"], 1), "rw_frac": _r(k["rw"]["frac"]),
-            "flatten_frac": _r(k["flatten"]["frac"]), "insert_frac": _r(k["insert"]["frac"])}
+            "flatten_frac": _r(k["flatten"]["frac"]), "insert_frac": _r(k["insert"]["frac"]),
+            "insert_one_launch_Gelem_s": _r(k["insert"]["one_launch"]["Gelem_s"], 1)}
     bl = line.get("baselines") or {}
     for key, src in (("static", bl.get("static")),):
         if src:

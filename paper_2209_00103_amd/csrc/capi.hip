@@ -379,6 +379,20 @@ int ggarray_insert_gen_shrink(ggarray* a, const gga_gen* g, uint64_t n_threads, 
   return launch_insert(a, d, S(s), num, den);
 }
 
+int ggarray_insert_gen_rounds(ggarray* a, const gga_gen* gens, const uint64_t* n_threads, uint32_t n_rounds,
+                              uint32_t num, uint32_t den, gga_stream s) {
+  if (!a || den == 0 || num > den || n_rounds > GGA_MAX_ROUNDS || (n_rounds && (!gens || !n_threads)))
+    return GGA_EINVAL;
+  InsertDesc ds[GGA_MAX_ROUNDS];
+  for (uint32_t r = 0; r < n_rounds; ++r) {
+    uint32_t mode = 0, maxc = 0;
+    const int rc = check_gen(&gens[r], n_threads[r], &mode, &maxc);
+    if (rc) return rc;
+    ds[r] = gen_desc(&gens[r], mode, n_threads[r]);
+  }
+  return launch_insert_rounds(a, ds, n_rounds, S(s), num, den);
+}
+
 int ggarray_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,
                             gga_stream s) {
   if (!a || !prefix || (n_values && !values)) return GGA_EINVAL;

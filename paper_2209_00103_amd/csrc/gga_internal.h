@@ -405,6 +405,15 @@ __host__ __device__ constexpr uint32_t rw_tile_elems(uint32_t elem_log2) {
 // An insertion round, then (sh_den != 0) a shrink sh_num / sh_den fused into the
 // same launch where the round runs one wave per LFVector, else launched after it.
 int launch_insert(ggarray* a, const InsertDesc& d, hipStream_t s, uint32_t sh_num = 0, uint32_t sh_den = 0);
+// Round numbers and thread counts of the rounds one launch runs.
+constexpr uint32_t kMaxFusedRounds = GGA_MAX_ROUNDS;
+struct RoundList {
+  uint32_t n;
+  uint32_t round[kMaxFusedRounds];
+  uint64_t n_threads[kMaxFusedRounds];
+};
+int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream_t s, uint32_t sh_num,
+                         uint32_t sh_den);
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);

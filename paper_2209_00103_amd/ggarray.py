@@ -62,6 +62,7 @@ _SIGS = {
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
+    "ggarray_insert_gen_rounds": [_vp, _P(GenSpec), _P(ctypes.c_uint64), _u32, _u32, _u32, _vp],
     "ggarray_kernel_timing": [_vp, _u32],
     "ggarray_set_spin_limit": [_vp, _u32],
     "ggarray_kernel_ms": [_vp, _u32, _P(ctypes.c_float)],
@@ -296,6 +297,17 @@ class GGArray:
         """insert_gen then shrink(num, den), as one launch where the round allows it."""
         _check(lib().ggarray_insert_gen_shrink(self._h, ctypes.byref(gen), int(n_threads), num, den,
                                                _stream(stream)), "ggarray_insert_gen_shrink")
+
+    def insert_gen_rounds(self, gens, n_threads, num: int = 0, den: int = 1, stream=None):
+        """Rounds r = 0.. of n_threads[r] threads with gens[r], each followed by
+        shrink(num, den) when num > 0; one launch where the rounds allow it."""
+        n = len(gens)
+        if len(n_threads) != n:
+            raise ValueError("one thread count per generator")
+        ga = (GenSpec * max(n, 1))(*gens)
+        na = (ctypes.c_uint64 * max(n, 1))(*[int(x) for x in n_threads])
+        _check(lib().ggarray_insert_gen_rounds(self._h, ga, na, n, num, den, _stream(stream)),
+               "ggarray_insert_gen_rounds")
 
     def rw(self, op: int, stream=None):
         _check(lib().ggarray_rw(self._h, op, _stream(stream)), "ggarray_rw")

@@ -27,25 +27,30 @@ def _first_diff(got, ref):
     return f"{bad.size} differ, first at {bad[:4]}"
 
 
-@pytest.mark.parametrize("V,fused", [(512, True), (512, False), (256, True), (32, False)])
-def test_config2_full_size_exact(V, fused):
+@pytest.mark.parametrize("V,mode", [(512, "rounds"), (512, "fused"), (512, "unfused"), (256, "rounds"),
+                                    (256, "fused"), (32, "unfused")])
+def test_config2_full_size_exact(V, mode):
     """2^28 insertions over 12 rounds with shrink 1/10 after each, r/w x = 3x + 1,
-    flatten: every element against the list-form oracle.  With `fused` each round
-    and its shrink are one ggarray_insert_gen_shrink call, as the benchmark runs
-    them (one launch per round at V = 512; at V = 256 the rounds of more than 8
-    tiles per LFVector take two)."""
+    flatten: every element against the list-form oracle.  "rounds": all twelve in
+    one ggarray_insert_gen_rounds call, as the benchmark's step runs them (one
+    launch at V = 512; at V = 256 the rounds of more than 8 tiles per LFVector
+    keep it round by round); "fused": each round and its shrink one
+    ggarray_insert_gen_shrink call (one launch per round at V = 512, two for
+    those larger rounds at V = 256); "unfused": insert, then shrink."""
     G = gg()
     rounds = wl.cfg2_round_threads()
     pool = G.Pool(4 * GiB)
     a = G.GGArray(pool, 4, V, 1024)
     o = Oracle(4, V, 1024, forms=oracle.FORM_LIST)
     try:
+        gens = [G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=27) for r in range(len(rounds))]
+        if mode == "rounds":
+            a.insert_gen_rounds(gens, rounds, 1, 10)
         for r, n in enumerate(rounds):
-            gen = G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=27)
-            if fused:
-                a.insert_gen_shrink(gen, n, 1, 10)
-            else:
-                a.insert_gen(gen, n)
+            if mode == "fused":
+                a.insert_gen_shrink(gens[r], n, 1, 10)
+            elif mode == "unfused":
+                a.insert_gen(gens[r], n)
                 a.shrink(1, 10)
             o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=27)
             o.shrink(1, 10)
