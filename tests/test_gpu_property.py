@@ -1,7 +1,7 @@
 """Property-based GPU parity: random shapes (V, F, element size), random rounds of
 every producer kind (buffer with and without flags, Bernoulli, round-tag, keyed,
-per-thread counts, Poisson), random shrinks, rounds fused with their shrink and
-r/w passes, drawn by Hypothesis;
+per-thread counts, Poisson), random shrinks, rounds fused with their shrink,
+several rounds with their shrinks in one call, and r/w passes, drawn by Hypothesis;
 after every operation the GPU array must equal the CPU oracle bit for bit."""
 import numpy as np
 import pytest
@@ -26,6 +26,8 @@ OPS = st.one_of(
     st.tuples(st.just("shrink"), st.integers(0, 7), st.integers(1, 7)),
     st.tuples(st.just("rw"), st.integers(0, 2)),
     st.tuples(st.just("fused"), st.integers(0, 70000), st.booleans(), st.integers(0, 7), st.integers(1, 7)),
+    st.tuples(st.just("rounds"), st.lists(st.integers(0, 70000), min_size=2, max_size=4), st.booleans(),
+              st.integers(0, 7), st.integers(1, 7)),
 )
 
 
@@ -91,6 +93,21 @@ def test_random_operation_sequences_match_oracle(pool, elem, V, F_log2, ops, see
                     a.insert_gen_shrink(G.make_gen(G.GEN_ROUND_TAG, round=step, tag_shift=20), n, num, den)
                     o.insert_gen(oracle.GEN_ROUND_TAG, n, round=step, tag_shift=20)
                 o.shrink(num, den)
+            elif kind == "rounds":  # several rounds, each with the same shrink, in one call
+                ns, keyed, num, den = op[1], op[2], min(op[3], op[4]), op[4]
+                rs = [16 * step + k for k in range(len(ns))]
+                if keyed:
+                    a.insert_gen_rounds([G.make_gen(G.GEN_KEYED, seed=9, round=r, tag=5) for r in rs], ns, num, den)
+                else:
+                    a.insert_gen_rounds([G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=20) for r in rs], ns,
+                                        num, den)
+                for r, n in zip(rs, ns):
+                    if keyed:
+                        o.insert_gen(oracle.GEN_KEYED, n, seed=9, round=r, tag=5)
+                    else:
+                        o.insert_gen(oracle.GEN_ROUND_TAG, n, round=r, tag_shift=20)
+                    if num:
+                        o.shrink(num, den)
             else:
                 a.rw(op[1])
                 o.rw(op[1])
