@@ -103,7 +103,7 @@ def test_rounds_argument_errors_leave_the_array_unchanged():
         before = G.as_unsigned(a.flatten()).copy()
         bad_keyed = G.make_gen(G.GEN_KEYED, seed=1, round=4, tag_shift=0)  # tag_shift must be 1..47
         for gens, ns, num, den in [
-            (good[:1] + [bad_keyed] + good[1:], [100, 100, 100, 100], 1, 10),  # invalid generator in round 2
+            (good[:1] + [bad_keyed] + good[1:], [100, 100, 100, 100], 1, 10),  # invalid generator in the second round
             (good, [100, 100, 100], 2, 1),                                      # num > den
             (good, [100, 100, 100], 1, 0),                                      # den == 0
             (_gens(G, "round_tag", range(17), 27), [10] * 17, 1, 10),           # more than 16 rounds
