@@ -155,3 +155,37 @@ def test_rounds_in_a_captured_graph_replay():
         o.close()
         a.close()
         p.close()
+
+
+@pytest.mark.parametrize("V,fault_at", [(6, 1), (6, 5), (6, 20), (512, 1), (512, 400), (512, 1200)])
+def test_rounds_under_a_failed_allocation(V, fault_at):
+    """Allocation number fault_at fails inside the one launch: the array reports
+    GGA_ENOMEM; every LFVector holds one of the states its own rounds can leave it
+    in (the rounds before its failed one, then no more elements but every later
+    shrink), whichever LFVector the failure hit; and all its buckets go back to
+    the pool when it is destroyed."""
+    from tests.gpu_util import gpu_flat
+    from tests.test_gpu_fused import _frozen_candidates
+
+    G = gg()
+    F = 32
+    ns = [3000, 9000, 20000, 40000]
+    rounds = [(n, 1, 10, "round_tag", r) for r, n in enumerate(ns)]
+    pool = G.Pool(256 * MiB)
+    before = pool.stats()
+    a = G.GGArray(pool, 4, V, F)
+    try:
+        pool.set_fault(fault_at)
+        a.insert_gen_rounds([G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=20) for r in range(len(ns))], ns, 1, 10)
+        pool.set_fault(0)
+        assert a.last_error() == G.ENOMEM
+        cands = _frozen_candidates(4, V, F, rounds)
+        pre = a.prefix().cpu().numpy().astype(np.int64)
+        flat = gpu_flat(a)
+        for v in range(V):
+            seg = flat[pre[v]:pre[v + 1]]
+            assert any(np.array_equal(seg, c) for c in cands[v]), f"LFVector {v}: not a state of its rounds"
+    finally:
+        a.close()
+    assert pool.stats()["in_use"] == before["in_use"]
+    pool.close()
