@@ -485,3 +485,44 @@ def test_flagged_rounds_in_both_mask_layouts(pool, elem, F, case):
     assert a.last_error() == 0
     a.close()
     o.close()
+
+
+@pytest.mark.parametrize("n", [99996, 99997], ids=["lane-blocked", "slot-layout"])
+def test_two_pass_flagged_round_in_a_graph(pool, n):
+    """A flagged round from buffers captured after an eager round of its shape has
+    grown the per-array buffer: the capture holds the two passes (mask pass, scan,
+    grow, copy; lane-blocked masks when the chunk and the thread count are whole
+    16-byte vectors, the slot layout otherwise), and every replay, with eager
+    rounds and shrinks between replays, equals the oracle."""
+    from tests.gpu_util import dev
+
+    G = gg()
+    V, F = 5, 64  # chunks of 20000 threads: 5 tiles of 4096 per LFVector
+    a, o = G.GGArray(pool, 4, V, F), Oracle(4, V, F)
+    rng = np.random.default_rng(5)
+    vals, flags = wl.random_round(rng, n, 0.6, 4)
+    dv, df = dev(vals), dev(flags)
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            a.insert(dv, df, stream=s)  # eager: grows the buffer of the two passes
+        s.synchronize()
+        o.insert(vals, flags)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            a.insert(dv, df, stream=s)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            o.insert(vals, flags)
+            _check(G, a.flatten(), o, f"after replay {rep}")
+            a.insert(dv, df)
+            a.shrink(1, 3)
+            o.insert(vals, flags)
+            o.shrink(1, 3)
+            _check(G, a.flatten(), o, f"after eager round {rep}")
+        assert a.last_error() == 0
+    finally:
+        a.close()
+        o.close()
