@@ -5,12 +5,12 @@ Workload (one step): configuration 2 of the project, the paper's doubling-growth
 experiment at scale (Sec. VI-C) -- a GGArray of 512 LFVectors of uint32 with
 first bucket 1024 receives 2^28 insertions over 12 growth rounds (n_0 = 2^17,
 n_r = 2^(16+r)); after every round each LFVector pops a tenth of its elements
-(shrink 1/10); the twelve rounds and their shrinks are one
+(shrink 1/10); then one r/w pass x = 3x + 1 over every live element; then the
+prefix-sum flatten into a contiguous buffer.  Each step starts by emptying the
+array (shrink 1/1): that clear, the twelve rounds and their shrinks are one
 ggarray_insert_gen_rounds call, which runs them in one launch (each LFVector's
-wave takes it through every round); then one r/w pass x = 3x + 1 over every
-live element; then the
-prefix-sum flatten into a contiguous buffer; then the array is emptied (shrink
-1/1) for the next step.  Payloads are generated on the device: thread gid of
+wave takes it through every round, taking the buckets it kept through the clear
+again).  Payloads are generated on the device: thread gid of
 round r inserts (r << 27) | gid.  All input is synthetic.
 
 `value` is the step throughput in inserted elements per second (Gelem/s) with
@@ -240,14 +240,18 @@ class Timer:
 
 
 def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None, round_ms=None):
-    """One step.  The rounds run as one ggarray_insert_gen_rounds call (one launch),
-    except in the per-kernel pass (timer / round_ms given), which times each round
-    as its own ggarray_insert_gen_shrink launch (the round, then its shrink 1/10)."""
+    """One step: clear, 12 rounds with their shrinks, prefix, r/w, flatten.  The
+    clear and the rounds run as one ggarray_insert_gen_rounds call (one launch;
+    the clear keeps the buckets the rounds take again), except in the per-kernel
+    pass (timer / round_ms given), which times each round as its own
+    ggarray_insert_gen_shrink launch (the round, then its shrink 1/10) and the
+    clear as its own shrink 1/1 at the end of the step."""
     def span(name):
         return timer.span(name) if timer else _Null()
 
-    if timer is None and round_ms is None:
-        arr.insert_gen_rounds(gens, rounds, 1, 10)
+    fused = timer is None and round_ms is None
+    if fused:
+        arr.insert_gen_rounds(gens, rounds, 1, 10, clear_first=True)
     else:
         for r, n in enumerate(rounds):
             with span(f"insert{r}"):
@@ -260,8 +264,9 @@ def ggarray_step(G, arr, gens, rounds, out, prefix_buf, timer=None, round_ms=Non
         arr.rw(G.MUL3ADD1)
     with span("flatten"):
         arr.flatten_into(out)
-    with span("clear"):
-        arr.shrink(1, 1)
+    if not fused:
+        with span("clear"):
+            arr.shrink(1, 1)
 
 
 class _Null:
@@ -1182,6 +1187,9 @@ def main():
         log(f"graph replay failed: {e!r}\n{traceback.format_exc()}")
     log(f"graph replay: {graph_ms} ms/step")
 
+    arr.shrink(1, 1)  # the fused steps leave the array full; the per-kernel pass starts empty
+    torch.cuda.synchronize()
+
     # Per-kernel durations: the same K steps again with events around every call, and
     # the r/w and flatten kernels timed by events their own dispatches record at the
     # kernel's start and end (the spans around those calls also hold the tile-table
@@ -1197,18 +1205,20 @@ def main():
     torch.cuda.synchronize()
     assert arr.last_error() == 0, "device error during the per-kernel pass"
 
-    # The twelve rounds as the timed steps run them, one ggarray_insert_gen_rounds
-    # launch, timed alone from an empty array (each rep ends with the clear).
+    # The clear and the twelve rounds as the timed steps run them, one
+    # ggarray_insert_gen_rounds launch (clear_first), timed alone; each rep clears
+    # the full array the one before left.
     k_one = []
+    arr.insert_gen_rounds(gens, rounds, 1, 10)
     for _ in range(args.steps):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        arr.insert_gen_rounds(gens, rounds, 1, 10)
+        arr.insert_gen_rounds(gens, rounds, 1, 10, clear_first=True)
         e1.record()
-        arr.shrink(1, 1)
         torch.cuda.synchronize()
         k_one.append(e0.elapsed_time(e1))
+    arr.shrink(1, 1)
     assert arr.last_error() == 0, "device error during the one-launch rounds"
 
     # The same r/w and flatten with the caches cold: before each, 1 GiB of unrelated
@@ -1279,8 +1289,9 @@ def main():
                    "one_launch": {"avg_us": round(1e3 * statistics.mean(k_one), 2),
                                   "Gelem_s": (1 << 28) / (statistics.mean(k_one) * 1e-3) / 1e9,
                                   "GBps": gbps(sum(ins_bytes), statistics.mean(k_one)),
-                                  "note": "all twelve rounds and shrinks in one ggarray_insert_gen_rounds "
-                                          "launch, as the timed steps run them; events around the call"},
+                                  "note": "the clear of the full array, then all twelve rounds and shrinks, "
+                                          "in one ggarray_insert_gen_rounds launch, as the timed steps run "
+                                          "them; events around the call"},
                    "span_us": round(1e3 * sum(ins_span_ms) / len(rounds), 2),
                    "timing": "events recorded by each launch's own dispatch; span_us: events around the call"},
         "rw": {"launches_per_step": 1, "avg_us": 1e3 * rw_ms, "bytes_per_launch": rw_bytes,

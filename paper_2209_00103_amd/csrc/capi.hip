@@ -380,7 +380,7 @@ int ggarray_insert_gen_shrink(ggarray* a, const gga_gen* g, uint64_t n_threads, 
 }
 
 int ggarray_insert_gen_rounds(ggarray* a, const gga_gen* gens, const uint64_t* n_threads, uint32_t n_rounds,
-                              uint32_t num, uint32_t den, gga_stream s) {
+                              uint32_t num, uint32_t den, uint32_t clear_first, gga_stream s) {
   if (!a || den == 0 || num > den || n_rounds > GGA_MAX_ROUNDS || (n_rounds && (!gens || !n_threads)))
     return GGA_EINVAL;
   InsertDesc ds[GGA_MAX_ROUNDS];
@@ -390,7 +390,7 @@ int ggarray_insert_gen_rounds(ggarray* a, const gga_gen* gens, const uint64_t* n
     if (rc) return rc;
     ds[r] = gen_desc(&gens[r], mode, n_threads[r]);
   }
-  return launch_insert_rounds(a, ds, n_rounds, S(s), num, den);
+  return launch_insert_rounds(a, ds, n_rounds, S(s), num, den, clear_first != 0);
 }
 
 int ggarray_insert_segments(ggarray* a, const void* values, const uint64_t* prefix, uint64_t n_values,

@@ -413,7 +413,7 @@ struct RoundList {
   uint64_t n_threads[kMaxFusedRounds];
 };
 int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream_t s, uint32_t sh_num,
-                         uint32_t sh_den);
+                         uint32_t sh_den, bool clear);
 int launch_static_insert(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_static_insert_atomic(gga_static* st, const InsertDesc& d, hipStream_t s);
 int launch_scan(ggarray* a, hipStream_t s, uint64_t* copy = nullptr);

@@ -59,6 +59,7 @@ struct TileArgs {
   uint32_t elem_log2;
   uint32_t sh_num = 0;   // a shrink num / den fused after the round (sh_den 0: none;
   uint32_t sh_den = 0;   // honoured by the one-wave-per-LFVector grow + store only)
+  uint32_t reuse = 0;    // a clear came first in the same launch: buckets still in the table are taken again
 };
 
 struct StaticRef {
@@ -778,13 +779,29 @@ __device__ __forceinline__ void grow_store_range(const ArrRef& A, const TileArgs
   if (b < hi) {
     if (b >= (uint32_t)kMaxBuckets) {
       failed = true;
-    } else if (I.sh_den && b >= keep) {
-      failed = !pool_alloc_release(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
     } else {
-      uint8_t* p = pool_alloc(A.pool, bucket_class(log2F, I.elem_log2, b), pool_shard(v, b, A.salt));
-      q = p ? (uint64_t)p : kFailedPtr;
-      A.bptr[(uint64_t)v * kMaxBuckets + b] = q;
-      failed = !p;
+      // After a clear in the same launch (I.reuse) a bucket may still be in the
+      // table: the round takes it again, counted as the release the clear would
+      // have made and the allocation the round makes (pool_reuse); one the round
+      // reaches and its shrink releases goes back to the pool now.
+      uint64_t* slot = A.bptr + (uint64_t)v * kMaxBuckets + b;
+      const uint64_t kept = I.reuse ? *slot : 0;
+      const uint32_t cls = bucket_class(log2F, I.elem_log2, b);
+      if (I.sh_den && b >= keep) {
+        if (kept) {
+          pool_free(A.pool, reinterpret_cast<uint8_t*>(kept), cls, pool_shard(v, b, A.salt));
+          *slot = 0;
+        }
+        failed = !pool_alloc_release(A.pool, cls, pool_shard(v, b, A.salt));
+      } else if (kept) {
+        q = kept;
+        failed = !pool_reuse(A.pool, pool_shard(v, b, A.salt));
+      } else {
+        uint8_t* p = pool_alloc(A.pool, cls, pool_shard(v, b, A.salt));
+        q = p ? (uint64_t)p : kFailedPtr;
+        *slot = q;
+        failed = !p;
+      }
     }
   }
   // Bucket `lane`'s pointer when this round allocated it (lane lo + k holds bucket lo + k).
@@ -850,17 +867,36 @@ __global__ __launch_bounds__(256) void grow_store_kernel(ArrRef A, TileArgs I, P
 // once they are complete; a device-scope fence would also write back the XCD's
 // L2 each round (configuration 2's twelve rounds: 337 us with it, 225 us with
 // the workgroup fence, 309-317 us as twelve launches).
+//
+// With I.reuse the launch starts with a clear (every LFVector emptied, as a
+// shrink of 1/1): a live LFVector only sets its size to 0 and keeps its buckets
+// in the table for the rounds to take again (grow_store_range), and the ones no round
+// took go back to the pool at the end; a frozen LFVector releases them at once,
+// as the clear does.  Sizes, contents, capacity and pool counts are those of the
+// clear and the rounds as calls of their own.
 template <typename T, class Prod>
 __global__ __launch_bounds__(256) void grow_store_rounds_kernel(ArrRef A, TileArgs I, Prod prod, RoundList R) {
   const uint32_t v = blockIdx.x * 4u + (threadIdx.x >> 6);
   if (v >= A.V) return;
+  const uint32_t lane = lane_id();
+  if (I.reuse) {
+    if (A.dead[v])
+      shrink_vector(A, v, 1, 1, I.elem_log2);
+    else if (lane == 0)
+      A.size[v] = 0;
+  }
 #pragma unroll 1
   for (uint32_t r = 0; r < R.n; ++r) {
-    if (r) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    if (r || I.reuse) __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
     I.n_threads = R.n_threads[r];
     I.chunk = (I.n_threads + A.V - 1) / A.V;
     prod.round = R.round[r];
     grow_store_vector<T, Prod>(A, I, prod, v);
+  }
+  if (I.reuse) {  // buckets kept through the clear that no round took
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    const uint64_t s = A.size[v];
+    release_bucket(A, v, lane, nbuckets_for(A.log2F, s), kMaxBuckets, false, 0, I.elem_log2);
   }
 }
 
@@ -1878,9 +1914,9 @@ static bool flag_rounds_fit(const ggarray* a, uint64_t ntiles, hipStream_t s);
 // the thread count change between rounds; otherwise the rounds one by one.
 // Every round is checked before anything is queued.
 int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream_t s, uint32_t sh_num,
-                         uint32_t sh_den) {
+                         uint32_t sh_den, bool clear) {
   if (sh_num == 0) sh_den = 0;
-  bool fuse = n >= 2 && n <= kMaxFusedRounds;
+  bool fuse = (n >= 2 || (n == 1 && clear)) && n <= kMaxFusedRounds;
   for (uint32_t r = 0; r < n; ++r) {
     const InsertDesc& d = ds[r];
     const uint64_t chunk = (d.n_threads + a->V - 1) / a->V;
@@ -1894,6 +1930,10 @@ int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream
            d.seed == ds[0].seed && d.tag_shift == ds[0].tag_shift && d.tag == ds[0].tag && wave_per_vector(I, a->V);
   }
   if (!fuse) {
+    if (clear) {
+      const int st = launch_shrink(a, 1, 1, s);
+      if (st) return st;
+    }
     for (uint32_t r = 0; r < n; ++r) {
       const int st = launch_insert(a, ds[r], s, sh_num, sh_den);
       if (st) return st;
@@ -1901,6 +1941,7 @@ int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream
     return GGA_OK;
   }
   a->tev_set &= ~4u;  // not a timed round
+  if (clear) a->size_ub = 0;
   RoundList R{};
   R.n = n;
   for (uint32_t r = 0; r < n; ++r) {
@@ -1912,6 +1953,7 @@ int launch_insert_rounds(ggarray* a, const InsertDesc* ds, uint32_t n, hipStream
   I.elem_log2 = a->elem_log2;
   I.sh_num = sh_num;
   I.sh_den = sh_den;
+  I.reuse = clear ? 1u : 0u;
   const dim3 grid((a->V + 3) / 4), block(256);
   const InsertDesc& d = ds[0];
   if (d.mode == kModeRoundTag) {

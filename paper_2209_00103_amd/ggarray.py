@@ -62,7 +62,7 @@ _SIGS = {
     "ggarray_insert_gen": [_vp, _P(GenSpec), _u64, _vp],
     "ggarray_shrink": [_vp, _u32, _u32, _vp],
     "ggarray_insert_gen_shrink": [_vp, _P(GenSpec), _u64, _u32, _u32, _vp],
-    "ggarray_insert_gen_rounds": [_vp, _P(GenSpec), _P(ctypes.c_uint64), _u32, _u32, _u32, _vp],
+    "ggarray_insert_gen_rounds": [_vp, _P(GenSpec), _P(ctypes.c_uint64), _u32, _u32, _u32, _u32, _vp],
     "ggarray_kernel_timing": [_vp, _u32],
     "ggarray_set_spin_limit": [_vp, _u32],
     "ggarray_kernel_ms": [_vp, _u32, _P(ctypes.c_float)],
@@ -298,15 +298,18 @@ class GGArray:
         _check(lib().ggarray_insert_gen_shrink(self._h, ctypes.byref(gen), int(n_threads), num, den,
                                                _stream(stream)), "ggarray_insert_gen_shrink")
 
-    def insert_gen_rounds(self, gens, n_threads, num: int = 0, den: int = 1, stream=None):
-        """Rounds r = 0.. of n_threads[r] threads with gens[r], each followed by
-        shrink(num, den) when num > 0; one launch where the rounds allow it."""
+    def insert_gen_rounds(self, gens, n_threads, num: int = 0, den: int = 1, clear_first: bool = False,
+                          stream=None):
+        """With clear_first, shrink(1, 1) first; then rounds r = 0.. of n_threads[r]
+        threads with gens[r], each followed by shrink(num, den) when num > 0; one
+        launch where the rounds allow it."""
         n = len(gens)
         if len(n_threads) != n:
             raise ValueError("one thread count per generator")
         ga = (GenSpec * max(n, 1))(*gens)
         na = (ctypes.c_uint64 * max(n, 1))(*[int(x) for x in n_threads])
-        _check(lib().ggarray_insert_gen_rounds(self._h, ga, na, n, num, den, _stream(stream)),
+        _check(lib().ggarray_insert_gen_rounds(self._h, ga, na, n, num, den, int(bool(clear_first)),
+                                               _stream(stream)),
                "ggarray_insert_gen_rounds")
 
     def rw(self, op: int, stream=None):

@@ -67,7 +67,7 @@ def test_host_side_validation(G):
     assert L.ggarray_insert(None, None, None, 0, None) == EINVAL
     assert L.ggarray_insert_gen(None, None, 0, None) == EINVAL
     assert L.ggarray_shrink(None, 1, 2, None) == EINVAL
-    assert L.ggarray_insert_gen_rounds(None, None, None, 0, 1, 10, None) == EINVAL
+    assert L.ggarray_insert_gen_rounds(None, None, None, 0, 1, 10, 0, None) == EINVAL
     assert L.ggarray_rw(None, 0, None) == EINVAL
     assert L.ggarray_flatten(None, None, 0, None) == EINVAL
     assert L.ggarray_size(None, None, None) == EINVAL

@@ -57,8 +57,12 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("clear", [False, True], ids=["", "clear-first"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_rounds_equal_the_calls_one_by_one_and_the_oracle(case):
+def test_rounds_equal_the_calls_one_by_one_and_the_oracle(case, clear):
+    """With clear_first the launch starts with the clear of the array the pass
+    before left full, so its rounds take kept buckets again; the twin array calls
+    ggarray_shrink(1, 1) first."""
     c = CASES[case]
     G = gg()
     rounds = [5 + 2 * r for r in range(len(c["ns"]))]
@@ -70,7 +74,10 @@ def test_rounds_equal_the_calls_one_by_one_and_the_oracle(case):
     try:
         for rep in range(2):  # the second pass starts from the first's state
             print(f"case {case} pass {rep}", flush=True)
-            a.insert_gen_rounds(gens, c["ns"], c["num"], c["den"])
+            a.insert_gen_rounds(gens, c["ns"], c["num"], c["den"], clear_first=clear)
+            if clear:
+                b.shrink(1, 1)
+                o.shrink(1, 1)
             for g, n in zip(gens, c["ns"]):
                 if c["num"]:
                     b.insert_gen_shrink(g, n, c["num"], c["den"])
@@ -157,13 +164,15 @@ def test_rounds_in_a_captured_graph_replay():
         p.close()
 
 
+@pytest.mark.parametrize("clear", [False, True], ids=["", "clear-first"])
 @pytest.mark.parametrize("V,fault_at", [(6, 1), (6, 5), (6, 20), (512, 1), (512, 400), (512, 1200)])
-def test_rounds_under_a_failed_allocation(V, fault_at):
-    """Allocation number fault_at fails inside the one launch: the array reports
-    GGA_ENOMEM; every LFVector holds one of the states its own rounds can leave it
-    in (the rounds before its failed one, then no more elements but every later
-    shrink), whichever LFVector the failure hit; and all its buckets go back to
-    the pool when it is destroyed."""
+def test_rounds_under_a_failed_allocation(V, fault_at, clear):
+    """Allocation number fault_at fails inside the one launch (with clear_first,
+    after the clear of a full array, where a kept bucket's reuse may be the attempt
+    that fails): the array reports GGA_ENOMEM; every LFVector holds one of the
+    states its own rounds can leave it in (the rounds before its failed one, then
+    no more elements but every later shrink), whichever LFVector the failure hit;
+    and all its buckets go back to the pool when it is destroyed."""
     from tests.gpu_util import gpu_flat
     from tests.test_gpu_fused import _frozen_candidates
 
@@ -174,9 +183,12 @@ def test_rounds_under_a_failed_allocation(V, fault_at):
     pool = G.Pool(256 * MiB)
     before = pool.stats()
     a = G.GGArray(pool, 4, V, F)
+    gens = [G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=20) for r in range(len(ns))]
     try:
+        if clear:  # a full array first: the clear keeps its buckets for the rounds under the fault
+            a.insert_gen_rounds(gens, ns, 1, 10)
         pool.set_fault(fault_at)
-        a.insert_gen_rounds([G.make_gen(G.GEN_ROUND_TAG, round=r, tag_shift=20) for r in range(len(ns))], ns, 1, 10)
+        a.insert_gen_rounds(gens, ns, 1, 10, clear_first=clear)
         pool.set_fault(0)
         assert a.last_error() == G.ENOMEM
         cands = _frozen_candidates(4, V, F, rounds)
