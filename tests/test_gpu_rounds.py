@@ -128,9 +128,12 @@ def test_rounds_argument_errors_leave_the_array_unchanged():
         p.close()
 
 
-def test_rounds_in_a_captured_graph_replay():
+@pytest.mark.parametrize("clear", [False, True], ids=["", "clear-first"])
+def test_rounds_in_a_captured_graph_replay(clear):
     """The one-launch rounds captured in a graph: every replay, with an eager
-    flatten and clear between replays, equals the oracle's rounds."""
+    flatten between replays, equals the oracle's rounds; without clear_first an
+    eager clear follows each check, with it each replay clears the array the one
+    before filled and takes its buckets again."""
     G = gg()
     p = G.Pool(256 * MiB)
     V, F = 512, 1024
@@ -147,7 +150,7 @@ def test_rounds_in_a_captured_graph_replay():
         s.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            a.insert_gen_rounds(gens, ns, 1, 10, stream=s)
+            a.insert_gen_rounds(gens, ns, 1, 10, clear_first=clear, stream=s)
         torch.cuda.synchronize()
         for rep in range(3):
             g.replay()
@@ -155,7 +158,8 @@ def test_rounds_in_a_captured_graph_replay():
             _oracle_rounds(o, "round_tag", rounds, ns, 27, 1, 10)
             got, ref = G.as_unsigned(a.flatten()), o.flatten()
             assert got.size == ref.size and np.array_equal(got, ref), f"replay {rep}"
-            a.shrink(1, 1)
+            if not clear:
+                a.shrink(1, 1)
             o.shrink(1, 1)
         assert a.last_error() == 0
     finally:
