@@ -233,25 +233,24 @@ int ggarray_shrink(ggarray *a, uint32_t num, uint32_t den, gga_stream s);
 int ggarray_insert_gen_shrink(ggarray *a, const gga_gen *g, uint64_t n_threads, uint32_t num, uint32_t den,
                               gga_stream s);
 
-/* ggarray_insert_gen_rounds: with clear_first != 0 first ggarray_shrink(a, 1, 1);
+/* ggarray_insert_gen_rounds: with clear_first != 0, first ggarray_shrink(a, 1, 1);
  *   then n_rounds insertion rounds in order, round r of n_threads[r] logical
  *   threads with the payloads of gens[r] (as ggarray_insert_gen), each followed by
  *   ggarray_shrink(a, num, den) when num > 0 (the generic vector interface Sec. I
  *   names; a round is Alg. 1 with Alg. 2).  gens, n_threads: host arrays of
  *   n_rounds entries (at most GGA_MAX_ROUNDS), read before returning.  Sizes,
- *   contents, capacity and pool counts are those of the calls made one by one
- *   (in the one launch below, the clear keeps each bucket in place for the round
- *   that reaches it again, counted as released and allocated, and returns the
- *   others at the end of the launch).  Rounds of round-tag or keyed payloads that
- *   differ only in round and thread count, each running one wave per LFVector
- *   (at most 8 tiles of 4096 threads per LFVector, or 512 LFVectors or more),
- *   run in one launch in which each LFVector's wave takes it through every round;
- *   any other list runs round by round.  In the one launch the LFVectors reach
- *   the pool in another order, so when it runs dry the LFVectors that freeze
- *   (GGA_ENOMEM), and the buckets they keep, can differ from those of the calls
- *   one by one.  den == 0,
- *   num > den, too many rounds or an invalid generator or round size in any round:
- *   GGA_EINVAL, nothing launched. */
+ *   contents, capacity and pool counts are those of the calls made one by one.
+ *   One launch runs everything when the rounds are of round-tag or keyed payloads
+ *   that differ only in round and thread count, each runs one wave per LFVector
+ *   (at most 8 tiles of 4096 threads per LFVector, or 512 LFVectors or more), and
+ *   there are two rounds or more or a clear: each LFVector's wave takes it through
+ *   the clear and every round; the clear keeps each bucket in place for the round
+ *   that reaches it again (counted as released and allocated) and returns the
+ *   others at the end of the launch.  Any other list runs call by call.  In the one
+ *   launch the LFVectors reach the pool in another order, so when it runs dry the
+ *   LFVectors that freeze (GGA_ENOMEM), and the buckets they keep, can differ from
+ *   those of the calls one by one.  den == 0, num > den, too many rounds or an
+ *   invalid generator or round size in any round: GGA_EINVAL, nothing launched. */
 #define GGA_MAX_ROUNDS 16
 int ggarray_insert_gen_rounds(ggarray *a, const gga_gen *gens, const uint64_t *n_threads, uint32_t n_rounds,
                               uint32_t num, uint32_t den, uint32_t clear_first, gga_stream s);
